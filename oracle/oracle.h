@@ -1,0 +1,98 @@
+/*
+ * FP64 CPU oracle for the staggered embedded-boundary (cut-cell) update with
+ * weighted state redistribution.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link or
+ * call this code: only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark use it.  It shares no source with the HIP library.
+ *
+ * It is deliberately plain and slow: dense triple loops over every control
+ * volume, generic Sutherland-Hodgman polygon clipping with exact quadrature for
+ * the geometry, explicit neighbourhood sets for the redistribution.
+ *
+ * Storage convention used throughout the oracle: every instance (0 = cell
+ * centred, 1 = x-face, 2 = y-face, 3 = z-face control volumes) is held as a
+ * dense array of (nz+1) x ny x nx entries, x fastest.  Entry (i,j,k) of the
+ * x-face instance is the control volume around the x-face at node i, etc.
+ * Planes that are not control volumes (k = nz for instances 0-2; k = 0 and
+ * k = nz for the z-face instance) have volume fraction 0; their lower z-face
+ * data are still filled where the face exists (the domain top).
+ */
+#ifndef EBS_ORACLE_H
+#define EBS_ORACLE_H
+
+#include <stdint.h>
+
+/* geometry quantities per control volume (first index of the geometry array) */
+enum {
+    OQ_ALPHA = 0,         /* volume fraction                                       */
+    OQ_BX, OQ_BY, OQ_BZ,  /* area fractions of the lower x, y, z faces             */
+    OQ_FX1, OQ_FX2,       /* lower x-face centroid offset (y, z) / (dy, dz)        */
+    OQ_FY1, OQ_FY2,       /* lower y-face centroid offset (x, z) / (dx, dz)        */
+    OQ_FZ1, OQ_FZ2,       /* lower z-face centroid offset (x, y) / (dx, dy)        */
+    OQ_VCX, OQ_VCY, OQ_VCZ, /* volume centroid offset from the CV centre / dx_d    */
+    OQ_AX, OQ_AY, OQ_AZ,  /* EB area vector (into the fluid) / face area of dir d  */
+    OQ_AREA,              /* EB facet area / (dx*dy)                               */
+    OQ_EBX, OQ_EBY, OQ_EBZ, /* EB centroid offset from the CV centre / dx_d        */
+    OQ_N
+};
+
+/* redistribution quantities per control volume */
+enum {
+    OW_SMALL = 0,  /* 1 if the CV is small (0 < alpha < small_vfrac)            */
+    OW_TIER,       /* merge tier 1..3 for small CVs, 0 otherwise                 */
+    OW_MASK,       /* members of M as a 27-bit mask over offsets in {-1,0,1}^3   */
+    OW_NCOUNT,     /* N = |W| (number of neighbourhoods containing the CV)       */
+    OW_KAPPA, OW_OMEGA,
+    OW_VHAT,       /* neighbourhood volume / (dx dy dz)                          */
+    OW_XHX, OW_XHY, OW_XHZ, /* neighbourhood centroid offset from CV centre / dx_d */
+    OW_N
+};
+
+typedef struct {
+    int32_t n[3];
+    double dx[3];
+    double lo[3];
+    double small_vfrac;  /* V_target / (dx dy dz), 0.5 in the paper      */
+    int32_t limiter;     /* 0 component-wise BJ, 1 scalar BJ, 2 none      */
+    int32_t eb_flux;     /* 0 no-flux wall, 1 free-stream closure mode    */
+} orc_grid;
+
+/* geometry: geo[inst] points at OQ_N * (nz+1)*ny*nx doubles; ctype[inst] at
+ * (nz+1)*ny*nx bytes (0 covered or not a CV, 1 regular, 2 cut) */
+int orc_geometry(const orc_grid* g, const double* h_nodes, double* const geo[4],
+                 int8_t* const ctype[4]);
+
+/* redistribution tables: w[inst] points at OW_N * (nz+1)*ny*nx doubles */
+int orc_wsrd_setup(const orc_grid* g, double* const geo[4], double* const w[4]);
+
+/* One explicit stage: Uhat = Un + cdt * dU(Ucur).  Each state is five dense
+ * fields in instance storage: rho, rhotheta (inst 0), rhou (1), rhov (2),
+ * rhow (3).  Entries that are not fluid CVs are written as 0. */
+int orc_advance(const orc_grid* g, double* const geo[4], const double* const Un[5],
+                const double* const Ucur[5], double* const Uhat[5], double cdt);
+
+/* Redistribution of one provisional state, Uout = R(Uhat), field by field. */
+int orc_redistribute(const orc_grid* g, double* const geo[4], double* const w[4],
+                     const double* const Uhat[5], double* const Uout[5]);
+
+/* Same, also returning the limited gradient of every CV: sig[f] points at
+ * 3 * (nz+1)*ny*nx doubles (x, y, z interleaved per CV), physical units. */
+int orc_redistribute_sig(const orc_grid* g, double* const geo[4], double* const w[4],
+                         const double* const Uhat[5], double* const Uout[5],
+                         double* const sig[5]);
+
+/* Raw face fluxes, exposed for the telescoping and polynomial-exactness pins:
+ * F[d] receives the flux used in the divergence on the lower d-face of every
+ * CV of instance inst for field f (0 rho, 1 rhotheta, 2 rhou, 3 rhov, 4 rhow). */
+int orc_face_fluxes(const orc_grid* g, double* const geo[4], const double* const U[5],
+                    int field, double* const F[3], double* const Fhat[3]);
+
+/* Moments of the fluid part {z > terrain} of an axis-aligned box inside the
+ * xy-cell (ci,cj): exposed so tests can check the clipper against closed forms.
+ * out: [vol, mx, my, mz, area vector x,y,z, eb area, 6 face areas] with moments
+ * relative to the box corner. */
+int orc_box_moments(const orc_grid* g, const double* h_nodes, int ci, int cj,
+                    const double rect[4], double za, double zb, int bottom, double* out);
+
+#endif

@@ -1,0 +1,102 @@
+"""Independent test helpers: closed forms and brute-force samplers written
+from the definitions (fluid = {z > h(x, y)} with h the piecewise-linear
+interpolant of the nodal heights on the two triangles of each xy-cell).  They
+share no code with the oracle or the library."""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+
+def halfspace_box_volume(lo, hi, w, d):
+    """Exact volume of {p in box: w . p <= d} by inclusion-exclusion over the
+    box vertices (coefficients made non-negative by reflection; zero
+    coefficients factor out), evaluated in exact rational arithmetic on the
+    binary values of the inputs and rounded once at the end."""
+    from fractions import Fraction as Fr
+    lo = [Fr(float(v)) for v in lo]
+    L = [Fr(float(h)) - l for h, l in zip(hi, lo)]
+    w = [Fr(float(v)) for v in w]
+    D = Fr(float(d)) - sum(wi * li for wi, li in zip(w, lo))
+    c = []
+    Ls = []
+    factor = Fr(1)
+    for i in range(3):
+        if w[i] < 0:
+            D -= w[i] * L[i]
+            c.append(-w[i])
+            Ls.append(L[i])
+        elif w[i] > 0:
+            c.append(w[i])
+            Ls.append(L[i])
+        else:
+            factor *= L[i]
+    n = len(c)
+    if n == 0:
+        return float(factor) if D >= 0 else 0.0
+    tot = Fr(0)
+    for S in itertools.product((0, 1), repeat=n):
+        t = D - sum(c[i] * Ls[i] for i in range(n) if S[i])
+        if t > 0:
+            tot += (-1) ** sum(S) * t ** n
+    den = Fr(math.factorial(n))
+    for ci in c:
+        den *= ci
+    return float(factor * tot / den)
+
+
+def interp_h(h_nodes, grid, x, y):
+    """Piecewise-linear terrain at points (x, y) (arrays), two triangles per
+    xy-cell split along the (i,j)-(i+1,j+1) diagonal."""
+    nx, ny, _ = grid.n
+    dx, dy = grid.dx[0], grid.dx[1]
+    fx = (np.asarray(x) - grid.lo[0]) / dx
+    fy = (np.asarray(y) - grid.lo[1]) / dy
+    i = np.clip(np.floor(fx).astype(int), 0, nx - 1)
+    j = np.clip(np.floor(fy).astype(int), 0, ny - 1)
+    s = fx - i
+    t = fy - j
+    ha = h_nodes[j, i]
+    hb = h_nodes[j, i + 1]
+    hc = h_nodes[j + 1, i + 1]
+    hd = h_nodes[j + 1, i]
+    lower = s >= t
+    h = np.where(lower, ha + s * (hb - ha) + t * (hc - hb), ha + s * (hc - hd) + t * (hd - ha))
+    gx = np.where(lower, (hb - ha) / dx, (hc - hd) / dx)
+    gy = np.where(lower, (hc - hb) / dy, (hd - ha) / dy)
+    return h, gx, gy
+
+
+def sample_cv(h_nodes, grid, box, M=256):
+    """Brute-force moments of the fluid part of an axis-aligned box
+    (x0, x1, y0, y1, z0, z1) that stays inside the domain in x and y:
+    2-D midpoint rule in (x, y) with the z extent integrated exactly.
+    Returns volume, centroid (3), and the EB area vector (3)."""
+    x0, x1, y0, y1, z0, z1 = box
+    xs = x0 + (np.arange(M) + 0.5) * (x1 - x0) / M
+    ys = y0 + (np.arange(M) + 0.5) * (y1 - y0) / M
+    X, Y = np.meshgrid(xs, ys)
+    h, gx, gy = interp_h(h_nodes, grid, X, Y)
+    dA = (x1 - x0) * (y1 - y0) / (M * M)
+    zc = np.clip(h, z0, z1)
+    col = z1 - zc
+    V = col.sum() * dA
+    cx = (X * col).sum() * dA / V if V > 0 else 0.0
+    cy = (Y * col).sum() * dA / V if V > 0 else 0.0
+    cz = (0.5 * (z1 * z1 - zc * zc)).sum() * dA / V if V > 0 else 0.0
+    inside = (h >= z0) & (h < z1)
+    av = np.array([(-gx * inside).sum(), (-gy * inside).sum(), inside.sum()]) * dA
+    return V, np.array([cx, cy, cz]), av
+
+
+def sample_vface(h_nodes, grid, d, f, s0, s1, z0, z1, M=4096):
+    """Fluid fraction of the vertical face {x = f} (d = 0) or {y = f} (d = 1)
+    over s in [s0, s1] and z in [z0, z1] by a 1-D midpoint rule."""
+    s = s0 + (np.arange(M) + 0.5) * (s1 - s0) / M
+    if d == 0:
+        h, _, _ = interp_h(h_nodes, grid, np.full(M, f), s)
+    else:
+        h, _, _ = interp_h(h_nodes, grid, s, np.full(M, f))
+    return float((z1 - np.clip(h, z0, z1)).mean() / (z1 - z0))
