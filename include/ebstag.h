@@ -1,0 +1,205 @@
+/*
+ * ebstag — staggered-mesh embedded-boundary (cut-cell) update with weighted
+ * state redistribution, for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Every entry point returns an ebs_status; no C++ exception or
+ * longjmp crosses it.  Plain pointers and sizes only.
+ *
+ * Method (Kang et al., "An Embedded Boundary Scheme for Three-Dimensional Flow
+ * Over Terrain on a Staggered Mesh"):
+ *   - four geometry instances: cell-centred control volumes (CVs) and one
+ *     staggered CV per x-, y- and z-face (Section 3.2, staggered data built
+ *     from two half-cells of neighbouring cells);
+ *   - explicit update of Eqs. update-cc / update-fc (Section 3.1) with the
+ *     advective flux of Section 4.1 (third-order upwind, order reduction next
+ *     to covered cells, flux moved to the cut-face centroid, no flux through
+ *     walls); the source term is zero;
+ *   - weighted state redistribution applied to every variable after every
+ *     Runge-Kutta stage (Section 5.1, Algorithm 1 of Section 5.2).
+ *
+ * Grid and storage.  nx x ny x nz cells of size dx x dy x dz, lower corner lo.
+ * x and y are periodic, z is bounded by no-flux walls.  The terrain is a
+ * height function h(x, y) given on the (nx+1) x (ny+1) nodes (x fastest); the
+ * fluid is {z > h} with h the continuous piecewise-linear interpolant on the
+ * two triangles (i,j)(i+1,j)(i+1,j+1) and (i,j)(i+1,j+1)(i,j+1) of each
+ * xy-cell.  The last node row / column must repeat the first (periodicity),
+ * and the top cell layer must be free of terrain.
+ *
+ * State: five caller-owned device arrays, x fastest, element type double
+ * (EBS_F64) or float (EBS_F32_BULK):
+ *     rho, rhotheta : nz     x ny     x nx
+ *     rhou          : nz     x ny     x (nx+1)   entry nx repeats entry 0
+ *     rhov          : nz     x (ny+1) x nx       entry ny repeats entry 0
+ *     rhow          : (nz+1) x ny     x nx       planes 0 and nz are walls
+ * Inputs are read only where the entry is a fluid CV; every output entry is
+ * written (0 where the CV has no fluid, at the walls, and the periodic
+ * repeats copy entry 0).
+ */
+#ifndef EBSTAG_H
+#define EBSTAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EBS_OK = 0,
+    EBS_E_ARG = 1,         /* invalid argument; nothing was written          */
+    EBS_E_OOM = 2,         /* device or host allocation failed               */
+    EBS_E_HIP = 3,         /* a HIP runtime call failed                      */
+    EBS_E_ORDER = 4,       /* call made before the geometry was built        */
+    EBS_E_UNSUPPORTED = 5  /* valid request outside what this build supports */
+} ebs_status;
+
+typedef enum {
+    EBS_F64 = 0,      /* state and all arithmetic in double                          */
+    EBS_F32_BULK = 1  /* state in float; regular-region flux and update in float;    */
+                      /* geometry, cut-region fluxes, redistribution, sums in double  */
+} ebs_precision;
+
+typedef enum {
+    EBS_EB_WALL = 0,       /* zero normal convective flux through the EB (Section 4.1) */
+    EBS_EB_FREESTREAM = 1  /* test mode: EB flux = -(area vector).(mean provisional    */
+                           /* flux of the CV); any uniform flow is then steady         */
+} ebs_eb_flux;
+
+typedef enum {
+    EBS_LIM_BJ_COMPONENT = 0, /* Barth-Jespersen factor per gradient component (default) */
+    EBS_LIM_BJ_SCALAR = 1,    /* one factor for the whole gradient                      */
+    EBS_LIM_NONE = 2          /* unlimited linear reconstruction                        */
+} ebs_limiter;
+
+typedef struct {
+    int32_t n[3];        /* cells; nx, ny >= 8, nz >= 4                         */
+    double dx[3];        /* cell size, > 0                                      */
+    double lo[3];        /* lower domain corner                                 */
+    uint32_t periodic;   /* bit d set: axis d periodic; must be 0x3 (x, y)      */
+    double small_vfrac;  /* V_target / (dx dy dz), in (0, 1); the paper uses 0.5 */
+    int32_t precision;   /* ebs_precision */
+    int32_t limiter;     /* ebs_limiter   */
+    int32_t eb_flux;     /* ebs_eb_flux   */
+} ebs_grid;
+
+/* Half-open cell ranges [lo, hi); the list must tile the domain without
+ * overlap.  Boxes are the units of batched work (AMR-style patches of one
+ * level); results do not depend on the tiling. */
+typedef struct {
+    int32_t lo[3], hi[3];
+} ebs_box;
+
+/* Caller-owned device pointers (see the storage notes above). */
+typedef struct {
+    void* rho;
+    void* rhotheta;
+    void* rhou;
+    void* rhov;
+    void* rhow;
+} ebs_state;
+
+typedef struct ebs_ctx ebs_ctx;
+
+/* Geometry quantities for ebs_geometry_export (per CV of one instance). */
+enum {
+    EBS_Q_ALPHA = 0,                      /* volume fraction                          */
+    EBS_Q_BETA_X = 1, EBS_Q_BETA_Y = 2, EBS_Q_BETA_Z = 3, /* lower-face area fractions */
+    EBS_Q_FX_Y = 4, EBS_Q_FX_Z = 5,       /* lower x-face centroid offset / (dy, dz)  */
+    EBS_Q_FY_X = 6, EBS_Q_FY_Z = 7,       /* lower y-face centroid offset / (dx, dz)  */
+    EBS_Q_FZ_X = 8, EBS_Q_FZ_Y = 9,       /* lower z-face centroid offset / (dx, dy)  */
+    EBS_Q_VC_X = 10, EBS_Q_VC_Y = 11, EBS_Q_VC_Z = 12, /* volume centroid - CV centre, / dx_d */
+    EBS_Q_A_X = 13, EBS_Q_A_Y = 14, EBS_Q_A_Z = 15,    /* EB area vector (into fluid) / face area */
+    EBS_Q_AREA = 16,                      /* EB facet area / (dx dy)                  */
+    EBS_Q_EBC_X = 17, EBS_Q_EBC_Y = 18, EBS_Q_EBC_Z = 19, /* EB centroid - CV centre, / dx_d */
+    EBS_Q_TYPE = 20,                      /* 0 covered / not a CV, 1 regular, 2 cut   */
+    EBS_Q_SMALL = 21,                     /* 1 if 0 < alpha < small_vfrac             */
+    EBS_Q_TIER = 22,                      /* merge tier 1..3 of a small CV, else 0    */
+    EBS_Q_MASK = 23,                      /* members of M: bit (dz+1)*9+(dy+1)*3+(dx+1) */
+    EBS_Q_NCOUNT = 24,                    /* N = number of neighbourhoods containing it */
+    EBS_Q_KAPPA = 25, EBS_Q_OMEGA = 26,
+    EBS_Q_VHAT = 27,                      /* neighbourhood volume / (dx dy dz)        */
+    EBS_Q_XHAT_X = 28, EBS_Q_XHAT_Y = 29, EBS_Q_XHAT_Z = 30, /* nbhd centroid - CV centre, / dx_d */
+    EBS_Q_COUNT = 31
+};
+
+/* Create a context.  grid is copied.  boxes may be NULL (one box = the
+ * domain).  hip_stream is a hipStream_t (NULL = the null stream); all work of
+ * the context is enqueued on it.  Errors: EBS_E_ARG (bad sizes, boxes that do
+ * not tile the domain), EBS_E_UNSUPPORTED (non-periodic x or y), EBS_E_OOM. */
+ebs_status ebs_create(const ebs_grid* grid, const ebs_box* boxes, int32_t nbox, void* hip_stream,
+                      ebs_ctx** out);
+
+/* Build the four geometry instances and the redistribution tables from nodal
+ * terrain heights (Section 3.2; Section 5.1 precomputation).  h_nodes has
+ * (nx+1)*(ny+1) doubles, x fastest, on the host (on_device = 0) or device.
+ * Synchronous.  Errors: EBS_E_ARG (non-finite heights, non-periodic node rows,
+ * terrain reaching the top cell layer). */
+ebs_status ebs_build_geometry_terrain(ebs_ctx* ctx, const double* h_nodes, int32_t on_device);
+
+/* Copy one quantity (EBS_Q_*) of instance inst (0 cell, 1 x-face, 2 y-face,
+ * 3 z-face) to host memory in the instance's state layout (n = element count
+ * of that layout).  Synchronous. */
+ebs_status ebs_geometry_export(ebs_ctx* ctx, int32_t inst, int32_t qty, double* host, size_t n);
+
+/* Per instance: {cut, small, covered, tier1, tier2, tier3, general-region CVs,
+ * regular} -> out[4*8].  Synchronous. */
+ebs_status ebs_geometry_stats(ebs_ctx* ctx, int64_t* out);
+
+/* Algorithm 1 steps (1)-(3) for one stage, all four instances:
+ * Uhat = Un + cdt * dU(Ucur).  Un and Ucur may be the same state; Uhat must not
+ * alias Ucur (the stencil reads neighbours) but may alias Un.  Asynchronous. */
+ebs_status ebs_advance_stage(ebs_ctx* ctx, const ebs_state* Un, const ebs_state* Ucur,
+                             ebs_state* Uhat, double cdt);
+
+/* Algorithm 1 step (4): Uout = R(Uhat) field by field.  Uhat must be the
+ * output of the last ebs_advance_stage of this context (the cut region is
+ * read from the context's double-precision copy).  Uout may alias Uhat.
+ * Asynchronous. */
+ebs_status ebs_redistribute(ebs_ctx* ctx, const ebs_state* Uhat, ebs_state* Uout);
+
+/* One low-storage three-stage Runge-Kutta step (stage coefficients 1/3, 1/2,
+ * 1, each stage from U^n, redistribution after every stage).  U is updated in
+ * place; scratch points at two states of the same layout used as stage
+ * buffers.  use_graph != 0 captures the step in a HIP graph on first use and
+ * replays it while the pointers and dt stay the same.  Asynchronous. */
+ebs_status ebs_rk3_step(ebs_ctx* ctx, ebs_state* U, ebs_state* scratch, double dt,
+                        int32_t use_graph);
+
+/* Sum of V * U over the fluid CVs of each field (rho, rhotheta, rhou, rhov,
+ * rhow), as unevaluated double-double pairs hi + lo.  Synchronous. */
+ebs_status ebs_conserved_sums(ebs_ctx* ctx, const ebs_state* U, double hi[5], double lo[5]);
+
+/* Time the candidate tile shapes of the regular-region kernel on this
+ * context's grid and keep the fastest; the choice is cached in the JSON file
+ * (created if missing, keyed by precision and grid size; NULL = no cache).
+ * Synchronous; scratch states are allocated and freed internally. */
+ebs_status ebs_autotune(ebs_ctx* ctx, const char* cache_json_path);
+
+/* Tile shape of the regular-region kernel: tx in {32, 64, 128}, ty in {1, 2, 4, 8}
+ * with tx*ty in [64, 512]. */
+ebs_status ebs_set_tile(ebs_ctx* ctx, int32_t tx, int32_t ty);
+ebs_status ebs_get_tile(const ebs_ctx* ctx, int32_t* tx, int32_t* ty);
+
+/* Kernel timing: when enabled, every launch of the regular-region stage
+ * kernel is bracketed by HIP events on the context stream; read returns the
+ * summed duration (ms) and launch count since the last reset and resets. */
+ebs_status ebs_timing_enable(ebs_ctx* ctx, int32_t enable);
+ebs_status ebs_timing_read(ebs_ctx* ctx, double* ms_total, int64_t* launches);
+
+/* Bytes moved per call of the regular-region stage kernel by the method
+ * (reads of Un and Ucur, one write, over the regular-region CVs), for roofline
+ * accounting: out[0] = first-stage form (Un == Ucur), out[1] = later stages. */
+ebs_status ebs_algorithmic_bytes(const ebs_ctx* ctx, double out[2]);
+
+/* Static message describing the last error of the context (never NULL). */
+const char* ebs_last_error(const ebs_ctx* ctx);
+
+/* Free all device memory and graphs of the context.  ctx may be NULL. */
+ebs_status ebs_destroy(ebs_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EBSTAG_H */

@@ -1,0 +1,539 @@
+// C ABI of the ebstag library: argument checks, context lifetime, geometry
+// export, the Runge-Kutta driver (with optional HIP-graph capture), timing and
+// the tile autotuner.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "ebs_internal.h"
+
+namespace ebs {
+
+ebs_status hip_fail(ebs_ctx* c, hipError_t e, const char* what) {
+    if (c) {
+        c->err = std::string("HIP error: ") + hipGetErrorString(e) + " in " + what;
+    }
+    return EBS_E_HIP;
+}
+
+GeoView geo_view(const ebs_ctx* c) {
+    GeoView v;
+    v.nx = c->nx;
+    v.ny = c->ny;
+    v.nz = c->nz;
+    v.dx = c->g.dx[0];
+    v.dy = c->g.dx[1];
+    v.dz = c->g.dx[2];
+    v.lo_z = c->g.lo[2];
+    v.G = c->G;
+    v.g0 = c->d_g0;
+    v.g1 = c->d_g1;
+    v.goff = c->d_goff;
+    v.gcol = c->d_gcol;
+    v.kf = c->d_kf;
+    v.kr = c->d_kr;
+    v.geo = c->d_geo;
+    v.type = c->d_type;
+    return v;
+}
+
+}  // namespace ebs
+
+using namespace ebs;
+
+namespace {
+
+bool state_ok(const ebs_state* s) {
+    return s && s->rho && s->rhotheta && s->rhou && s->rhov && s->rhow;
+}
+
+ebs_status fail(ebs_ctx* c, ebs_status st, const char* msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+void free_ptr(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+void drop_graph(ebs_ctx* c) {
+    if (c->graph.exec) (void)hipGraphExecDestroy((hipGraphExec_t)c->graph.exec);
+    if (c->graph.graph) (void)hipGraphDestroy((hipGraph_t)c->graph.graph);
+    c->graph.exec = nullptr;
+    c->graph.graph = nullptr;
+}
+
+bool same_state(const ebs_state& a, const ebs_state& b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
+
+ebs_status rk3_enqueue(ebs_ctx* c, ebs_state* U, ebs_state* S, double dt) {
+    static const double cs[3] = {1.0 / 3.0, 0.5, 1.0};
+    ebs_state* cur = U;
+    ebs_state* outs[3] = {&S[0], &S[1], U};
+    for (int s = 0; s < 3; ++s) {
+        ebs_status st = launch_advance(c, U, cur, outs[s], cs[s] * dt);
+        if (st != EBS_OK) return st;
+        st = launch_redistribute(c, outs[s], outs[s]);
+        if (st != EBS_OK) return st;
+        cur = outs[s];
+    }
+    return EBS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ebs_last_error(const ebs_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+ebs_status ebs_create(const ebs_grid* grid, const ebs_box* boxes, int32_t nbox, void* hip_stream,
+                      ebs_ctx** out) {
+    if (!grid || !out) return EBS_E_ARG;
+    *out = nullptr;
+    const ebs_grid& g = *grid;
+    if (g.n[0] < 8 || g.n[1] < 8 || g.n[2] < 4) return EBS_E_ARG;
+    if ((int64_t)g.n[0] * g.n[1] * g.n[2] > (int64_t)1 << 31) return EBS_E_UNSUPPORTED;
+    for (int d = 0; d < 3; ++d)
+        if (!(g.dx[d] > 0.0) || !isfinite(g.dx[d]) || !isfinite(g.lo[d])) return EBS_E_ARG;
+    if (!(g.small_vfrac > 0.0 && g.small_vfrac < 1.0)) return EBS_E_ARG;
+    if (g.precision != EBS_F64 && g.precision != EBS_F32_BULK) return EBS_E_ARG;
+    if (g.limiter < 0 || g.limiter > 2 || g.eb_flux < 0 || g.eb_flux > 1) return EBS_E_ARG;
+    if ((g.periodic & 0x7u) != 0x3u) return EBS_E_UNSUPPORTED;
+    if (nbox < 0 || (nbox > 0 && !boxes)) return EBS_E_ARG;
+    ebs_ctx* c = new (std::nothrow) ebs_ctx();
+    if (!c) return EBS_E_OOM;
+    c->g = g;
+    c->nx = g.n[0];
+    c->ny = g.n[1];
+    c->nz = g.n[2];
+    c->ncol = c->nx * c->ny;
+    c->stream = (hipStream_t)hip_stream;
+    if (nbox == 0) {
+        ebs_box b = {{0, 0, 0}, {c->nx, c->ny, c->nz}};
+        c->boxes.push_back(b);
+    } else {
+        // the boxes must tile the domain exactly once
+        std::vector<uint8_t> cover((size_t)c->nx * c->ny * c->nz, 0);
+        for (int b = 0; b < nbox; ++b) {
+            const ebs_box& B = boxes[b];
+            for (int d = 0; d < 3; ++d)
+                if (B.lo[d] < 0 || B.hi[d] > g.n[d] || B.lo[d] >= B.hi[d]) {
+                    delete c;
+                    return EBS_E_ARG;
+                }
+            for (int k = B.lo[2]; k < B.hi[2]; ++k)
+                for (int j = B.lo[1]; j < B.hi[1]; ++j)
+                    for (int i = B.lo[0]; i < B.hi[0]; ++i) {
+                        uint8_t& v = cover[((size_t)k * c->ny + j) * c->nx + i];
+                        if (v) {
+                            delete c;
+                            return EBS_E_ARG;
+                        }
+                        v = 1;
+                    }
+            c->boxes.push_back(B);
+        }
+        for (uint8_t v : cover)
+            if (!v) {
+                delete c;
+                return EBS_E_ARG;
+            }
+    }
+    const size_t ncol = c->ncol;
+    bool ok = hipMalloc(&c->d_kf, sizeof(int32_t) * NINST * ncol) == hipSuccess;
+    ok = ok && hipMalloc(&c->d_kr, sizeof(int32_t) * NINST * ncol) == hipSuccess;
+    ok = ok && hipMalloc(&c->d_g0, sizeof(int32_t) * ncol) == hipSuccess;
+    ok = ok && hipMalloc(&c->d_g1, sizeof(int32_t) * ncol) == hipSuccess;
+    if (!ok) {
+        ebs_destroy(c);
+        return EBS_E_OOM;
+    }
+    *out = c;
+    return EBS_OK;
+}
+
+ebs_status ebs_destroy(ebs_ctx* c) {
+    if (!c) return EBS_OK;
+    drop_graph(c);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    void* ptrs[] = {c->d_kf,   c->d_kr,        c->d_g0,      c->d_g1,   c->d_goff, c->d_gcol,
+                    c->d_geo,  c->d_type,      c->d_mask,    c->d_small, c->d_tier, c->d_w,
+                    c->d_smalllist, c->d_actlist, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles,
+                    c->d_part, c->d_dummy};
+    for (void* p : ptrs) free_ptr(p);
+    delete c;
+    return EBS_OK;
+}
+
+ebs_status ebs_build_geometry_terrain(ebs_ctx* c, const double* h_nodes, int32_t on_device) {
+    if (!c || !h_nodes) return fail(c, EBS_E_ARG, "null argument");
+    const size_t nn = (size_t)(c->nx + 1) * (c->ny + 1);
+    std::vector<double> h(nn);
+    if (on_device) {
+        EBS_HIP(c, hipMemcpy(h.data(), h_nodes, sizeof(double) * nn, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(h.data(), h_nodes, sizeof(double) * nn);
+    }
+    const double ztop_clear = c->g.lo[2] + (double)(c->nz - 1) * c->g.dx[2];
+    for (size_t q = 0; q < nn; ++q) {
+        if (!isfinite(h[q])) return fail(c, EBS_E_ARG, "non-finite terrain height");
+        if (!(h[q] < ztop_clear)) return fail(c, EBS_E_ARG, "terrain reaches the top cell layer");
+    }
+    const int W = c->nx + 1;
+    for (int j = 0; j <= c->ny; ++j)
+        if (h[(size_t)j * W + c->nx] != h[(size_t)j * W]) return fail(c, EBS_E_ARG, "terrain not periodic in x");
+    for (int i = 0; i <= c->nx; ++i)
+        if (h[(size_t)c->ny * W + i] != h[i]) return fail(c, EBS_E_ARG, "terrain not periodic in y");
+    double* d_h = nullptr;
+    if (hipMalloc(&d_h, sizeof(double) * nn) != hipSuccess) return fail(c, EBS_E_OOM, "terrain upload");
+    hipError_t e = hipMemcpy(d_h, h.data(), sizeof(double) * nn, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d_h);
+        return hip_fail(c, e, "terrain upload");
+    }
+    ebs_status st = build_geometry(c, d_h);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(d_h);
+    if (st != EBS_OK) return st;
+    st = wsrd_setup(c);
+    if (st != EBS_OK) return st;
+    st = build_tiles(c);
+    if (st != EBS_OK) return st;
+    drop_graph(c);
+    EBS_HIP(c, hipStreamSynchronize(c->stream));
+    c->have_geom = true;
+    return EBS_OK;
+}
+
+ebs_status ebs_geometry_export(ebs_ctx* c, int32_t inst, int32_t qty, double* host, size_t n) {
+    if (!c || !host) return fail(c, EBS_E_ARG, "null argument");
+    if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
+    if (inst < 0 || inst > 3 || qty < 0 || qty >= EBS_Q_COUNT) return fail(c, EBS_E_ARG, "bad instance or quantity");
+    const int nx = c->nx, ny = c->ny, nz = c->nz;
+    const int ex = nx + (inst == 1), ey = ny + (inst == 2), ez = nz + (inst == 3);
+    if (n != (size_t)ex * ey * ez) return fail(c, EBS_E_ARG, "wrong element count");
+    const size_t G = std::max(c->G, 1);
+    std::vector<double> geo, w;
+    std::vector<int8_t> ty, sm, tr;
+    std::vector<int32_t> mk;
+    std::vector<int32_t> kf(c->ncol), kr(c->ncol);
+    EBS_HIP(c, hipMemcpy(kf.data(), c->d_kf + (size_t)inst * c->ncol, sizeof(int32_t) * c->ncol, hipMemcpyDeviceToHost));
+    EBS_HIP(c, hipMemcpy(kr.data(), c->d_kr + (size_t)inst * c->ncol, sizeof(int32_t) * c->ncol, hipMemcpyDeviceToHost));
+    if (c->G > 0) {
+        if (qty < GQ_N) {
+            geo.resize(G);
+            EBS_HIP(c, hipMemcpy(geo.data(), c->d_geo + ((size_t)inst * GQ_N + qty) * c->G, sizeof(double) * c->G, hipMemcpyDeviceToHost));
+        }
+        ty.resize(G);
+        EBS_HIP(c, hipMemcpy(ty.data(), c->d_type + (size_t)inst * c->G, c->G, hipMemcpyDeviceToHost));
+        if (qty > EBS_Q_TYPE) {
+            sm.resize(G); tr.resize(G); mk.resize(G);
+            w.resize((size_t)WQ_COUNT * G);
+            EBS_HIP(c, hipMemcpy(sm.data(), c->d_small + (size_t)inst * c->G, c->G, hipMemcpyDeviceToHost));
+            EBS_HIP(c, hipMemcpy(tr.data(), c->d_tier + (size_t)inst * c->G, c->G, hipMemcpyDeviceToHost));
+            EBS_HIP(c, hipMemcpy(mk.data(), c->d_mask + (size_t)inst * c->G, sizeof(int32_t) * c->G, hipMemcpyDeviceToHost));
+            EBS_HIP(c, hipMemcpy(w.data(), c->d_w + (size_t)inst * WQ_COUNT * c->G, sizeof(double) * WQ_COUNT * c->G, hipMemcpyDeviceToHost));
+        }
+    }
+    auto value = [&](int i, int j, int k) -> double {
+        const bool cv = inst == 3 ? (k >= 1 && k <= nz - 1) : (k <= nz - 1);
+        if (!cv) return 0.0;
+        const int col = j * nx + i;
+        const int a = c->h_g0[col], b = c->h_g1[col];
+        int t;  // type
+        int gi = -1;
+        if (k < a) t = 0;
+        else if (k >= b) t = 1;
+        else { gi = c->h_goff[col] + (k - a); t = ty[gi]; }
+        if (qty == EBS_Q_TYPE) return t;
+        if (qty < GQ_N) {
+            if (gi >= 0) return geo[gi];
+            if (t == 0) return 0.0;
+            return (qty == GQ_ALPHA || qty == GQ_BX || qty == GQ_BY || qty == GQ_BZ) ? 1.0 : 0.0;
+        }
+        if (t == 0) return 0.0;
+        if (gi < 0) {  // regular CV outside the general range: trivial neighbourhood
+            switch (qty) {
+                case EBS_Q_MASK: return (double)(1 << 13);
+                case EBS_Q_NCOUNT: return 1.0;
+                case EBS_Q_OMEGA: return 1.0;
+                case EBS_Q_VHAT: return 1.0;
+                default: return 0.0;
+            }
+        }
+        switch (qty) {
+            case EBS_Q_SMALL: return sm[gi];
+            case EBS_Q_TIER: return tr[gi];
+            case EBS_Q_MASK: return (double)mk[gi];
+            case EBS_Q_NCOUNT: return w[(size_t)WQ_N * G + gi];
+            case EBS_Q_KAPPA: return w[(size_t)WQ_KAPPA * G + gi];
+            case EBS_Q_OMEGA: return w[(size_t)WQ_OMEGA * G + gi];
+            case EBS_Q_VHAT: return w[(size_t)WQ_VHAT * G + gi];
+            case EBS_Q_XHAT_X: return w[(size_t)WQ_XHX * G + gi];
+            case EBS_Q_XHAT_Y: return w[(size_t)WQ_XHY * G + gi];
+            default: return w[(size_t)WQ_XHZ * G + gi];
+        }
+    };
+    (void)kf; (void)kr;
+    for (int k = 0; k < ez; ++k)
+        for (int j = 0; j < ey; ++j)
+            for (int i = 0; i < ex; ++i)
+                host[((size_t)k * ey + j) * ex + i] = value(i % nx, j % ny, k);
+    return EBS_OK;
+}
+
+ebs_status ebs_geometry_stats(ebs_ctx* c, int64_t* out) {
+    if (!c || !out) return fail(c, EBS_E_ARG, "null argument");
+    if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
+    const size_t G = c->G;
+    std::vector<int8_t> ty(std::max<size_t>(G, 1)), sm(std::max<size_t>(G, 1)), tr(std::max<size_t>(G, 1));
+    for (int inst = 0; inst < NINST; ++inst) {
+        int64_t* o = out + 8 * inst;
+        for (int q = 0; q < 8; ++q) o[q] = 0;
+        if (G > 0) {
+            EBS_HIP(c, hipMemcpy(ty.data(), c->d_type + inst * G, G, hipMemcpyDeviceToHost));
+            EBS_HIP(c, hipMemcpy(sm.data(), c->d_small + inst * G, G, hipMemcpyDeviceToHost));
+            EBS_HIP(c, hipMemcpy(tr.data(), c->d_tier + inst * G, G, hipMemcpyDeviceToHost));
+        }
+        for (size_t g = 0; g < G; ++g) {
+            if (ty[g] == 2) o[0]++;
+            if (sm[g]) o[1]++;
+            if (ty[g] == 0) o[2]++;
+            if (tr[g] >= 1 && tr[g] <= 3) o[2 + tr[g]]++;
+            if (ty[g] == 1) o[7]++;
+        }
+        o[6] = (int64_t)G;
+        // covered and regular CVs outside the general range
+        const int kmin = inst == 3 ? 1 : 0, kmax = c->nz - 1;
+        for (int col = 0; col < c->ncol; ++col) {
+            o[2] += std::max(0, std::min(c->h_g0[col], kmax + 1) - kmin);
+            o[7] += std::max(0, kmax + 1 - std::max(c->h_g1[col], kmin));
+        }
+    }
+    return EBS_OK;
+}
+
+ebs_status ebs_advance_stage(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uhat, double cdt) {
+    if (!c) return EBS_E_ARG;
+    if (!state_ok(Un) || !state_ok(Ucur) || !state_ok(Uhat)) return fail(c, EBS_E_ARG, "null state pointer");
+    if (!isfinite(cdt)) return fail(c, EBS_E_ARG, "non-finite time step");
+    if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
+    if (Uhat->rho == Ucur->rho || Uhat->rhou == Ucur->rhou || Uhat->rhow == Ucur->rhow)
+        return fail(c, EBS_E_ARG, "output aliases the stencil input");
+    return launch_advance(c, Un, Ucur, Uhat, cdt);
+}
+
+ebs_status ebs_redistribute(ebs_ctx* c, const ebs_state* Uhat, ebs_state* Uout) {
+    if (!c) return EBS_E_ARG;
+    if (!state_ok(Uhat) || !state_ok(Uout)) return fail(c, EBS_E_ARG, "null state pointer");
+    if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
+    return launch_redistribute(c, Uhat, Uout);
+}
+
+ebs_status ebs_rk3_step(ebs_ctx* c, ebs_state* U, ebs_state* scratch, double dt, int32_t use_graph) {
+    if (!c) return EBS_E_ARG;
+    if (!state_ok(U) || !scratch || !state_ok(&scratch[0]) || !state_ok(&scratch[1]))
+        return fail(c, EBS_E_ARG, "null state pointer");
+    if (!isfinite(dt)) return fail(c, EBS_E_ARG, "non-finite time step");
+    if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
+    if (!use_graph || c->timing) return rk3_enqueue(c, U, scratch, dt);
+    const bool hit = c->graph.exec && same_state(c->graph.U, *U) && same_state(c->graph.S0, scratch[0]) &&
+                     same_state(c->graph.S1, scratch[1]) && c->graph.dt == dt;
+    if (!hit) {
+        drop_graph(c);
+        hipStream_t s = c->stream;
+        bool own = false;
+        if (!s) {  // the legacy null stream cannot be captured
+            EBS_HIP(c, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            own = true;
+        }
+        hipStream_t saved = c->stream;
+        c->stream = s;
+        EBS_HIP(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        ebs_status st = rk3_enqueue(c, U, scratch, dt);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        c->stream = saved;
+        if (st != EBS_OK) return st;
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(c, e, "hipGraphInstantiate");
+        }
+        if (own) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+        c->graph.graph = graph;
+        c->graph.exec = exec;
+        c->graph.U = *U;
+        c->graph.S0 = scratch[0];
+        c->graph.S1 = scratch[1];
+        c->graph.dt = dt;
+    }
+    EBS_HIP(c, hipGraphLaunch((hipGraphExec_t)c->graph.exec, c->stream));
+    return EBS_OK;
+}
+
+ebs_status ebs_conserved_sums(ebs_ctx* c, const ebs_state* U, double hi[5], double lo[5]) {
+    if (!c || !hi || !lo) return EBS_E_ARG;
+    if (!state_ok(U)) return fail(c, EBS_E_ARG, "null state pointer");
+    if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
+    return conserved_sums(c, U, hi, lo);
+}
+
+ebs_status ebs_set_tile(ebs_ctx* c, int32_t tx, int32_t ty) {
+    if (!c) return EBS_E_ARG;
+    if (!(tx == 32 || tx == 64 || tx == 128) || !(ty == 1 || ty == 2 || ty == 4 || ty == 8) ||
+        tx * ty < 64 || tx * ty > 512)
+        return fail(c, EBS_E_ARG, "unsupported tile shape");
+    c->tile_x = tx;
+    c->tile_y = ty;
+    drop_graph(c);
+    if (c->have_geom) return build_tiles(c);
+    return EBS_OK;
+}
+
+ebs_status ebs_get_tile(const ebs_ctx* c, int32_t* tx, int32_t* ty) {
+    if (!c || !tx || !ty) return EBS_E_ARG;
+    *tx = c->tile_x;
+    *ty = c->tile_y;
+    return EBS_OK;
+}
+
+ebs_status ebs_timing_enable(ebs_ctx* c, int32_t enable) {
+    if (!c) return EBS_E_ARG;
+    c->timing = enable != 0;
+    c->ev_used = 0;
+    return EBS_OK;
+}
+
+ebs_status ebs_timing_read(ebs_ctx* c, double* ms_total, int64_t* launches) {
+    if (!c || !ms_total || !launches) return EBS_E_ARG;
+    EBS_HIP(c, hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (size_t q = 0; q + 1 < c->ev_used; q += 2) {
+        float ms = 0.f;
+        EBS_HIP(c, hipEventElapsedTime(&ms, c->ev_pool[q], c->ev_pool[q + 1]));
+        tot += ms;
+    }
+    *ms_total = tot;
+    *launches = (int64_t)(c->ev_used / 2);
+    c->ev_used = 0;
+    return EBS_OK;
+}
+
+ebs_status ebs_algorithmic_bytes(const ebs_ctx* c, double out[2]) {
+    if (!c || !out) return EBS_E_ARG;
+    if (!c->have_geom) return EBS_E_ORDER;
+    out[0] = c->alg_bytes[0];
+    out[1] = c->alg_bytes[1];
+    return EBS_OK;
+}
+
+ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
+    if (!c) return EBS_E_ARG;
+    if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
+    const char* prec = c->g.precision == EBS_F32_BULK ? "f32bulk" : "f64";
+    char key[160];
+    std::snprintf(key, sizeof(key), "%s_%dx%dx%d_b%zu", prec, c->nx, c->ny, c->nz, c->boxes.size());
+    // cached choice
+    if (cache_json_path) {
+        std::ifstream in(cache_json_path);
+        if (in) {
+            std::stringstream ss;
+            ss << in.rdbuf();
+            const std::string txt = ss.str();
+            const std::string pat = std::string("\"") + key + "\": [";
+            const size_t p = txt.find(pat);
+            if (p != std::string::npos) {
+                int tx = 0, ty = 0;
+                if (std::sscanf(txt.c_str() + p + pat.size(), "%d, %d", &tx, &ty) == 2 &&
+                    ebs_set_tile(c, tx, ty) == EBS_OK)
+                    return EBS_OK;
+            }
+        }
+    }
+    // scratch states
+    const size_t es = c->g.precision == EBS_F32_BULK ? 4 : 8;
+    const size_t nx = c->nx, ny = c->ny, nz = c->nz;
+    const size_t cnt[5] = {nx * ny * nz, nx * ny * nz, (nx + 1) * ny * nz, nx * (ny + 1) * nz, nx * ny * (nz + 1)};
+    void* buf[2][5] = {{nullptr}};
+    ebs_state st[2];
+    for (int s = 0; s < 2; ++s) {
+        for (int f = 0; f < 5; ++f) {
+            if (hipMalloc(&buf[s][f], es * cnt[f]) != hipSuccess) {
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 5; ++b) free_ptr(buf[a][b]);
+                return fail(c, EBS_E_OOM, "autotune scratch");
+            }
+            (void)hipMemsetAsync(buf[s][f], 0, es * cnt[f], c->stream);
+        }
+        st[s] = {buf[s][0], buf[s][1], buf[s][2], buf[s][3], buf[s][4]};
+    }
+    // timing only: the values (zeros) do not change the work done
+    (void)hipStreamSynchronize(c->stream);
+    const int cand[][2] = {{32, 2}, {32, 4}, {32, 8}, {64, 1}, {64, 2}, {64, 4}, {64, 8}, {128, 1}, {128, 2}, {128, 4}};
+    double best = 1e300;
+    int bx = c->tile_x, by = c->tile_y;
+    const bool was_timing = c->timing;
+    c->timing = false;
+    hipEvent_t e0, e1;
+    EBS_HIP(c, hipEventCreate(&e0));
+    EBS_HIP(c, hipEventCreate(&e1));
+    for (auto& cd : cand) {
+        if (ebs_set_tile(c, cd[0], cd[1]) != EBS_OK) continue;
+        for (int rep = 0; rep < 2; ++rep) (void)launch_advance(c, &st[0], &st[0], &st[1], 0.0);
+        (void)hipEventRecord(e0, c->stream);
+        const int reps = 5;
+        for (int rep = 0; rep < reps; ++rep) (void)launch_advance(c, &st[0], &st[0], &st[1], 0.0);
+        (void)hipEventRecord(e1, c->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) { best = ms; bx = cd[0]; by = cd[1]; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->timing = was_timing;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 5; ++b) free_ptr(buf[a][b]);
+    ebs_status sst = ebs_set_tile(c, bx, by);
+    if (sst != EBS_OK) return sst;
+    if (cache_json_path) {
+        std::string txt;
+        {
+            std::ifstream in(cache_json_path);
+            if (in) {
+                std::stringstream ss;
+                ss << in.rdbuf();
+                txt = ss.str();
+            }
+        }
+        // append the entry to a flat JSON object
+        const size_t close = txt.rfind('}');
+        char ent[256];
+        std::snprintf(ent, sizeof(ent), "\"%s\": [%d, %d]", key, bx, by);
+        if (close == std::string::npos) {
+            txt = std::string("{\n  ") + ent + "\n}\n";
+        } else {
+            const bool empty = txt.find('"') == std::string::npos;
+            txt = txt.substr(0, close) + (empty ? "  " : ",\n  ") + ent + "\n}\n";
+        }
+        std::ofstream outf(cache_json_path);
+        outf << txt;
+    }
+    return EBS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,189 @@
+// Internal declarations of the ebstag library (not part of the C ABI).
+//
+// Data layout in device memory
+// ----------------------------
+// The terrain is a height function, so in every xy-column each of the four
+// instances is covered below a level kf, cut in a band, and regular above a
+// level kr.  The library stores geometry only for a per-column "general"
+// range of cell positions [g0, g1):
+//     g0 = min over instances of kf (below: every instance covered),
+//     g1 = max over instances and over the 7 x 7 neighbouring columns of kr,
+//          plus 3 (above: every CV and every CV within the flux stencil and
+//          the redistribution radius is regular), clamped to nz.
+// General cells are numbered column by column (goff[c] + k - g0[c]); each has
+// a geometry record per instance (structure of arrays, GQ_* quantities) and
+// redistribution data.  Everything above g1 is processed by the regular-region
+// kernel, which reads no geometry at all.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "ebstag.h"
+
+namespace ebs {
+
+constexpr int NINST = 4;
+// geometry record quantities (same order as the EBS_Q_* export ids 0..19)
+enum : int {
+    GQ_ALPHA = 0, GQ_BX, GQ_BY, GQ_BZ, GQ_FX1, GQ_FX2, GQ_FY1, GQ_FY2, GQ_FZ1, GQ_FZ2,
+    GQ_VCX, GQ_VCY, GQ_VCZ, GQ_AX, GQ_AY, GQ_AZ, GQ_AREA, GQ_EBX, GQ_EBY, GQ_EBZ, GQ_N
+};
+// redistribution tables per general cell and instance (doubles)
+enum : int { WQ_N = 0, WQ_KAPPA, WQ_OMEGA, WQ_VHAT, WQ_XHX, WQ_XHY, WQ_XHZ, WQ_COUNT };
+
+// margins of the general region around the cut band (cells)
+constexpr int GEN_RXY = 3;
+constexpr int GEN_RZ = 3;
+// tie / threshold tolerance of the discrete redistribution decisions
+constexpr double TIE = 1e-12;
+
+// Read-only view of the geometry passed to kernels by value.
+struct GeoView {
+    int nx, ny, nz;
+    double dx, dy, dz;
+    double lo_z;
+    int32_t G;                 // number of general cells
+    const int32_t* g0;         // [ncol]
+    const int32_t* g1;         // [ncol]
+    const int32_t* goff;       // [ncol]
+    const int32_t* gcol;       // [G] column of each general cell
+    const int32_t* kf;         // [4][ncol] first fluid CV level
+    const int32_t* kr;         // [4][ncol] first regular level
+    const double* geo;         // [4][GQ_N][G]
+    const int8_t* type;        // [4][G]
+};
+
+struct WsrdView {
+    const int32_t* mask;       // [4][G] 27-bit member mask (0 = not a fluid CV)
+    const int8_t* small;       // [4][G]
+    const int8_t* tier;        // [4][G]
+    const double* w;           // [4][WQ_COUNT][G]
+    int limiter;
+    double vt;                 // V_target / (dx dy dz)
+};
+
+// A state as typed device pointers (T = double or float)
+template <typename T>
+struct StateP {
+    T* f[5];
+};
+
+__host__ __device__ inline int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// general index of cell position (i, j, k) (i, j wrapped), -2 below the general
+// range (every instance covered), -1 above it (every instance regular)
+__device__ inline int gidx(const GeoView& v, int i, int j, int k) {
+    const int c = j * v.nx + i;
+    const int a = v.g0[c];
+    if (k < a) return -2;
+    if (k >= v.g1[c]) return -1;
+    return v.goff[c] + (k - a);
+}
+
+// is plane k a CV plane of instance inst
+__device__ inline bool cv_plane(const GeoView& v, int inst, int k) {
+    return inst == 3 ? (k >= 1 && k <= v.nz - 1) : (k >= 0 && k <= v.nz - 1);
+}
+
+__device__ inline double gq(const GeoView& v, int inst, int q, int g) {
+    return v.geo[((size_t)inst * GQ_N + q) * v.G + g];
+}
+
+}  // namespace ebs
+
+// ---------------------------------------------------------------- context
+struct ebs_tile {
+    int32_t x0, y0, z0;
+    int16_t ex, ey, ez, flags;  // extents; flags bit0: tile has cells below g1
+};
+
+struct ebs_graph_cache {
+    void* exec = nullptr;  // hipGraphExec_t
+    void* graph = nullptr; // hipGraph_t
+    ebs_state U{}, S0{}, S1{};
+    double dt = 0.0;
+};
+
+struct ebs_ctx {
+    ebs_grid g{};
+    int nx = 0, ny = 0, nz = 0;
+    int ncol = 0;
+    hipStream_t stream = nullptr;
+    std::vector<ebs_box> boxes;
+    std::string err = "no error";
+
+    // geometry
+    bool have_geom = false;
+    int32_t* d_kf = nullptr;
+    int32_t* d_kr = nullptr;
+    int32_t* d_g0 = nullptr;
+    int32_t* d_g1 = nullptr;
+    int32_t* d_goff = nullptr;
+    int32_t* d_gcol = nullptr;
+    int32_t G = 0;
+    double* d_geo = nullptr;
+    int8_t* d_type = nullptr;
+    std::vector<int32_t> h_g0, h_g1, h_goff;
+
+    // redistribution
+    int32_t* d_mask = nullptr;
+    int8_t* d_small = nullptr;
+    int8_t* d_tier = nullptr;
+    double* d_w = nullptr;
+    int32_t* d_smalllist = nullptr;  // [4][G] general indices of small CVs with kappa > 0
+    int32_t nsmall[4] = {0, 0, 0, 0};
+    int32_t* d_actlist = nullptr;    // [4][G] general indices of CVs R may change
+    int32_t nact[4] = {0, 0, 0, 0};
+
+    // per-stage buffers (cut region, double)
+    double* d_uhat = nullptr;  // [5][G] provisional state of the last advance
+    double* d_qhat = nullptr;  // [5][G]
+    double* d_sig = nullptr;   // [5][3][G]
+
+    // regular-region tiles
+    int tile_x = 64, tile_y = 4, tile_z = 8;
+    std::vector<ebs_tile> h_tiles;
+    ebs_tile* d_tiles = nullptr;
+    int32_t ntiles = 0;
+    double alg_bytes[2] = {0, 0};
+
+    // sums
+    double* d_part = nullptr;
+    int npart = 0;
+
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+
+    ebs_graph_cache graph;
+    double* d_dummy = nullptr;
+};
+
+namespace ebs {
+// geometry (geom.hip)
+ebs_status build_geometry(ebs_ctx* c, const double* d_h);
+// stage kernels (stage.hip)
+ebs_status launch_advance(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uhat,
+                          double cdt);
+ebs_status build_tiles(ebs_ctx* c);
+// redistribution (wsrd.hip)
+ebs_status wsrd_setup(ebs_ctx* c);
+ebs_status launch_redistribute(ebs_ctx* c, const ebs_state* Uhat, ebs_state* Uout);
+// sums (reduce.hip)
+ebs_status conserved_sums(ebs_ctx* c, const ebs_state* U, double hi[5], double lo[5]);
+
+GeoView geo_view(const ebs_ctx* c);
+WsrdView wsrd_view(const ebs_ctx* c);
+ebs_status hip_fail(ebs_ctx* c, hipError_t e, const char* what);
+}  // namespace ebs
+
+#define EBS_HIP(ctx, call)                                              \
+    do {                                                                \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess) return ebs::hip_fail((ctx), e_, #call);   \
+    } while (0)

@@ -1,0 +1,581 @@
+// Geometry builder: classification of the four instances, the general region,
+// and the moments of every CV in it (Section 3.2 of the paper).
+//
+// Formulation used here.  Inside an xy-cell the terrain is linear on the two
+// triangles a b c and a c d (a = node (i,j), b = (i+1,j), c = (i+1,j+1),
+// d = (i,j+1)).  Every box a control volume is made of (the whole cell, or a
+// half-cell split at a mid plane) is covered by at most four sub-triangles
+// whose corners lie on the half-grid {0, 1/2, 1}^2 of the cell.  With
+// d(x,y) = level - h(x,y), the fluid column above the terrain between two
+// levels is (zb - h)^+ - (za - h)^+, so every volume moment is a difference of
+// positive-part integrals of a linear function over a triangle.  Those have
+// closed forms: the positive part is the whole triangle, nothing, a corner
+// triangle, or the whole triangle minus a corner triangle, and a linear (or
+// squared linear) weight integrates exactly from its corner values.  Vertical
+// faces use the same construction in one dimension.
+//
+// The file is compiled without floating-point contraction so that the
+// heights at half-grid points, (0.5 p + 0.5 q), and the plane levels,
+// lo + k dz, are rounded exactly as written: the discrete classification is
+// made by comparing those values.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "ebs_internal.h"
+
+namespace ebs {
+namespace {
+
+// ------------------------------------------------------------ level planes
+__host__ __device__ inline double zplane(double lo, double dz, int k) { return lo + (double)k * dz; }
+__host__ __device__ inline double zmidp(double lo, double dz, int k) {
+    return lo + ((double)k + 0.5) * dz;
+}
+
+struct Heights {
+    double a, b, c, d;  // nodal heights
+};
+
+// height at half-grid point (s2, t2) in {0,1,2}^2 of the cell
+__device__ inline double hhalf(const Heights& H, int s2, int t2) {
+    const int key = s2 * 3 + t2;
+    switch (key) {
+        case 0: return H.a;                       // (0,0)
+        case 6: return H.b;                       // (2,0)
+        case 8: return H.c;                       // (2,2)
+        case 2: return H.d;                       // (0,2)
+        case 3: return 0.5 * H.a + 0.5 * H.b;     // (1,0)
+        case 7: return 0.5 * H.b + 0.5 * H.c;     // (2,1)
+        case 5: return 0.5 * H.d + 0.5 * H.c;     // (1,2)
+        case 1: return 0.5 * H.a + 0.5 * H.d;     // (0,1)
+        default: return 0.5 * H.a + 0.5 * H.c;    // (1,1) on the diagonal
+    }
+}
+
+// sub-triangles of each box part: {triangle (0: a b c, 1: a c d), 3 half-grid corners}
+// parts: 0 whole, 1 x-lower half, 2 x-upper half, 3 y-lower half, 4 y-upper half
+struct Piece {
+    int8_t tri, s[3], t[3];
+};
+__constant__ Piece kPieces[5][4] = {
+    {{0, {0, 2, 2}, {0, 0, 2}}, {1, {0, 2, 0}, {0, 2, 2}}, {-1, {0}, {0}}, {-1, {0}, {0}}},
+    {{0, {0, 1, 1}, {0, 0, 1}}, {1, {0, 1, 1}, {0, 1, 2}}, {1, {0, 1, 0}, {0, 2, 2}}, {-1, {0}, {0}}},
+    {{0, {1, 2, 2}, {0, 0, 2}}, {0, {1, 2, 1}, {0, 2, 1}}, {1, {1, 2, 1}, {1, 2, 2}}, {-1, {0}, {0}}},
+    {{0, {0, 2, 2}, {0, 0, 1}}, {0, {0, 2, 1}, {0, 1, 1}}, {1, {0, 1, 0}, {0, 1, 1}}, {-1, {0}, {0}}},
+    {{0, {1, 2, 2}, {1, 1, 2}}, {1, {1, 2, 0}, {1, 2, 2}}, {1, {1, 0, 0}, {1, 2, 1}}, {-1, {0}, {0}}},
+};
+
+// positive-part integrals over a triangle
+struct PP {
+    double I, Ix, Iy, J;  // int d+, int x d+, int y d+, int (d+)^2
+    double A, Ax, Ay;     // area of {d > 0} and its first moments
+};
+
+struct TriW {
+    double x[3], y[3], d[3];
+};
+
+// exact integrals of a linear weight d over a triangle
+__device__ inline void tri_int(const TriW& T, double& S, double& Id, double& Ixd, double& Iyd,
+                               double& Idd, double& Ix, double& Iy) {
+    S = 0.5 * fabs((T.x[1] - T.x[0]) * (T.y[2] - T.y[0]) - (T.x[2] - T.x[0]) * (T.y[1] - T.y[0]));
+    const double sd = T.d[0] + T.d[1] + T.d[2];
+    const double sx = T.x[0] + T.x[1] + T.x[2];
+    const double sy = T.y[0] + T.y[1] + T.y[2];
+    Id = S * sd / 3.0;
+    Ix = S * sx / 3.0;
+    Iy = S * sy / 3.0;
+    Ixd = S / 12.0 * (T.x[0] * T.d[0] + T.x[1] * T.d[1] + T.x[2] * T.d[2] + sx * sd);
+    Iyd = S / 12.0 * (T.y[0] * T.d[0] + T.y[1] * T.d[1] + T.y[2] * T.d[2] + sy * sd);
+    Idd = S / 12.0 * (T.d[0] * T.d[0] + T.d[1] * T.d[1] + T.d[2] * T.d[2] + sd * sd);
+}
+
+// corner triangle at vertex v where d changes sign along both edges
+__device__ inline TriW corner(const TriW& T, int v) {
+    const int p = (v + 1) % 3, q = (v + 2) % 3;
+    const double lp = T.d[v] / (T.d[v] - T.d[p]);
+    const double lq = T.d[v] / (T.d[v] - T.d[q]);
+    TriW C;
+    C.x[0] = T.x[v]; C.y[0] = T.y[v]; C.d[0] = T.d[v];
+    C.x[1] = T.x[v] + lp * (T.x[p] - T.x[v]);
+    C.y[1] = T.y[v] + lp * (T.y[p] - T.y[v]);
+    C.d[1] = 0.0;
+    C.x[2] = T.x[v] + lq * (T.x[q] - T.x[v]);
+    C.y[2] = T.y[v] + lq * (T.y[q] - T.y[v]);
+    C.d[2] = 0.0;
+    return C;
+}
+
+__device__ inline PP pos_part(const TriW& T) {
+    PP r = {0, 0, 0, 0, 0, 0, 0};
+    int np = 0, vpos = 0, vneg = 0;
+    for (int v = 0; v < 3; ++v) {
+        if (T.d[v] > 0.0) { ++np; vpos = v; } else { vneg = v; }
+    }
+    if (np == 0) return r;
+    double S, Id, Ixd, Iyd, Idd, Ix, Iy;
+    if (np == 3) {
+        tri_int(T, S, Id, Ixd, Iyd, Idd, Ix, Iy);
+        r.I = Id; r.Ix = Ixd; r.Iy = Iyd; r.J = Idd; r.A = S; r.Ax = Ix; r.Ay = Iy;
+        return r;
+    }
+    if (np == 1) {
+        const TriW C = corner(T, vpos);
+        tri_int(C, S, Id, Ixd, Iyd, Idd, Ix, Iy);
+        r.I = Id; r.Ix = Ixd; r.Iy = Iyd; r.J = Idd; r.A = S; r.Ax = Ix; r.Ay = Iy;
+        return r;
+    }
+    // two positive corners: whole triangle minus the negative corner triangle
+    tri_int(T, S, Id, Ixd, Iyd, Idd, Ix, Iy);
+    const TriW C = corner(T, vneg);
+    double S2, Id2, Ixd2, Iyd2, Idd2, Ix2, Iy2;
+    tri_int(C, S2, Id2, Ixd2, Iyd2, Idd2, Ix2, Iy2);
+    r.I = Id - Id2; r.Ix = Ixd - Ixd2; r.Iy = Iyd - Iyd2; r.J = Idd - Idd2;
+    r.A = S - S2; r.Ax = Ix - Ix2; r.Ay = Iy - Iy2;
+    return r;
+}
+
+// one-dimensional positive part over a segment u in [u0, u1] with d linear
+struct PP1 {
+    double I, Iu, J;
+};
+__device__ inline PP1 pos_part1(double u0, double d0, double u1, double d1) {
+    PP1 r = {0, 0, 0};
+    const double L = u1 - u0;
+    if (!(L > 0.0)) return r;
+    if (d0 > 0.0 && d1 > 0.0) {
+        r.I = L * (d0 + d1) * 0.5;
+        r.Iu = L / 6.0 * (u0 * (2.0 * d0 + d1) + u1 * (d0 + 2.0 * d1));
+        r.J = L / 3.0 * (d0 * d0 + d0 * d1 + d1 * d1);
+    } else if (d0 > 0.0) {
+        const double lam = d0 / (d0 - d1);
+        const double ue = u0 + lam * L;
+        r.I = lam * L * d0 * 0.5;
+        r.Iu = lam * L / 6.0 * (2.0 * u0 * d0 + ue * d0);
+        r.J = lam * L * d0 * d0 / 3.0;
+    } else if (d1 > 0.0) {
+        const double lam = d1 / (d1 - d0);
+        const double us = u1 - lam * L;
+        r.I = lam * L * d1 * 0.5;
+        r.Iu = lam * L / 6.0 * (us * d1 + 2.0 * u1 * d1);
+        r.J = lam * L * d1 * d1 / 3.0;
+    }
+    return r;
+}
+
+// Moments of the fluid part of one box, relative to the cell node (X_i, Y_j, Z_k).
+struct BoxM {
+    double vol, m[3];
+    double fa[6], ft[6][2];  // face areas; moments of the two tangential coordinates
+    double fz[6];            // (unused slot kept for z-faces symmetry)
+    double av[3], area, em[3];
+};
+
+// Evaluate a box: part 0..4 (footprint), z-range [za, zb]; zk is the cell's lower
+// node plane; bottom marks the domain bottom.
+__device__ void box_eval(const Heights& H, double DX, double DY, int part, double za, double zb,
+                         double zk, bool bottom, BoxM& o) {
+    for (int q = 0; q < 6; ++q) { o.fa[q] = 0; o.ft[q][0] = o.ft[q][1] = 0; o.fz[q] = 0; }
+    o.vol = o.m[0] = o.m[1] = o.m[2] = 0;
+    o.av[0] = o.av[1] = o.av[2] = o.area = o.em[0] = o.em[1] = o.em[2] = 0;
+    const double hx = 0.5 * DX, hy = 0.5 * DY;
+    const double gx[2] = {(H.b - H.a) / DX, (H.c - H.d) / DX};
+    const double gy[2] = {(H.c - H.b) / DY, (H.d - H.a) / DY};
+    const double zal = za - zk;
+    for (int p = 0; p < 4; ++p) {
+        const Piece& P = kPieces[part][p];
+        if (P.tri < 0) break;
+        TriW Tb, Tt;
+        double hv[3];
+        for (int v = 0; v < 3; ++v) {
+            Tb.x[v] = Tt.x[v] = P.s[v] * hx;
+            Tb.y[v] = Tt.y[v] = P.t[v] * hy;
+            hv[v] = hhalf(H, P.s[v], P.t[v]);
+            Tb.d[v] = za - hv[v];
+            Tt.d[v] = zb - hv[v];
+        }
+        const PP lo = pos_part(Tb), hi = pos_part(Tt);
+        // volume and moments (z relative to za, shifted below)
+        o.vol += hi.I - lo.I;
+        o.m[0] += hi.Ix - lo.Ix;
+        o.m[1] += hi.Iy - lo.Iy;
+        o.m[2] += (zb - za) * hi.I - 0.5 * hi.J + 0.5 * lo.J;
+        // area below each level: A{h < level}; at the domain bottom the lower
+        // face also counts terrain lying exactly on it (flat piece at za)
+        double Alo = lo.A, Axlo = lo.Ax, Aylo = lo.Ay;
+        const bool flat = (hv[0] == hv[1]) && (hv[1] == hv[2]);
+        double S, Id, Ixd, Iyd, Idd, Ix, Iy;
+        tri_int(Tb, S, Id, Ixd, Iyd, Idd, Ix, Iy);
+        if (bottom && flat && hv[0] == za) { Alo = S; Axlo = Ix; Aylo = Iy; }
+        o.fa[4] += Alo;
+        o.ft[4][0] += Axlo;
+        o.ft[4][1] += Aylo;
+        o.fa[5] += hi.A;
+        o.ft[5][0] += hi.Ax;
+        o.ft[5][1] += hi.Ay;
+        // EB facet: za <= h < zb (za < h at the domain bottom)
+        const double pa = hi.A - Alo;
+        if (pa > 0.0) {
+            const double sq = sqrt(1.0 + gx[P.tri] * gx[P.tri] + gy[P.tri] * gy[P.tri]);
+            o.av[0] += -gx[P.tri] * pa;
+            o.av[1] += -gy[P.tri] * pa;
+            o.av[2] += pa;
+            o.area += sq * pa;
+            o.em[0] += sq * (hi.Ax - Axlo);
+            o.em[1] += sq * (hi.Ay - Aylo);
+            // integral of (h - zk) over the facet footprint:
+            // int_{h<c} (h - zk) = (c - zk) A - I(c)
+            const double hlo = (bottom && flat && hv[0] == za) ? (zal * Alo - lo.I) : (zal * lo.A - lo.I);
+            o.em[2] += sq * (((zb - zk) * hi.A - hi.I) - hlo);
+        }
+    }
+    o.m[2] += zal * o.vol;
+    // vertical faces: x-faces at the footprint's x bounds, y-faces at its y bounds
+    int s_lo = 0, s_hi = 2, t_lo = 0, t_hi = 2;
+    if (part == 1) s_hi = 1;
+    if (part == 2) s_lo = 1;
+    if (part == 3) t_hi = 1;
+    if (part == 4) t_lo = 1;
+    for (int side = 0; side < 2; ++side) {
+        // x-face at s = S: triangle abc covers t in [0, S], acd covers [S, 2]
+        {
+            const int S2 = side ? s_hi : s_lo;
+            const int br[3] = {t_lo, std::min(std::max(S2, t_lo), t_hi), t_hi};
+            for (int seg = 0; seg < 2; ++seg) {
+                const int ta = br[seg], tb = br[seg + 1];
+                if (tb <= ta) continue;
+                const double u0 = ta * hy, u1 = tb * hy;
+                const double h0 = hhalf(H, S2, ta), h1 = hhalf(H, S2, tb);
+                const PP1 L = pos_part1(u0, za - h0, u1, za - h1);
+                const PP1 U = pos_part1(u0, zb - h0, u1, zb - h1);
+                const int f = 0 + side;
+                o.fa[f] += U.I - L.I;
+                o.ft[f][0] += U.Iu - L.Iu;
+                o.ft[f][1] += (zb - za) * U.I - 0.5 * U.J + 0.5 * L.J + zal * (U.I - L.I);
+            }
+        }
+        // y-face at t = T: triangle acd covers s in [0, T], abc covers [T, 2]
+        {
+            const int T2 = side ? t_hi : t_lo;
+            const int br[3] = {s_lo, std::min(std::max(T2, s_lo), s_hi), s_hi};
+            for (int seg = 0; seg < 2; ++seg) {
+                const int sa = br[seg], sb = br[seg + 1];
+                if (sb <= sa) continue;
+                const double u0 = sa * hx, u1 = sb * hx;
+                const double h0 = hhalf(H, sa, T2), h1 = hhalf(H, sb, T2);
+                const PP1 L = pos_part1(u0, za - h0, u1, za - h1);
+                const PP1 U = pos_part1(u0, zb - h0, u1, zb - h1);
+                const int f = 2 + side;
+                o.fa[f] += U.I - L.I;
+                o.ft[f][0] += U.Iu - L.Iu;
+                o.ft[f][1] += (zb - za) * U.I - 0.5 * U.J + 0.5 * L.J + zal * (U.I - L.I);
+            }
+        }
+    }
+}
+
+__device__ inline void shift_box(BoxM& o, double sx, double sy, double sz) {
+    o.m[0] += sx * o.vol; o.m[1] += sy * o.vol; o.m[2] += sz * o.vol;
+    o.em[0] += sx * o.area; o.em[1] += sy * o.area; o.em[2] += sz * o.area;
+    // tangential coordinates of the faces: x-faces (y, z), y-faces (x, z), z-faces (x, y)
+    const double s[3] = {sx, sy, sz};
+    const int tg[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+    for (int f = 0; f < 6; ++f) {
+        const int d = f / 2;
+        o.ft[f][0] += s[tg[d][0]] * o.fa[f];
+        o.ft[f][1] += s[tg[d][1]] * o.fa[f];
+    }
+}
+
+// union of two boxes adjacent along d (A lower, B upper)
+__device__ inline void combine_box(const BoxM& A, const BoxM& B, int d, BoxM& o) {
+    o.vol = A.vol + B.vol;
+    o.area = A.area + B.area;
+    for (int e = 0; e < 3; ++e) {
+        o.m[e] = A.m[e] + B.m[e];
+        o.av[e] = A.av[e] + B.av[e];
+        o.em[e] = A.em[e] + B.em[e];
+    }
+    for (int f = 0; f < 6; ++f) {
+        if (f / 2 == d) {
+            const BoxM& S = (f % 2) ? B : A;
+            o.fa[f] = S.fa[f]; o.ft[f][0] = S.ft[f][0]; o.ft[f][1] = S.ft[f][1];
+        } else {
+            o.fa[f] = A.fa[f] + B.fa[f];
+            o.ft[f][0] = A.ft[f][0] + B.ft[f][0];
+            o.ft[f][1] = A.ft[f][1] + B.ft[f][1];
+        }
+    }
+}
+
+struct GeomArgs {
+    int nx, ny, nz;
+    double dx, dy, dz, lo_z;
+    const double* h;   // nodes (ny+1) x (nx+1)
+    int32_t* kf;       // [4][ncol]
+    int32_t* kr;
+    int32_t* g0;
+    int32_t* g1;
+};
+
+__device__ inline Heights cell_heights(const double* h, int nx, int ny, int i, int j) {
+    i = wrapi(i, nx);
+    j = wrapi(j, ny);
+    Heights H;
+    H.a = h[(size_t)j * (nx + 1) + i];
+    H.b = h[(size_t)j * (nx + 1) + i + 1];
+    H.c = h[(size_t)(j + 1) * (nx + 1) + i + 1];
+    H.d = h[(size_t)(j + 1) * (nx + 1) + i];
+    return H;
+}
+
+// min / max of the terrain over a half cell (its piece corners)
+__device__ inline void half_range(const Heights& H, int part, double& mn, double& mx) {
+    mn = INFINITY;
+    mx = -INFINITY;
+    for (int p = 0; p < 4; ++p) {
+        const Piece& P = kPieces[part][p];
+        if (P.tri < 0) break;
+        for (int v = 0; v < 3; ++v) {
+            const double x = hhalf(H, P.s[v], P.t[v]);
+            mn = fmin(mn, x);
+            mx = fmax(mx, x);
+        }
+    }
+}
+
+// first fluid and first regular level of instance inst in column (i, j)
+__global__ void k_classify(GeomArgs a) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncol = a.nx * a.ny;
+    if (c >= ncol) return;
+    const int i = c % a.nx, j = c / a.nx;
+    const Heights H = cell_heights(a.h, a.nx, a.ny, i, j);
+    double mn[4], mx[4];
+    half_range(H, 0, mn[0], mx[0]);
+    mn[3] = mn[0];
+    mx[3] = mx[0];
+    {
+        double m1, x1, m2, x2;
+        half_range(cell_heights(a.h, a.nx, a.ny, i - 1, j), 2, m1, x1);
+        half_range(H, 1, m2, x2);
+        mn[1] = fmin(m1, m2); mx[1] = fmax(x1, x2);
+        half_range(cell_heights(a.h, a.nx, a.ny, i, j - 1), 4, m1, x1);
+        half_range(H, 3, m2, x2);
+        mn[2] = fmin(m1, m2); mx[2] = fmax(x1, x2);
+    }
+    int gmin = a.nz;
+    for (int inst = 0; inst < 4; ++inst) {
+        int kf = -1, kr = -1;
+        const int k0 = inst == 3 ? 1 : 0, k1 = inst == 3 ? a.nz - 1 : a.nz - 1;
+        for (int k = k0; k <= k1; ++k) {
+            bool covered, regular;
+            if (inst == 3) {
+                covered = mn[3] >= zmidp(a.lo_z, a.dz, k);
+                regular = mx[3] < zmidp(a.lo_z, a.dz, k - 1);
+            } else {
+                covered = mn[inst] >= zplane(a.lo_z, a.dz, k + 1);
+                regular = (k == 0) ? (mx[inst] <= zplane(a.lo_z, a.dz, 0))
+                                   : (mx[inst] < zplane(a.lo_z, a.dz, k));
+            }
+            if (kf < 0 && !covered) kf = k;
+            if (kr < 0 && regular) { kr = k; break; }
+        }
+        if (kf < 0) kf = k1 + 1;
+        if (kr < 0) kr = k1 + 1;
+        if (kf > kr) kf = kr;
+        a.kf[inst * ncol + c] = kf;
+        a.kr[inst * ncol + c] = kr;
+        gmin = min(gmin, kf);
+    }
+    a.g0[c] = gmin;
+}
+
+__global__ void k_g1(GeomArgs a) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncol = a.nx * a.ny;
+    if (c >= ncol) return;
+    const int i = c % a.nx, j = c / a.nx;
+    int m = 0;
+    for (int dj = -GEN_RXY; dj <= GEN_RXY; ++dj)
+        for (int di = -GEN_RXY; di <= GEN_RXY; ++di) {
+            const int cc = wrapi(j + dj, a.ny) * a.nx + wrapi(i + di, a.nx);
+            for (int inst = 0; inst < 4; ++inst) m = max(m, a.kr[inst * ncol + cc]);
+        }
+    a.g1[c] = min(a.nz, max(m + GEN_RZ, a.g0[c]));
+}
+
+struct RecArgs {
+    GeomArgs a;
+    const int32_t* goff;
+    const int32_t* gcol;
+    int32_t G;
+    double* geo;   // [4][GQ_N][G]
+    int8_t* type;  // [4][G]
+};
+
+__device__ inline void put(const RecArgs& r, int inst, int q, int g, double v) {
+    r.geo[((size_t)inst * GQ_N + q) * r.G + g] = v;
+}
+
+__global__ void k_records(RecArgs r) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int inst = blockIdx.y;
+    if (g >= r.G) return;
+    const GeomArgs& a = r.a;
+    const int ncol = a.nx * a.ny;
+    const int c = r.gcol[g];
+    const int i = c % a.nx, j = c / a.nx;
+    const int k = a.g0[c] + (g - r.goff[c]);
+    const bool is_cv = inst == 3 ? (k >= 1 && k <= a.nz - 1) : (k <= a.nz - 1);
+    int ty;
+    if (!is_cv || k < a.kf[inst * ncol + c]) ty = 0;
+    else if (k >= a.kr[inst * ncol + c]) ty = 1;
+    else ty = 2;
+    r.type[(size_t)inst * r.G + g] = (int8_t)ty;
+    if (ty != 2) {
+        for (int q = 0; q < GQ_N; ++q) put(r, inst, q, g, 0.0);
+        if (ty == 1) {
+            put(r, inst, GQ_ALPHA, g, 1.0);
+            put(r, inst, GQ_BX, g, 1.0);
+            put(r, inst, GQ_BY, g, 1.0);
+            put(r, inst, GQ_BZ, g, 1.0);
+        }
+        return;
+    }
+    const double DX = a.dx, DY = a.dy, DZ = a.dz;
+    const Heights H = cell_heights(a.h, a.nx, a.ny, i, j);
+    const double zk = zplane(a.lo_z, DZ, k);
+    BoxM o;
+    double cx = 0.5 * DX, cy = 0.5 * DY, cz = 0.5 * DZ;
+    if (inst == 0) {
+        box_eval(H, DX, DY, 0, zk, zplane(a.lo_z, DZ, k + 1), zk, k == 0, o);
+    } else if (inst == 1) {
+        BoxM A, B;
+        box_eval(cell_heights(a.h, a.nx, a.ny, i - 1, j), DX, DY, 2, zk, zplane(a.lo_z, DZ, k + 1),
+                 zk, k == 0, A);
+        box_eval(H, DX, DY, 1, zk, zplane(a.lo_z, DZ, k + 1), zk, k == 0, B);
+        shift_box(A, -DX, 0.0, 0.0);
+        combine_box(A, B, 0, o);
+        cx = 0.0;
+    } else if (inst == 2) {
+        BoxM A, B;
+        box_eval(cell_heights(a.h, a.nx, a.ny, i, j - 1), DX, DY, 4, zk, zplane(a.lo_z, DZ, k + 1),
+                 zk, k == 0, A);
+        box_eval(H, DX, DY, 3, zk, zplane(a.lo_z, DZ, k + 1), zk, k == 0, B);
+        shift_box(A, 0.0, -DY, 0.0);
+        combine_box(A, B, 1, o);
+        cy = 0.0;
+    } else {
+        BoxM A, B;
+        const double zkm = zplane(a.lo_z, DZ, k - 1);
+        box_eval(H, DX, DY, 0, zmidp(a.lo_z, DZ, k - 1), zk, zkm, false, A);
+        box_eval(H, DX, DY, 0, zk, zmidp(a.lo_z, DZ, k), zk, k == 0, B);
+        shift_box(A, 0.0, 0.0, -DZ);
+        combine_box(A, B, 2, o);
+        cz = 0.0;
+    }
+    const double dv = DX * DY * DZ;
+    const double del[3] = {DX, DY, DZ};
+    const double ctr[3] = {cx, cy, cz};
+    const double farea[3] = {DY * DZ, DX * DZ, DX * DY};
+    const int tg[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+    put(r, inst, GQ_ALPHA, g, o.vol / dv);
+    for (int d = 0; d < 3; ++d) {
+        const double fa = o.fa[2 * d];
+        put(r, inst, GQ_BX + d, g, fa / farea[d]);
+        for (int t = 0; t < 2; ++t) {
+            const int e = tg[d][t];
+            put(r, inst, GQ_FX1 + 2 * d + t, g, fa > 0.0 ? (o.ft[2 * d][t] / fa - ctr[e]) / del[e] : 0.0);
+        }
+        put(r, inst, GQ_VCX + d, g, o.vol > 0.0 ? (o.m[d] / o.vol - ctr[d]) / del[d] : 0.0);
+        put(r, inst, GQ_AX + d, g, o.av[d] / farea[d]);
+        put(r, inst, GQ_EBX + d, g, o.area > 0.0 ? (o.em[d] / o.area - ctr[d]) / del[d] : 0.0);
+    }
+    put(r, inst, GQ_AREA, g, o.area / (DX * DY));
+}
+
+}  // namespace
+
+ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
+    const int ncol = cx->ncol;
+    GeomArgs a;
+    a.nx = cx->nx; a.ny = cx->ny; a.nz = cx->nz;
+    a.dx = cx->g.dx[0]; a.dy = cx->g.dx[1]; a.dz = cx->g.dx[2];
+    a.lo_z = cx->g.lo[2];
+    a.h = d_h;
+    a.kf = cx->d_kf; a.kr = cx->d_kr; a.g0 = cx->d_g0; a.g1 = cx->d_g1;
+    const int tb = 256;
+    hipLaunchKernelGGL(k_classify, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
+    EBS_HIP(cx, hipGetLastError());
+    hipLaunchKernelGGL(k_g1, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
+    EBS_HIP(cx, hipGetLastError());
+    cx->h_g0.assign(ncol, 0);
+    cx->h_g1.assign(ncol, 0);
+    EBS_HIP(cx, hipMemcpyAsync(cx->h_g0.data(), cx->d_g0, sizeof(int32_t) * ncol,
+                               hipMemcpyDeviceToHost, cx->stream));
+    EBS_HIP(cx, hipMemcpyAsync(cx->h_g1.data(), cx->d_g1, sizeof(int32_t) * ncol,
+                               hipMemcpyDeviceToHost, cx->stream));
+    EBS_HIP(cx, hipStreamSynchronize(cx->stream));
+    cx->h_goff.assign(ncol, 0);
+    int64_t G = 0;
+    for (int c = 0; c < ncol; ++c) {
+        cx->h_goff[c] = (int32_t)G;
+        G += cx->h_g1[c] - cx->h_g0[c];
+    }
+    if (G > INT32_MAX / 8) {
+        cx->err = "general region too large";
+        return EBS_E_UNSUPPORTED;
+    }
+    std::vector<int32_t> gcol((size_t)std::max<int64_t>(G, 1));
+    for (int c = 0; c < ncol; ++c)
+        for (int k = cx->h_g0[c]; k < cx->h_g1[c]; ++k) gcol[cx->h_goff[c] + (k - cx->h_g0[c])] = c;
+    cx->G = (int32_t)G;
+    const size_t Gs = (size_t)std::max<int64_t>(G, 1);
+    auto alloc = [&](void** p, size_t bytes) -> bool {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+        return hipMalloc(p, bytes) == hipSuccess;
+    };
+    bool ok = true;
+    ok &= alloc((void**)&cx->d_goff, sizeof(int32_t) * ncol);
+    ok &= alloc((void**)&cx->d_gcol, sizeof(int32_t) * Gs);
+    ok &= alloc((void**)&cx->d_geo, sizeof(double) * NINST * GQ_N * Gs);
+    ok &= alloc((void**)&cx->d_type, NINST * Gs);
+    ok &= alloc((void**)&cx->d_mask, sizeof(int32_t) * NINST * Gs);
+    ok &= alloc((void**)&cx->d_small, NINST * Gs);
+    ok &= alloc((void**)&cx->d_tier, NINST * Gs);
+    ok &= alloc((void**)&cx->d_w, sizeof(double) * NINST * WQ_COUNT * Gs);
+    ok &= alloc((void**)&cx->d_smalllist, sizeof(int32_t) * NINST * Gs);
+    ok &= alloc((void**)&cx->d_actlist, sizeof(int32_t) * NINST * Gs);
+    ok &= alloc((void**)&cx->d_uhat, sizeof(double) * 5 * Gs);
+    ok &= alloc((void**)&cx->d_qhat, sizeof(double) * 5 * Gs);
+    ok &= alloc((void**)&cx->d_sig, sizeof(double) * 15 * Gs);
+    if (!ok) {
+        cx->err = "device allocation of geometry tables failed";
+        return EBS_E_OOM;
+    }
+    EBS_HIP(cx, hipMemcpyAsync(cx->d_goff, cx->h_goff.data(), sizeof(int32_t) * ncol,
+                               hipMemcpyHostToDevice, cx->stream));
+    EBS_HIP(cx, hipMemcpyAsync(cx->d_gcol, gcol.data(), sizeof(int32_t) * Gs, hipMemcpyHostToDevice,
+                               cx->stream));
+    EBS_HIP(cx, hipMemsetAsync(cx->d_uhat, 0, sizeof(double) * 5 * Gs, cx->stream));
+    if (G > 0) {
+        RecArgs r;
+        r.a = a;
+        r.goff = cx->d_goff;
+        r.gcol = cx->d_gcol;
+        r.G = cx->G;
+        r.geo = cx->d_geo;
+        r.type = cx->d_type;
+        hipLaunchKernelGGL(k_records, dim3((G + 127) / 128, NINST), dim3(128), 0, cx->stream, r);
+        EBS_HIP(cx, hipGetLastError());
+    }
+    EBS_HIP(cx, hipStreamSynchronize(cx->stream));
+    return EBS_OK;
+}
+
+}  // namespace ebs

@@ -1,0 +1,610 @@
+// Weighted state redistribution on the four instances (Section 5.1 of the
+// paper; applied after every stage, Algorithm 1 step 4).
+//
+// Setup (once per geometry): small flags, merge neighbourhoods M (first along
+// the EB normal, then the next largest normal component completing a 2x2x1
+// block, then the 2x2x2 block, until the neighbourhood volume reaches
+// V_target), N = |W|, kappa (Eq. kappa), omega (Eq. omega), neighbourhood
+// volume (Eq. nbhd_vol) and centroid.  W is never stored: every kernel that
+// needs it gathers over the 26 neighbours and tests their member masks, so no
+// atomics are involved and results do not depend on thread order.
+//
+// Apply (per stage, per field of each instance): Q-hat (Eq. qhat_omega) on
+// small CVs, a least-squares gradient of Q-hat with a Barth-Jespersen-style
+// limiter, and the final gathered update (Eqs. qrecon, final_update_omega) on
+// the CVs the operator can change.  Everything is in double precision and reads
+// the double copy of the provisional state kept by the stage kernel.
+//
+// Readings (the paper is silent or garbled): small <=> 0 < alpha <
+// small_vfrac (1 - 1e-12); a tier is accepted once the member volume reaches
+// V_target (1 - 1e-12); axes ordered by |n_d| descending with ties (within
+// 1e-12 max|n|) to the lower axis, steps along sgn(n_d) (+ for |n_d| within the
+// tie tolerance); kappa = min(1, (V_target - V) / sum_{M-} V); N includes the CV's
+// own neighbourhood; gradient for small CVs with |M| >= 2 only, unweighted
+// least squares anchored at Q-hat_i over the fluid CVs of the 3x3x3 box, a
+// direction widened to 5 when the member centroids spread less than half a
+// cell along it, zero gradient with < 3 points, too little spread after
+// widening, or reciprocal condition number < 1e-10; limiter factor per
+// component from the values of the reconstruction at the centroids of M_i.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "ebs_internal.h"
+
+namespace ebs {
+namespace {
+
+__device__ inline int bit_of(int ox, int oy, int oz) { return (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1); }
+constexpr int32_t SELF_BIT = 1 << 13;
+
+struct WArgs {
+    GeoView v;
+    int32_t* mask;
+    int8_t* small;
+    int8_t* tier;
+    double* w;      // [4][WQ_COUNT][G]
+    double vfrac;   // small_vfrac
+    double dv;
+};
+
+__device__ inline double& wq(const WArgs& a, int inst, int q, int g) {
+    return a.w[((size_t)inst * WQ_COUNT + q) * a.v.G + g];
+}
+
+// general index of a neighbour CV, -1 if it is a regular CV outside the
+// general range, -2 if it is not a fluid CV
+__device__ inline int nbr(const GeoView& v, int inst, int i, int j, int k) {
+    if (!cv_plane(v, inst, k)) return -2;
+    i = wrapi(i, v.nx);
+    j = wrapi(j, v.ny);
+    const int g = gidx(v, i, j, k);
+    if (g == -2) return -2;
+    if (g == -1) return -1;
+    if (v.type[(size_t)inst * v.G + g] == 0) return -2;
+    return g;
+}
+
+__device__ inline double alpha_of(const GeoView& v, int inst, int g) {
+    return g == -1 ? 1.0 : (g < 0 ? 0.0 : gq(v, inst, GQ_ALPHA, g));
+}
+
+__device__ inline void cell_of(const GeoView& v, int g, int& i, int& j, int& k) {
+    const int c = v.gcol[g];
+    i = c % v.nx;
+    j = c / v.nx;
+    k = v.g0[c] + (g - v.goff[c]);
+}
+
+__global__ void k_merge(WArgs a) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int inst = blockIdx.y;
+    if (g >= a.v.G) return;
+    const GeoView& v = a.v;
+    const size_t o = (size_t)inst * v.G + g;
+    a.small[o] = 0;
+    a.tier[o] = 0;
+    if (v.type[o] == 0) { a.mask[o] = 0; return; }
+    const double al = gq(v, inst, GQ_ALPHA, g);
+    if (!(al < a.vfrac * (1.0 - TIE))) { a.mask[o] = SELF_BIT; return; }
+    a.small[o] = 1;
+    int i, j, k;
+    cell_of(v, g, i, j, k);
+    const double n[3] = {gq(v, inst, GQ_AX, g) * v.dy * v.dz, gq(v, inst, GQ_AY, g) * v.dx * v.dz,
+                         gq(v, inst, GQ_AZ, g) * v.dx * v.dy};
+    const double mx = fmax(fabs(n[0]), fmax(fabs(n[1]), fabs(n[2])));
+    const double tol = TIE * mx;
+    int order[3];
+    bool used[3] = {false, false, false};
+    for (int r = 0; r < 3; ++r) {
+        double best = -1.0;
+        for (int d = 0; d < 3; ++d)
+            if (!used[d]) best = fmax(best, fabs(n[d]));
+        for (int d = 0; d < 3; ++d)
+            if (!used[d] && fabs(n[d]) >= best - tol) { order[r] = d; used[d] = true; break; }
+    }
+    int sg[3];
+    for (int d = 0; d < 3; ++d) sg[d] = (n[d] < -tol) ? -1 : 1;
+    int32_t mask = SELF_BIT;
+    const double dv = a.dv;
+    const double vt = a.vfrac * dv;
+    double vsum = al * dv;
+    int tier = 0;
+    for (int t = 1; t <= 3; ++t) {
+        tier = t;
+        for (int p = 0; p <= (t >= 1); ++p)
+            for (int q = 0; q <= (t >= 2); ++q)
+                for (int e = 0; e <= (t >= 3); ++e) {
+                    int off[3] = {0, 0, 0};
+                    off[order[0]] += p * sg[order[0]];
+                    off[order[1]] += q * sg[order[1]];
+                    off[order[2]] += e * sg[order[2]];
+                    const int bt = bit_of(off[0], off[1], off[2]);
+                    if ((mask >> bt) & 1) continue;
+                    const int gn = nbr(v, inst, i + off[0], j + off[1], k + off[2]);
+                    if (gn == -2) continue;
+                    mask |= 1 << bt;
+                    vsum += alpha_of(v, inst, gn) * dv;
+                }
+        if (vsum >= vt * (1.0 - TIE)) break;
+    }
+    a.mask[o] = mask;
+    a.tier[o] = (int8_t)tier;
+}
+
+__device__ inline int32_t mask_of(const WArgs& a, int inst, int g) {
+    return g == -1 ? SELF_BIT : (g < 0 ? 0 : a.mask[(size_t)inst * a.v.G + g]);
+}
+
+__global__ void k_count(WArgs a) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int inst = blockIdx.y;
+    if (g >= a.v.G) return;
+    const GeoView& v = a.v;
+    if (v.type[(size_t)inst * v.G + g] == 0) { wq(a, inst, WQ_N, g) = 0.0; return; }
+    int i, j, k;
+    cell_of(v, g, i, j, k);
+    int cnt = 0;
+    for (int oz = -1; oz <= 1; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                const int gr = nbr(v, inst, i - ox, j - oy, k - oz);
+                if (gr == -2) continue;
+                if ((mask_of(a, inst, gr) >> bit_of(ox, oy, oz)) & 1) ++cnt;
+            }
+    wq(a, inst, WQ_N, g) = (double)cnt;
+}
+
+__global__ void k_kappa(WArgs a) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int inst = blockIdx.y;
+    if (g >= a.v.G) return;
+    const GeoView& v = a.v;
+    double kap = 0.0;
+    const size_t o = (size_t)inst * v.G + g;
+    if (a.small[o]) {
+        int i, j, k;
+        cell_of(v, g, i, j, k);
+        const double dv = a.dv, vt = a.vfrac * dv;
+        const double V = gq(v, inst, GQ_ALPHA, g) * dv;
+        const int32_t m = a.mask[o];
+        double s = 0.0;
+        for (int oz = -1; oz <= 1; ++oz)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int ox = -1; ox <= 1; ++ox) {
+                    if (ox == 0 && oy == 0 && oz == 0) continue;
+                    if (!((m >> bit_of(ox, oy, oz)) & 1)) continue;
+                    s += alpha_of(v, inst, nbr(v, inst, i + ox, j + oy, k + oz)) * dv;
+                }
+        if (V < vt && s > 0.0) kap = fmin(1.0, (vt - V) / s);
+    }
+    wq(a, inst, WQ_KAPPA, g) = kap;
+}
+
+__global__ void k_omega(WArgs a) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int inst = blockIdx.y;
+    if (g >= a.v.G) return;
+    const GeoView& v = a.v;
+    if (v.type[(size_t)inst * v.G + g] == 0) { wq(a, inst, WQ_OMEGA, g) = 0.0; return; }
+    int i, j, k;
+    cell_of(v, g, i, j, k);
+    double ks = 0.0;
+    for (int oz = -1; oz <= 1; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                if (ox == 0 && oy == 0 && oz == 0) continue;
+                const int gr = nbr(v, inst, i - ox, j - oy, k - oz);
+                if (gr < 0) continue;  // regular CVs outside the range have kappa 0
+                if ((a.mask[(size_t)inst * v.G + gr] >> bit_of(ox, oy, oz)) & 1)
+                    ks += wq(a, inst, WQ_KAPPA, gr);
+            }
+    wq(a, inst, WQ_OMEGA, g) = 1.0 - ks / wq(a, inst, WQ_N, g);
+}
+
+__global__ void k_vhat(WArgs a) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int inst = blockIdx.y;
+    if (g >= a.v.G) return;
+    const GeoView& v = a.v;
+    if (v.type[(size_t)inst * v.G + g] == 0) {
+        for (int q = WQ_VHAT; q <= WQ_XHZ; ++q) wq(a, inst, q, g) = 0.0;
+        return;
+    }
+    int i, j, k;
+    cell_of(v, g, i, j, k);
+    const double dv = a.dv;
+    const double V = gq(v, inst, GQ_ALPHA, g) * dv;
+    const double om = wq(a, inst, WQ_OMEGA, g);
+    const double kap = wq(a, inst, WQ_KAPPA, g);
+    const int32_t m = a.mask[(size_t)inst * v.G + g];
+    double vh = om * V;
+    double xs[3];
+    for (int d = 0; d < 3; ++d) xs[d] = om * V * gq(v, inst, GQ_VCX + d, g);
+    for (int oz = -1; oz <= 1; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                if (ox == 0 && oy == 0 && oz == 0) continue;
+                if (!((m >> bit_of(ox, oy, oz)) & 1)) continue;
+                const int gr = nbr(v, inst, i + ox, j + oy, k + oz);
+                const double Vr = alpha_of(v, inst, gr) * dv;
+                const double Nr = gr >= 0 ? wq(a, inst, WQ_N, gr) : 1.0;
+                const int off[3] = {ox, oy, oz};
+                vh += kap * Vr / Nr;
+                for (int d = 0; d < 3; ++d)
+                    xs[d] += kap * Vr / Nr * (off[d] + (gr >= 0 ? gq(v, inst, GQ_VCX + d, gr) : 0.0));
+            }
+    wq(a, inst, WQ_VHAT, g) = vh / dv;
+    for (int d = 0; d < 3; ++d) wq(a, inst, WQ_XHX + d, g) = xs[d] / vh;
+}
+
+// ------------------------------------------------------------------ apply
+struct AArgs {
+    GeoView v;
+    const int32_t* mask;
+    const int8_t* small;
+    const double* w;
+    const double* uhat;   // [5][G]
+    double* qhat;         // [5][G]
+    double* sig;          // [5][3][G]
+    const int32_t* list;  // general indices
+    int32_t nlist;
+    int inst;
+    int f0, nf;           // fields of the instance
+    int limiter;
+    double dv;
+};
+
+__device__ inline double wv(const AArgs& a, int q, int g) {
+    return a.w[((size_t)a.inst * WQ_COUNT + q) * a.v.G + g];
+}
+
+__global__ void k_qhat(AArgs a) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.nlist) return;
+    const int g = a.list[t];
+    const GeoView& v = a.v;
+    int i, j, k;
+    cell_of(v, g, i, j, k);
+    const double V = gq(v, a.inst, GQ_ALPHA, g) * a.dv;
+    const double om = wv(a, WQ_OMEGA, g), kap = wv(a, WQ_KAPPA, g);
+    const double den = wv(a, WQ_VHAT, g) * a.dv;
+    const int32_t m = a.mask[(size_t)a.inst * v.G + g];
+    for (int f = a.f0; f < a.f0 + a.nf; ++f) {
+        const double* U = a.uhat + (size_t)f * v.G;
+        double s = om * V * U[g];
+        for (int oz = -1; oz <= 1; ++oz)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int ox = -1; ox <= 1; ++ox) {
+                    if (ox == 0 && oy == 0 && oz == 0) continue;
+                    if (!((m >> bit_of(ox, oy, oz)) & 1)) continue;
+                    const int gr = nbr(v, a.inst, i + ox, j + oy, k + oz);
+                    // every member of a small CV's neighbourhood lies in the
+                    // general range (its margin exceeds the merge radius)
+                    if (gr < 0) continue;
+                    const double Vr = gq(v, a.inst, GQ_ALPHA, gr) * a.dv;
+                    const double Nr = wv(a, WQ_N, gr);
+                    s += kap * Vr / Nr * U[gr];
+                }
+        a.qhat[(size_t)f * v.G + g] = s / den;
+    }
+}
+
+// Q-hat of a CV inside the general range: small CVs with kappa > 0 carry
+// their own, every other CV has a single-cell neighbourhood (Q-hat = U-hat)
+__device__ inline double qh_of(const AArgs& a, int f, int g) {
+    const size_t o = (size_t)a.inst * a.v.G + g;
+    if (a.small[o] && wv(a, WQ_KAPPA, g) > 0.0) return a.qhat[(size_t)f * a.v.G + g];
+    return a.uhat[(size_t)f * a.v.G + g];
+}
+
+__device__ inline double psi(double delta, double qi, double qmin, double qmax) {
+    if (delta > 0.0) return fmin(1.0, (qmax - qi) / delta);
+    if (delta < 0.0) return fmin(1.0, (qmin - qi) / delta);
+    return 1.0;
+}
+
+__global__ void k_grad(AArgs a) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.nlist) return;
+    const int g = a.list[t];
+    const GeoView& v = a.v;
+    int i, j, k;
+    cell_of(v, g, i, j, k);
+    const double xh[3] = {wv(a, WQ_XHX, g), wv(a, WQ_XHY, g), wv(a, WQ_XHZ, g)};
+    // fit box: widen directions with too little centroid spread
+    int wd[3] = {1, 1, 1};
+    double spread[3];
+    int npts = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        spread[0] = spread[1] = spread[2] = 0.0;
+        npts = 0;
+        for (int oz = -wd[2]; oz <= wd[2]; ++oz)
+            for (int oy = -wd[1]; oy <= wd[1]; ++oy)
+                for (int ox = -wd[0]; ox <= wd[0]; ++ox) {
+                    if (ox == 0 && oy == 0 && oz == 0) continue;
+                    const int gs = nbr(v, a.inst, i + ox, j + oy, k + oz);
+                    if (gs < 0) continue;  // not fluid (regular CVs lie outside the fit radius)
+                    const int off[3] = {ox, oy, oz};
+                    for (int d = 0; d < 3; ++d)
+                        spread[d] = fmax(spread[d], fabs(off[d] + wv(a, WQ_XHX + d, gs) - xh[d]));
+                    ++npts;
+                }
+        if (pass == 1) break;
+        bool widened = false;
+        for (int d = 0; d < 3; ++d)
+            if (spread[d] < 0.5 * (1.0 - TIE)) { wd[d] = 2; widened = true; }
+        if (!widened) break;
+    }
+    bool zero = npts < 3;
+    for (int d = 0; d < 3; ++d)
+        if (spread[d] < 0.5 * (1.0 - TIE)) zero = true;
+    // normal matrix in mesh units (same for every field)
+    double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    if (!zero) {
+        for (int oz = -wd[2]; oz <= wd[2]; ++oz)
+            for (int oy = -wd[1]; oy <= wd[1]; ++oy)
+                for (int ox = -wd[0]; ox <= wd[0]; ++ox) {
+                    if (ox == 0 && oy == 0 && oz == 0) continue;
+                    const int gs = nbr(v, a.inst, i + ox, j + oy, k + oz);
+                    if (gs < 0) continue;
+                    const double e[3] = {ox + wv(a, WQ_XHX, gs) - xh[0], oy + wv(a, WQ_XHY, gs) - xh[1],
+                                         oz + wv(a, WQ_XHZ, gs) - xh[2]};
+                    for (int r = 0; r < 3; ++r)
+                        for (int q = 0; q < 3; ++q) A[r][q] += e[r] * e[q];
+                }
+    }
+    // inverse by the adjugate; reciprocal condition number in the 1-norm
+    double inv[3][3];
+    if (!zero) {
+        const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+        const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+        const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+        const double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+        if (!(fabs(det) > 0.0)) {
+            zero = true;
+        } else {
+            const double id = 1.0 / det;
+            inv[0][0] = c00 * id;
+            inv[1][0] = c01 * id;
+            inv[2][0] = c02 * id;
+            inv[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id;
+            inv[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id;
+            inv[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * id;
+            inv[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id;
+            inv[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id;
+            inv[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
+            double n1 = 0.0, ni = 0.0;
+            for (int q = 0; q < 3; ++q) {
+                n1 = fmax(n1, fabs(A[0][q]) + fabs(A[1][q]) + fabs(A[2][q]));
+                ni = fmax(ni, fabs(inv[0][q]) + fabs(inv[1][q]) + fabs(inv[2][q]));
+            }
+            if (!(1.0 / (n1 * ni) >= 1e-10)) zero = true;
+        }
+    }
+    // evaluation points of the limiter: centroids of the members of M_i
+    const int32_t m = a.mask[(size_t)a.inst * v.G + g];
+    const double del[3] = {v.dx, v.dy, v.dz};
+    for (int f = a.f0; f < a.f0 + a.nf; ++f) {
+        double s[3] = {0.0, 0.0, 0.0};
+        if (!zero) {
+            const double qi = a.qhat[(size_t)f * v.G + g];
+            double b[3] = {0.0, 0.0, 0.0};
+            double qmin = qi, qmax = qi;
+            for (int oz = -wd[2]; oz <= wd[2]; ++oz)
+                for (int oy = -wd[1]; oy <= wd[1]; ++oy)
+                    for (int ox = -wd[0]; ox <= wd[0]; ++ox) {
+                        if (ox == 0 && oy == 0 && oz == 0) continue;
+                        const int gs = nbr(v, a.inst, i + ox, j + oy, k + oz);
+                        if (gs < 0) continue;
+                        const double qs = qh_of(a, f, gs);
+                        const double e[3] = {ox + wv(a, WQ_XHX, gs) - xh[0],
+                                             oy + wv(a, WQ_XHY, gs) - xh[1],
+                                             oz + wv(a, WQ_XHZ, gs) - xh[2]};
+                        for (int r = 0; r < 3; ++r) b[r] += e[r] * (qs - qi);
+                        qmin = fmin(qmin, qs);
+                        qmax = fmax(qmax, qs);
+                    }
+            for (int r = 0; r < 3; ++r) s[r] = inv[r][0] * b[0] + inv[r][1] * b[1] + inv[r][2] * b[2];
+            if (a.limiter != EBS_LIM_NONE) {
+                double lam[3] = {1.0, 1.0, 1.0};
+                double lall = 1.0;
+                for (int oz = -1; oz <= 1; ++oz)
+                    for (int oy = -1; oy <= 1; ++oy)
+                        for (int ox = -1; ox <= 1; ++ox) {
+                            if (!((m >> bit_of(ox, oy, oz)) & 1)) continue;
+                            const int gj = nbr(v, a.inst, i + ox, j + oy, k + oz);
+                            const int off[3] = {ox, oy, oz};
+                            double ev[3];
+                            for (int d = 0; d < 3; ++d)
+                                ev[d] = off[d] + (gj >= 0 ? gq(v, a.inst, GQ_VCX + d, gj) : 0.0) - xh[d];
+                            if (a.limiter == EBS_LIM_BJ_COMPONENT) {
+                                for (int d = 0; d < 3; ++d) lam[d] = fmin(lam[d], psi(s[d] * ev[d], qi, qmin, qmax));
+                            } else {
+                                lall = fmin(lall, psi(s[0] * ev[0] + s[1] * ev[1] + s[2] * ev[2], qi, qmin, qmax));
+                            }
+                        }
+                if (a.limiter == EBS_LIM_BJ_COMPONENT) {
+                    for (int d = 0; d < 3; ++d) s[d] *= lam[d];
+                } else {
+                    for (int d = 0; d < 3; ++d) s[d] *= lall;
+                }
+            }
+        }
+        for (int d = 0; d < 3; ++d) a.sig[((size_t)f * 3 + d) * v.G + g] = s[d] / del[d];
+    }
+}
+
+template <typename T>
+struct FArgs {
+    AArgs a;
+    int nx, ny, nz;
+    T* out[5];
+};
+
+template <typename T>
+__global__ void k_final(FArgs<T> F) {
+    const AArgs& a = F.a;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.nlist) return;
+    const int g = a.list[t];
+    const GeoView& v = a.v;
+    int i, j, k;
+    cell_of(v, g, i, j, k);
+    const double om = wv(a, WQ_OMEGA, g), Ni = wv(a, WQ_N, g);
+    const double del[3] = {v.dx, v.dy, v.dz};
+    const size_t oi = (size_t)a.inst * v.G + g;
+    const bool ismall = a.small[oi] && wv(a, WQ_KAPPA, g) > 0.0;
+    for (int f = a.f0; f < a.f0 + a.nf; ++f) {
+        double qi = qh_of(a, f, g);
+        if (ismall)
+            for (int d = 0; d < 3; ++d)
+                qi += a.sig[((size_t)f * 3 + d) * v.G + g] *
+                      (gq(v, a.inst, GQ_VCX + d, g) - wv(a, WQ_XHX + d, g)) * del[d];
+        double s = 0.0;
+        for (int oz = -1; oz <= 1; ++oz)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int ox = -1; ox <= 1; ++ox) {
+                    if (ox == 0 && oy == 0 && oz == 0) continue;
+                    const int gr = nbr(v, a.inst, i - ox, j - oy, k - oz);
+                    if (gr < 0) continue;
+                    if (!((a.mask[(size_t)a.inst * v.G + gr] >> bit_of(ox, oy, oz)) & 1)) continue;
+                    const int off[3] = {ox, oy, oz};
+                    double qr = a.qhat[(size_t)f * v.G + gr];
+                    for (int d = 0; d < 3; ++d)
+                        qr += a.sig[((size_t)f * 3 + d) * v.G + gr] *
+                              (off[d] + gq(v, a.inst, GQ_VCX + d, g) - wv(a, WQ_XHX + d, gr)) * del[d];
+                    s += wv(a, WQ_KAPPA, gr) * qr;
+                }
+        const double val = om * qi + s / Ni;
+        // write into the state layout (with the periodic repeat)
+        const int nx = F.nx, ny = F.ny;
+        size_t idx;
+        if (f == 2) idx = ((size_t)k * ny + j) * (nx + 1) + i;
+        else if (f == 3) idx = ((size_t)k * (ny + 1) + j) * nx + i;
+        else idx = ((size_t)k * ny + j) * nx + i;
+        F.out[f][idx] = (T)val;
+        if (f == 2 && i == 0) F.out[2][((size_t)k * ny + j) * (nx + 1) + nx] = (T)val;
+        if (f == 3 && j == 0) F.out[3][((size_t)k * (ny + 1) + ny) * nx + i] = (T)val;
+    }
+}
+
+}  // namespace
+
+WsrdView wsrd_view(const ebs_ctx* c) {
+    WsrdView w;
+    w.mask = c->d_mask;
+    w.small = c->d_small;
+    w.tier = c->d_tier;
+    w.w = c->d_w;
+    w.limiter = c->g.limiter;
+    w.vt = c->g.small_vfrac;
+    return w;
+}
+
+ebs_status wsrd_setup(ebs_ctx* cx) {
+    if (cx->G == 0) return EBS_OK;
+    WArgs a;
+    a.v = geo_view(cx);
+    a.mask = cx->d_mask;
+    a.small = cx->d_small;
+    a.tier = cx->d_tier;
+    a.w = cx->d_w;
+    a.vfrac = cx->g.small_vfrac;
+    a.dv = cx->g.dx[0] * cx->g.dx[1] * cx->g.dx[2];
+    const dim3 grid((cx->G + 127) / 128, NINST), blk(128);
+    hipLaunchKernelGGL(k_merge, grid, blk, 0, cx->stream, a);
+    hipLaunchKernelGGL(k_count, grid, blk, 0, cx->stream, a);
+    hipLaunchKernelGGL(k_kappa, grid, blk, 0, cx->stream, a);
+    hipLaunchKernelGGL(k_omega, grid, blk, 0, cx->stream, a);
+    hipLaunchKernelGGL(k_vhat, grid, blk, 0, cx->stream, a);
+    EBS_HIP(cx, hipGetLastError());
+    // work lists: small CVs with kappa > 0, and every CV the operator may change
+    const size_t G = cx->G;
+    std::vector<int8_t> small(NINST * G);
+    std::vector<double> w((size_t)NINST * WQ_COUNT * G);
+    EBS_HIP(cx, hipMemcpyAsync(small.data(), cx->d_small, NINST * G, hipMemcpyDeviceToHost, cx->stream));
+    EBS_HIP(cx, hipMemcpyAsync(w.data(), cx->d_w, sizeof(double) * NINST * WQ_COUNT * G,
+                               hipMemcpyDeviceToHost, cx->stream));
+    EBS_HIP(cx, hipStreamSynchronize(cx->stream));
+    std::vector<int32_t> sl, al;
+    for (int inst = 0; inst < NINST; ++inst) {
+        sl.clear();
+        al.clear();
+        const double* N = &w[((size_t)inst * WQ_COUNT + WQ_N) * G];
+        const double* K = &w[((size_t)inst * WQ_COUNT + WQ_KAPPA) * G];
+        for (size_t g = 0; g < G; ++g) {
+            const bool sm = small[inst * G + g] && K[g] > 0.0;
+            if (sm) sl.push_back((int32_t)g);
+            if (sm || N[g] > 1.0) al.push_back((int32_t)g);
+        }
+        cx->nsmall[inst] = (int32_t)sl.size();
+        cx->nact[inst] = (int32_t)al.size();
+        if (!sl.empty())
+            EBS_HIP(cx, hipMemcpy(cx->d_smalllist + inst * G, sl.data(), sizeof(int32_t) * sl.size(),
+                                  hipMemcpyHostToDevice));
+        if (!al.empty())
+            EBS_HIP(cx, hipMemcpy(cx->d_actlist + inst * G, al.data(), sizeof(int32_t) * al.size(),
+                                  hipMemcpyHostToDevice));
+    }
+    return EBS_OK;
+}
+
+template <typename T>
+static ebs_status redistribute_t(ebs_ctx* cx, ebs_state* Uout) {
+    void* const ou[5] = {Uout->rho, Uout->rhotheta, Uout->rhou, Uout->rhov, Uout->rhow};
+    const int f0s[4] = {0, 2, 3, 4}, nfs[4] = {2, 1, 1, 1};
+    for (int inst = 0; inst < NINST; ++inst) {
+        AArgs a;
+        a.v = geo_view(cx);
+        a.mask = cx->d_mask;
+        a.small = cx->d_small;
+        a.w = cx->d_w;
+        a.uhat = cx->d_uhat;
+        a.qhat = cx->d_qhat;
+        a.sig = cx->d_sig;
+        a.inst = inst;
+        a.f0 = f0s[inst];
+        a.nf = nfs[inst];
+        a.limiter = cx->g.limiter;
+        a.dv = cx->g.dx[0] * cx->g.dx[1] * cx->g.dx[2];
+        if (cx->nsmall[inst] > 0) {
+            a.list = cx->d_smalllist + (size_t)inst * cx->G;
+            a.nlist = cx->nsmall[inst];
+            hipLaunchKernelGGL(k_qhat, dim3((a.nlist + 127) / 128), dim3(128), 0, cx->stream, a);
+            hipLaunchKernelGGL(k_grad, dim3((a.nlist + 63) / 64), dim3(64), 0, cx->stream, a);
+        }
+        if (cx->nact[inst] > 0) {
+            FArgs<T> F;
+            F.a = a;
+            F.a.list = cx->d_actlist + (size_t)inst * cx->G;
+            F.a.nlist = cx->nact[inst];
+            F.nx = cx->nx;
+            F.ny = cx->ny;
+            F.nz = cx->nz;
+            for (int f = 0; f < 5; ++f) F.out[f] = (T*)ou[f];
+            hipLaunchKernelGGL(k_final<T>, dim3((F.a.nlist + 127) / 128), dim3(128), 0, cx->stream, F);
+        }
+        EBS_HIP(cx, hipGetLastError());
+    }
+    return EBS_OK;
+}
+
+ebs_status launch_redistribute(ebs_ctx* cx, const ebs_state* Uhat, ebs_state* Uout) {
+    // copy the provisional state where R is the identity when the output is separate
+    void* const in[5] = {Uhat->rho, Uhat->rhotheta, Uhat->rhou, Uhat->rhov, Uhat->rhow};
+    void* const ou[5] = {Uout->rho, Uout->rhotheta, Uout->rhou, Uout->rhov, Uout->rhow};
+    const size_t es = cx->g.precision == EBS_F32_BULK ? 4 : 8;
+    const size_t nx = cx->nx, ny = cx->ny, nz = cx->nz;
+    const size_t cnt[5] = {nx * ny * nz, nx * ny * nz, (nx + 1) * ny * nz, nx * (ny + 1) * nz,
+                           nx * ny * (nz + 1)};
+    for (int f = 0; f < 5; ++f)
+        if (in[f] != ou[f])
+            EBS_HIP(cx, hipMemcpyAsync(ou[f], in[f], es * cnt[f], hipMemcpyDeviceToDevice, cx->stream));
+    if (cx->G == 0) return EBS_OK;
+    if (cx->g.precision == EBS_F32_BULK) return redistribute_t<float>(cx, Uout);
+    return redistribute_t<double>(cx, Uout);
+}
+
+}  // namespace ebs

@@ -1,0 +1,78 @@
+"""The C-ABI library builds, loads and exports every entry point declared in
+include/ebstag.h; argument checks that happen before any device work.  CPU
+only (no kernel is launched)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2604_11959_amd as ebs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "ebstag.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ebs_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_bound_symbols():
+    assert _declared() == sorted(ebs.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ebs.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert lib.ebs_last_error(None) == b"null context"
+
+
+def _grid(n=(16, 16, 8), periodic=0x3, vfrac=0.5, prec=0):
+    return ebs.Grid((C.c_int32 * 3)(*n), (C.c_double * 3)(1.0, 1.0, 1.0),
+                    (C.c_double * 3)(0.0, 0.0, 0.0), periodic, vfrac, prec, 0, 0)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=(4, 16, 8)), ebs.EBS_E_ARG),
+    (dict(n=(16, 16, 2)), ebs.EBS_E_ARG),
+    (dict(vfrac=1.5), ebs.EBS_E_ARG),
+    (dict(prec=7), ebs.EBS_E_ARG),
+    (dict(periodic=0x1), ebs.EBS_E_UNSUPPORTED),
+    (dict(periodic=0x7), ebs.EBS_E_UNSUPPORTED),
+])
+def test_create_rejects_bad_grids(kw, status):
+    lib = ebs.load()
+    h = C.c_void_p()
+    g = _grid(**kw)
+    assert lib.ebs_create(C.byref(g), None, 0, None, C.byref(h)) == status
+    assert not h.value
+
+
+def test_create_rejects_box_lists_that_do_not_tile():
+    lib = ebs.load()
+    g = _grid()
+    h = C.c_void_p()
+    # overlap
+    boxes = (ebs.Box * 2)(ebs.Box((0, 0, 0), (16, 16, 8)), ebs.Box((0, 0, 0), (8, 8, 8)))
+    assert lib.ebs_create(C.byref(g), boxes, 2, None, C.byref(h)) == ebs.EBS_E_ARG
+    # gap
+    boxes = (ebs.Box * 1)(ebs.Box((0, 0, 0), (16, 16, 4)))
+    assert lib.ebs_create(C.byref(g), boxes, 1, None, C.byref(h)) == ebs.EBS_E_ARG
+    # outside the domain
+    boxes = (ebs.Box * 1)(ebs.Box((0, 0, 0), (17, 16, 8)))
+    assert lib.ebs_create(C.byref(g), boxes, 1, None, C.byref(h)) == ebs.EBS_E_ARG
+    assert lib.ebs_destroy(None) == ebs.EBS_OK
+
+
+def test_box_splitter_tiles_the_domain():
+    import synth
+    for n, target in (((512, 512, 128), 512), ((1024, 1024, 192), 3072)):
+        boxes = synth.boxes_split(n, 4, target)
+        assert len(boxes) == target
+        vol = sum((h[0] - l[0]) * (h[1] - l[1]) * (h[2] - l[2]) for l, h in boxes)
+        assert vol == n[0] * n[1] * n[2]
+        for l, h in boxes:
+            for d in range(3):
+                assert (h[d] - l[d]) % 16 == 0 and 16 <= h[d] - l[d] <= 64
