@@ -36,7 +36,7 @@ def _log(msg):
 
 
 def run_workload(cfg: int, precision: int, steps: int, warmup: int, use_graph: bool,
-                 autotune: bool, timing: bool):
+                 autotune: bool, timing: bool, tile=None):
     import torch
 
     import paper_2604_11959_amd as ebs
@@ -49,10 +49,12 @@ def run_workload(cfg: int, precision: int, steps: int, warmup: int, use_graph: b
     t0 = time.time()
     ctx.build_geometry(w.h_nodes)
     _log(f"{w.name}: geometry built in {time.time() - t0:.1f}s")
-    tile = None
-    if autotune:
+    if tile:
+        ctx.set_tile(*tile)
+    elif autotune:
         tile = ctx.autotune(os.environ.get("EBS_TILE_CACHE", "/tmp/ebstag_tiles.json"))
         _log(f"{w.name}: tile {tile}")
+    tile = ctx.get_tile()
     U = ctx.new_state(synth.make_state(w))
     S = [ctx.new_state(), ctx.new_state()]
     stream = torch.cuda.current_stream()
@@ -111,7 +113,20 @@ def main(argv=None):
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--tile", default=None, help="fixed tile shape TXxTY (skips the autotuner)")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args(argv)
+    if args.calib_copy:
+        import torch
+
+        x = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": x.numel() * 4, "calib_copy_bytes_written": y.numel() * 4}))
+        return 0
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is described in the design notes but not built.",
@@ -124,14 +139,19 @@ def main(argv=None):
     cfg = int(args.workload[1:])
     precision = ebs.EBS_F64 if cfg == 2 else ebs.EBS_F32_BULK
     # main timed region: graph replays of the RK3 step
-    main = run_workload(cfg, precision, args.steps, args.warmup, not args.no_graph, True, False)
+    tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
+    main = run_workload(cfg, precision, args.steps, args.warmup, not args.no_graph, True, False, tile)
     w = main["workload"]
     N = w.grid.ncells
     ms_step = main["ms"] / args.steps
     value = N * 3 / (ms_step * 1e-3) / 1e6
     _log(f"main: {ms_step:.3f} ms/step, {value:.0f} Mcell-upd/s")
     # dominant kernel timed with HIP events on the context stream (direct launches)
-    kt = run_workload(cfg, precision, args.steps, 1, False, True, True)
+    if args.no_kernel_timing:
+        kt = main
+        kt["kern"] = (float("nan"), 1)
+    else:
+        kt = run_workload(cfg, precision, args.steps, 1, False, True, True, main["tile"])
     kms, nl = kt["kern"]
     avg_ms = kms / max(nl, 1)
     alg0, alg1 = kt["alg"]

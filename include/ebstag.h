@@ -176,8 +176,10 @@ ebs_status ebs_conserved_sums(ebs_ctx* ctx, const ebs_state* U, double hi[5], do
  * Synchronous; scratch states are allocated and freed internally. */
 ebs_status ebs_autotune(ebs_ctx* ctx, const char* cache_json_path);
 
-/* Tile shape of the regular-region kernel: tx in {32, 64, 128}, ty in {1, 2, 4, 8}
- * with tx*ty in [64, 512]. */
+/* Tile shape (columns per block) of the regular-region kernel: tx in
+ * {16, 32, 64}, ty in {2, 4, 8, 16}, tx*ty in [64, 256], (tx+5)(ty+5) <=
+ * 4 tx ty, and its LDS rings within 64 KiB (26 (tx+5)(ty+5) elements of the
+ * state type).  EBS_E_ARG otherwise. */
 ebs_status ebs_set_tile(ebs_ctx* ctx, int32_t tx, int32_t ty);
 ebs_status ebs_get_tile(const ebs_ctx* ctx, int32_t* tx, int32_t* ty);
 

@@ -39,6 +39,7 @@ GeoView geo_view(const ebs_ctx* c) {
     v.g1 = c->d_g1;
     v.goff = c->d_goff;
     v.gcol = c->d_gcol;
+    v.col = c->d_col;
     v.kf = c->d_kf;
     v.kr = c->d_kr;
     v.geo = c->d_geo;
@@ -116,6 +117,10 @@ ebs_status ebs_create(const ebs_grid* grid, const ebs_box* boxes, int32_t nbox, 
     c->nz = g.n[2];
     c->ncol = c->nx * c->ny;
     c->stream = (hipStream_t)hip_stream;
+    if (g.precision == EBS_F64) {  // double LDS rings: smaller default tile
+        c->tile_x = 16;
+        c->tile_y = 4;
+    }
     if (nbox == 0) {
         ebs_box b = {{0, 0, 0}, {c->nx, c->ny, c->nz}};
         c->boxes.push_back(b);
@@ -166,7 +171,7 @@ ebs_status ebs_destroy(ebs_ctx* c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     void* ptrs[] = {c->d_kf,   c->d_kr,        c->d_g0,      c->d_g1,   c->d_goff, c->d_gcol,
                     c->d_geo,  c->d_type,      c->d_mask,    c->d_small, c->d_tier, c->d_w,
-                    c->d_smalllist, c->d_actlist, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles,
+                    c->d_smalllist, c->d_actlist, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles, c->d_prim, c->d_fh, c->d_bf, c->d_col,
                     c->d_part, c->d_dummy};
     for (void* p : ptrs) free_ptr(p);
     delete c;
@@ -394,9 +399,13 @@ ebs_status ebs_conserved_sums(ebs_ctx* c, const ebs_state* U, double hi[5], doub
 
 ebs_status ebs_set_tile(ebs_ctx* c, int32_t tx, int32_t ty) {
     if (!c) return EBS_E_ARG;
-    if (!(tx == 32 || tx == 64 || tx == 128) || !(ty == 1 || ty == 2 || ty == 4 || ty == 8) ||
-        tx * ty < 64 || tx * ty > 512)
+    if (!(tx == 16 || tx == 32 || tx == 64) || !(ty == 2 || ty == 4 || ty == 8 || ty == 16) ||
+        tx * ty < 64 || tx * ty > 256)
         return fail(c, EBS_E_ARG, "unsupported tile shape");
+    if ((tx + 5) * (ty + 5) > 4 * tx * ty)
+        return fail(c, EBS_E_ARG, "tile shape has more halo points than the block covers");
+    if (bulk_lds_bytes(tx, ty, c->g.precision) > 64 * 1024)
+        return fail(c, EBS_E_ARG, "tile shape needs more LDS than a block may use");
     c->tile_x = tx;
     c->tile_y = ty;
     drop_graph(c);
@@ -483,7 +492,7 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
     }
     // timing only: the values (zeros) do not change the work done
     (void)hipStreamSynchronize(c->stream);
-    const int cand[][2] = {{32, 2}, {32, 4}, {32, 8}, {64, 1}, {64, 2}, {64, 4}, {64, 8}, {128, 1}, {128, 2}, {128, 4}};
+    const int cand[][2] = {{16, 4}, {16, 8}, {16, 16}, {32, 4}, {32, 8}, {64, 2}, {64, 4}};
     double best = 1e300;
     int bx = c->tile_x, by = c->tile_y;
     const bool was_timing = c->timing;

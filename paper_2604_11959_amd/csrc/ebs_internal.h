@@ -50,6 +50,7 @@ struct GeoView {
     const int32_t* g0;         // [ncol]
     const int32_t* g1;         // [ncol]
     const int32_t* goff;       // [ncol]
+    const int4* col;           // [ncol] {g0, g1, goff, 0}: one load per lookup
     const int32_t* gcol;       // [G] column of each general cell
     const int32_t* kf;         // [4][ncol] first fluid CV level
     const int32_t* kr;         // [4][ncol] first regular level
@@ -77,11 +78,10 @@ __host__ __device__ inline int wrapi(int i, int n) { return i < 0 ? i + n : (i >
 // general index of cell position (i, j, k) (i, j wrapped), -2 below the general
 // range (every instance covered), -1 above it (every instance regular)
 __device__ inline int gidx(const GeoView& v, int i, int j, int k) {
-    const int c = j * v.nx + i;
-    const int a = v.g0[c];
-    if (k < a) return -2;
-    if (k >= v.g1[c]) return -1;
-    return v.goff[c] + (k - a);
+    const int4 ci = v.col[j * v.nx + i];
+    if (k < ci.x) return -2;
+    if (k >= ci.y) return -1;
+    return ci.z + (k - ci.x);
 }
 
 // is plane k a CV plane of instance inst
@@ -98,7 +98,7 @@ __device__ inline double gq(const GeoView& v, int inst, int q, int g) {
 // ---------------------------------------------------------------- context
 struct ebs_tile {
     int32_t x0, y0, z0;
-    int16_t ex, ey, ez, flags;  // extents; flags bit0: tile has cells below g1
+    int16_t ex, ey, ez, flags;  // extents; flags: offset of the first plane with regular-region work
 };
 
 struct ebs_graph_cache {
@@ -124,6 +124,7 @@ struct ebs_ctx {
     int32_t* d_g1 = nullptr;
     int32_t* d_goff = nullptr;
     int32_t* d_gcol = nullptr;
+    int4* d_col = nullptr;
     int32_t G = 0;
     double* d_geo = nullptr;
     int8_t* d_type = nullptr;
@@ -143,9 +144,12 @@ struct ebs_ctx {
     double* d_uhat = nullptr;  // [5][G] provisional state of the last advance
     double* d_qhat = nullptr;  // [5][G]
     double* d_sig = nullptr;   // [5][3][G]
+    double* d_prim = nullptr;  // [4][G] advected quantities of the general range
+    double* d_fh = nullptr;    // [5][3][G] provisional lower-face fluxes
+    double* d_bf = nullptr;    // [5][3][G] area fraction x flux on the lower faces
 
     // regular-region tiles
-    int tile_x = 64, tile_y = 4, tile_z = 8;
+    int tile_x = 32, tile_y = 8, tile_z = 64;
     std::vector<ebs_tile> h_tiles;
     ebs_tile* d_tiles = nullptr;
     int32_t ntiles = 0;
@@ -171,6 +175,7 @@ ebs_status build_geometry(ebs_ctx* c, const double* d_h);
 ebs_status launch_advance(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uhat,
                           double cdt);
 ebs_status build_tiles(ebs_ctx* c);
+size_t bulk_lds_bytes(int tx, int ty, int precision);
 // redistribution (wsrd.hip)
 ebs_status wsrd_setup(ebs_ctx* c);
 ebs_status launch_redistribute(ebs_ctx* c, const ebs_state* Uhat, ebs_state* Uout);

@@ -542,6 +542,7 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
     };
     bool ok = true;
     ok &= alloc((void**)&cx->d_goff, sizeof(int32_t) * ncol);
+    ok &= alloc((void**)&cx->d_col, sizeof(int4) * ncol);
     ok &= alloc((void**)&cx->d_gcol, sizeof(int32_t) * Gs);
     ok &= alloc((void**)&cx->d_geo, sizeof(double) * NINST * GQ_N * Gs);
     ok &= alloc((void**)&cx->d_type, NINST * Gs);
@@ -554,6 +555,9 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
     ok &= alloc((void**)&cx->d_uhat, sizeof(double) * 5 * Gs);
     ok &= alloc((void**)&cx->d_qhat, sizeof(double) * 5 * Gs);
     ok &= alloc((void**)&cx->d_sig, sizeof(double) * 15 * Gs);
+    ok &= alloc((void**)&cx->d_prim, sizeof(double) * 4 * Gs);
+    ok &= alloc((void**)&cx->d_fh, sizeof(double) * 15 * Gs);
+    ok &= alloc((void**)&cx->d_bf, sizeof(double) * 15 * Gs);
     if (!ok) {
         cx->err = "device allocation of geometry tables failed";
         return EBS_E_OOM;
@@ -561,6 +565,10 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
     EBS_HIP(cx, hipMemcpyAsync(cx->d_goff, cx->h_goff.data(), sizeof(int32_t) * ncol,
                                hipMemcpyHostToDevice, cx->stream));
     EBS_HIP(cx, hipMemcpyAsync(cx->d_gcol, gcol.data(), sizeof(int32_t) * Gs, hipMemcpyHostToDevice,
+                               cx->stream));
+    std::vector<int4> colinfo(ncol);
+    for (int c = 0; c < ncol; ++c) colinfo[c] = make_int4(cx->h_g0[c], cx->h_g1[c], cx->h_goff[c], 0);
+    EBS_HIP(cx, hipMemcpyAsync(cx->d_col, colinfo.data(), sizeof(int4) * ncol, hipMemcpyHostToDevice,
                                cx->stream));
     EBS_HIP(cx, hipMemsetAsync(cx->d_uhat, 0, sizeof(double) * 5 * Gs, cx->stream));
     if (G > 0) {

@@ -57,204 +57,320 @@ __device__ inline C upw(C m, C pLL, C pL, C pR, C pRR, bool okLL, bool okRR) {
     return (C(2) * pL + C(5) * pR - pRR) * sixth;
 }
 
+// field pointer by runtime index without indexing the kernel-argument array
+// (dynamic indexing would place the argument struct in scratch memory)
+template <typename P>
+__device__ inline P pick5(const P (&p)[5], int f) {
+    return f == 0 ? p[0] : f == 1 ? p[1] : f == 2 ? p[2] : f == 3 ? p[3] : p[4];
+}
+
 // write helper covering the periodic repeats and the top wall plane
 template <typename T>
-__device__ inline void put_field(const Dims& D, T* const* out, int f, int i, int j, int k, T v) {
-    out[f][fidx(D, f, i, j, k)] = v;
+__device__ inline void put_field(const Dims& D, T* const (&out)[5], int f, int i, int j, int k, T v) {
+    pick5(out, f)[fidx(D, f, i, j, k)] = v;
     if (f == 2 && i == 0) out[2][iu(D, D.nx, j, k)] = v;
     if (f == 3 && j == 0) out[3][iv(D, i, D.ny, k)] = v;
     if (f == 4 && k == D.nz - 1) out[4][ic(D, i, j, D.nz)] = T(0);
 }
 
 // ------------------------------------------------------------------ bulk
+//
+// 2.5-D z-march.  A block owns an xy tile of TX x TY columns and walks up the
+// tile's z-range.  Every plane of the five fields is read from HBM exactly once
+// per block, over the tile plus a halo (3 cells on the low sides, 2 on the high
+// sides), into LDS rings; the advected quantities (theta, u, v, w) are then
+// computed once per point from LDS.  Rings: rho 2 planes, momenta 4 planes
+// (k-1..k+2), advected quantities 3 planes (k..k+2); the own column's planes
+// k-1 and k-2 of the advected quantities stay in registers.  Only U^n and the
+// outputs go to HBM directly.  Consecutive blocks are spread so that each XCD
+// receives a contiguous run of neighbouring tiles (shared halos stay in its
+// L2).  Stencil points beyond the top wall are flagged and never loaded.
 template <typename T>
 struct BulkArgs {
     Dims D;
-    const T* un[5];
-    const T* cur[5];
+    const T* __restrict__ un[5];
+    const T* __restrict__ cur[5];
     T* out[5];
     T cdt;
     T rdx, rdy, rdz;
-    const int32_t* g0;
-    const int32_t* g1;
-    const ebs_tile* tiles;
+    const int32_t* __restrict__ g0;
+    const int32_t* __restrict__ g1;
+    const ebs_tile* __restrict__ tiles;
     int32_t ntiles;
+    int32_t per_xcd;  // tiles per XCD chunk
 };
 
 template <typename T>
-struct BulkCell {
-    const BulkArgs<T>& a;
-    int i, j, k;
-    __device__ BulkCell(const BulkArgs<T>& a_, int i_, int j_, int k_) : a(a_), i(i_), j(j_), k(k_) {}
-    __device__ int X(int o) const { return wrapi(i + o, a.D.nx); }
-    __device__ int Y(int o) const { return wrapi(j + o, a.D.ny); }
-    __device__ T R(int ii, int jj, int kk) const { return a.cur[0][ic(a.D, ii, jj, kk)]; }
-    __device__ T RU(int ii, int jj, int kk) const { return a.cur[2][iu(a.D, ii, jj, kk)]; }
-    __device__ T RV(int ii, int jj, int kk) const { return a.cur[3][iv(a.D, ii, jj, kk)]; }
-    __device__ T RW(int ii, int jj, int kk) const { return a.cur[4][ic(a.D, ii, jj, kk)]; }
-    __device__ T TH(int ii, int jj, int kk) const {
-        if (kk < 0 || kk >= a.D.nz) return T(0);
-        return a.cur[1][ic(a.D, ii, jj, kk)] / R(ii, jj, kk);
-    }
-    __device__ T UU(int ii, int jj, int kk) const {
-        if (kk < 0 || kk >= a.D.nz) return T(0);
-        return RU(ii, jj, kk) / (T(0.5) * (R(wrapi(ii - 1, a.D.nx), jj, kk) + R(ii, jj, kk)));
-    }
-    __device__ T VV(int ii, int jj, int kk) const {
-        if (kk < 0 || kk >= a.D.nz) return T(0);
-        return RV(ii, jj, kk) / (T(0.5) * (R(ii, wrapi(jj - 1, a.D.ny), kk) + R(ii, jj, kk)));
-    }
-    __device__ T WW(int ii, int jj, int kk) const {
-        if (kk < 1 || kk > a.D.nz - 1) return T(0);
-        return RW(ii, jj, kk) / (T(0.5) * (R(ii, jj, kk - 1) + R(ii, jj, kk)));
-    }
-};
+__device__ inline T qdiv(T a, T b) {
+    return a / b;
+}
+template <>
+__device__ inline float qdiv<float>(float a, float b) {
+    return a * __builtin_amdgcn_rcpf(b);
+}
+
+constexpr int HALO_PTS = 4;  // region points per thread: (TX+5)(TY+5) <= 4 TX TY for TX*TY >= 64
+constexpr int NXCD = 8;
+
+// LDS arrays, each WS entries: rho[2], rhou[4], rhov[4], rhow[4], prim[4 quantities][3]
+enum : int { L_RHO = 0, L_RU = 2, L_RV = 6, L_RW = 10, L_PRIM = 14, L_COUNT = 26 };
 
 template <typename T>
-__device__ void bulk_update(const BulkArgs<T>& a, int i, int j, int k) {
-    const BulkCell<T> c(a, i, j, k);
-    const int nz = a.D.nz;
-    const int xm2 = c.X(-2), xm1 = c.X(-1), xp1 = c.X(1), xp2 = c.X(2);
-    const int ym2 = c.Y(-2), ym1 = c.Y(-1), yp1 = c.Y(1), yp2 = c.Y(2);
-    const bool top = (k + 1 == nz);
-    // ---- cell-centred instance: rho and rho theta
-    {
-        T m, tf;
-        T dr = 0, dt = 0;
-        // x
-        m = c.RU(i, j, k);
-        tf = upw<T>(m, c.TH(xm2, j, k), c.TH(xm1, j, k), c.TH(i, j, k), c.TH(xp1, j, k), true, true);
-        dr -= m * a.rdx; dt -= m * tf * a.rdx;
-        m = c.RU(xp1, j, k);
-        tf = upw<T>(m, c.TH(xm1, j, k), c.TH(i, j, k), c.TH(xp1, j, k), c.TH(xp2, j, k), true, true);
-        dr += m * a.rdx; dt += m * tf * a.rdx;
-        // y
-        m = c.RV(i, j, k);
-        tf = upw<T>(m, c.TH(i, ym2, k), c.TH(i, ym1, k), c.TH(i, j, k), c.TH(i, yp1, k), true, true);
-        dr -= m * a.rdy; dt -= m * tf * a.rdy;
-        m = c.RV(i, yp1, k);
-        tf = upw<T>(m, c.TH(i, ym1, k), c.TH(i, j, k), c.TH(i, yp1, k), c.TH(i, yp2, k), true, true);
-        dr += m * a.rdy; dt += m * tf * a.rdy;
-        // z (the bulk range starts above the bottom margin)
-        m = c.RW(i, j, k);
-        tf = upw<T>(m, c.TH(i, j, k - 2), c.TH(i, j, k - 1), c.TH(i, j, k), c.TH(i, j, k + 1), true,
-                    k + 1 <= nz - 1);
-        dr -= m * a.rdz; dt -= m * tf * a.rdz;
-        if (!top) {
-            m = c.RW(i, j, k + 1);
-            tf = upw<T>(m, c.TH(i, j, k - 1), c.TH(i, j, k), c.TH(i, j, k + 1), c.TH(i, j, k + 2), true,
-                        k + 2 <= nz - 1);
-            dr += m * a.rdz; dt += m * tf * a.rdz;
-        }
-        const size_t id = ic(a.D, i, j, k);
-        put_field<T>(a.D, a.out, 0, i, j, k, a.un[0][id] - a.cdt * dr);
-        put_field<T>(a.D, a.out, 1, i, j, k, a.un[1][id] - a.cdt * dt);
+__device__ inline void prims_direct(const BulkArgs<T>& a, uint32_t c, uint32_t u, int dxm, int dym, int p,
+                                    uint32_t pc, uint32_t pu, uint32_t pv, T* q) {
+    if (p >= a.D.nz) {
+        q[0] = q[1] = q[2] = q[3] = T(0);
+        return;
     }
-    // ---- x-face instance (rho u at face i)
-    {
-        T m, f, du = 0;
-        m = T(0.5) * (c.RU(xm1, j, k) + c.RU(i, j, k));
-        f = upw<T>(m, c.UU(xm2, j, k), c.UU(xm1, j, k), c.UU(i, j, k), c.UU(xp1, j, k), true, true);
-        du -= m * f * a.rdx;
-        m = T(0.5) * (c.RU(i, j, k) + c.RU(xp1, j, k));
-        f = upw<T>(m, c.UU(xm1, j, k), c.UU(i, j, k), c.UU(xp1, j, k), c.UU(xp2, j, k), true, true);
-        du += m * f * a.rdx;
-        m = T(0.5) * (c.RV(xm1, j, k) + c.RV(i, j, k));
-        f = upw<T>(m, c.UU(i, ym2, k), c.UU(i, ym1, k), c.UU(i, j, k), c.UU(i, yp1, k), true, true);
-        du -= m * f * a.rdy;
-        m = T(0.5) * (c.RV(xm1, yp1, k) + c.RV(i, yp1, k));
-        f = upw<T>(m, c.UU(i, ym1, k), c.UU(i, j, k), c.UU(i, yp1, k), c.UU(i, yp2, k), true, true);
-        du += m * f * a.rdy;
-        m = T(0.5) * (c.RW(xm1, j, k) + c.RW(i, j, k));
-        f = upw<T>(m, c.UU(i, j, k - 2), c.UU(i, j, k - 1), c.UU(i, j, k), c.UU(i, j, k + 1), true,
-                   k + 1 <= nz - 1);
-        du -= m * f * a.rdz;
-        if (!top) {
-            m = T(0.5) * (c.RW(xm1, j, k + 1) + c.RW(i, j, k + 1));
-            f = upw<T>(m, c.UU(i, j, k - 1), c.UU(i, j, k), c.UU(i, j, k + 1), c.UU(i, j, k + 2), true,
-                       k + 2 <= nz - 1);
-            du += m * f * a.rdz;
-        }
-        put_field<T>(a.D, a.out, 2, i, j, k, a.un[2][iu(a.D, i, j, k)] - a.cdt * du);
-    }
-    // ---- y-face instance (rho v at face j)
-    {
-        T m, f, dv = 0;
-        m = T(0.5) * (c.RU(i, ym1, k) + c.RU(i, j, k));
-        f = upw<T>(m, c.VV(xm2, j, k), c.VV(xm1, j, k), c.VV(i, j, k), c.VV(xp1, j, k), true, true);
-        dv -= m * f * a.rdx;
-        m = T(0.5) * (c.RU(xp1, ym1, k) + c.RU(xp1, j, k));
-        f = upw<T>(m, c.VV(xm1, j, k), c.VV(i, j, k), c.VV(xp1, j, k), c.VV(xp2, j, k), true, true);
-        dv += m * f * a.rdx;
-        m = T(0.5) * (c.RV(i, ym1, k) + c.RV(i, j, k));
-        f = upw<T>(m, c.VV(i, ym2, k), c.VV(i, ym1, k), c.VV(i, j, k), c.VV(i, yp1, k), true, true);
-        dv -= m * f * a.rdy;
-        m = T(0.5) * (c.RV(i, j, k) + c.RV(i, yp1, k));
-        f = upw<T>(m, c.VV(i, ym1, k), c.VV(i, j, k), c.VV(i, yp1, k), c.VV(i, yp2, k), true, true);
-        dv += m * f * a.rdy;
-        m = T(0.5) * (c.RW(i, ym1, k) + c.RW(i, j, k));
-        f = upw<T>(m, c.VV(i, j, k - 2), c.VV(i, j, k - 1), c.VV(i, j, k), c.VV(i, j, k + 1), true,
-                   k + 1 <= nz - 1);
-        dv -= m * f * a.rdz;
-        if (!top) {
-            m = T(0.5) * (c.RW(i, ym1, k + 1) + c.RW(i, j, k + 1));
-            f = upw<T>(m, c.VV(i, j, k - 1), c.VV(i, j, k), c.VV(i, j, k + 1), c.VV(i, j, k + 2), true,
-                       k + 2 <= nz - 1);
-            dv += m * f * a.rdz;
-        }
-        put_field<T>(a.D, a.out, 3, i, j, k, a.un[3][iv(a.D, i, j, k)] - a.cdt * dv);
-    }
-    // ---- z-face instance (rho w at face k; k >= 1 in the bulk range)
-    {
-        T m, f, dw = 0;
-        m = T(0.5) * (c.RU(i, j, k - 1) + c.RU(i, j, k));
-        f = upw<T>(m, c.WW(xm2, j, k), c.WW(xm1, j, k), c.WW(i, j, k), c.WW(xp1, j, k), true, true);
-        dw -= m * f * a.rdx;
-        m = T(0.5) * (c.RU(xp1, j, k - 1) + c.RU(xp1, j, k));
-        f = upw<T>(m, c.WW(xm1, j, k), c.WW(i, j, k), c.WW(xp1, j, k), c.WW(xp2, j, k), true, true);
-        dw += m * f * a.rdx;
-        m = T(0.5) * (c.RV(i, j, k - 1) + c.RV(i, j, k));
-        f = upw<T>(m, c.WW(i, ym2, k), c.WW(i, ym1, k), c.WW(i, j, k), c.WW(i, yp1, k), true, true);
-        dw -= m * f * a.rdy;
-        m = T(0.5) * (c.RV(i, yp1, k - 1) + c.RV(i, yp1, k));
-        f = upw<T>(m, c.WW(i, ym1, k), c.WW(i, j, k), c.WW(i, yp1, k), c.WW(i, yp2, k), true, true);
-        dw += m * f * a.rdy;
-        if (k != 1) {
-            m = T(0.5) * (c.RW(i, j, k - 1) + c.RW(i, j, k));
-            f = upw<T>(m, c.WW(i, j, k - 2), c.WW(i, j, k - 1), c.WW(i, j, k), c.WW(i, j, k + 1),
-                       k - 2 >= 1, k + 1 <= nz - 1);
-            dw -= m * f * a.rdz;
-        }
-        if (k != nz - 1) {
-            m = T(0.5) * (c.RW(i, j, k) + c.RW(i, j, k + 1));
-            f = upw<T>(m, c.WW(i, j, k - 1), c.WW(i, j, k), c.WW(i, j, k + 1), c.WW(i, j, k + 2),
-                       k - 1 >= 1, k + 2 <= nz - 1);
-            dw += m * f * a.rdz;
-        }
-        put_field<T>(a.D, a.out, 4, i, j, k, a.un[4][ic(a.D, i, j, k)] - a.cdt * dw);
-    }
+    const uint32_t oc = (uint32_t)p * pc + c;
+    const T r = a.cur[0][oc];
+    q[0] = qdiv<T>(a.cur[1][oc], r);
+    q[1] = qdiv<T>(T(2) * a.cur[2][(uint32_t)p * pu + u], a.cur[0][oc + dxm] + r);
+    q[2] = qdiv<T>(T(2) * a.cur[3][(uint32_t)p * pv + c], a.cur[0][oc + dym] + r);
+    q[3] = qdiv<T>(T(2) * a.cur[4][oc], a.cur[0][oc - pc] + r);
+}
+
+// six times the upwind face value (the 1/6 is applied once per CV): branch-free
+// third-order upwind, second-order centred when the stencil end is unavailable
+template <typename T>
+__device__ __forceinline__ T upw6(T m, T pLL, T pL, T pR, T pRR, bool okLL, bool okRR) {
+    const bool up = m >= T(0);
+    const T a = up ? pL : pR, b = up ? pR : pL, e = up ? pLL : pRR;
+    const bool ok = up ? okLL : okRR;
+    return ok ? (T(5) * a + T(2) * b - e) : T(3) * (a + b);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(512) k_bulk(BulkArgs<T> a) {
-    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        const ebs_tile tl = a.tiles[t];
-        const int i = tl.x0 + (int)threadIdx.x;
-        const int j = tl.y0 + (int)threadIdx.y;
-        if ((int)threadIdx.x >= tl.ex || (int)threadIdx.y >= tl.ey) continue;
-        const int c = j * a.D.nx + i;
-        const int gb = a.g0[c], ge = a.g1[c];
-        for (int k = tl.z0; k < tl.z0 + tl.ez; ++k) {
-            if (k >= ge) {
-                bulk_update<T>(a, i, j, k);
-            } else if (k < gb) {
-                for (int f = 0; f < 5; ++f) put_field<T>(a.D, a.out, f, i, j, k, T(0));
+__device__ __forceinline__ T ld(const T* __restrict__ base, uint32_t off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (size_t)off * sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st(T* base, uint32_t off, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (size_t)off * sizeof(T)) = v;
+}
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
+    constexpr int WX = TX + 5, WS = WX * (TY + 5), NTHR = TX * TY;
+    constexpr int NPTS = (WS + NTHR - 1) / NTHR;
+    static_assert(NPTS <= HALO_PTS, "halo points per thread");
+    extern __shared__ unsigned char smem_raw[];
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    const int nx = a.D.nx, ny = a.D.ny, nz = a.D.nz;
+    const uint32_t pc = (uint32_t)nx * ny, pu = (uint32_t)(nx + 1) * ny, pv = (uint32_t)nx * (ny + 1);
+    const int t = (blockIdx.x % NXCD) * a.per_xcd + blockIdx.x / NXCD;
+    if (t >= a.ntiles) return;
+    const ebs_tile tl = a.tiles[t];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = ty * TX + tx;
+    const bool act = tx < tl.ex && ty < tl.ey;
+    const int i = tl.x0 + (act ? tx : 0), j = tl.y0 + (act ? ty : 0);
+    const int z1 = tl.z0 + tl.ez;
+    int ge = nz;
+    if (act) {
+        const int c = j * nx + i;
+        const int gb = a.g0[c];
+        ge = a.g1[c];
+        for (int k = tl.z0; k < min(gb, z1); ++k)
+            for (int f = 0; f < 5; ++f) put_field<T>(a.D, a.out, f, i, j, k, T(0));
+    }
+    const int k0 = tl.z0 + tl.flags;  // first plane with regular-region work (block uniform)
+    if (k0 >= z1) return;
+    uint32_t rc[NPTS], ru[NPTS];
+#pragma unroll
+    for (int q = 0; q < NPTS; ++q) {
+        const int r = tid + q * NTHR;
+        const int x = wrapi(tl.x0 - 3 + r % WX, nx), y = wrapi(tl.y0 - 3 + r / WX, ny);
+        rc[q] = (uint32_t)(y * nx + x);
+        ru[q] = (uint32_t)(y * (nx + 1) + x);
+    }
+    T rth[NPTS];
+    auto load_raw = [&](int p, bool need_rt) {
+        const bool in = p < nz;
+        const int pp = min(p, nz - 1);
+        const uint32_t oc0 = (uint32_t)pp * pc, ou0 = (uint32_t)pp * pu, ov0 = (uint32_t)pp * pv;
+        T* RHO = sm + (L_RHO + (p & 1)) * WS;
+        T* RU = sm + (L_RU + (p & 3)) * WS;
+        T* RV = sm + (L_RV + (p & 3)) * WS;
+        T* RW = sm + (L_RW + (p & 3)) * WS;
+#pragma unroll
+        for (int q = 0; q < NPTS; ++q) {
+            const int r = tid + q * NTHR;
+            if (q == NPTS - 1 && r >= WS) break;
+            T vr = T(0), vu = T(0), vv = T(0), vw = T(0), vt = T(0);
+            if (in) {
+                vr = ld(a.cur[0], oc0 + rc[q]);
+                vu = ld(a.cur[2], ou0 + ru[q]);
+                vv = ld(a.cur[3], ov0 + rc[q]);
+                vw = ld(a.cur[4], oc0 + rc[q]);
+                if (need_rt) vt = ld(a.cur[1], oc0 + rc[q]);
+            }
+            RHO[r] = vr;
+            RU[r] = vu;
+            RV[r] = vv;
+            RW[r] = vw;
+            rth[q] = vt;
+        }
+    };
+    auto make_prims = [&](int p) {
+        const T* RHO = sm + (L_RHO + (p & 1)) * WS;
+        const T* RHOm = sm + (L_RHO + ((p + 1) & 1)) * WS;
+        const T* RU = sm + (L_RU + (p & 3)) * WS;
+        const T* RV = sm + (L_RV + (p & 3)) * WS;
+        const T* RW = sm + (L_RW + (p & 3)) * WS;
+        T* P = sm + (L_PRIM + p % 3) * WS;
+        const bool in = p < nz;
+#pragma unroll
+        for (int q = 0; q < NPTS; ++q) {
+            const int r = tid + q * NTHR;
+            if (q == NPTS - 1 && r >= WS) break;
+            if (r < WX || r % WX == 0) continue;
+            T th = T(0), u = T(0), v = T(0), w = T(0);
+            if (in) {
+                const T rr = RHO[r];
+                th = qdiv<T>(rth[q], rr);
+                u = qdiv<T>(T(2) * RU[r], RHO[r - 1] + rr);
+                v = qdiv<T>(T(2) * RV[r], RHO[r - WX] + rr);
+                w = qdiv<T>(T(2) * RW[r], RHOm[r] + rr);
+            }
+            P[0 * 3 * WS + r] = th;
+            P[1 * 3 * WS + r] = u;
+            P[2 * 3 * WS + r] = v;
+            P[3 * 3 * WS + r] = w;
+        }
+    };
+    const int me = (ty + 3) * WX + (tx + 3);
+    const int dxm = (i == 0) ? nx - 1 : -1;
+    const int dym = (j == 0) ? ny - 1 : -1;
+    const uint32_t c0 = (uint32_t)(j * nx + i), u0 = (uint32_t)(j * (nx + 1) + i);
+    T m2[4], m1[4];
+    prims_direct<T>(a, c0, u0, dxm, dym * nx, k0 - 2, pc, pu, pv, m2);
+    prims_direct<T>(a, c0, u0, dxm, dym * nx, k0 - 1, pc, pu, pv, m1);
+    load_raw(k0 - 1, false);
+    load_raw(k0, true);
+    __syncthreads();
+    make_prims(k0);
+    load_raw(k0 + 1, true);
+    __syncthreads();
+    make_prims(k0 + 1);
+    const T sixth = T(1) / T(6);
+    for (int k = k0; k < z1; ++k) {
+        load_raw(k + 2, true);
+        __syncthreads();
+        make_prims(k + 2);
+        __syncthreads();
+        const int s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
+        const T* P0 = sm + (L_PRIM + s0) * WS + me;  // quantity q at + q * 3 * WS
+        const T* P1 = sm + (L_PRIM + s1) * WS + me;
+        const T* P2 = sm + (L_PRIM + s2) * WS + me;
+        const T* TH = P0;
+        const T* UU = P0 + 3 * WS;
+        const T* VV = P0 + 6 * WS;
+        const T* WW = P0 + 9 * WS;
+        const T* RUk = sm + (L_RU + (k & 3)) * WS + me;
+        const T* RVk = sm + (L_RV + (k & 3)) * WS + me;
+        const T* RUm = sm + (L_RU + ((k + 3) & 3)) * WS + me;  // plane k-1
+        const T* RVm = sm + (L_RV + ((k + 3) & 3)) * WS + me;
+        const T* RWk = sm + (L_RW + (k & 3)) * WS + me;
+        const T* RWp = sm + (L_RW + ((k + 1) & 3)) * WS + me;
+        const T* RWm = sm + (L_RW + ((k + 3) & 3)) * WS + me;
+        if (act && k >= ge) {
+            const bool top = (k + 1 == nz);
+            const bool okR1 = k + 1 <= nz - 1, okR2 = k + 2 <= nz - 1;
+            T zc[4][5];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                zc[q][0] = m2[q];
+                zc[q][1] = m1[q];
+                zc[q][2] = P0[q * 3 * WS];
+                zc[q][3] = P1[q * 3 * WS];
+                zc[q][4] = P2[q * 3 * WS];
+            }
+            const uint32_t oc = (uint32_t)k * pc + c0;
+            const uint32_t ou = (uint32_t)k * pu + u0;
+            const uint32_t ov = (uint32_t)k * pv + c0;
+            const T ru_i = RUk[0], ru_ip = RUk[1], ru_im = RUk[-1];
+            const T rv_j = RVk[0], rv_jp = RVk[WX], rv_jm = RVk[-WX];
+            const T rw_k = RWk[0], rw_kp = top ? T(0) : RWp[0];
+            const T h = T(0.5);
+            // ---- cell-centred instance
+            {
+                const T ex = ru_ip - ru_i, ey = rv_jp - rv_j, ez = rw_kp - rw_k;
+                const T fx = ru_ip * upw6<T>(ru_ip, TH[-1], TH[0], TH[1], TH[2], true, true) -
+                             ru_i * upw6<T>(ru_i, TH[-2], TH[-1], TH[0], TH[1], true, true);
+                const T fy = rv_jp * upw6<T>(rv_jp, TH[-WX], TH[0], TH[WX], TH[2 * WX], true, true) -
+                             rv_j * upw6<T>(rv_j, TH[-2 * WX], TH[-WX], TH[0], TH[WX], true, true);
+                const T fz = rw_kp * upw6<T>(rw_kp, zc[0][1], zc[0][2], zc[0][3], zc[0][4], true, okR2) -
+                             rw_k * upw6<T>(rw_k, zc[0][0], zc[0][1], zc[0][2], zc[0][3], true, okR1);
+                const T dr = ex * a.rdx + ey * a.rdy + ez * a.rdz;
+                const T dt = (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
+                st(a.out[0], oc, ld(a.un[0], oc) - a.cdt * dr);
+                st(a.out[1], oc, ld(a.un[1], oc) - a.cdt * dt);
+            }
+            // ---- x-face instance
+            {
+                const T mxl = h * (ru_im + ru_i), mxh = h * (ru_i + ru_ip);
+                const T myl = h * (RVk[-1] + rv_j), myh = h * (RVk[WX - 1] + rv_jp);
+                const T mzl = h * (RWk[-1] + rw_k), mzh = top ? T(0) : h * (RWp[-1] + rw_kp);
+                const T fx = mxh * upw6<T>(mxh, UU[-1], UU[0], UU[1], UU[2], true, true) -
+                             mxl * upw6<T>(mxl, UU[-2], UU[-1], UU[0], UU[1], true, true);
+                const T fy = myh * upw6<T>(myh, UU[-WX], UU[0], UU[WX], UU[2 * WX], true, true) -
+                             myl * upw6<T>(myl, UU[-2 * WX], UU[-WX], UU[0], UU[WX], true, true);
+                const T fz = mzh * upw6<T>(mzh, zc[1][1], zc[1][2], zc[1][3], zc[1][4], true, okR2) -
+                             mzl * upw6<T>(mzl, zc[1][0], zc[1][1], zc[1][2], zc[1][3], true, okR1);
+                const T val = ld(a.un[2], ou) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
+                st(a.out[2], ou, val);
+                if (i == 0) st(a.out[2], ou + nx, val);
+            }
+            // ---- y-face instance
+            {
+                const T mxl = h * (RUk[-WX] + ru_i), mxh = h * (RUk[1 - WX] + ru_ip);
+                const T myl = h * (rv_jm + rv_j), myh = h * (rv_j + rv_jp);
+                const T mzl = h * (RWk[-WX] + rw_k), mzh = top ? T(0) : h * (RWp[-WX] + rw_kp);
+                const T fx = mxh * upw6<T>(mxh, VV[-1], VV[0], VV[1], VV[2], true, true) -
+                             mxl * upw6<T>(mxl, VV[-2], VV[-1], VV[0], VV[1], true, true);
+                const T fy = myh * upw6<T>(myh, VV[-WX], VV[0], VV[WX], VV[2 * WX], true, true) -
+                             myl * upw6<T>(myl, VV[-2 * WX], VV[-WX], VV[0], VV[WX], true, true);
+                const T fz = mzh * upw6<T>(mzh, zc[2][1], zc[2][2], zc[2][3], zc[2][4], true, okR2) -
+                             mzl * upw6<T>(mzl, zc[2][0], zc[2][1], zc[2][2], zc[2][3], true, okR1);
+                const T val = ld(a.un[3], ov) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
+                st(a.out[3], ov, val);
+                if (j == 0) st(a.out[3], ov + (uint32_t)ny * nx, val);
+            }
+            // ---- z-face instance (k >= 1 in the regular range); zero flux
+            // through the mid planes of the bottom and top cell layers
+            {
+                const T mxl = h * (RUm[0] + ru_i), mxh = h * (RUm[1] + ru_ip);
+                const T myl = h * (RVm[0] + rv_j), myh = h * (RVm[WX] + rv_jp);
+                const T mzl = (k != 1) ? h * (RWm[0] + rw_k) : T(0);
+                const T mzh = (k != nz - 1) ? h * (rw_k + rw_kp) : T(0);
+                const T fx = mxh * upw6<T>(mxh, WW[-1], WW[0], WW[1], WW[2], true, true) -
+                             mxl * upw6<T>(mxl, WW[-2], WW[-1], WW[0], WW[1], true, true);
+                const T fy = myh * upw6<T>(myh, WW[-WX], WW[0], WW[WX], WW[2 * WX], true, true) -
+                             myl * upw6<T>(myl, WW[-2 * WX], WW[-WX], WW[0], WW[WX], true, true);
+                const T fz = mzh * upw6<T>(mzh, zc[3][1], zc[3][2], zc[3][3], zc[3][4], k - 1 >= 1, okR2) -
+                             mzl * upw6<T>(mzl, zc[3][0], zc[3][1], zc[3][2], zc[3][3], k - 2 >= 1, okR1);
+                st(a.out[4], oc, ld(a.un[4], oc) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth);
+                if (k == nz - 1) st(a.out[4], oc + pc, T(0));
             }
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            m2[q] = m1[q];
+            m1[q] = P0[q * 3 * WS];
+        }
+        __syncthreads();
     }
 }
 
 // --------------------------------------------------------------- general
+//
+// The general range is processed in four passes over its cells (double
+// precision throughout): advected quantities per cell, provisional fluxes per
+// lower face, cut-face interpolation (stored as area fraction x flux), and the
+// divergence / update.  Each quantity is computed once; faces of CVs outside
+// the range (always full faces of regular CVs, or covered) are evaluated on the
+// fly with the same formulas.
 template <typename T>
 struct GenArgs {
     Dims D;
@@ -263,30 +379,35 @@ struct GenArgs {
     const T* cur[5];
     T* out[5];
     double* uhat;  // [5][G]
+    double* prim;  // [4][G] theta, u, v, w
+    double* fh;    // [5][3][G] provisional flux on the lower faces
+    double* bf;    // [5][3][G] area fraction x flux on the lower faces
     double cdt;
-    double del[3];
+    double rdel[3];
     int eb_mode;
+    __device__ double rd(int d) const { return d == 0 ? rdel[0] : d == 1 ? rdel[1] : rdel[2]; }
 };
 
 template <typename T>
 struct Gen {
     const GenArgs<T>& a;
-    __device__ explicit Gen(const GenArgs<T>& a_) : a(a_) {}
+    __device__ __forceinline__ explicit Gen(const GenArgs<T>& a_) : a(a_) {}
 
-    // 0: not fluid, 1: fluid; alpha in *al
-    __device__ bool fluid(int inst, int i, int j, int k, double* al = nullptr) const {
+    // fluid test of a CV; on success *g holds its general index (-1 outside)
+    __device__ __forceinline__ bool fluid(int inst, int i, int j, int k, int* gout = nullptr, double* al = nullptr) const {
         if (!cv_plane(a.v, inst, k)) return false;
         i = wrapi(i, a.D.nx);
         j = wrapi(j, a.D.ny);
         const int g = gidx(a.v, i, j, k);
         if (g == -2) return false;
+        if (gout) *gout = g;
         if (g == -1) { if (al) *al = 1.0; return true; }
         if (a.v.type[(size_t)inst * a.v.G + g] == 0) return false;
         if (al) *al = gq(a.v, inst, GQ_ALPHA, g);
         return true;
     }
     // lower-face fraction of CV (i,j,k) in direction d; plane nz is the top face
-    __device__ double beta(int inst, int d, int i, int j, int k) const {
+    __device__ __forceinline__ double beta(int inst, int d, int i, int j, int k) const {
         if (k == a.D.nz) return d == 2 ? 1.0 : 0.0;
         if (!cv_plane(a.v, inst, k)) return 0.0;
         i = wrapi(i, a.D.nx);
@@ -296,27 +417,19 @@ struct Gen {
         if (g == -1) return 1.0;
         return gq(a.v, inst, GQ_BX + d, g);
     }
-    __device__ void gam(int inst, int d, int i, int j, int k, double& g1, double& g2) const {
-        g1 = g2 = 0.0;
-        if (k >= a.D.nz || !cv_plane(a.v, inst, k)) return;
-        i = wrapi(i, a.D.nx);
-        j = wrapi(j, a.D.ny);
-        const int g = gidx(a.v, i, j, k);
-        if (g < 0) return;
+    __device__ __forceinline__ void gam(int inst, int d, int g, double& g1, double& g2) const {
         g1 = gq(a.v, inst, GQ_FX1 + 2 * d, g);
         g2 = gq(a.v, inst, GQ_FX1 + 2 * d + 1, g);
     }
     // state value, zero where the CV is not fluid
-    __device__ double sv(const T* const* U, int f, int i, int j, int k) const {
+    __device__ __forceinline__ double sv(const T* const (&U)[5], int f, int i, int j, int k) const {
         const int inst = f < 2 ? 0 : f - 1;
         if (!fluid(inst, i, j, k)) return 0.0;
-        return (double)U[f][fidx(a.D, f, wrapi(i, a.D.nx), wrapi(j, a.D.ny), k)];
+        return (double)pick5(U, f)[fidx(a.D, f, wrapi(i, a.D.nx), wrapi(j, a.D.ny), k)];
     }
-    // advected quantity of field f (1: theta, 2..4: velocity) at a CV of its instance
-    __device__ double phi(int f, int i, int j, int k) const {
-        const int inst = f < 2 ? 0 : f - 1;
-        if (!fluid(inst, i, j, k)) return 0.0;
-        const int ii = wrapi(i, a.D.nx), jj = wrapi(j, a.D.ny);
+    // advected quantity of field f (1: theta, 2..4: velocity) at a fluid CV
+    // (i, j wrapped), computed from the state
+    __device__ __forceinline__ double phi_direct(int f, int ii, int jj, int k) const {
         if (f == 1) return (double)a.cur[1][ic(a.D, ii, jj, k)] / (double)a.cur[0][ic(a.D, ii, jj, k)];
         int i0 = ii, j0 = jj, k0 = k;
         if (f == 2) i0 = wrapi(ii - 1, a.D.nx);
@@ -327,9 +440,16 @@ struct Gen {
         if (fluid(0, i0, j0, k0)) { s += (double)a.cur[0][ic(a.D, i0, j0, k0)]; ++cnt; }
         if (fluid(0, ii, jj, k)) { s += (double)a.cur[0][ic(a.D, ii, jj, k)]; ++cnt; }
         if (cnt == 0) return 0.0;
-        return (double)a.cur[f][fidx(a.D, f, ii, jj, k)] / (s / cnt);
+        return (double)pick5(a.cur, f)[fidx(a.D, f, ii, jj, k)] / (s / cnt);
     }
-    __device__ double mass(int inst, int d, int i, int j, int k) const {
+    __device__ __forceinline__ double phi(int f, int i, int j, int k) const {
+        const int inst = f < 2 ? 0 : f - 1;
+        int g;
+        if (!fluid(inst, i, j, k, &g)) return 0.0;
+        if (g >= 0) return a.prim[(size_t)(f - 1) * a.v.G + g];
+        return phi_direct(f, wrapi(i, a.D.nx), wrapi(j, a.D.ny), k);
+    }
+    __device__ __forceinline__ double mass(int inst, int d, int i, int j, int k) const {
         const int mf = 2 + d;
         if (inst == 0) return sv(a.cur, mf, i, j, k);
         int i0 = i, j0 = j, k0 = k;
@@ -339,7 +459,7 @@ struct Gen {
         return 0.5 * (sv(a.cur, mf, i0, j0, k0) + sv(a.cur, mf, i, j, k));
     }
     // provisional flux on the lower d-face of CV (i,j,k)
-    __device__ double fhat(int f, int d, int i, int j, int k) const {
+    __device__ __forceinline__ double fhat(int f, int d, int i, int j, int k) const {
         const int inst = f < 2 ? 0 : f - 1;
         if (d == 2) {
             if (inst != 3 && (k == 0 || k == a.D.nz)) return 0.0;
@@ -356,75 +476,137 @@ struct Gen {
         const bool okRR = fluid(inst, i + o0, j + o1, k + o2);
         return m * upw<double>(m, pLL, pL, pR, pRR, okLL, okRR);
     }
-    // flux used in the divergence on the lower d-face, moved to the cut-face centroid
-    __device__ double face(int f, int d, int i, int j, int k) const {
+    // provisional flux from the pass-2 buffer when the CV is in the range
+    __device__ __forceinline__ double fhat_any(int f, int d, int i, int j, int k) const {
+        if (k >= 0 && k < a.D.nz) {
+            const int g = gidx(a.v, wrapi(i, a.D.nx), wrapi(j, a.D.ny), k);
+            if (g >= 0) return a.fh[((size_t)f * 3 + d) * a.v.G + g];
+        }
+        return fhat(f, d, i, j, k);
+    }
+    // flux on the lower d-face moved to the cut-face centroid (g >= 0: own cell)
+    __device__ __forceinline__ double face(int f, int d, int i, int j, int k, int g, double b) const {
         const int inst = f < 2 ? 0 : f - 1;
-        const double b = beta(inst, d, i, j, k);
-        if (!(b > 0.0)) return 0.0;
-        const double F0 = fhat(f, d, i, j, k);
+        const double F0 = a.fh[((size_t)f * 3 + d) * a.v.G + g];
         if (!(b < 1.0)) return F0;
         double g1, g2;
-        gam(inst, d, i, j, k, g1, g2);
+        gam(inst, d, g, g1, g2);
         const int s1 = g1 > 0.0 ? 1 : (g1 < 0.0 ? -1 : 0);
         const int s2 = g2 > 0.0 ? 1 : (g2 < 0.0 ? -1 : 0);
         if (s1 == 0 && s2 == 0) return F0;
-        int e1[3] = {0, 0, 0}, e2[3] = {0, 0, 0};
-        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-        e1[t1] = s1;
-        e2[t2] = s2;
-        const int nb[3][3] = {{i + e1[0], j + e1[1], k + e1[2]},
-                              {i + e2[0], j + e2[1], k + e2[2]},
-                              {i + e1[0] + e2[0], j + e1[1] + e2[1], k + e1[2] + e2[2]}};
-        const bool use[3] = {s1 != 0, s2 != 0, s1 != 0 && s2 != 0};
-        for (int q = 0; q < 3; ++q) {
-            if (!use[q]) continue;
-            if (nb[q][2] != k && !cv_plane(a.v, inst, nb[q][2])) return F0;
-            if (!(beta(inst, d, nb[q][0], nb[q][1], nb[q][2]) > 0.0)) return F0;
+        // tangential steps: first tangential axis is y for x-faces, x otherwise;
+        // second is y for z-faces, z otherwise
+        const int ax = d == 0 ? 0 : s1, ay = d == 0 ? s1 : 0;
+        const int by = d == 2 ? s2 : 0, bz = d == 2 ? 0 : s2;
+        const bool u1 = s1 != 0, u2 = s2 != 0, u12 = u1 && u2;
+        // all-or-nothing: every weighted neighbour face must carry fluid and lie inside
+        if (u1 && !(beta(inst, d, i + ax, j + ay, k) > 0.0)) return F0;
+        if (u2) {
+            if (bz != 0 && !cv_plane(a.v, inst, k + bz)) return F0;
+            if (!(beta(inst, d, i, j + by, k + bz) > 0.0)) return F0;
         }
+        if (u12 && !(beta(inst, d, i + ax, j + ay + by, k + bz) > 0.0)) return F0;
         const double w1 = fabs(g1), w2 = fabs(g2);
         double F = (1.0 - w1) * (1.0 - w2) * F0;
-        if (use[0]) F += w1 * (1.0 - w2) * fhat(f, d, nb[0][0], nb[0][1], nb[0][2]);
-        if (use[1]) F += (1.0 - w1) * w2 * fhat(f, d, nb[1][0], nb[1][1], nb[1][2]);
-        if (use[2]) F += w1 * w2 * fhat(f, d, nb[2][0], nb[2][1], nb[2][2]);
+        if (u1) F += w1 * (1.0 - w2) * fhat_any(f, d, i + ax, j + ay, k);
+        if (u2) F += (1.0 - w1) * w2 * fhat_any(f, d, i, j + by, k + bz);
+        if (u12) F += w1 * w2 * fhat_any(f, d, i + ax, j + ay + by, k + bz);
         return F;
     }
-    // provisional value of field f at CV (i,j,k) (fluid, alpha al)
-    __device__ double update(int f, int i, int j, int k, double al, int g) const {
-        const int inst = f < 2 ? 0 : f - 1;
-        double br = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            const int ip = i + (d == 0), jp = j + (d == 1), kp = k + (d == 2);
-            const double blo = beta(inst, d, i, j, k);
-            const double bhi = beta(inst, d, ip, jp, kp);
-            const double Flo = face(f, d, i, j, k);
-            const double Fhi = face(f, d, ip, jp, kp);
-            br += (bhi * Fhi - blo * Flo) / a.del[d];
-            if (a.eb_mode == 1 && g >= 0) {
-                double s = 0.0;
-                int cnt = 0;
-                if (blo > 0.0) { s += fhat(f, d, i, j, k); ++cnt; }
-                if (bhi > 0.0) { s += fhat(f, d, ip, jp, kp); ++cnt; }
-                const double fb = cnt ? s / cnt : 0.0;
-                br -= gq(a.v, inst, GQ_AX + d, g) * fb / a.del[d];
-            }
+    // area fraction x flux on the lower d-face of any CV
+    __device__ __forceinline__ double bflux(int f, int d, int i, int j, int k) const {
+        if (k >= 0 && k < a.D.nz) {
+            const int g = gidx(a.v, wrapi(i, a.D.nx), wrapi(j, a.D.ny), k);
+            if (g >= 0) return a.bf[((size_t)f * 3 + d) * a.v.G + g];
         }
-        return sv(a.un, f, i, j, k) - a.cdt * br / al;
+        const int inst = f < 2 ? 0 : f - 1;
+        const double b = beta(inst, d, i, j, k);  // 1 or 0 outside the range
+        return b > 0.0 ? b * fhat(f, d, i, j, k) : 0.0;
     }
 };
 
+__device__ inline void gen_cell(const GeoView& v, int g, int& i, int& j, int& k) {
+    const int c = v.gcol[g];
+    const int4 ci = v.col[c];
+    i = c % v.nx;
+    j = c / v.nx;
+    k = ci.x + (g - ci.z);
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_general(GenArgs<T> a) {
+__global__ void __launch_bounds__(256) k_gen_prims(GenArgs<T> a) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.v.G) return;
     const Gen<T> G(a);
-    const int c = a.v.gcol[g];
-    const int i = c % a.D.nx, j = c / a.D.nx;
-    const int k = a.v.g0[c] + (g - a.v.goff[c]);
+    int i, j, k;
+    gen_cell(a.v, g, i, j, k);
+    for (int f = 1; f < 5; ++f) {
+        const int inst = f < 2 ? 0 : f - 1;
+        const double p = G.fluid(inst, i, j, k) ? G.phi_direct(f, i, j, k) : 0.0;
+        a.prim[(size_t)(f - 1) * a.v.G + g] = p;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gen_fhat(GenArgs<T> a) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.v.G) return;
+    const Gen<T> G(a);
+    int i, j, k;
+    gen_cell(a.v, g, i, j, k);
+    for (int f = 0; f < 5; ++f) {
+        const int inst = f < 2 ? 0 : f - 1;
+        for (int d = 0; d < 3; ++d) {
+            const double b = G.beta(inst, d, i, j, k);
+            a.fh[((size_t)f * 3 + d) * a.v.G + g] = b > 0.0 ? G.fhat(f, d, i, j, k) : 0.0;
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gen_face(GenArgs<T> a) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.v.G) return;
+    const Gen<T> G(a);
+    int i, j, k;
+    gen_cell(a.v, g, i, j, k);
+    for (int f = 0; f < 5; ++f) {
+        const int inst = f < 2 ? 0 : f - 1;
+        for (int d = 0; d < 3; ++d) {
+            const double b = G.beta(inst, d, i, j, k);
+            a.bf[((size_t)f * 3 + d) * a.v.G + g] = b > 0.0 ? b * G.face(f, d, i, j, k, g, b) : 0.0;
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gen_update(GenArgs<T> a) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.v.G) return;
+    const Gen<T> G(a);
+    int i, j, k;
+    gen_cell(a.v, g, i, j, k);
     for (int f = 0; f < 5; ++f) {
         const int inst = f < 2 ? 0 : f - 1;
         double al = 0.0;
         double val = 0.0;
-        if (G.fluid(inst, i, j, k, &al)) val = G.update(f, i, j, k, al, g);
+        if (G.fluid(inst, i, j, k, nullptr, &al)) {
+            double br = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                const int ip = i + (d == 0), jp = j + (d == 1), kp = k + (d == 2);
+                br += (G.bflux(f, d, ip, jp, kp) - a.bf[((size_t)f * 3 + d) * a.v.G + g]) * a.rd(d);
+                if (a.eb_mode == 1) {
+                    const double blo = G.beta(inst, d, i, j, k), bhi = G.beta(inst, d, ip, jp, kp);
+                    double s = 0.0;
+                    int cnt = 0;
+                    if (blo > 0.0) { s += a.fh[((size_t)f * 3 + d) * a.v.G + g]; ++cnt; }
+                    if (bhi > 0.0) { s += G.fhat_any(f, d, ip, jp, kp); ++cnt; }
+                    const double fb = cnt ? s / cnt : 0.0;
+                    br -= gq(a.v, inst, GQ_AX + d, g) * fb * a.rd(d);
+                }
+            }
+            val = G.sv(a.un, f, i, j, k) - a.cdt * br / al;
+        }
         a.uhat[(size_t)f * a.v.G + g] = val;
         put_field<T>(a.D, a.out, f, i, j, k, (T)val);
     }
@@ -433,6 +615,10 @@ __global__ void __launch_bounds__(256) k_general(GenArgs<T> a) {
 }  // namespace
 
 // ------------------------------------------------------------- host side
+size_t bulk_lds_bytes(int tx, int ty, int precision) {
+    return (precision == EBS_F32_BULK ? 4 : 8) * (size_t)L_COUNT * (tx + 5) * (ty + 5);
+}
+
 ebs_status build_tiles(ebs_ctx* cx) {
     cx->h_tiles.clear();
     const int TX = cx->tile_x, TY = cx->tile_y, TZ = cx->tile_z;
@@ -445,7 +631,12 @@ ebs_status build_tiles(ebs_ctx* cx) {
                     t.ex = (int16_t)std::min(TX, b.hi[0] - x);
                     t.ey = (int16_t)std::min(TY, b.hi[1] - y);
                     t.ez = (int16_t)std::min(TZ, b.hi[2] - z);
-                    t.flags = 0;
+                    // first plane at or above the general range of every column
+                    int kmin = cx->nz;
+                    for (int yy = y; yy < y + t.ey; ++yy)
+                        for (int xx = x; xx < x + t.ex; ++xx)
+                            kmin = std::min(kmin, cx->h_g1.empty() ? 0 : cx->h_g1[yy * cx->nx + xx]);
+                    t.flags = (int16_t)std::min<int>(std::max(kmin - z, 0), t.ez);
                     cx->h_tiles.push_back(t);
                 }
     }
@@ -505,9 +696,20 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
             e1 = cx->ev_pool[cx->ev_used++];
             EBS_HIP(cx, hipEventRecord(e0, cx->stream));
         }
-        const int blocks = std::min(cx->ntiles, 256 * 16);
-        if (blocks > 0) {
-            hipLaunchKernelGGL(k_bulk<T>, dim3(blocks), dim3(cx->tile_x, cx->tile_y), 0, cx->stream, a);
+        const size_t lds = bulk_lds_bytes(cx->tile_x, cx->tile_y, cx->g.precision);
+        a.per_xcd = (cx->ntiles + NXCD - 1) / NXCD;
+        if (cx->ntiles > 0) {
+            const dim3 grid(a.per_xcd * NXCD), blk(cx->tile_x, cx->tile_y);
+#define EBS_BULK_CASE(X, Y)                                                                   \
+    if (cx->tile_x == X && cx->tile_y == Y) {                                                 \
+        hipLaunchKernelGGL((k_bulk<T, X, Y>), grid, blk, lds, cx->stream, a);                 \
+    } else
+            EBS_BULK_CASE(16, 4) EBS_BULK_CASE(16, 8) EBS_BULK_CASE(16, 16) EBS_BULK_CASE(32, 4)
+            EBS_BULK_CASE(32, 8) EBS_BULK_CASE(64, 2) EBS_BULK_CASE(64, 4) {
+                cx->err = "tile shape without a compiled kernel";
+                return EBS_E_UNSUPPORTED;
+            }
+#undef EBS_BULK_CASE
             EBS_HIP(cx, hipGetLastError());
         }
         if (cx->timing) EBS_HIP(cx, hipEventRecord(e1, cx->stream));
@@ -522,10 +724,19 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
             a.out[f] = (T*)ou[f];
         }
         a.uhat = cx->d_uhat;
+        a.prim = cx->d_prim;
+        a.fh = cx->d_fh;
+        a.bf = cx->d_bf;
         a.cdt = cdt;
-        for (int d = 0; d < 3; ++d) a.del[d] = cx->g.dx[d];
+        for (int d = 0; d < 3; ++d) a.rdel[d] = 1.0 / cx->g.dx[d];
         a.eb_mode = cx->g.eb_flux;
-        hipLaunchKernelGGL(k_general<T>, dim3((cx->G + 255) / 256), dim3(256), 0, cx->stream, a);
+        const dim3 grid((cx->G + 255) / 256), blk(256);
+        // the first three passes only read the input state; the update writes
+        // the output (which may alias U^n, never U_cur)
+        hipLaunchKernelGGL(k_gen_prims<T>, grid, blk, 0, cx->stream, a);
+        hipLaunchKernelGGL(k_gen_fhat<T>, grid, blk, 0, cx->stream, a);
+        hipLaunchKernelGGL(k_gen_face<T>, grid, blk, 0, cx->stream, a);
+        hipLaunchKernelGGL(k_gen_update<T>, grid, blk, 0, cx->stream, a);
         EBS_HIP(cx, hipGetLastError());
     }
     return EBS_OK;

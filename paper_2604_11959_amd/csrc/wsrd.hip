@@ -72,9 +72,10 @@ __device__ inline double alpha_of(const GeoView& v, int inst, int g) {
 
 __device__ inline void cell_of(const GeoView& v, int g, int& i, int& j, int& k) {
     const int c = v.gcol[g];
+    const int4 ci = v.col[c];
     i = c % v.nx;
     j = c / v.nx;
-    k = v.g0[c] + (g - v.goff[c]);
+    k = ci.x + (g - ci.z);
 }
 
 __global__ void k_merge(WArgs a) {
@@ -484,7 +485,8 @@ __global__ void k_final(FArgs<T> F) {
         if (f == 2) idx = ((size_t)k * ny + j) * (nx + 1) + i;
         else if (f == 3) idx = ((size_t)k * (ny + 1) + j) * nx + i;
         else idx = ((size_t)k * ny + j) * nx + i;
-        F.out[f][idx] = (T)val;
+        T* o = f == 0 ? F.out[0] : f == 1 ? F.out[1] : f == 2 ? F.out[2] : f == 3 ? F.out[3] : F.out[4];
+        o[idx] = (T)val;
         if (f == 2 && i == 0) F.out[2][((size_t)k * ny + j) * (nx + 1) + nx] = (T)val;
         if (f == 3 && j == 0) F.out[3][((size_t)k * (ny + 1) + ny) * nx + i] = (T)val;
     }

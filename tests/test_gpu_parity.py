@@ -278,14 +278,18 @@ def test_free_stream_mode_c2():
         assert np.abs(h[f] - ref)[m[f]].max() <= 1e-12 * scale, f
 
 
-def test_box_list_and_tiles_do_not_change_results():
+@pytest.mark.parametrize("precision,tiles", [
+    (ebs.EBS_F64, ((16, 4), (16, 8))),
+    (ebs.EBS_F32_BULK, ((16, 4), (16, 16), (32, 8), (64, 2))),
+])
+def test_box_list_and_tiles_do_not_change_results(precision, tiles):
     """Uneven AMR-style boxes and different tile shapes give identical bits."""
     w = synth.make_workload(2)
     U0 = synth.make_state(w)
     boxes = synth.boxes_split(w.grid.n, 7, 40, block=32, unit=16)
     res = []
-    for bx, tile in ((None, (64, 4)), (boxes, (64, 4)), (boxes, (32, 8)), (boxes, (128, 1))):
-        c = _ctx(w, boxes=bx)
+    for bx, tile in [(None, tiles[0])] + [(boxes, t) for t in tiles]:
+        c = _ctx(w, precision=precision, boxes=bx)
         c.set_tile(*tile)
         U = c.new_state(U0)
         S = [c.new_state(), c.new_state()]
