@@ -184,11 +184,31 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
         rc[q] = (uint32_t)(y * nx + x);
         ru[q] = (uint32_t)(y * (nx + 1) + x);
     }
-    T rth[NPTS];
-    auto load_raw = [&](int p, bool need_rt) {
-        const bool in = p < nz;
-        const int pp = min(p, nz - 1);
-        const uint32_t oc0 = (uint32_t)pp * pc, ou0 = (uint32_t)pp * pu, ov0 = (uint32_t)pp * pv;
+    // Raw values of the next plane to enter the rings are loaded into registers
+    // one z-iteration ahead (fetch) and written to LDS at the top of the next
+    // iteration (commit), so the global-load latency overlaps a whole plane of
+    // arithmetic.  rth keeps rho*theta of the committed plane for make_prims.
+    T pf[NPTS][5], rth[NPTS];
+    auto fetch = [&](int p) {
+        const bool in = p < nz;  // block uniform
+        const uint32_t oc0 = (uint32_t)p * pc, ou0 = (uint32_t)p * pu;
+#pragma unroll
+        for (int q = 0; q < NPTS; ++q) {
+            const int r = tid + q * NTHR;
+            if (q == NPTS - 1 && r >= WS) break;
+            if (in) {
+                pf[q][0] = ld(a.cur[0], oc0 + rc[q]);
+                pf[q][1] = ld(a.cur[1], oc0 + rc[q]);
+                pf[q][2] = ld(a.cur[2], ou0 + ru[q]);
+                pf[q][3] = ld(a.cur[3], (uint32_t)p * pv + rc[q]);
+                pf[q][4] = ld(a.cur[4], oc0 + rc[q]);
+            } else {
+#pragma unroll
+                for (int f = 0; f < 5; ++f) pf[q][f] = T(0);
+            }
+        }
+    };
+    auto commit = [&](int p) {
         T* RHO = sm + (L_RHO + (p & 1)) * WS;
         T* RU = sm + (L_RU + (p & 3)) * WS;
         T* RV = sm + (L_RV + (p & 3)) * WS;
@@ -197,19 +217,11 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
         for (int q = 0; q < NPTS; ++q) {
             const int r = tid + q * NTHR;
             if (q == NPTS - 1 && r >= WS) break;
-            T vr = T(0), vu = T(0), vv = T(0), vw = T(0), vt = T(0);
-            if (in) {
-                vr = ld(a.cur[0], oc0 + rc[q]);
-                vu = ld(a.cur[2], ou0 + ru[q]);
-                vv = ld(a.cur[3], ov0 + rc[q]);
-                vw = ld(a.cur[4], oc0 + rc[q]);
-                if (need_rt) vt = ld(a.cur[1], oc0 + rc[q]);
-            }
-            RHO[r] = vr;
-            RU[r] = vu;
-            RV[r] = vv;
-            RW[r] = vw;
-            rth[q] = vt;
+            RHO[r] = pf[q][0];
+            rth[q] = pf[q][1];
+            RU[r] = pf[q][2];
+            RV[r] = pf[q][3];
+            RW[r] = pf[q][4];
         }
     };
     auto make_prims = [&](int p) {
@@ -246,16 +258,41 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
     T m2[4], m1[4];
     prims_direct<T>(a, c0, u0, dxm, dym * nx, k0 - 2, pc, pu, pv, m2);
     prims_direct<T>(a, c0, u0, dxm, dym * nx, k0 - 1, pc, pu, pv, m1);
-    load_raw(k0 - 1, false);
-    load_raw(k0, true);
+    fetch(k0 - 1);
+    commit(k0 - 1);
+    fetch(k0);
+    commit(k0);
+    fetch(k0 + 1);
     __syncthreads();
     make_prims(k0);
-    load_raw(k0 + 1, true);
+    __syncthreads();  // the density slot of plane k0 - 1 is reused by plane k0 + 1
+    commit(k0 + 1);
+    fetch(k0 + 2);
     __syncthreads();
     make_prims(k0 + 1);
+    __syncthreads();  // the density slot of plane k0 is reused by plane k0 + 2
+    // own-cell values of Un for the next plane (prefetched like the rings)
+    const uint32_t ov0 = (uint32_t)(j * nx + i);
+    T unc[5];
+    auto fetch_un = [&](int kk, T (&dst)[5]) {
+        if (act && kk < z1 && kk >= ge) {
+            dst[0] = ld(a.un[0], (uint32_t)kk * pc + c0);
+            dst[1] = ld(a.un[1], (uint32_t)kk * pc + c0);
+            dst[2] = ld(a.un[2], (uint32_t)kk * pu + u0);
+            dst[3] = ld(a.un[3], (uint32_t)kk * pv + ov0);
+            dst[4] = ld(a.un[4], (uint32_t)kk * pc + c0);
+        } else {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) dst[f] = T(0);
+        }
+    };
+    fetch_un(k0, unc);
     const T sixth = T(1) / T(6);
     for (int k = k0; k < z1; ++k) {
-        load_raw(k + 2, true);
+        commit(k + 2);
+        fetch(k + 3);
+        T unn[5];
+        fetch_un(k + 1, unn);
         __syncthreads();
         make_prims(k + 2);
         __syncthreads();
@@ -304,8 +341,8 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                              rw_k * upw6<T>(rw_k, zc[0][0], zc[0][1], zc[0][2], zc[0][3], true, okR1);
                 const T dr = ex * a.rdx + ey * a.rdy + ez * a.rdz;
                 const T dt = (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
-                st(a.out[0], oc, ld(a.un[0], oc) - a.cdt * dr);
-                st(a.out[1], oc, ld(a.un[1], oc) - a.cdt * dt);
+                st(a.out[0], oc, unc[0] - a.cdt * dr);
+                st(a.out[1], oc, unc[1] - a.cdt * dt);
             }
             // ---- x-face instance
             {
@@ -318,7 +355,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                              myl * upw6<T>(myl, UU[-2 * WX], UU[-WX], UU[0], UU[WX], true, true);
                 const T fz = mzh * upw6<T>(mzh, zc[1][1], zc[1][2], zc[1][3], zc[1][4], true, okR2) -
                              mzl * upw6<T>(mzl, zc[1][0], zc[1][1], zc[1][2], zc[1][3], true, okR1);
-                const T val = ld(a.un[2], ou) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
+                const T val = unc[2] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
                 st(a.out[2], ou, val);
                 if (i == 0) st(a.out[2], ou + nx, val);
             }
@@ -333,7 +370,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                              myl * upw6<T>(myl, VV[-2 * WX], VV[-WX], VV[0], VV[WX], true, true);
                 const T fz = mzh * upw6<T>(mzh, zc[2][1], zc[2][2], zc[2][3], zc[2][4], true, okR2) -
                              mzl * upw6<T>(mzl, zc[2][0], zc[2][1], zc[2][2], zc[2][3], true, okR1);
-                const T val = ld(a.un[3], ov) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
+                const T val = unc[3] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
                 st(a.out[3], ov, val);
                 if (j == 0) st(a.out[3], ov + (uint32_t)ny * nx, val);
             }
@@ -350,7 +387,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                              myl * upw6<T>(myl, WW[-2 * WX], WW[-WX], WW[0], WW[WX], true, true);
                 const T fz = mzh * upw6<T>(mzh, zc[3][1], zc[3][2], zc[3][3], zc[3][4], k - 1 >= 1, okR2) -
                              mzl * upw6<T>(mzl, zc[3][0], zc[3][1], zc[3][2], zc[3][3], k - 2 >= 1, okR1);
-                st(a.out[4], oc, ld(a.un[4], oc) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth);
+                st(a.out[4], oc, unc[4] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth);
                 if (k == nz - 1) st(a.out[4], oc + pc, T(0));
             }
         }
@@ -359,6 +396,8 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             m2[q] = m1[q];
             m1[q] = P0[q * 3 * WS];
         }
+#pragma unroll
+        for (int f = 0; f < 5; ++f) unc[f] = unn[f];
         __syncthreads();
     }
 }
@@ -640,6 +679,20 @@ ebs_status build_tiles(ebs_ctx* cx) {
                     cx->h_tiles.push_back(t);
                 }
     }
+    // Order: z band, then Morton order of the tile origin in 16-cell units.  The
+    // launch hands each XCD a contiguous run of this list, so the blocks resident
+    // on one XCD cover a compact patch at similar heights and share their halo
+    // cache lines in that XCD's L2.
+    auto morton = [](uint32_t x, uint32_t y) {
+        uint64_t m = 0;
+        for (int b = 0; b < 16; ++b) m |= (uint64_t)((x >> b) & 1) << (2 * b) | (uint64_t)((y >> b) & 1) << (2 * b + 1);
+        return m;
+    };
+    std::stable_sort(cx->h_tiles.begin(), cx->h_tiles.end(), [&](const ebs_tile& p, const ebs_tile& q) {
+        const int bp = p.z0 / TZ, bq = q.z0 / TZ;
+        if (bp != bq) return bp < bq;
+        return morton(p.x0 >> 4, p.y0 >> 4) < morton(q.x0 >> 4, q.y0 >> 4);
+    });
     cx->ntiles = (int32_t)cx->h_tiles.size();
     if (cx->d_tiles) (void)hipFree(cx->d_tiles);
     cx->d_tiles = nullptr;
