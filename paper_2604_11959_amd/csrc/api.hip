@@ -44,6 +44,7 @@ GeoView geo_view(const ebs_ctx* c) {
     v.kr = c->d_kr;
     v.geo = c->d_geo;
     v.type = c->d_type;
+    v.type4 = c->d_type4;
     return v;
 }
 
@@ -171,7 +172,7 @@ ebs_status ebs_destroy(ebs_ctx* c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     void* ptrs[] = {c->d_kf,   c->d_kr,        c->d_g0,      c->d_g1,   c->d_goff, c->d_gcol,
                     c->d_geo,  c->d_type,      c->d_mask,    c->d_small, c->d_tier, c->d_w,
-                    c->d_smalllist, c->d_actlist, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles, c->d_prim, c->d_fh, c->d_bf, c->d_col,
+                    c->d_smalllist, c->d_actlist, c->d_lsq_off, c->d_lsq_idx, c->d_lsq_c, c->d_lsq_ev, c->d_lsq_nev, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles, c->d_prim, c->d_fh, c->d_type4, c->d_col,
                     c->d_part, c->d_dummy};
     for (void* p : ptrs) free_ptr(p);
     delete c;

@@ -56,6 +56,7 @@ struct GeoView {
     const int32_t* kr;         // [4][ncol] first regular level
     const double* geo;         // [4][GQ_N][G]
     const int8_t* type;        // [4][G]
+    const uint32_t* type4;     // [G] the four instance types packed, byte s = instance s
 };
 
 struct WsrdView {
@@ -128,6 +129,7 @@ struct ebs_ctx {
     int32_t G = 0;
     double* d_geo = nullptr;
     int8_t* d_type = nullptr;
+    uint32_t* d_type4 = nullptr;
     std::vector<int32_t> h_g0, h_g1, h_goff;
 
     // redistribution
@@ -139,14 +141,21 @@ struct ebs_ctx {
     int32_t nsmall[4] = {0, 0, 0, 0};
     int32_t* d_actlist = nullptr;    // [4][G] general indices of CVs R may change
     int32_t nact[4] = {0, 0, 0, 0};
+    int32_t sbase[4] = {0, 0, 0, 0};  // offset of each instance in the concatenated small list
+    int32_t nlsq = 0;                 // small CVs with kappa > 0, all instances
+    int64_t nlsq_pts = 0;             // least-squares fit points, all small CVs
+    int32_t* d_lsq_off = nullptr;     // [nlsq + 1] first fit point of each small CV
+    uint32_t* d_lsq_idx = nullptr;    // [pts] general index (| flag: Q-hat is the CV's own)
+    double* d_lsq_c = nullptr;        // [pts][3] A^-1 e_s in mesh units
+    double* d_lsq_ev = nullptr;       // [nlsq][8][3] limiter evaluation offsets
+    int8_t* d_lsq_nev = nullptr;      // [nlsq]
 
     // per-stage buffers (cut region, double)
     double* d_uhat = nullptr;  // [5][G] provisional state of the last advance
     double* d_qhat = nullptr;  // [5][G]
     double* d_sig = nullptr;   // [5][3][G]
-    double* d_prim = nullptr;  // [4][G] advected quantities of the general range
+    double* d_prim = nullptr;  // [G][4] advected quantities of the general range
     double* d_fh = nullptr;    // [5][3][G] provisional lower-face fluxes
-    double* d_bf = nullptr;    // [5][3][G] area fraction x flux on the lower faces
 
     // regular-region tiles
     int tile_x = 32, tile_y = 8, tile_z = 64;

@@ -421,6 +421,15 @@ __device__ inline void put(const RecArgs& r, int inst, int q, int g, double v) {
     r.geo[((size_t)inst * GQ_N + q) * r.G + g] = v;
 }
 
+// the four instance types of each general cell in one word (byte s = instance s)
+__global__ void k_pack_types(const int8_t* type, uint32_t* type4, int32_t G) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    uint32_t w = 0;
+    for (int s = 0; s < NINST; ++s) w |= (uint32_t)(uint8_t)type[(size_t)s * G + g] << (8 * s);
+    type4[g] = w;
+}
+
 __global__ void k_records(RecArgs r) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const int inst = blockIdx.y;
@@ -557,7 +566,7 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
     ok &= alloc((void**)&cx->d_sig, sizeof(double) * 15 * Gs);
     ok &= alloc((void**)&cx->d_prim, sizeof(double) * 4 * Gs);
     ok &= alloc((void**)&cx->d_fh, sizeof(double) * 15 * Gs);
-    ok &= alloc((void**)&cx->d_bf, sizeof(double) * 15 * Gs);
+    ok &= alloc((void**)&cx->d_type4, sizeof(uint32_t) * Gs);
     if (!ok) {
         cx->err = "device allocation of geometry tables failed";
         return EBS_E_OOM;
@@ -580,6 +589,8 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
         r.geo = cx->d_geo;
         r.type = cx->d_type;
         hipLaunchKernelGGL(k_records, dim3((G + 127) / 128, NINST), dim3(128), 0, cx->stream, r);
+        hipLaunchKernelGGL(k_pack_types, dim3((G + 255) / 256), dim3(256), 0, cx->stream, cx->d_type,
+                           cx->d_type4, cx->G);
         EBS_HIP(cx, hipGetLastError());
     }
     EBS_HIP(cx, hipStreamSynchronize(cx->stream));

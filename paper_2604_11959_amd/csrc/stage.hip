@@ -8,7 +8,7 @@
 //     geometry: face fractions are one, no flux is moved to a centroid, and
 //     the only special cases are the top wall.  It runs over a tile list
 //     derived from the box list, in the state precision.
-//   * k_general handles the general range of each column (the cut band and a
+//   * the k_gen_* passes handle the general range of each column (the cut band and a
 //     margin) in double precision with the full rules: area / volume
 //     fractions, covered stencil ends (order reduction), interpolation to the
 //     cut-face centroid, walls.  It also keeps a double-precision copy of the
@@ -404,12 +404,21 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
 
 // --------------------------------------------------------------- general
 //
-// The general range is processed in four passes over its cells (double
-// precision throughout): advected quantities per cell, provisional fluxes per
-// lower face, cut-face interpolation (stored as area fraction x flux), and the
-// divergence / update.  Each quantity is computed once; faces of CVs outside
-// the range (always full faces of regular CVs, or covered) are evaluated on the
-// fly with the same formulas.
+// The general range is processed in three passes over its cells, in double
+// precision: the advected quantities of every cell (prims), the provisional
+// fluxes on its three lower faces (fhat), and the update, which moves the
+// provisional flux of every cut face to the face centroid (bilinear
+// interpolation of neighbouring provisional fluxes), multiplies by the area
+// fraction and takes the divergence over the six faces.
+//
+// A stencil position is resolved through its column's range info (loaded once
+// per neighbouring column): general (an index into the range), below the range
+// (no instance is fluid) or above it.  The range's top is chosen so that a
+// position above it has only regular CVs within three cells in x and y and
+// below it; its advected quantities and fluxes therefore follow the plain
+// formulas (every neighbour inside the domain is fluid, faces are full).  Every
+// neighbour a cut-face interpolation reads lies within one cell of a CV that is
+// not regular, hence inside or below its column's range.
 template <typename T>
 struct GenArgs {
     Dims D;
@@ -418,13 +427,23 @@ struct GenArgs {
     const T* cur[5];
     T* out[5];
     double* uhat;  // [5][G]
-    double* prim;  // [4][G] theta, u, v, w
+    double* prim;  // [G][4] theta, u, v, w
     double* fh;    // [5][3][G] provisional flux on the lower faces
-    double* bf;    // [5][3][G] area fraction x flux on the lower faces
     double cdt;
     double rdel[3];
     int eb_mode;
-    __device__ double rd(int d) const { return d == 0 ? rdel[0] : d == 1 ? rdel[1] : rdel[2]; }
+};
+
+// bit s set <=> plane k holds CVs of instance s
+__device__ inline int plane_mask(int nz, int k) {
+    return (k >= 0 && k <= nz - 1 ? 0x7 : 0) | (k >= 1 && k <= nz - 1 ? 0x8 : 0);
+}
+__device__ inline int finst(int f) { return f < 2 ? 0 : f - 1; }
+
+// a resolved stencil position: wrapped (i, j), plane k, general index (>= 0)
+// or -1 above / -2 below the column's range, fluid bits per instance
+struct Pt {
+    int i, j, k, g, fl;
 };
 
 template <typename T>
@@ -432,141 +451,223 @@ struct Gen {
     const GenArgs<T>& a;
     __device__ __forceinline__ explicit Gen(const GenArgs<T>& a_) : a(a_) {}
 
-    // fluid test of a CV; on success *g holds its general index (-1 outside)
-    __device__ __forceinline__ bool fluid(int inst, int i, int j, int k, int* gout = nullptr, double* al = nullptr) const {
-        if (!cv_plane(a.v, inst, k)) return false;
-        i = wrapi(i, a.D.nx);
-        j = wrapi(j, a.D.ny);
-        const int g = gidx(a.v, i, j, k);
-        if (g == -2) return false;
-        if (gout) *gout = g;
-        if (g == -1) { if (al) *al = 1.0; return true; }
-        if (a.v.type[(size_t)inst * a.v.G + g] == 0) return false;
-        if (al) *al = gq(a.v, inst, GQ_ALPHA, g);
-        return true;
+    __device__ __forceinline__ int wx(int i) const { return wrapi(i, a.D.nx); }
+    __device__ __forceinline__ int wy(int j) const { return wrapi(j, a.D.ny); }
+    __device__ __forceinline__ int4 colinfo(int i, int j) const { return a.v.col[j * a.D.nx + i]; }
+    __device__ __forceinline__ Pt at(int i, int j, int k, const int4& ci) const {
+        Pt p;
+        p.i = i;
+        p.j = j;
+        p.k = k;
+        p.g = k < ci.x ? -2 : (k >= ci.y ? -1 : ci.z + (k - ci.x));
+        int fl = p.g == -1 ? 0xF : 0;
+        if (p.g >= 0) {
+            const uint32_t t4 = a.v.type4[p.g];
+            fl = ((t4 & 0xFFu) ? 1 : 0) | ((t4 & 0xFF00u) ? 2 : 0) | ((t4 & 0xFF0000u) ? 4 : 0) |
+                 ((t4 >> 24) ? 8 : 0);
+        }
+        p.fl = fl & plane_mask(a.D.nz, k);
+        return p;
     }
-    // lower-face fraction of CV (i,j,k) in direction d; plane nz is the top face
-    __device__ __forceinline__ double beta(int inst, int d, int i, int j, int k) const {
-        if (k == a.D.nz) return d == 2 ? 1.0 : 0.0;
-        if (!cv_plane(a.v, inst, k)) return 0.0;
-        i = wrapi(i, a.D.nx);
-        j = wrapi(j, a.D.ny);
-        const int g = gidx(a.v, i, j, k);
-        if (g == -2) return 0.0;
-        if (g == -1) return 1.0;
-        return gq(a.v, inst, GQ_BX + d, g);
+    __device__ __forceinline__ Pt at(int i, int j, int k) const { return at(i, j, k, colinfo(i, j)); }
+    __device__ __forceinline__ double st(const T* const (&U)[5], int f, int i, int j, int k) const {
+        return (double)pick5(U, f)[fidx(a.D, f, i, j, k)];
     }
-    __device__ __forceinline__ void gam(int inst, int d, int g, double& g1, double& g2) const {
-        g1 = gq(a.v, inst, GQ_FX1 + 2 * d, g);
-        g2 = gq(a.v, inst, GQ_FX1 + 2 * d + 1, g);
-    }
-    // state value, zero where the CV is not fluid
-    __device__ __forceinline__ double sv(const T* const (&U)[5], int f, int i, int j, int k) const {
-        const int inst = f < 2 ? 0 : f - 1;
-        if (!fluid(inst, i, j, k)) return 0.0;
-        return (double)pick5(U, f)[fidx(a.D, f, wrapi(i, a.D.nx), wrapi(j, a.D.ny), k)];
-    }
-    // advected quantity of field f (1: theta, 2..4: velocity) at a fluid CV
-    // (i, j wrapped), computed from the state
-    __device__ __forceinline__ double phi_direct(int f, int ii, int jj, int k) const {
-        if (f == 1) return (double)a.cur[1][ic(a.D, ii, jj, k)] / (double)a.cur[0][ic(a.D, ii, jj, k)];
-        int i0 = ii, j0 = jj, k0 = k;
-        if (f == 2) i0 = wrapi(ii - 1, a.D.nx);
-        if (f == 3) j0 = wrapi(jj - 1, a.D.ny);
-        if (f == 4) k0 = k - 1;
+    __device__ __forceinline__ double geo(int s, int q, int g) const { return gq(a.v, s, q, g); }
+
+    // advected quantity of field F (1 theta, 2..4 velocity) at a fluid CV from
+    // the state; the density of the face is the mean over the fluid cells on
+    // either side (lo_fluid: the cell below / left of the face is fluid)
+    template <int F>
+    __device__ __forceinline__ double phi_state(const Pt& p, bool lo_fluid) const {
+        if (F == 1) return st(a.cur, 1, p.i, p.j, p.k) / st(a.cur, 0, p.i, p.j, p.k);
+        int i0 = p.i, j0 = p.j, k0 = p.k;
+        if (F == 2) i0 = wx(p.i - 1);
+        if (F == 3) j0 = wy(p.j - 1);
+        if (F == 4) k0 = p.k - 1;
         double s = 0.0;
         int cnt = 0;
-        if (fluid(0, i0, j0, k0)) { s += (double)a.cur[0][ic(a.D, i0, j0, k0)]; ++cnt; }
-        if (fluid(0, ii, jj, k)) { s += (double)a.cur[0][ic(a.D, ii, jj, k)]; ++cnt; }
+        if (lo_fluid) { s += st(a.cur, 0, i0, j0, k0); ++cnt; }
+        if (p.fl & 1) { s += st(a.cur, 0, p.i, p.j, p.k); ++cnt; }
         if (cnt == 0) return 0.0;
-        return (double)pick5(a.cur, f)[fidx(a.D, f, ii, jj, k)] / (s / cnt);
+        return st(a.cur, F, p.i, p.j, p.k) / (s / cnt);
     }
-    __device__ __forceinline__ double phi(int f, int i, int j, int k) const {
-        const int inst = f < 2 ? 0 : f - 1;
-        int g;
-        if (!fluid(inst, i, j, k, &g)) return 0.0;
-        if (g >= 0) return a.prim[(size_t)(f - 1) * a.v.G + g];
-        return phi_direct(f, wrapi(i, a.D.nx), wrapi(j, a.D.ny), k);
+    // advected quantity at any stencil position
+    template <int F>
+    __device__ __forceinline__ double phi(const Pt& p) const {
+        if (!((p.fl >> finst(F)) & 1)) return 0.0;
+        if (p.g >= 0) return a.prim[4 * (size_t)p.g + (F - 1)];
+        return phi_state<F>(p, true);  // above the range: the lower neighbour is fluid
     }
-    __device__ __forceinline__ double mass(int inst, int d, int i, int j, int k) const {
-        const int mf = 2 + d;
-        if (inst == 0) return sv(a.cur, mf, i, j, k);
-        int i0 = i, j0 = j, k0 = k;
-        if (inst == 1) i0 = i - 1;
-        if (inst == 2) j0 = j - 1;
-        if (inst == 3) k0 = k - 1;
-        return 0.5 * (sv(a.cur, mf, i0, j0, k0) + sv(a.cur, mf, i, j, k));
+    // momentum component D at a position, zero where its CV is not fluid
+    template <int D>
+    __device__ __forceinline__ double mom(const Pt& p) const {
+        return ((p.fl >> (D + 1)) & 1) ? st(a.cur, 2 + D, p.i, p.j, p.k) : 0.0;
     }
-    // provisional flux on the lower d-face of CV (i,j,k)
-    __device__ __forceinline__ double fhat(int f, int d, int i, int j, int k) const {
-        const int inst = f < 2 ? 0 : f - 1;
-        if (d == 2) {
-            if (inst != 3 && (k == 0 || k == a.D.nz)) return 0.0;
-            if (inst == 3 && (k == 1 || k == a.D.nz)) return 0.0;
+    // provisional flux of field F on the lower D-face of the CV at P, from the
+    // four stencil positions (LL, L, P, RR) and the position below P along the
+    // staggering direction of the field's instance (ls)
+    template <int F, int D>
+    __device__ __forceinline__ double fhat(const Pt& LL, const Pt& L, const Pt& P, const Pt& RR,
+                                           const Pt& ls) const {
+        constexpr int s = F < 2 ? 0 : F - 1;
+        if (D == 2) {
+            if (s != 3 && (P.k == 0 || P.k == a.D.nz)) return 0.0;
+            if (s == 3 && (P.k == 1 || P.k == a.D.nz)) return 0.0;
         }
-        const double m = mass(inst, d, i, j, k);
-        if (f == 0) return m;
-        const int o0 = d == 0, o1 = d == 1, o2 = d == 2;
-        const double pLL = phi(f, i - 2 * o0, j - 2 * o1, k - 2 * o2);
-        const double pL = phi(f, i - o0, j - o1, k - o2);
-        const double pR = phi(f, i, j, k);
-        const double pRR = phi(f, i + o0, j + o1, k + o2);
-        const bool okLL = fluid(inst, i - 2 * o0, j - 2 * o1, k - 2 * o2);
-        const bool okRR = fluid(inst, i + o0, j + o1, k + o2);
-        return m * upw<double>(m, pLL, pL, pR, pRR, okLL, okRR);
+        const double m = s == 0 ? mom<D>(P) : 0.5 * (mom<D>(ls) + mom<D>(P));
+        if (F == 0) return m;
+        return m * upw<double>(m, phi<F>(LL), phi<F>(L), phi<F>(P), phi<F>(RR), (LL.fl >> s) & 1,
+                               (RR.fl >> s) & 1);
     }
-    // provisional flux from the pass-2 buffer when the CV is in the range
-    __device__ __forceinline__ double fhat_any(int f, int d, int i, int j, int k) const {
-        if (k >= 0 && k < a.D.nz) {
-            const int g = gidx(a.v, wrapi(i, a.D.nx), wrapi(j, a.D.ny), k);
-            if (g >= 0) return a.fh[((size_t)f * 3 + d) * a.v.G + g];
+    // stencil of the lower D-face of P
+    template <int D>
+    __device__ __forceinline__ void stencil(const Pt& P, Pt& LL, Pt& L, Pt& RR) const {
+        if (D == 0) {
+            LL = at(wx(P.i - 2), P.j, P.k);
+            L = at(wx(P.i - 1), P.j, P.k);
+            RR = at(wx(P.i + 1), P.j, P.k);
+        } else if (D == 1) {
+            LL = at(P.i, wy(P.j - 2), P.k);
+            L = at(P.i, wy(P.j - 1), P.k);
+            RR = at(P.i, wy(P.j + 1), P.k);
+        } else {
+            const int4 ci = colinfo(P.i, P.j);
+            LL = at(P.i, P.j, P.k - 2, ci);
+            L = at(P.i, P.j, P.k - 1, ci);
+            RR = at(P.i, P.j, P.k + 1, ci);
         }
-        return fhat(f, d, i, j, k);
     }
-    // flux on the lower d-face moved to the cut-face centroid (g >= 0: own cell)
-    __device__ __forceinline__ double face(int f, int d, int i, int j, int k, int g, double b) const {
-        const int inst = f < 2 ? 0 : f - 1;
-        const double F0 = a.fh[((size_t)f * 3 + d) * a.v.G + g];
-        if (!(b < 1.0)) return F0;
-        double g1, g2;
-        gam(inst, d, g, g1, g2);
+    // the position below P along the staggering direction of instance S
+    template <int S>
+    __device__ __forceinline__ Pt stag(const Pt& P) const {
+        if (S == 1) return at(wx(P.i - 1), P.j, P.k);
+        if (S == 2) return at(P.i, wy(P.j - 1), P.k);
+        return at(P.i, P.j, P.k - 1, colinfo(P.i, P.j));
+    }
+    // provisional flux on the lower D-face of any CV (computed from scratch)
+    template <int F, int D>
+    __device__ __forceinline__ double fhat_at(const Pt& P) const {
+        Pt LL, L, RR;
+        stencil<D>(P, LL, L, RR);
+        constexpr int s = F < 2 ? 0 : F - 1;
+        const Pt ls = s == 0 ? P : stag<s == 0 ? 3 : s>(P);
+        return fhat<F, D>(LL, L, P, RR, ls);
+    }
+    // provisional flux on the lower D-face of a CV in the range (pass-2 buffer)
+    // or above it
+    template <int F, int D>
+    __device__ __forceinline__ double fhat_any(const Pt& P) const {
+        if (P.g >= 0) return a.fh[((size_t)F * 3 + D) * a.v.G + P.g];
+        return fhat_at<F, D>(P);
+    }
+    // area fraction of the lower D-face of the CV of instance S at P
+    template <int S, int D>
+    __device__ __forceinline__ double beta(const Pt& P) const {
+        if (P.k == a.D.nz) return D == 2 ? 1.0 : 0.0;
+        if (!((plane_mask(a.D.nz, P.k) >> S) & 1)) return 0.0;
+        if (P.g == -2) return 0.0;
+        if (P.g == -1) return 1.0;
+        return geo(S, GQ_BX + D, P.g);
+    }
+    // area fraction x flux on the lower D-face of the CV at P, the flux moved
+    // to the face centroid when the face is cut
+    template <int F, int D>
+    __device__ __forceinline__ double bface(const Pt& P) const {
+        constexpr int s = F < 2 ? 0 : F - 1;
+        const double b = beta<s, D>(P);
+        if (!(b > 0.0)) return 0.0;
+        if (P.k == a.D.nz) return 0.0;  // top wall: zero flux
+        const double F0 = fhat_any<F, D>(P);
+        if (!(b < 1.0) || P.g < 0) return b * F0;
+        const double g1 = geo(s, GQ_FX1 + 2 * D, P.g), g2 = geo(s, GQ_FX1 + 2 * D + 1, P.g);
         const int s1 = g1 > 0.0 ? 1 : (g1 < 0.0 ? -1 : 0);
         const int s2 = g2 > 0.0 ? 1 : (g2 < 0.0 ? -1 : 0);
-        if (s1 == 0 && s2 == 0) return F0;
-        // tangential steps: first tangential axis is y for x-faces, x otherwise;
-        // second is y for z-faces, z otherwise
-        const int ax = d == 0 ? 0 : s1, ay = d == 0 ? s1 : 0;
-        const int by = d == 2 ? s2 : 0, bz = d == 2 ? 0 : s2;
+        if (s1 == 0 && s2 == 0) return b * F0;
+        // tangential steps: the first tangential axis is y for x-faces and x
+        // otherwise; the second is y for z-faces and z otherwise
+        const int ax = D == 0 ? 0 : s1, ay = D == 0 ? s1 : 0;
+        const int by = D == 2 ? s2 : 0, bz = D == 2 ? 0 : s2;
         const bool u1 = s1 != 0, u2 = s2 != 0, u12 = u1 && u2;
-        // all-or-nothing: every weighted neighbour face must carry fluid and lie inside
-        if (u1 && !(beta(inst, d, i + ax, j + ay, k) > 0.0)) return F0;
+        if (u2 && bz != 0 && !((plane_mask(a.D.nz, P.k + bz) >> s) & 1)) return b * F0;
+        Pt N1, N2, N12;
+        if (u1) {
+            N1 = at(wx(P.i + ax), wy(P.j + ay), P.k);
+            if (!(beta<s, D>(N1) > 0.0)) return b * F0;
+        }
         if (u2) {
-            if (bz != 0 && !cv_plane(a.v, inst, k + bz)) return F0;
-            if (!(beta(inst, d, i, j + by, k + bz) > 0.0)) return F0;
+            N2 = at(P.i, wy(P.j + by), P.k + bz);
+            if (!(beta<s, D>(N2) > 0.0)) return b * F0;
         }
-        if (u12 && !(beta(inst, d, i + ax, j + ay + by, k + bz) > 0.0)) return F0;
+        if (u12) {
+            N12 = at(wx(P.i + ax), wy(P.j + ay + by), P.k + bz);
+            if (!(beta<s, D>(N12) > 0.0)) return b * F0;
+        }
         const double w1 = fabs(g1), w2 = fabs(g2);
-        double F = (1.0 - w1) * (1.0 - w2) * F0;
-        if (u1) F += w1 * (1.0 - w2) * fhat_any(f, d, i + ax, j + ay, k);
-        if (u2) F += (1.0 - w1) * w2 * fhat_any(f, d, i, j + by, k + bz);
-        if (u12) F += w1 * w2 * fhat_any(f, d, i + ax, j + ay + by, k + bz);
-        return F;
+        double Fv = (1.0 - w1) * (1.0 - w2) * F0;
+        if (u1) Fv += w1 * (1.0 - w2) * fhat_any<F, D>(N1);
+        if (u2) Fv += (1.0 - w1) * w2 * fhat_any<F, D>(N2);
+        if (u12) Fv += w1 * w2 * fhat_any<F, D>(N12);
+        return b * Fv;
     }
-    // area fraction x flux on the lower d-face of any CV
-    __device__ __forceinline__ double bflux(int f, int d, int i, int j, int k) const {
-        if (k >= 0 && k < a.D.nz) {
-            const int g = gidx(a.v, wrapi(i, a.D.nx), wrapi(j, a.D.ny), k);
-            if (g >= 0) return a.bf[((size_t)f * 3 + d) * a.v.G + g];
+    // divergence term of field F at the CV P (upper neighbours Ux, Uy, Uz)
+    template <int F, int D>
+    __device__ __forceinline__ double div_dir(const Pt& P, const Pt& U, int g) const {
+        constexpr int s = F < 2 ? 0 : F - 1;
+        const double rd = a.rdel[D];
+        double br = (bface<F, D>(U) - bface<F, D>(P)) * rd;
+        if (a.eb_mode == 1) {
+            const double blo = beta<s, D>(P), bhi = beta<s, D>(U);
+            double sm = 0.0;
+            int cnt = 0;
+            if (blo > 0.0) { sm += a.fh[((size_t)F * 3 + D) * a.v.G + g]; ++cnt; }
+            if (bhi > 0.0) { sm += U.k == a.D.nz ? 0.0 : fhat_any<F, D>(U); ++cnt; }
+            const double fb = cnt ? sm / cnt : 0.0;
+            br -= geo(s, GQ_AX + D, g) * fb * rd;
         }
-        const int inst = f < 2 ? 0 : f - 1;
-        const double b = beta(inst, d, i, j, k);  // 1 or 0 outside the range
-        return b > 0.0 ? b * fhat(f, d, i, j, k) : 0.0;
+        return br;
+    }
+    template <int F>
+    __device__ __forceinline__ void update(const Pt& P, const Pt& Ux, const Pt& Uy, const Pt& Uz, int g) const {
+        constexpr int s = F < 2 ? 0 : F - 1;
+        double val = 0.0;
+        if ((P.fl >> s) & 1) {
+            const double al = geo(s, GQ_ALPHA, g);
+            double br = div_dir<F, 0>(P, Ux, g);
+            br += div_dir<F, 1>(P, Uy, g);
+            br += div_dir<F, 2>(P, Uz, g);
+            val = st(a.un, F, P.i, P.j, P.k) - a.cdt * br / al;
+        }
+        a.uhat[(size_t)F * a.v.G + g] = val;
+        put_field<T>(a.D, a.out, F, P.i, P.j, P.k, (T)val);
+    }
+    template <int D>
+    __device__ __forceinline__ void fhat_dir(const Pt& P, const Pt& Lx, const Pt& Ly, const Pt& Lz,
+                                             const int4& ci, int g) const {
+        Pt LL, RR;
+        const Pt& L = D == 0 ? Lx : D == 1 ? Ly : Lz;
+        if (D == 0) {
+            LL = at(wx(P.i - 2), P.j, P.k);
+            RR = at(wx(P.i + 1), P.j, P.k);
+        } else if (D == 1) {
+            LL = at(P.i, wy(P.j - 2), P.k);
+            RR = at(P.i, wy(P.j + 1), P.k);
+        } else {
+            LL = at(P.i, P.j, P.k - 2, ci);
+            RR = at(P.i, P.j, P.k + 1, ci);
+        }
+        const size_t G = a.v.G;
+        a.fh[(0 * 3 + D) * G + g] = beta<0, D>(P) > 0.0 ? fhat<0, D>(LL, L, P, RR, P) : 0.0;
+        a.fh[(1 * 3 + D) * G + g] = beta<0, D>(P) > 0.0 ? fhat<1, D>(LL, L, P, RR, P) : 0.0;
+        a.fh[(2 * 3 + D) * G + g] = beta<1, D>(P) > 0.0 ? fhat<2, D>(LL, L, P, RR, Lx) : 0.0;
+        a.fh[(3 * 3 + D) * G + g] = beta<2, D>(P) > 0.0 ? fhat<3, D>(LL, L, P, RR, Ly) : 0.0;
+        a.fh[(4 * 3 + D) * G + g] = beta<3, D>(P) > 0.0 ? fhat<4, D>(LL, L, P, RR, Lz) : 0.0;
     }
 };
 
-__device__ inline void gen_cell(const GeoView& v, int g, int& i, int& j, int& k) {
+__device__ inline void gen_cell(const GeoView& v, int g, int& i, int& j, int& k, int4& ci) {
     const int c = v.gcol[g];
-    const int4 ci = v.col[c];
+    ci = v.col[c];
     i = c % v.nx;
     j = c / v.nx;
     k = ci.x + (g - ci.z);
@@ -578,12 +679,17 @@ __global__ void __launch_bounds__(256) k_gen_prims(GenArgs<T> a) {
     if (g >= a.v.G) return;
     const Gen<T> G(a);
     int i, j, k;
-    gen_cell(a.v, g, i, j, k);
-    for (int f = 1; f < 5; ++f) {
-        const int inst = f < 2 ? 0 : f - 1;
-        const double p = G.fluid(inst, i, j, k) ? G.phi_direct(f, i, j, k) : 0.0;
-        a.prim[(size_t)(f - 1) * a.v.G + g] = p;
-    }
+    int4 ci;
+    gen_cell(a.v, g, i, j, k, ci);
+    const Pt P = G.at(i, j, k, ci);
+    const bool lx = G.at(G.wx(i - 1), j, k).fl & 1;
+    const bool ly = G.at(i, G.wy(j - 1), k).fl & 1;
+    const bool lz = G.at(i, j, k - 1, ci).fl & 1;
+    double* o = a.prim + 4 * (size_t)g;
+    o[0] = (P.fl & 1) ? G.template phi_state<1>(P, false) : 0.0;
+    o[1] = (P.fl & 2) ? G.template phi_state<2>(P, lx) : 0.0;
+    o[2] = (P.fl & 4) ? G.template phi_state<3>(P, ly) : 0.0;
+    o[3] = (P.fl & 8) ? G.template phi_state<4>(P, lz) : 0.0;
 }
 
 template <typename T>
@@ -592,30 +698,14 @@ __global__ void __launch_bounds__(256) k_gen_fhat(GenArgs<T> a) {
     if (g >= a.v.G) return;
     const Gen<T> G(a);
     int i, j, k;
-    gen_cell(a.v, g, i, j, k);
-    for (int f = 0; f < 5; ++f) {
-        const int inst = f < 2 ? 0 : f - 1;
-        for (int d = 0; d < 3; ++d) {
-            const double b = G.beta(inst, d, i, j, k);
-            a.fh[((size_t)f * 3 + d) * a.v.G + g] = b > 0.0 ? G.fhat(f, d, i, j, k) : 0.0;
-        }
-    }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_gen_face(GenArgs<T> a) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.v.G) return;
-    const Gen<T> G(a);
-    int i, j, k;
-    gen_cell(a.v, g, i, j, k);
-    for (int f = 0; f < 5; ++f) {
-        const int inst = f < 2 ? 0 : f - 1;
-        for (int d = 0; d < 3; ++d) {
-            const double b = G.beta(inst, d, i, j, k);
-            a.bf[((size_t)f * 3 + d) * a.v.G + g] = b > 0.0 ? b * G.face(f, d, i, j, k, g, b) : 0.0;
-        }
-    }
+    int4 ci;
+    gen_cell(a.v, g, i, j, k, ci);
+    const Pt P = G.at(i, j, k, ci);
+    // positions below P along x, y, z (the staggering neighbours of instances 1-3)
+    const Pt Lx = G.at(G.wx(i - 1), j, k), Ly = G.at(i, G.wy(j - 1), k), Lz = G.at(i, j, k - 1, ci);
+    G.template fhat_dir<0>(P, Lx, Ly, Lz, ci, g);
+    G.template fhat_dir<1>(P, Lx, Ly, Lz, ci, g);
+    G.template fhat_dir<2>(P, Lx, Ly, Lz, ci, g);
 }
 
 template <typename T>
@@ -624,31 +714,16 @@ __global__ void __launch_bounds__(256) k_gen_update(GenArgs<T> a) {
     if (g >= a.v.G) return;
     const Gen<T> G(a);
     int i, j, k;
-    gen_cell(a.v, g, i, j, k);
-    for (int f = 0; f < 5; ++f) {
-        const int inst = f < 2 ? 0 : f - 1;
-        double al = 0.0;
-        double val = 0.0;
-        if (G.fluid(inst, i, j, k, nullptr, &al)) {
-            double br = 0.0;
-            for (int d = 0; d < 3; ++d) {
-                const int ip = i + (d == 0), jp = j + (d == 1), kp = k + (d == 2);
-                br += (G.bflux(f, d, ip, jp, kp) - a.bf[((size_t)f * 3 + d) * a.v.G + g]) * a.rd(d);
-                if (a.eb_mode == 1) {
-                    const double blo = G.beta(inst, d, i, j, k), bhi = G.beta(inst, d, ip, jp, kp);
-                    double s = 0.0;
-                    int cnt = 0;
-                    if (blo > 0.0) { s += a.fh[((size_t)f * 3 + d) * a.v.G + g]; ++cnt; }
-                    if (bhi > 0.0) { s += G.fhat_any(f, d, ip, jp, kp); ++cnt; }
-                    const double fb = cnt ? s / cnt : 0.0;
-                    br -= gq(a.v, inst, GQ_AX + d, g) * fb * a.rd(d);
-                }
-            }
-            val = G.sv(a.un, f, i, j, k) - a.cdt * br / al;
-        }
-        a.uhat[(size_t)f * a.v.G + g] = val;
-        put_field<T>(a.D, a.out, f, i, j, k, (T)val);
-    }
+    int4 ci;
+    gen_cell(a.v, g, i, j, k, ci);
+    const Pt P = G.at(i, j, k, ci);
+    // the upper neighbours: their lower faces are this CV's upper faces
+    const Pt Ux = G.at(G.wx(i + 1), j, k), Uy = G.at(i, G.wy(j + 1), k), Uz = G.at(i, j, k + 1, ci);
+    G.template update<0>(P, Ux, Uy, Uz, g);
+    G.template update<1>(P, Ux, Uy, Uz, g);
+    G.template update<2>(P, Ux, Uy, Uz, g);
+    G.template update<3>(P, Ux, Uy, Uz, g);
+    G.template update<4>(P, Ux, Uy, Uz, g);
 }
 
 }  // namespace
@@ -779,16 +854,14 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
         a.uhat = cx->d_uhat;
         a.prim = cx->d_prim;
         a.fh = cx->d_fh;
-        a.bf = cx->d_bf;
         a.cdt = cdt;
         for (int d = 0; d < 3; ++d) a.rdel[d] = 1.0 / cx->g.dx[d];
         a.eb_mode = cx->g.eb_flux;
         const dim3 grid((cx->G + 255) / 256), blk(256);
-        // the first three passes only read the input state; the update writes
+        // the first two passes only read the input state; the update writes
         // the output (which may alias U^n, never U_cur)
         hipLaunchKernelGGL(k_gen_prims<T>, grid, blk, 0, cx->stream, a);
         hipLaunchKernelGGL(k_gen_fhat<T>, grid, blk, 0, cx->stream, a);
-        hipLaunchKernelGGL(k_gen_face<T>, grid, blk, 0, cx->stream, a);
         hipLaunchKernelGGL(k_gen_update<T>, grid, blk, 0, cx->stream, a);
         EBS_HIP(cx, hipGetLastError());
     }

@@ -241,6 +241,15 @@ __global__ void k_vhat(WArgs a) {
 }
 
 // ------------------------------------------------------------------ apply
+// Each field belongs to one instance: rho and rho theta to the cell-centred
+// CVs, rho u / rho v / rho w to the x-, y-, z-face CVs.
+__device__ inline int field_inst(int f) { return f < 2 ? 0 : f - 1; }
+__device__ inline int inst_f0(int inst) { return inst == 0 ? 0 : inst + 1; }
+__device__ inline int inst_nf(int inst) { return inst == 0 ? 2 : 1; }
+
+constexpr uint32_t LSQ_QHAT = 0x80000000u;  // fit point whose Q-hat differs from U-hat
+constexpr int LSQ_MAXEV = 8;                // members of a 2x2x2 neighbourhood
+
 struct AArgs {
     GeoView v;
     const int32_t* mask;
@@ -249,55 +258,60 @@ struct AArgs {
     const double* uhat;   // [5][G]
     double* qhat;         // [5][G]
     double* sig;          // [5][3][G]
-    const int32_t* list;  // general indices
-    int32_t nlist;
-    int inst;
-    int f0, nf;           // fields of the instance
+    const int32_t* slist; // [4][G] small CVs with kappa > 0 (per instance)
+    const int32_t* alist; // [4][G] CVs the operator may change
+    int32_t ns[NINST], na[NINST];
+    int32_t sbase[NINST]; // offset of each instance in the concatenated small list
+    const int32_t* loff;  // [S+1] least-squares operators (CSR)
+    const uint32_t* lidx; // [P]
+    const double* lc;     // [P][3]
+    const double* lev;    // [S][LSQ_MAXEV][3]
+    const int8_t* lnev;   // [S]
     int limiter;
     double dv;
 };
 
-__device__ inline double wv(const AArgs& a, int q, int g) {
-    return a.w[((size_t)a.inst * WQ_COUNT + q) * a.v.G + g];
+__device__ inline double wv(const AArgs& a, int inst, int q, int g) {
+    return a.w[((size_t)inst * WQ_COUNT + q) * a.v.G + g];
 }
 
-__global__ void k_qhat(AArgs a) {
+// Q-hat (Eq. qhat_omega) of the small CVs with kappa > 0; all instances in one
+// launch (blockIdx.y = instance)
+__global__ void __launch_bounds__(128) k_qhat(AArgs a) {
+    const int inst = blockIdx.y;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.nlist) return;
-    const int g = a.list[t];
+    if (t >= a.ns[inst]) return;
+    const int g = a.slist[(size_t)inst * a.v.G + t];
     const GeoView& v = a.v;
     int i, j, k;
     cell_of(v, g, i, j, k);
-    const double V = gq(v, a.inst, GQ_ALPHA, g) * a.dv;
-    const double om = wv(a, WQ_OMEGA, g), kap = wv(a, WQ_KAPPA, g);
-    const double den = wv(a, WQ_VHAT, g) * a.dv;
-    const int32_t m = a.mask[(size_t)a.inst * v.G + g];
-    for (int f = a.f0; f < a.f0 + a.nf; ++f) {
+    const double V = gq(v, inst, GQ_ALPHA, g) * a.dv;
+    const double om = wv(a, inst, WQ_OMEGA, g), kap = wv(a, inst, WQ_KAPPA, g);
+    const double den = wv(a, inst, WQ_VHAT, g) * a.dv;
+    const int32_t m = a.mask[(size_t)inst * v.G + g];
+    // members (every member of a small CV's neighbourhood lies in the general
+    // range: its margin exceeds the merge radius)
+    int gm[LSQ_MAXEV - 1];
+    double wm[LSQ_MAXEV - 1];
+    int nm = 0;
+    for (int oz = -1; oz <= 1; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                if (ox == 0 && oy == 0 && oz == 0) continue;
+                if (!((m >> bit_of(ox, oy, oz)) & 1)) continue;
+                const int gr = nbr(v, inst, i + ox, j + oy, k + oz);
+                if (gr < 0 || nm >= LSQ_MAXEV - 1) continue;
+                gm[nm] = gr;
+                wm[nm] = kap * gq(v, inst, GQ_ALPHA, gr) * a.dv / wv(a, inst, WQ_N, gr);
+                ++nm;
+            }
+    const int f0 = inst_f0(inst), nf = inst_nf(inst);
+    for (int f = f0; f < f0 + nf; ++f) {
         const double* U = a.uhat + (size_t)f * v.G;
         double s = om * V * U[g];
-        for (int oz = -1; oz <= 1; ++oz)
-            for (int oy = -1; oy <= 1; ++oy)
-                for (int ox = -1; ox <= 1; ++ox) {
-                    if (ox == 0 && oy == 0 && oz == 0) continue;
-                    if (!((m >> bit_of(ox, oy, oz)) & 1)) continue;
-                    const int gr = nbr(v, a.inst, i + ox, j + oy, k + oz);
-                    // every member of a small CV's neighbourhood lies in the
-                    // general range (its margin exceeds the merge radius)
-                    if (gr < 0) continue;
-                    const double Vr = gq(v, a.inst, GQ_ALPHA, gr) * a.dv;
-                    const double Nr = wv(a, WQ_N, gr);
-                    s += kap * Vr / Nr * U[gr];
-                }
+        for (int q = 0; q < nm; ++q) s += wm[q] * U[gm[q]];
         a.qhat[(size_t)f * v.G + g] = s / den;
     }
-}
-
-// Q-hat of a CV inside the general range: small CVs with kappa > 0 carry
-// their own, every other CV has a single-cell neighbourhood (Q-hat = U-hat)
-__device__ inline double qh_of(const AArgs& a, int f, int g) {
-    const size_t o = (size_t)a.inst * a.v.G + g;
-    if (a.small[o] && wv(a, WQ_KAPPA, g) > 0.0) return a.qhat[(size_t)f * a.v.G + g];
-    return a.uhat[(size_t)f * a.v.G + g];
 }
 
 __device__ inline double psi(double delta, double qi, double qmin, double qmax) {
@@ -306,15 +320,152 @@ __device__ inline double psi(double delta, double qi, double qmin, double qmax) 
     return 1.0;
 }
 
-__global__ void k_grad(AArgs a) {
+// Limited least-squares gradient of Q-hat for one field (blockIdx.y = field),
+// from the precomputed operator: sigma = sum_s c_s (Q-hat_s - Q-hat_i) with
+// c_s = A^-1 e_s, then the Barth-Jespersen-style limiter.
+__global__ void __launch_bounds__(128) k_grad(AArgs a) {
+    const int f = blockIdx.y;
+    const int inst = field_inst(f);
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.nlist) return;
-    const int g = a.list[t];
+    if (t >= a.ns[inst]) return;
     const GeoView& v = a.v;
+    const int g = a.slist[(size_t)inst * v.G + t];
+    const int e = a.sbase[inst] + t;
+    const int p0 = a.loff[e], p1 = a.loff[e + 1];
+    double s[3] = {0.0, 0.0, 0.0};
+    if (p1 > p0) {
+        const double* Qh = a.qhat + (size_t)f * v.G;
+        const double* Uh = a.uhat + (size_t)f * v.G;
+        const double qi = Qh[g];
+        double qmin = qi, qmax = qi;
+        for (int p = p0; p < p1; ++p) {
+            const uint32_t id = a.lidx[p];
+            const double qs = (id & LSQ_QHAT) ? Qh[id & ~LSQ_QHAT] : Uh[id];
+            const double dq = qs - qi;
+            s[0] += a.lc[3 * (size_t)p] * dq;
+            s[1] += a.lc[3 * (size_t)p + 1] * dq;
+            s[2] += a.lc[3 * (size_t)p + 2] * dq;
+            qmin = fmin(qmin, qs);
+            qmax = fmax(qmax, qs);
+        }
+        if (a.limiter != EBS_LIM_NONE) {
+            const int nev = a.lnev[e];
+            const double* ev = a.lev + (size_t)e * LSQ_MAXEV * 3;
+            double lam[3] = {1.0, 1.0, 1.0};
+            double lall = 1.0;
+            for (int q = 0; q < nev; ++q) {
+                if (a.limiter == EBS_LIM_BJ_COMPONENT) {
+                    for (int d = 0; d < 3; ++d) lam[d] = fmin(lam[d], psi(s[d] * ev[3 * q + d], qi, qmin, qmax));
+                } else {
+                    lall = fmin(lall, psi(s[0] * ev[3 * q] + s[1] * ev[3 * q + 1] + s[2] * ev[3 * q + 2], qi,
+                                          qmin, qmax));
+                }
+            }
+            if (a.limiter == EBS_LIM_BJ_COMPONENT) {
+                for (int d = 0; d < 3; ++d) s[d] *= lam[d];
+            } else {
+                for (int d = 0; d < 3; ++d) s[d] *= lall;
+            }
+        }
+    }
+    const double del[3] = {v.dx, v.dy, v.dz};
+    for (int d = 0; d < 3; ++d) a.sig[((size_t)f * 3 + d) * v.G + g] = s[d] / del[d];
+}
+
+template <typename T>
+struct FArgs {
+    AArgs a;
+    int nx, ny, nz;
+    T* out[5];
+};
+
+// Final update (Eqs. qrecon, final_update_omega) of one field (blockIdx.y)
+// on the CVs the operator may change, gathered over W.
+template <typename T>
+__global__ void __launch_bounds__(128) k_final(FArgs<T> F) {
+    const AArgs& a = F.a;
+    const int f = blockIdx.y;
+    const int inst = field_inst(f);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.na[inst]) return;
+    const GeoView& v = a.v;
+    const int g = a.alist[(size_t)inst * v.G + t];
     int i, j, k;
     cell_of(v, g, i, j, k);
-    const double xh[3] = {wv(a, WQ_XHX, g), wv(a, WQ_XHY, g), wv(a, WQ_XHZ, g)};
-    // fit box: widen directions with too little centroid spread
+    const double om = wv(a, inst, WQ_OMEGA, g), Ni = wv(a, inst, WQ_N, g);
+    const double del[3] = {v.dx, v.dy, v.dz};
+    const size_t oi = (size_t)inst * v.G + g;
+    const bool ismall = a.small[oi] && wv(a, inst, WQ_KAPPA, g) > 0.0;
+    const double vc[3] = {gq(v, inst, GQ_VCX, g), gq(v, inst, GQ_VCY, g), gq(v, inst, GQ_VCZ, g)};
+    const double* Qh = a.qhat + (size_t)f * v.G;
+    double qi = ismall ? Qh[g] : a.uhat[(size_t)f * v.G + g];
+    if (ismall)
+        for (int d = 0; d < 3; ++d)
+            qi += a.sig[((size_t)f * 3 + d) * v.G + g] * (vc[d] - wv(a, inst, WQ_XHX + d, g)) * del[d];
+    double s = 0.0;
+    for (int oz = -1; oz <= 1; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                if (ox == 0 && oy == 0 && oz == 0) continue;
+                const int gr = nbr(v, inst, i - ox, j - oy, k - oz);
+                if (gr < 0) continue;
+                if (!((a.mask[(size_t)inst * v.G + gr] >> bit_of(ox, oy, oz)) & 1)) continue;
+                const int off[3] = {ox, oy, oz};
+                double qr = Qh[gr];
+                for (int d = 0; d < 3; ++d)
+                    qr += a.sig[((size_t)f * 3 + d) * v.G + gr] *
+                          (off[d] + vc[d] - wv(a, inst, WQ_XHX + d, gr)) * del[d];
+                s += wv(a, inst, WQ_KAPPA, gr) * qr;
+            }
+    const double val = om * qi + s / Ni;
+    // write into the state layout (with the periodic repeat)
+    const int nx = F.nx, ny = F.ny;
+    size_t idx;
+    if (f == 2) idx = ((size_t)k * ny + j) * (nx + 1) + i;
+    else if (f == 3) idx = ((size_t)k * (ny + 1) + j) * nx + i;
+    else idx = ((size_t)k * ny + j) * nx + i;
+    T* o = f == 0 ? F.out[0] : f == 1 ? F.out[1] : f == 2 ? F.out[2] : f == 3 ? F.out[3] : F.out[4];
+    o[idx] = (T)val;
+    if (f == 2 && i == 0) F.out[2][((size_t)k * ny + j) * (nx + 1) + nx] = (T)val;
+    if (f == 3 && j == 0) F.out[3][((size_t)k * (ny + 1) + ny) * nx + i] = (T)val;
+}
+
+// ------------------------------------------------ least-squares operators
+// Built once per geometry for every small CV with kappa > 0: the fit points
+// (fluid CVs of the 3x3x3 box, widened to 5 along directions whose centroid
+// spread is below half a cell), the normal matrix A = sum e_s e_s^T of the
+// centroid offsets e_s (mesh units), its inverse by the adjugate with the
+// reciprocal 1-norm condition number test, and c_s = A^-1 e_s.  A zero
+// gradient is encoded as an empty point list.  The limiter's evaluation
+// offsets (centroids of the members of M_i relative to the neighbourhood
+// centroid) are stored beside them.
+struct LArgs {
+    GeoView v;
+    const int32_t* mask;
+    const int8_t* small;
+    const double* w;
+    const int32_t* slist;  // [4][G]
+    int32_t ns[NINST], sbase[NINST];
+    int fill;              // 0: count points, 1: write them
+    int32_t* cnt;          // [S]
+    const int32_t* off;    // [S+1]
+    uint32_t* idx;
+    double* c;
+    double* ev;
+    int8_t* nev;
+};
+
+__global__ void __launch_bounds__(64) k_lsq(LArgs a) {
+    const int inst = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.ns[inst]) return;
+    const GeoView& v = a.v;
+    const int g = a.slist[(size_t)inst * v.G + t];
+    const int e = a.sbase[inst] + t;
+    auto W = [&](int q, int gg) { return a.w[((size_t)inst * WQ_COUNT + q) * v.G + gg]; };
+    int i, j, k;
+    cell_of(v, g, i, j, k);
+    const double xh[3] = {W(WQ_XHX, g), W(WQ_XHY, g), W(WQ_XHZ, g)};
     int wd[3] = {1, 1, 1};
     double spread[3];
     int npts = 0;
@@ -325,11 +476,10 @@ __global__ void k_grad(AArgs a) {
             for (int oy = -wd[1]; oy <= wd[1]; ++oy)
                 for (int ox = -wd[0]; ox <= wd[0]; ++ox) {
                     if (ox == 0 && oy == 0 && oz == 0) continue;
-                    const int gs = nbr(v, a.inst, i + ox, j + oy, k + oz);
+                    const int gs = nbr(v, inst, i + ox, j + oy, k + oz);
                     if (gs < 0) continue;  // not fluid (regular CVs lie outside the fit radius)
-                    const int off[3] = {ox, oy, oz};
-                    for (int d = 0; d < 3; ++d)
-                        spread[d] = fmax(spread[d], fabs(off[d] + wv(a, WQ_XHX + d, gs) - xh[d]));
+                    const int o[3] = {ox, oy, oz};
+                    for (int d = 0; d < 3; ++d) spread[d] = fmax(spread[d], fabs(o[d] + W(WQ_XHX + d, gs) - xh[d]));
                     ++npts;
                 }
         if (pass == 1) break;
@@ -341,22 +491,20 @@ __global__ void k_grad(AArgs a) {
     bool zero = npts < 3;
     for (int d = 0; d < 3; ++d)
         if (spread[d] < 0.5 * (1.0 - TIE)) zero = true;
-    // normal matrix in mesh units (same for every field)
     double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     if (!zero) {
         for (int oz = -wd[2]; oz <= wd[2]; ++oz)
             for (int oy = -wd[1]; oy <= wd[1]; ++oy)
                 for (int ox = -wd[0]; ox <= wd[0]; ++ox) {
                     if (ox == 0 && oy == 0 && oz == 0) continue;
-                    const int gs = nbr(v, a.inst, i + ox, j + oy, k + oz);
+                    const int gs = nbr(v, inst, i + ox, j + oy, k + oz);
                     if (gs < 0) continue;
-                    const double e[3] = {ox + wv(a, WQ_XHX, gs) - xh[0], oy + wv(a, WQ_XHY, gs) - xh[1],
-                                         oz + wv(a, WQ_XHZ, gs) - xh[2]};
+                    const double es[3] = {ox + W(WQ_XHX, gs) - xh[0], oy + W(WQ_XHY, gs) - xh[1],
+                                          oz + W(WQ_XHZ, gs) - xh[2]};
                     for (int r = 0; r < 3; ++r)
-                        for (int q = 0; q < 3; ++q) A[r][q] += e[r] * e[q];
+                        for (int q = 0; q < 3; ++q) A[r][q] += es[r] * es[q];
                 }
     }
-    // inverse by the adjugate; reciprocal condition number in the 1-norm
     double inv[3][3];
     if (!zero) {
         const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
@@ -384,112 +532,43 @@ __global__ void k_grad(AArgs a) {
             if (!(1.0 / (n1 * ni) >= 1e-10)) zero = true;
         }
     }
-    // evaluation points of the limiter: centroids of the members of M_i
-    const int32_t m = a.mask[(size_t)a.inst * v.G + g];
-    const double del[3] = {v.dx, v.dy, v.dz};
-    for (int f = a.f0; f < a.f0 + a.nf; ++f) {
-        double s[3] = {0.0, 0.0, 0.0};
-        if (!zero) {
-            const double qi = a.qhat[(size_t)f * v.G + g];
-            double b[3] = {0.0, 0.0, 0.0};
-            double qmin = qi, qmax = qi;
-            for (int oz = -wd[2]; oz <= wd[2]; ++oz)
-                for (int oy = -wd[1]; oy <= wd[1]; ++oy)
-                    for (int ox = -wd[0]; ox <= wd[0]; ++ox) {
-                        if (ox == 0 && oy == 0 && oz == 0) continue;
-                        const int gs = nbr(v, a.inst, i + ox, j + oy, k + oz);
-                        if (gs < 0) continue;
-                        const double qs = qh_of(a, f, gs);
-                        const double e[3] = {ox + wv(a, WQ_XHX, gs) - xh[0],
-                                             oy + wv(a, WQ_XHY, gs) - xh[1],
-                                             oz + wv(a, WQ_XHZ, gs) - xh[2]};
-                        for (int r = 0; r < 3; ++r) b[r] += e[r] * (qs - qi);
-                        qmin = fmin(qmin, qs);
-                        qmax = fmax(qmax, qs);
-                    }
-            for (int r = 0; r < 3; ++r) s[r] = inv[r][0] * b[0] + inv[r][1] * b[1] + inv[r][2] * b[2];
-            if (a.limiter != EBS_LIM_NONE) {
-                double lam[3] = {1.0, 1.0, 1.0};
-                double lall = 1.0;
-                for (int oz = -1; oz <= 1; ++oz)
-                    for (int oy = -1; oy <= 1; ++oy)
-                        for (int ox = -1; ox <= 1; ++ox) {
-                            if (!((m >> bit_of(ox, oy, oz)) & 1)) continue;
-                            const int gj = nbr(v, a.inst, i + ox, j + oy, k + oz);
-                            const int off[3] = {ox, oy, oz};
-                            double ev[3];
-                            for (int d = 0; d < 3; ++d)
-                                ev[d] = off[d] + (gj >= 0 ? gq(v, a.inst, GQ_VCX + d, gj) : 0.0) - xh[d];
-                            if (a.limiter == EBS_LIM_BJ_COMPONENT) {
-                                for (int d = 0; d < 3; ++d) lam[d] = fmin(lam[d], psi(s[d] * ev[d], qi, qmin, qmax));
-                            } else {
-                                lall = fmin(lall, psi(s[0] * ev[0] + s[1] * ev[1] + s[2] * ev[2], qi, qmin, qmax));
-                            }
-                        }
-                if (a.limiter == EBS_LIM_BJ_COMPONENT) {
-                    for (int d = 0; d < 3; ++d) s[d] *= lam[d];
-                } else {
-                    for (int d = 0; d < 3; ++d) s[d] *= lall;
-                }
+    if (!a.fill) {
+        a.cnt[e] = zero ? 0 : npts;
+        return;
+    }
+    if (zero) {
+        a.nev[e] = 0;
+        return;
+    }
+    int p = a.off[e];
+    for (int oz = -wd[2]; oz <= wd[2]; ++oz)
+        for (int oy = -wd[1]; oy <= wd[1]; ++oy)
+            for (int ox = -wd[0]; ox <= wd[0]; ++ox) {
+                if (ox == 0 && oy == 0 && oz == 0) continue;
+                const int gs = nbr(v, inst, i + ox, j + oy, k + oz);
+                if (gs < 0) continue;
+                const double es[3] = {ox + W(WQ_XHX, gs) - xh[0], oy + W(WQ_XHY, gs) - xh[1],
+                                      oz + W(WQ_XHZ, gs) - xh[2]};
+                const bool own = a.small[(size_t)inst * v.G + gs] && W(WQ_KAPPA, gs) > 0.0;
+                a.idx[p] = (uint32_t)gs | (own ? LSQ_QHAT : 0u);
+                for (int r = 0; r < 3; ++r)
+                    a.c[3 * (size_t)p + r] = inv[r][0] * es[0] + inv[r][1] * es[1] + inv[r][2] * es[2];
+                ++p;
             }
-        }
-        for (int d = 0; d < 3; ++d) a.sig[((size_t)f * 3 + d) * v.G + g] = s[d] / del[d];
-    }
-}
-
-template <typename T>
-struct FArgs {
-    AArgs a;
-    int nx, ny, nz;
-    T* out[5];
-};
-
-template <typename T>
-__global__ void k_final(FArgs<T> F) {
-    const AArgs& a = F.a;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.nlist) return;
-    const int g = a.list[t];
-    const GeoView& v = a.v;
-    int i, j, k;
-    cell_of(v, g, i, j, k);
-    const double om = wv(a, WQ_OMEGA, g), Ni = wv(a, WQ_N, g);
-    const double del[3] = {v.dx, v.dy, v.dz};
-    const size_t oi = (size_t)a.inst * v.G + g;
-    const bool ismall = a.small[oi] && wv(a, WQ_KAPPA, g) > 0.0;
-    for (int f = a.f0; f < a.f0 + a.nf; ++f) {
-        double qi = qh_of(a, f, g);
-        if (ismall)
-            for (int d = 0; d < 3; ++d)
-                qi += a.sig[((size_t)f * 3 + d) * v.G + g] *
-                      (gq(v, a.inst, GQ_VCX + d, g) - wv(a, WQ_XHX + d, g)) * del[d];
-        double s = 0.0;
-        for (int oz = -1; oz <= 1; ++oz)
-            for (int oy = -1; oy <= 1; ++oy)
-                for (int ox = -1; ox <= 1; ++ox) {
-                    if (ox == 0 && oy == 0 && oz == 0) continue;
-                    const int gr = nbr(v, a.inst, i - ox, j - oy, k - oz);
-                    if (gr < 0) continue;
-                    if (!((a.mask[(size_t)a.inst * v.G + gr] >> bit_of(ox, oy, oz)) & 1)) continue;
-                    const int off[3] = {ox, oy, oz};
-                    double qr = a.qhat[(size_t)f * v.G + gr];
-                    for (int d = 0; d < 3; ++d)
-                        qr += a.sig[((size_t)f * 3 + d) * v.G + gr] *
-                              (off[d] + gq(v, a.inst, GQ_VCX + d, g) - wv(a, WQ_XHX + d, gr)) * del[d];
-                    s += wv(a, WQ_KAPPA, gr) * qr;
-                }
-        const double val = om * qi + s / Ni;
-        // write into the state layout (with the periodic repeat)
-        const int nx = F.nx, ny = F.ny;
-        size_t idx;
-        if (f == 2) idx = ((size_t)k * ny + j) * (nx + 1) + i;
-        else if (f == 3) idx = ((size_t)k * (ny + 1) + j) * nx + i;
-        else idx = ((size_t)k * ny + j) * nx + i;
-        T* o = f == 0 ? F.out[0] : f == 1 ? F.out[1] : f == 2 ? F.out[2] : f == 3 ? F.out[3] : F.out[4];
-        o[idx] = (T)val;
-        if (f == 2 && i == 0) F.out[2][((size_t)k * ny + j) * (nx + 1) + nx] = (T)val;
-        if (f == 3 && j == 0) F.out[3][((size_t)k * (ny + 1) + ny) * nx + i] = (T)val;
-    }
+    const int32_t m = a.mask[(size_t)inst * v.G + g];
+    int n = 0;
+    double* evo = a.ev + (size_t)e * LSQ_MAXEV * 3;
+    for (int oz = -1; oz <= 1; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                if (!((m >> bit_of(ox, oy, oz)) & 1) || n >= LSQ_MAXEV) continue;
+                const int gj = nbr(v, inst, i + ox, j + oy, k + oz);
+                const int o[3] = {ox, oy, oz};
+                for (int d = 0; d < 3; ++d)
+                    evo[3 * n + d] = o[d] + (gj >= 0 ? gq(v, inst, GQ_VCX + d, gj) : 0.0) - xh[d];
+                ++n;
+            }
+    a.nev[e] = (int8_t)n;
 }
 
 }  // namespace
@@ -550,46 +629,130 @@ ebs_status wsrd_setup(ebs_ctx* cx) {
             EBS_HIP(cx, hipMemcpy(cx->d_actlist + inst * G, al.data(), sizeof(int32_t) * al.size(),
                                   hipMemcpyHostToDevice));
     }
+    // least-squares operators of the small CVs: count, prefix sum, fill
+    int32_t S = 0, nsmax = 0;
+    for (int inst = 0; inst < NINST; ++inst) {
+        cx->sbase[inst] = S;
+        S += cx->nsmall[inst];
+        nsmax = std::max(nsmax, cx->nsmall[inst]);
+    }
+    cx->nlsq = S;
+    auto alloc = [&](void** p, size_t bytes) -> bool {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+        return hipMalloc(p, bytes) == hipSuccess;
+    };
+    bool ok = alloc((void**)&cx->d_lsq_off, sizeof(int32_t) * (S + 1));
+    ok &= alloc((void**)&cx->d_lsq_ev, sizeof(double) * 3 * LSQ_MAXEV * std::max(S, 1));
+    ok &= alloc((void**)&cx->d_lsq_nev, std::max(S, 1));
+    if (!ok) {
+        cx->err = "device allocation of the least-squares tables failed";
+        return EBS_E_OOM;
+    }
+    LArgs L;
+    L.v = geo_view(cx);
+    L.mask = cx->d_mask;
+    L.small = cx->d_small;
+    L.w = cx->d_w;
+    L.slist = cx->d_smalllist;
+    for (int inst = 0; inst < NINST; ++inst) {
+        L.ns[inst] = cx->nsmall[inst];
+        L.sbase[inst] = cx->sbase[inst];
+    }
+    L.fill = 0;
+    L.cnt = cx->d_lsq_off;  // counts first, replaced by the offsets below
+    L.off = nullptr;
+    L.idx = nullptr;
+    L.c = nullptr;
+    L.ev = nullptr;
+    L.nev = nullptr;
+    const dim3 lgrid((std::max(nsmax, 1) + 63) / 64, NINST);
+    if (S > 0) {
+        hipLaunchKernelGGL(k_lsq, lgrid, dim3(64), 0, cx->stream, L);
+        EBS_HIP(cx, hipGetLastError());
+    }
+    std::vector<int32_t> off(S + 1, 0);
+    if (S > 0)
+        EBS_HIP(cx, hipMemcpyAsync(off.data(), cx->d_lsq_off, sizeof(int32_t) * S, hipMemcpyDeviceToHost,
+                                   cx->stream));
+    EBS_HIP(cx, hipStreamSynchronize(cx->stream));
+    int64_t P = 0;
+    for (int32_t e = 0; e < S; ++e) {
+        const int32_t n = off[e];
+        off[e] = (int32_t)P;
+        P += n;
+    }
+    if (P > INT32_MAX / 4) {
+        cx->err = "least-squares tables too large";
+        return EBS_E_UNSUPPORTED;
+    }
+    off[S] = (int32_t)P;
+    cx->nlsq_pts = P;
+    ok = alloc((void**)&cx->d_lsq_idx, sizeof(uint32_t) * std::max<int64_t>(P, 1));
+    ok &= alloc((void**)&cx->d_lsq_c, sizeof(double) * 3 * std::max<int64_t>(P, 1));
+    if (!ok) {
+        cx->err = "device allocation of the least-squares tables failed";
+        return EBS_E_OOM;
+    }
+    EBS_HIP(cx, hipMemcpyAsync(cx->d_lsq_off, off.data(), sizeof(int32_t) * (S + 1), hipMemcpyHostToDevice,
+                               cx->stream));
+    if (S > 0) {
+        L.fill = 1;
+        L.cnt = nullptr;
+        L.off = cx->d_lsq_off;
+        L.idx = cx->d_lsq_idx;
+        L.c = cx->d_lsq_c;
+        L.ev = cx->d_lsq_ev;
+        L.nev = cx->d_lsq_nev;
+        hipLaunchKernelGGL(k_lsq, lgrid, dim3(64), 0, cx->stream, L);
+        EBS_HIP(cx, hipGetLastError());
+    }
+    EBS_HIP(cx, hipStreamSynchronize(cx->stream));
     return EBS_OK;
 }
 
 template <typename T>
 static ebs_status redistribute_t(ebs_ctx* cx, ebs_state* Uout) {
     void* const ou[5] = {Uout->rho, Uout->rhotheta, Uout->rhou, Uout->rhov, Uout->rhow};
-    const int f0s[4] = {0, 2, 3, 4}, nfs[4] = {2, 1, 1, 1};
+    AArgs a;
+    a.v = geo_view(cx);
+    a.mask = cx->d_mask;
+    a.small = cx->d_small;
+    a.w = cx->d_w;
+    a.uhat = cx->d_uhat;
+    a.qhat = cx->d_qhat;
+    a.sig = cx->d_sig;
+    a.slist = cx->d_smalllist;
+    a.alist = cx->d_actlist;
+    int nsmax = 0, namax = 0;
     for (int inst = 0; inst < NINST; ++inst) {
-        AArgs a;
-        a.v = geo_view(cx);
-        a.mask = cx->d_mask;
-        a.small = cx->d_small;
-        a.w = cx->d_w;
-        a.uhat = cx->d_uhat;
-        a.qhat = cx->d_qhat;
-        a.sig = cx->d_sig;
-        a.inst = inst;
-        a.f0 = f0s[inst];
-        a.nf = nfs[inst];
-        a.limiter = cx->g.limiter;
-        a.dv = cx->g.dx[0] * cx->g.dx[1] * cx->g.dx[2];
-        if (cx->nsmall[inst] > 0) {
-            a.list = cx->d_smalllist + (size_t)inst * cx->G;
-            a.nlist = cx->nsmall[inst];
-            hipLaunchKernelGGL(k_qhat, dim3((a.nlist + 127) / 128), dim3(128), 0, cx->stream, a);
-            hipLaunchKernelGGL(k_grad, dim3((a.nlist + 63) / 64), dim3(64), 0, cx->stream, a);
-        }
-        if (cx->nact[inst] > 0) {
-            FArgs<T> F;
-            F.a = a;
-            F.a.list = cx->d_actlist + (size_t)inst * cx->G;
-            F.a.nlist = cx->nact[inst];
-            F.nx = cx->nx;
-            F.ny = cx->ny;
-            F.nz = cx->nz;
-            for (int f = 0; f < 5; ++f) F.out[f] = (T*)ou[f];
-            hipLaunchKernelGGL(k_final<T>, dim3((F.a.nlist + 127) / 128), dim3(128), 0, cx->stream, F);
-        }
-        EBS_HIP(cx, hipGetLastError());
+        a.ns[inst] = cx->nsmall[inst];
+        a.na[inst] = cx->nact[inst];
+        a.sbase[inst] = cx->sbase[inst];
+        nsmax = std::max(nsmax, cx->nsmall[inst]);
+        namax = std::max(namax, cx->nact[inst]);
     }
+    a.loff = cx->d_lsq_off;
+    a.lidx = cx->d_lsq_idx;
+    a.lc = cx->d_lsq_c;
+    a.lev = cx->d_lsq_ev;
+    a.lnev = cx->d_lsq_nev;
+    a.limiter = cx->g.limiter;
+    a.dv = cx->g.dx[0] * cx->g.dx[1] * cx->g.dx[2];
+    if (nsmax > 0) {
+        hipLaunchKernelGGL(k_qhat, dim3((nsmax + 127) / 128, NINST), dim3(128), 0, cx->stream, a);
+        hipLaunchKernelGGL(k_grad, dim3((nsmax + 127) / 128, 5), dim3(128), 0, cx->stream, a);
+    }
+    if (namax > 0) {
+        FArgs<T> F;
+        F.a = a;
+        F.nx = cx->nx;
+        F.ny = cx->ny;
+        F.nz = cx->nz;
+        for (int f = 0; f < 5; ++f) F.out[f] = (T*)ou[f];
+        hipLaunchKernelGGL(k_final<T>, dim3((namax + 127) / 128, 5), dim3(128), 0, cx->stream, F);
+    }
+    EBS_HIP(cx, hipGetLastError());
     return EBS_OK;
 }
 
