@@ -73,7 +73,7 @@ typedef enum {
 } ebs_limiter;
 
 typedef struct {
-    int32_t n[3];        /* cells; nx, ny >= 8, nz >= 4                         */
+    int32_t n[3];        /* cells; nx, ny >= 8, 4 <= nz <= 32767                */
     double dx[3];        /* cell size, > 0                                      */
     double lo[3];        /* lower domain corner                                 */
     uint32_t periodic;   /* bit d set: axis d periodic; must be 0x3 (x, y)      */

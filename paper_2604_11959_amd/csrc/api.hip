@@ -40,6 +40,9 @@ GeoView geo_view(const ebs_ctx* c) {
     v.goff = c->d_goff;
     v.gcol = c->d_gcol;
     v.col = c->d_col;
+    v.Ge = c->Ge;
+    v.gcole = c->d_gcole;
+    v.fflag = c->d_fflag;
     v.kf = c->d_kf;
     v.kr = c->d_kr;
     v.geo = c->d_geo;
@@ -101,7 +104,7 @@ ebs_status ebs_create(const ebs_grid* grid, const ebs_box* boxes, int32_t nbox, 
     if (!grid || !out) return EBS_E_ARG;
     *out = nullptr;
     const ebs_grid& g = *grid;
-    if (g.n[0] < 8 || g.n[1] < 8 || g.n[2] < 4) return EBS_E_ARG;
+    if (g.n[0] < 8 || g.n[1] < 8 || g.n[2] < 4 || g.n[2] > 32767) return EBS_E_ARG;
     if ((int64_t)g.n[0] * g.n[1] * g.n[2] > (int64_t)1 << 31) return EBS_E_UNSUPPORTED;
     for (int d = 0; d < 3; ++d)
         if (!(g.dx[d] > 0.0) || !isfinite(g.dx[d]) || !isfinite(g.lo[d])) return EBS_E_ARG;
@@ -172,7 +175,7 @@ ebs_status ebs_destroy(ebs_ctx* c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     void* ptrs[] = {c->d_kf,   c->d_kr,        c->d_g0,      c->d_g1,   c->d_goff, c->d_gcol,
                     c->d_geo,  c->d_type,      c->d_mask,    c->d_small, c->d_tier, c->d_w,
-                    c->d_smalllist, c->d_actlist, c->d_lsq_off, c->d_lsq_idx, c->d_lsq_c, c->d_lsq_ev, c->d_lsq_nev, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles, c->d_prim, c->d_fh, c->d_type4, c->d_col,
+                    c->d_smalllist, c->d_actlist, c->d_lsq_off, c->d_lsq_idx, c->d_lsq_c, c->d_lsq_ev, c->d_lsq_nev, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles, c->d_prim, c->d_fh, c->d_type4, c->d_col, c->d_gcole, c->d_fflag, c->d_cbase, c->d_crec,
                     c->d_part, c->d_dummy};
     for (void* p : ptrs) free_ptr(p);
     delete c;
@@ -208,6 +211,8 @@ ebs_status ebs_build_geometry_terrain(ebs_ctx* c, const double* h_nodes, int32_t
     ebs_status st = build_geometry(c, d_h);
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(d_h);
+    if (st != EBS_OK) return st;
+    st = build_cut_faces(c);
     if (st != EBS_OK) return st;
     st = wsrd_setup(c);
     if (st != EBS_OK) return st;

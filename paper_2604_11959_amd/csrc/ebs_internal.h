@@ -50,7 +50,10 @@ struct GeoView {
     const int32_t* g0;         // [ncol]
     const int32_t* g1;         // [ncol]
     const int32_t* goff;       // [ncol]
-    const int4* col;           // [ncol] {g0, g1, goff, 0}: one load per lookup
+    const int4* col;           // [ncol] {g0 | g1 << 16, g1e, goff, goffe}: one load per lookup
+    int32_t Ge;                // cells of the extended face range (see below)
+    const int32_t* gcole;      // [Ge] column of each cell of the extended face range
+    const uint32_t* fflag;     // [G] lower-face flags: FF_POS / FF_FULL bits per (instance, dir)
     const int32_t* gcol;       // [G] column of each general cell
     const int32_t* kf;         // [4][ncol] first fluid CV level
     const int32_t* kr;         // [4][ncol] first regular level
@@ -76,13 +79,29 @@ struct StateP {
 
 __host__ __device__ inline int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// Column range info.  Planes [g0, g1) form the column's general range (general
+// index goff + k - g0).  Provisional face fluxes are kept for the longer range
+// [g0, g1e), g1e = min(nz, max(g1 + 1, g1 of the -x and -y neighbours)), with
+// index goffe + k - g0: it holds the lower faces of every CV whose face is an
+// upper face of a general CV.
+__host__ __device__ inline int col_g0(const int4& c) { return c.x & 0xFFFF; }
+__host__ __device__ inline int col_g1(const int4& c) { return (int)((uint32_t)c.x >> 16); }
+__host__ __device__ inline int4 col_pack(int g0, int g1, int g1e, int goff, int goffe) {
+    return make_int4(g0 | (g1 << 16), g1e, goff, goffe);
+}
+
+// lower-face flags of a general cell: area fraction > 0, and == 1
+__host__ __device__ constexpr uint32_t ff_pos(int inst, int d) { return 1u << (inst * 3 + d); }
+__host__ __device__ constexpr uint32_t ff_full(int inst, int d) { return 1u << (16 + inst * 3 + d); }
+
 // general index of cell position (i, j, k) (i, j wrapped), -2 below the general
 // range (every instance covered), -1 above it (every instance regular)
 __device__ inline int gidx(const GeoView& v, int i, int j, int k) {
     const int4 ci = v.col[j * v.nx + i];
-    if (k < ci.x) return -2;
-    if (k >= ci.y) return -1;
-    return ci.z + (k - ci.x);
+    const int g0 = col_g0(ci);
+    if (k < g0) return -2;
+    if (k >= col_g1(ci)) return -1;
+    return ci.z + (k - g0);
 }
 
 // is plane k a CV plane of instance inst
@@ -127,6 +146,12 @@ struct ebs_ctx {
     int32_t* d_gcol = nullptr;
     int4* d_col = nullptr;
     int32_t G = 0;
+    int32_t Ge = 0;                  // cells of the extended face range
+    int32_t* d_gcole = nullptr;      // [Ge]
+    uint32_t* d_fflag = nullptr;     // [G]
+    int32_t* d_cbase = nullptr;      // [G] first cut-face record of each general cell
+    void* d_crec = nullptr;          // cut-face interpolation records (stage.hip)
+    int32_t ncut = 0;
     double* d_geo = nullptr;
     int8_t* d_type = nullptr;
     uint32_t* d_type4 = nullptr;
@@ -155,7 +180,7 @@ struct ebs_ctx {
     double* d_qhat = nullptr;  // [5][G]
     double* d_sig = nullptr;   // [5][3][G]
     double* d_prim = nullptr;  // [G][4] advected quantities of the general range
-    double* d_fh = nullptr;    // [5][3][G] provisional lower-face fluxes
+    double* d_fh = nullptr;    // [5][3][Ge] provisional lower-face fluxes (extended range)
 
     // regular-region tiles
     int tile_x = 32, tile_y = 8, tile_z = 64;
@@ -184,6 +209,7 @@ ebs_status build_geometry(ebs_ctx* c, const double* d_h);
 ebs_status launch_advance(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uhat,
                           double cdt);
 ebs_status build_tiles(ebs_ctx* c);
+ebs_status build_cut_faces(ebs_ctx* c);
 size_t bulk_lds_bytes(int tx, int ty, int precision);
 // redistribution (wsrd.hip)
 ebs_status wsrd_setup(ebs_ctx* c);

@@ -421,13 +421,26 @@ __device__ inline void put(const RecArgs& r, int inst, int q, int g, double v) {
     r.geo[((size_t)inst * GQ_N + q) * r.G + g] = v;
 }
 
-// the four instance types of each general cell in one word (byte s = instance s)
-__global__ void k_pack_types(const int8_t* type, uint32_t* type4, int32_t G) {
+// Per general cell: the four instance types in one word (byte s = instance s)
+// and the lower-face flags (area fraction > 0, area fraction == 1) of every
+// instance and direction; planes without CVs of an instance have no faces.
+__global__ void k_pack_types(RecArgs r, uint32_t* type4, uint32_t* fflag, const int4* col) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= G) return;
-    uint32_t w = 0;
-    for (int s = 0; s < NINST; ++s) w |= (uint32_t)(uint8_t)type[(size_t)s * G + g] << (8 * s);
+    if (g >= r.G) return;
+    const int c = r.gcol[g];
+    const int k = col_g0(col[c]) + (g - col[c].z);
+    uint32_t w = 0, f = 0;
+    for (int s = 0; s < NINST; ++s) {
+        w |= (uint32_t)(uint8_t)r.type[(size_t)s * r.G + g] << (8 * s);
+        const bool plane = s == 3 ? (k >= 1 && k <= r.a.nz - 1) : (k >= 0 && k <= r.a.nz - 1);
+        for (int d = 0; d < 3; ++d) {
+            const double b = plane ? r.geo[((size_t)s * GQ_N + GQ_BX + d) * r.G + g] : 0.0;
+            if (b > 0.0) f |= ff_pos(s, d);
+            if (b == 1.0) f |= ff_full(s, d);
+        }
+    }
     type4[g] = w;
+    fflag[g] = f;
 }
 
 __global__ void k_records(RecArgs r) {
@@ -544,6 +557,27 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
         for (int k = cx->h_g0[c]; k < cx->h_g1[c]; ++k) gcol[cx->h_goff[c] + (k - cx->h_g0[c])] = c;
     cx->G = (int32_t)G;
     const size_t Gs = (size_t)std::max<int64_t>(G, 1);
+    // extended face range: the lower faces of every CV whose face bounds a
+    // general CV from above (+x, +y neighbours and the cell above the range)
+    std::vector<int32_t> g1e(ncol), goffe(ncol);
+    int64_t Ge = 0;
+    for (int c = 0; c < ncol; ++c) {
+        const int i = c % cx->nx, j = c / cx->nx;
+        const int cxm = j * cx->nx + (i == 0 ? cx->nx - 1 : i - 1);
+        const int cym = (j == 0 ? cx->ny - 1 : j - 1) * cx->nx + i;
+        g1e[c] = std::min(cx->nz, std::max(cx->h_g1[c] + 1, std::max(cx->h_g1[cxm], cx->h_g1[cym])));
+        goffe[c] = (int32_t)Ge;
+        Ge += g1e[c] - cx->h_g0[c];
+    }
+    if (Ge > INT32_MAX / 16) {
+        cx->err = "general region too large";
+        return EBS_E_UNSUPPORTED;
+    }
+    std::vector<int32_t> gcole((size_t)std::max<int64_t>(Ge, 1));
+    for (int c = 0; c < ncol; ++c)
+        for (int k = cx->h_g0[c]; k < g1e[c]; ++k) gcole[goffe[c] + (k - cx->h_g0[c])] = c;
+    cx->Ge = (int32_t)Ge;
+    const size_t Ges = (size_t)std::max<int64_t>(Ge, 1);
     auto alloc = [&](void** p, size_t bytes) -> bool {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
@@ -565,7 +599,9 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
     ok &= alloc((void**)&cx->d_qhat, sizeof(double) * 5 * Gs);
     ok &= alloc((void**)&cx->d_sig, sizeof(double) * 15 * Gs);
     ok &= alloc((void**)&cx->d_prim, sizeof(double) * 4 * Gs);
-    ok &= alloc((void**)&cx->d_fh, sizeof(double) * 15 * Gs);
+    ok &= alloc((void**)&cx->d_fh, sizeof(double) * 15 * Ges);
+    ok &= alloc((void**)&cx->d_gcole, sizeof(int32_t) * Ges);
+    ok &= alloc((void**)&cx->d_fflag, sizeof(uint32_t) * Gs);
     ok &= alloc((void**)&cx->d_type4, sizeof(uint32_t) * Gs);
     if (!ok) {
         cx->err = "device allocation of geometry tables failed";
@@ -576,7 +612,9 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
     EBS_HIP(cx, hipMemcpyAsync(cx->d_gcol, gcol.data(), sizeof(int32_t) * Gs, hipMemcpyHostToDevice,
                                cx->stream));
     std::vector<int4> colinfo(ncol);
-    for (int c = 0; c < ncol; ++c) colinfo[c] = make_int4(cx->h_g0[c], cx->h_g1[c], cx->h_goff[c], 0);
+    for (int c = 0; c < ncol; ++c) colinfo[c] = col_pack(cx->h_g0[c], cx->h_g1[c], g1e[c], cx->h_goff[c], goffe[c]);
+    EBS_HIP(cx, hipMemcpyAsync(cx->d_gcole, gcole.data(), sizeof(int32_t) * Ges, hipMemcpyHostToDevice,
+                               cx->stream));
     EBS_HIP(cx, hipMemcpyAsync(cx->d_col, colinfo.data(), sizeof(int4) * ncol, hipMemcpyHostToDevice,
                                cx->stream));
     EBS_HIP(cx, hipMemsetAsync(cx->d_uhat, 0, sizeof(double) * 5 * Gs, cx->stream));
@@ -589,8 +627,8 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
         r.geo = cx->d_geo;
         r.type = cx->d_type;
         hipLaunchKernelGGL(k_records, dim3((G + 127) / 128, NINST), dim3(128), 0, cx->stream, r);
-        hipLaunchKernelGGL(k_pack_types, dim3((G + 255) / 256), dim3(256), 0, cx->stream, cx->d_type,
-                           cx->d_type4, cx->G);
+        hipLaunchKernelGGL(k_pack_types, dim3((G + 255) / 256), dim3(256), 0, cx->stream, r, cx->d_type4,
+                           cx->d_fflag, cx->d_col);
         EBS_HIP(cx, hipGetLastError());
     }
     EBS_HIP(cx, hipStreamSynchronize(cx->stream));

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "ebs_internal.h"
 
@@ -428,10 +429,25 @@ struct GenArgs {
     T* out[5];
     double* uhat;  // [5][G]
     double* prim;  // [G][4] theta, u, v, w
-    double* fh;    // [5][3][G] provisional flux on the lower faces
+    double* fh;    // [5][3][Ge] provisional flux on the lower faces
+    const int32_t* cbase;  // [G] first cut-face record of each general cell
+    const struct CutRec* crec;
     double cdt;
     double rdel[3];
     int eb_mode;
+};
+
+// Interpolation of the flux on one cut face (area fraction b in (0, 1), or not
+// exactly 1) to its centroid, fixed by the geometry: area fraction x flux =
+// b (c[0] F(own face) + sum_q c[q+1] F(face n[q])) over the lower faces of the
+// same direction at the neighbouring CVs n[q] (indices into the extended face
+// range, -1 when unused), summed in that order.  A cell's records are
+// consecutive, in the order of (instance, direction) of its partial faces.
+struct CutRec {
+    int32_t n[3];
+    int32_t pad;
+    double b;
+    double c[4];
 };
 
 // bit s set <=> plane k holds CVs of instance s
@@ -441,9 +457,11 @@ __device__ inline int plane_mask(int nz, int k) {
 __device__ inline int finst(int f) { return f < 2 ? 0 : f - 1; }
 
 // a resolved stencil position: wrapped (i, j), plane k, general index (>= 0)
-// or -1 above / -2 below the column's range, fluid bits per instance
+// or -1 above / -2 below the column's range, index in the extended face range
+// (-1 beyond it), fluid bits per instance, lower-face flags (when loaded)
 struct Pt {
-    int i, j, k, g, fl;
+    int i, j, k, g, ge, fl;
+    uint32_t ff;
 };
 
 template <typename T>
@@ -454,12 +472,33 @@ struct Gen {
     __device__ __forceinline__ int wx(int i) const { return wrapi(i, a.D.nx); }
     __device__ __forceinline__ int wy(int j) const { return wrapi(j, a.D.ny); }
     __device__ __forceinline__ int4 colinfo(int i, int j) const { return a.v.col[j * a.D.nx + i]; }
-    __device__ __forceinline__ Pt at(int i, int j, int k, const int4& ci) const {
+    // position without fluid bits (face data only)
+    __device__ __forceinline__ Pt atf(int i, int j, int k, const int4& ci) const {
         Pt p;
         p.i = i;
         p.j = j;
         p.k = k;
-        p.g = k < ci.x ? -2 : (k >= ci.y ? -1 : ci.z + (k - ci.x));
+        const int g0 = col_g0(ci);
+        p.g = k < g0 ? -2 : (k >= col_g1(ci) ? -1 : ci.z + (k - g0));
+        p.ge = k < g0 ? -2 : (k >= ci.y ? -1 : ci.w + (k - g0));
+        p.fl = 0;
+        p.ff = 0;
+        return p;
+    }
+    // lower-face flags of a position (general: stored; above the range: full
+    // faces on the planes that hold CVs; below: none)
+    __device__ __forceinline__ uint32_t fflags(const Pt& p) const {
+        if (p.g >= 0) return a.v.fflag[p.g];
+        if (p.g == -2) return 0u;
+        const int pm = plane_mask(a.D.nz, p.k);
+        uint32_t f = 0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if ((pm >> s) & 1) f |= (ff_pos(s, 0) | ff_pos(s, 1) | ff_pos(s, 2)) * 0x10001u;
+        return f;
+    }
+    __device__ __forceinline__ Pt at(int i, int j, int k, const int4& ci) const {
+        Pt p = atf(i, j, k, ci);
         int fl = p.g == -1 ? 0xF : 0;
         if (p.g >= 0) {
             const uint32_t t4 = a.v.type4[p.g];
@@ -558,7 +597,7 @@ struct Gen {
     // or above it
     template <int F, int D>
     __device__ __forceinline__ double fhat_any(const Pt& P) const {
-        if (P.g >= 0) return a.fh[((size_t)F * 3 + D) * a.v.G + P.g];
+        if (P.ge >= 0) return a.fh[((size_t)F * 3 + D) * a.v.Ge + P.ge];
         return fhat_at<F, D>(P);
     }
     // area fraction of the lower D-face of the CV of instance S at P
@@ -571,44 +610,75 @@ struct Gen {
         return geo(S, GQ_BX + D, P.g);
     }
     // area fraction x flux on the lower D-face of the CV at P, the flux moved
-    // to the face centroid when the face is cut
+    // to the face centroid when the face is cut (precomputed record)
     template <int F, int D>
     __device__ __forceinline__ double bface(const Pt& P) const {
         constexpr int s = F < 2 ? 0 : F - 1;
-        const double b = beta<s, D>(P);
-        if (!(b > 0.0)) return 0.0;
         if (P.k == a.D.nz) return 0.0;  // top wall: zero flux
+        if (!(P.ff & ff_pos(s, D))) return 0.0;
         const double F0 = fhat_any<F, D>(P);
-        if (!(b < 1.0) || P.g < 0) return b * F0;
+        if (P.ff & ff_full(s, D)) return F0;
+        const uint32_t part = (P.ff & 0xFFFu) & ~(P.ff >> 16);
+        const CutRec& r = a.crec[a.cbase[P.g] + __popc(part & (ff_pos(s, D) - 1u))];
+        const double* fhd = a.fh + ((size_t)F * 3 + D) * a.v.Ge;
+        double Fv = r.c[0] * F0;
+        if (r.n[0] >= 0) Fv += r.c[1] * fhd[r.n[0]];
+        if (r.n[1] >= 0) Fv += r.c[2] * fhd[r.n[1]];
+        if (r.n[2] >= 0) Fv += r.c[3] * fhd[r.n[2]];
+        return r.b * Fv;
+    }
+    // area fraction with a runtime instance (set-up only)
+    template <int D>
+    __device__ double beta_rt(int s, const Pt& P) const {
+        if (P.k == a.D.nz) return D == 2 ? 1.0 : 0.0;
+        if (!((plane_mask(a.D.nz, P.k) >> s) & 1)) return 0.0;
+        if (P.g == -2) return 0.0;
+        if (P.g == -1) return 1.0;
+        return geo(s, GQ_BX + D, P.g);
+    }
+    // Builds the record of the partial lower D-face of instance s at the general
+    // CV P: neighbours chosen by the signs of the face-centroid offsets (first
+    // tangential axis y for x-faces and x otherwise, second y for z-faces and z
+    // otherwise), weights from their magnitudes, all-or-nothing when a
+    // neighbour face has no fluid or lies beyond a wall.  Returns false if a
+    // neighbour face lies outside the stored face range.
+    template <int D>
+    __device__ bool cut_record(int s, const Pt& P, CutRec& r) const {
+        const double b = geo(s, GQ_BX + D, P.g);
+        r.n[0] = r.n[1] = r.n[2] = -1;
+        r.pad = 0;
+        r.b = b;
+        r.c[0] = 1.0;
+        r.c[1] = r.c[2] = r.c[3] = 0.0;
+        if (!(b < 1.0)) return true;
         const double g1 = geo(s, GQ_FX1 + 2 * D, P.g), g2 = geo(s, GQ_FX1 + 2 * D + 1, P.g);
         const int s1 = g1 > 0.0 ? 1 : (g1 < 0.0 ? -1 : 0);
         const int s2 = g2 > 0.0 ? 1 : (g2 < 0.0 ? -1 : 0);
-        if (s1 == 0 && s2 == 0) return b * F0;
-        // tangential steps: the first tangential axis is y for x-faces and x
-        // otherwise; the second is y for z-faces and z otherwise
+        if (s1 == 0 && s2 == 0) return true;
         const int ax = D == 0 ? 0 : s1, ay = D == 0 ? s1 : 0;
         const int by = D == 2 ? s2 : 0, bz = D == 2 ? 0 : s2;
         const bool u1 = s1 != 0, u2 = s2 != 0, u12 = u1 && u2;
-        if (u2 && bz != 0 && !((plane_mask(a.D.nz, P.k + bz) >> s) & 1)) return b * F0;
+        if (u2 && bz != 0 && !((plane_mask(a.D.nz, P.k + bz) >> s) & 1)) return true;
         Pt N1, N2, N12;
         if (u1) {
             N1 = at(wx(P.i + ax), wy(P.j + ay), P.k);
-            if (!(beta<s, D>(N1) > 0.0)) return b * F0;
+            if (!(beta_rt<D>(s, N1) > 0.0)) return true;
         }
         if (u2) {
             N2 = at(P.i, wy(P.j + by), P.k + bz);
-            if (!(beta<s, D>(N2) > 0.0)) return b * F0;
+            if (!(beta_rt<D>(s, N2) > 0.0)) return true;
         }
         if (u12) {
             N12 = at(wx(P.i + ax), wy(P.j + ay + by), P.k + bz);
-            if (!(beta<s, D>(N12) > 0.0)) return b * F0;
+            if (!(beta_rt<D>(s, N12) > 0.0)) return true;
         }
         const double w1 = fabs(g1), w2 = fabs(g2);
-        double Fv = (1.0 - w1) * (1.0 - w2) * F0;
-        if (u1) Fv += w1 * (1.0 - w2) * fhat_any<F, D>(N1);
-        if (u2) Fv += (1.0 - w1) * w2 * fhat_any<F, D>(N2);
-        if (u12) Fv += w1 * w2 * fhat_any<F, D>(N12);
-        return b * Fv;
+        r.c[0] = (1.0 - w1) * (1.0 - w2);
+        bool ok = true;
+        if (u1) { r.n[0] = N1.ge; r.c[1] = w1 * (1.0 - w2); ok &= N1.ge >= 0; }
+        if (u2) { r.n[1] = N2.ge; r.c[2] = (1.0 - w1) * w2; ok &= N2.ge >= 0; }
+        if (u12) { r.n[2] = N12.ge; r.c[3] = w1 * w2; ok &= N12.ge >= 0; }
+        return ok;
     }
     // divergence term of field F at the CV P (upper neighbours Ux, Uy, Uz)
     template <int F, int D>
@@ -620,7 +690,7 @@ struct Gen {
             const double blo = beta<s, D>(P), bhi = beta<s, D>(U);
             double sm = 0.0;
             int cnt = 0;
-            if (blo > 0.0) { sm += a.fh[((size_t)F * 3 + D) * a.v.G + g]; ++cnt; }
+            if (blo > 0.0) { sm += fhat_any<F, D>(P); ++cnt; }
             if (bhi > 0.0) { sm += U.k == a.D.nz ? 0.0 : fhat_any<F, D>(U); ++cnt; }
             const double fb = cnt ? sm / cnt : 0.0;
             br -= geo(s, GQ_AX + D, g) * fb * rd;
@@ -656,7 +726,7 @@ struct Gen {
             LL = at(P.i, P.j, P.k - 2, ci);
             RR = at(P.i, P.j, P.k + 1, ci);
         }
-        const size_t G = a.v.G;
+        const size_t G = a.v.Ge;
         a.fh[(0 * 3 + D) * G + g] = beta<0, D>(P) > 0.0 ? fhat<0, D>(LL, L, P, RR, P) : 0.0;
         a.fh[(1 * 3 + D) * G + g] = beta<0, D>(P) > 0.0 ? fhat<1, D>(LL, L, P, RR, P) : 0.0;
         a.fh[(2 * 3 + D) * G + g] = beta<1, D>(P) > 0.0 ? fhat<2, D>(LL, L, P, RR, Lx) : 0.0;
@@ -670,7 +740,15 @@ __device__ inline void gen_cell(const GeoView& v, int g, int& i, int& j, int& k,
     ci = v.col[c];
     i = c % v.nx;
     j = c / v.nx;
-    k = ci.x + (g - ci.z);
+    k = col_g0(ci) + (g - ci.z);
+}
+// cell of the extended face range
+__device__ inline void face_cell(const GeoView& v, int e, int& i, int& j, int& k, int4& ci) {
+    const int c = v.gcole[e];
+    ci = v.col[c];
+    i = c % v.nx;
+    j = c / v.nx;
+    k = col_g0(ci) + (e - ci.w);
 }
 
 template <typename T>
@@ -694,12 +772,12 @@ __global__ void __launch_bounds__(256) k_gen_prims(GenArgs<T> a) {
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_gen_fhat(GenArgs<T> a) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.v.G) return;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;  // extended face range
+    if (g >= a.v.Ge) return;
     const Gen<T> G(a);
     int i, j, k;
     int4 ci;
-    gen_cell(a.v, g, i, j, k, ci);
+    face_cell(a.v, g, i, j, k, ci);
     const Pt P = G.at(i, j, k, ci);
     // positions below P along x, y, z (the staggering neighbours of instances 1-3)
     const Pt Lx = G.at(G.wx(i - 1), j, k), Ly = G.at(i, G.wy(j - 1), k), Lz = G.at(i, j, k - 1, ci);
@@ -716,9 +794,14 @@ __global__ void __launch_bounds__(256) k_gen_update(GenArgs<T> a) {
     int i, j, k;
     int4 ci;
     gen_cell(a.v, g, i, j, k, ci);
-    const Pt P = G.at(i, j, k, ci);
+    Pt P = G.at(i, j, k, ci);
+    P.ff = G.fflags(P);
     // the upper neighbours: their lower faces are this CV's upper faces
-    const Pt Ux = G.at(G.wx(i + 1), j, k), Uy = G.at(i, G.wy(j + 1), k), Uz = G.at(i, j, k + 1, ci);
+    const int ip = G.wx(i + 1), jp = G.wy(j + 1);
+    Pt Ux = G.atf(ip, j, k, G.colinfo(ip, j)), Uy = G.atf(i, jp, k, G.colinfo(i, jp)), Uz = G.atf(i, j, k + 1, ci);
+    Ux.ff = G.fflags(Ux);
+    Uy.ff = G.fflags(Uy);
+    Uz.ff = G.fflags(Uz);
     G.template update<0>(P, Ux, Uy, Uz, g);
     G.template update<1>(P, Ux, Uy, Uz, g);
     G.template update<2>(P, Ux, Uy, Uz, g);
@@ -726,9 +809,95 @@ __global__ void __launch_bounds__(256) k_gen_update(GenArgs<T> a) {
     G.template update<4>(P, Ux, Uy, Uz, g);
 }
 
+// number of partial lower faces (area fraction > 0 and not exactly 1) per general cell
+__global__ void __launch_bounds__(256) k_cut_count(GeoView v, int32_t* cnt) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= v.G) return;
+    const uint32_t ff = v.fflag[g];
+    cnt[g] = __popc((ff & 0xFFFu) & ~(ff >> 16));
+}
+
+__global__ void __launch_bounds__(128) k_cut_fill(GenArgs<double> a, CutRec* rec, int32_t* bad) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.v.G) return;
+    const Gen<double> G(a);
+    int i, j, k;
+    int4 ci;
+    gen_cell(a.v, g, i, j, k, ci);
+    const Pt P = G.at(i, j, k, ci);
+    const uint32_t ff = a.v.fflag[g];
+    const uint32_t part = (ff & 0xFFFu) & ~(ff >> 16);
+    int r = a.cbase[g];
+    bool ok = true;
+    for (int s = 0; s < 4; ++s) {
+        if (part & ff_pos(s, 0)) ok &= G.template cut_record<0>(s, P, rec[r++]);
+        if (part & ff_pos(s, 1)) ok &= G.template cut_record<1>(s, P, rec[r++]);
+        if (part & ff_pos(s, 2)) ok &= G.template cut_record<2>(s, P, rec[r++]);
+    }
+    if (!ok) atomicAdd(bad, 1);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- host side
+ebs_status build_cut_faces(ebs_ctx* cx) {
+    const int32_t G = cx->G;
+    if (cx->d_cbase) (void)hipFree(cx->d_cbase);
+    if (cx->d_crec) (void)hipFree(cx->d_crec);
+    cx->d_cbase = nullptr;
+    cx->d_crec = nullptr;
+    cx->ncut = 0;
+    if (G == 0) return EBS_OK;
+    int32_t* d_bad = nullptr;
+    if (hipMalloc(&cx->d_cbase, sizeof(int32_t) * G) != hipSuccess ||
+        hipMalloc(&d_bad, sizeof(int32_t)) != hipSuccess) {
+        if (d_bad) (void)hipFree(d_bad);
+        cx->err = "cut-face table allocation failed";
+        return EBS_E_OOM;
+    }
+    const GeoView v = geo_view(cx);
+    hipLaunchKernelGGL(k_cut_count, dim3((G + 255) / 256), dim3(256), 0, cx->stream, v, cx->d_cbase);
+    EBS_HIP(cx, hipGetLastError());
+    std::vector<int32_t> cnt(G);
+    EBS_HIP(cx, hipMemcpyAsync(cnt.data(), cx->d_cbase, sizeof(int32_t) * G, hipMemcpyDeviceToHost, cx->stream));
+    EBS_HIP(cx, hipStreamSynchronize(cx->stream));
+    int64_t tot = 0;
+    for (int32_t g = 0; g < G; ++g) {
+        const int32_t n = cnt[g];
+        cnt[g] = (int32_t)tot;
+        tot += n;
+    }
+    if (tot > INT32_MAX / 2) {
+        (void)hipFree(d_bad);
+        cx->err = "too many cut faces";
+        return EBS_E_UNSUPPORTED;
+    }
+    cx->ncut = (int32_t)tot;
+    if (hipMalloc(&cx->d_crec, sizeof(CutRec) * std::max<int64_t>(tot, 1)) != hipSuccess) {
+        (void)hipFree(d_bad);
+        cx->err = "cut-face table allocation failed";
+        return EBS_E_OOM;
+    }
+    EBS_HIP(cx, hipMemcpyAsync(cx->d_cbase, cnt.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, cx->stream));
+    EBS_HIP(cx, hipMemsetAsync(d_bad, 0, sizeof(int32_t), cx->stream));
+    GenArgs<double> a{};
+    a.D = Dims{cx->nx, cx->ny, cx->nz};
+    a.v = v;
+    a.cbase = cx->d_cbase;
+    hipLaunchKernelGGL(k_cut_fill, dim3((G + 127) / 128), dim3(128), 0, cx->stream, a, (CutRec*)cx->d_crec,
+                       d_bad);
+    EBS_HIP(cx, hipGetLastError());
+    int32_t bad = 0;
+    EBS_HIP(cx, hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, cx->stream));
+    EBS_HIP(cx, hipStreamSynchronize(cx->stream));
+    (void)hipFree(d_bad);
+    if (bad != 0) {
+        cx->err = "a cut-face interpolation neighbour lies outside the stored face range";
+        return EBS_E_UNSUPPORTED;
+    }
+    return EBS_OK;
+}
+
 size_t bulk_lds_bytes(int tx, int ty, int precision) {
     return (precision == EBS_F32_BULK ? 4 : 8) * (size_t)L_COUNT * (tx + 5) * (ty + 5);
 }
@@ -854,14 +1023,16 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
         a.uhat = cx->d_uhat;
         a.prim = cx->d_prim;
         a.fh = cx->d_fh;
+        a.cbase = cx->d_cbase;
+        a.crec = (const CutRec*)cx->d_crec;
         a.cdt = cdt;
         for (int d = 0; d < 3; ++d) a.rdel[d] = 1.0 / cx->g.dx[d];
         a.eb_mode = cx->g.eb_flux;
-        const dim3 grid((cx->G + 255) / 256), blk(256);
+        const dim3 grid((cx->G + 255) / 256), gride((cx->Ge + 255) / 256), blk(256);
         // the first two passes only read the input state; the update writes
         // the output (which may alias U^n, never U_cur)
         hipLaunchKernelGGL(k_gen_prims<T>, grid, blk, 0, cx->stream, a);
-        hipLaunchKernelGGL(k_gen_fhat<T>, grid, blk, 0, cx->stream, a);
+        hipLaunchKernelGGL(k_gen_fhat<T>, gride, blk, 0, cx->stream, a);
         hipLaunchKernelGGL(k_gen_update<T>, grid, blk, 0, cx->stream, a);
         EBS_HIP(cx, hipGetLastError());
     }

@@ -75,7 +75,7 @@ __device__ inline void cell_of(const GeoView& v, int g, int& i, int& j, int& k) 
     const int4 ci = v.col[c];
     i = c % v.nx;
     j = c / v.nx;
-    k = ci.x + (g - ci.z);
+    k = col_g0(ci) + (g - ci.z);
 }
 
 __global__ void k_merge(WArgs a) {
