@@ -126,7 +126,9 @@ enum {
 /* Create a context.  grid is copied.  boxes may be NULL (one box = the
  * domain).  hip_stream is a hipStream_t (NULL = the null stream); all work of
  * the context is enqueued on it.  Errors: EBS_E_ARG (bad sizes, boxes that do
- * not tile the domain), EBS_E_UNSUPPORTED (non-periodic x or y), EBS_E_OOM. */
+ * not tile the domain), EBS_E_UNSUPPORTED (non-periodic x or y, more than 2^31
+ * cells, or (nx+1)(ny+1)(nz+1) elements of the state type reaching 4 GiB),
+ * EBS_E_OOM. */
 ebs_status ebs_create(const ebs_grid* grid, const ebs_box* boxes, int32_t nbox, void* hip_stream,
                       ebs_ctx** out);
 
@@ -176,12 +178,14 @@ ebs_status ebs_conserved_sums(ebs_ctx* ctx, const ebs_state* U, double hi[5], do
  * Synchronous; scratch states are allocated and freed internally. */
 ebs_status ebs_autotune(ebs_ctx* ctx, const char* cache_json_path);
 
-/* Tile shape (columns per block) of the regular-region kernel: tx in
+/* Tile shape of the regular-region kernel: tx x ty columns per block and at
+ * most tz planes per tile (a tile never crosses a box boundary).  tx in
  * {16, 32, 64}, ty in {2, 4, 8, 16}, tx*ty in [64, 256], (tx+5)(ty+5) <=
- * 4 tx ty, and its LDS rings within 64 KiB (26 (tx+5)(ty+5) elements of the
- * state type).  EBS_E_ARG otherwise. */
-ebs_status ebs_set_tile(ebs_ctx* ctx, int32_t tx, int32_t ty);
-ebs_status ebs_get_tile(const ebs_ctx* ctx, int32_t* tx, int32_t* ty);
+ * 4 tx ty, LDS rings within 64 KiB (26 (tx+5)(ty+5) elements of the state
+ * type); tz in {16, 32, 64}, or 0 to keep the current value.  EBS_E_ARG
+ * otherwise. */
+ebs_status ebs_set_tile(ebs_ctx* ctx, int32_t tx, int32_t ty, int32_t tz);
+ebs_status ebs_get_tile(const ebs_ctx* ctx, int32_t* tx, int32_t* ty, int32_t* tz);
 
 /* Kernel timing: when enabled, every launch of the regular-region stage
  * kernel is bracketed by HIP events on the context stream; read returns the

@@ -76,8 +76,8 @@ def load(path: str = LIB_PATH):
         "ebs_rk3_step": [C.c_void_p, P(State), P(State), C.c_double, C.c_int32],
         "ebs_conserved_sums": [C.c_void_p, P(State), P(C.c_double), P(C.c_double)],
         "ebs_autotune": [C.c_void_p, C.c_char_p],
-        "ebs_set_tile": [C.c_void_p, C.c_int32, C.c_int32],
-        "ebs_get_tile": [C.c_void_p, P(C.c_int32), P(C.c_int32)],
+        "ebs_set_tile": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32],
+        "ebs_get_tile": [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)],
         "ebs_timing_enable": [C.c_void_p, C.c_int32],
         "ebs_timing_read": [C.c_void_p, P(C.c_double), P(C.c_int64)],
         "ebs_algorithmic_bytes": [C.c_void_p, P(C.c_double)],
@@ -221,13 +221,14 @@ class Context:
         self._check(self.lib.ebs_autotune(self.h, p), "ebs_autotune")
         return self.get_tile()
 
-    def set_tile(self, tx: int, ty: int):
-        self._check(self.lib.ebs_set_tile(self.h, int(tx), int(ty)), "ebs_set_tile")
+    def set_tile(self, tx: int, ty: int, tz: int = 0):
+        """Tile of the regular-region kernel: tx x ty columns, tz planes (0 keeps it)."""
+        self._check(self.lib.ebs_set_tile(self.h, int(tx), int(ty), int(tz)), "ebs_set_tile")
 
     def get_tile(self):
-        tx, ty = C.c_int32(), C.c_int32()
-        self._check(self.lib.ebs_get_tile(self.h, C.byref(tx), C.byref(ty)), "ebs_get_tile")
-        return tx.value, ty.value
+        tx, ty, tz = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.lib.ebs_get_tile(self.h, C.byref(tx), C.byref(ty), C.byref(tz)), "ebs_get_tile")
+        return tx.value, ty.value, tz.value
 
     def timing(self, enable: bool):
         self._check(self.lib.ebs_timing_enable(self.h, int(enable)), "ebs_timing_enable")

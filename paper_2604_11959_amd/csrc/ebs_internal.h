@@ -174,6 +174,12 @@ struct ebs_ctx {
     double* d_lsq_c = nullptr;        // [pts][3] A^-1 e_s in mesh units
     double* d_lsq_ev = nullptr;       // [nlsq][8][3] limiter evaluation offsets
     int8_t* d_lsq_nev = nullptr;      // [nlsq]
+    int32_t abase[4] = {0, 0, 0, 0};  // offset of each instance in the concatenated active list
+    int32_t* d_wl_off = nullptr;      // [A + 1] contributors of each active CV (CSR)
+    int32_t* d_wl_idx = nullptr;      // [E] general index of the contributing small CV
+    double* d_wl_geo = nullptr;       // [E][4] kappa_r and the centroid offset
+    double* d_wl_self = nullptr;      // [A][5] omega, N and the own centroid offset
+    int8_t* d_wl_small = nullptr;     // [A]
 
     // per-stage buffers (cut region, double)
     double* d_uhat = nullptr;  // [5][G] provisional state of the last advance

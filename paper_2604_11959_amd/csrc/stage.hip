@@ -141,13 +141,15 @@ __device__ __forceinline__ T upw6(T m, T pLL, T pL, T pR, T pRR, bool okLL, bool
     return ok ? (T(5) * a + T(2) * b - e) : T(3) * (a + b);
 }
 
+// element access with a 32-bit byte offset (every field is below 4 GiB; the
+// context checks it), so the address is a scalar base plus a vector offset
 template <typename T>
 __device__ __forceinline__ T ld(const T* __restrict__ base, uint32_t off) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (size_t)off * sizeof(T));
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(off * (uint32_t)sizeof(T)));
 }
 template <typename T>
 __device__ __forceinline__ void st(T* base, uint32_t off, T v) {
-    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (size_t)off * sizeof(T)) = v;
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(off * (uint32_t)sizeof(T))) = v;
 }
 
 template <typename T, int TX, int TY>
@@ -189,8 +191,8 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
     // one z-iteration ahead (fetch) and written to LDS at the top of the next
     // iteration (commit), so the global-load latency overlaps a whole plane of
     // arithmetic.  rth keeps rho*theta of the committed plane for make_prims.
-    T pf[NPTS][5], rth[NPTS];
-    auto fetch = [&](int p) {
+    T pfA[NPTS][5], pfB[NPTS][5], rth[NPTS];
+    auto fetch = [&](int p, T (&pf)[NPTS][5]) {
         const bool in = p < nz;  // block uniform
         const uint32_t oc0 = (uint32_t)p * pc, ou0 = (uint32_t)p * pu;
 #pragma unroll
@@ -209,7 +211,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             }
         }
     };
-    auto commit = [&](int p) {
+    auto commit = [&](int p, const T (&pf)[NPTS][5]) {
         T* RHO = sm + (L_RHO + (p & 1)) * WS;
         T* RU = sm + (L_RU + (p & 3)) * WS;
         T* RV = sm + (L_RV + (p & 3)) * WS;
@@ -259,22 +261,23 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
     T m2[4], m1[4];
     prims_direct<T>(a, c0, u0, dxm, dym * nx, k0 - 2, pc, pu, pv, m2);
     prims_direct<T>(a, c0, u0, dxm, dym * nx, k0 - 1, pc, pu, pv, m1);
-    fetch(k0 - 1);
-    commit(k0 - 1);
-    fetch(k0);
-    commit(k0);
-    fetch(k0 + 1);
+    // Raw planes run two z-iterations ahead in two register sets (pfA, pfB,
+    // alternating), the own-cell Un values likewise (unA, unB).
+    fetch(k0 - 1, pfA);
+    commit(k0 - 1, pfA);
+    fetch(k0, pfA);
+    commit(k0, pfA);
+    fetch(k0 + 1, pfA);
     __syncthreads();
     make_prims(k0);
     __syncthreads();  // the density slot of plane k0 - 1 is reused by plane k0 + 1
-    commit(k0 + 1);
-    fetch(k0 + 2);
+    commit(k0 + 1, pfA);
+    fetch(k0 + 2, pfA);
+    fetch(k0 + 3, pfB);
     __syncthreads();
     make_prims(k0 + 1);
     __syncthreads();  // the density slot of plane k0 is reused by plane k0 + 2
-    // own-cell values of Un for the next plane (prefetched like the rings)
     const uint32_t ov0 = (uint32_t)(j * nx + i);
-    T unc[5];
     auto fetch_un = [&](int kk, T (&dst)[5]) {
         if (act && kk < z1 && kk >= ge) {
             dst[0] = ld(a.un[0], (uint32_t)kk * pc + c0);
@@ -287,13 +290,16 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             for (int f = 0; f < 5; ++f) dst[f] = T(0);
         }
     };
-    fetch_un(k0, unc);
+    T unA[5], unB[5];
+    T fzc[4] = {T(0), T(0), T(0), T(0)};  // upper z-face flux terms of the last plane
+    fetch_un(k0, unA);
+    fetch_un(k0 + 1, unB);
     const T sixth = T(1) / T(6);
-    for (int k = k0; k < z1; ++k) {
-        commit(k + 2);
-        fetch(k + 3);
-        T unn[5];
-        fetch_un(k + 1, unn);
+    // one z-iteration: plane k is updated; rp holds raw plane k + 2 on entry and
+    // plane k + 4 on exit, uc the Un values of plane k on entry and k + 2 on exit
+    auto step = [&](int k, T (&rp)[NPTS][5], T (&uc)[5]) __attribute__((always_inline)) {
+        commit(k + 2, rp);
+        fetch(k + 4, rp);
         __syncthreads();
         make_prims(k + 2);
         __syncthreads();
@@ -331,6 +337,20 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             const T rv_j = RVk[0], rv_jp = RVk[WX], rv_jm = RVk[-WX];
             const T rw_k = RWk[0], rw_kp = top ? T(0) : RWp[0];
             const T h = T(0.5);
+            // lower z-face flux terms: carried from the upper faces of plane k - 1
+            // when this thread updated it (same values, same arithmetic)
+            T zl[4];
+            if (k > k0 && k - 1 >= ge) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) zl[q] = fzc[q];
+            } else {
+                zl[0] = rw_k * upw6<T>(rw_k, zc[0][0], zc[0][1], zc[0][2], zc[0][3], true, okR1);
+                const T m1l = h * (RWk[-1] + rw_k), m2l = h * (RWk[-WX] + rw_k);
+                const T m3l = (k != 1) ? h * (RWm[0] + rw_k) : T(0);
+                zl[1] = m1l * upw6<T>(m1l, zc[1][0], zc[1][1], zc[1][2], zc[1][3], true, okR1);
+                zl[2] = m2l * upw6<T>(m2l, zc[2][0], zc[2][1], zc[2][2], zc[2][3], true, okR1);
+                zl[3] = m3l * upw6<T>(m3l, zc[3][0], zc[3][1], zc[3][2], zc[3][3], k - 2 >= 1, okR1);
+            }
             // ---- cell-centred instance
             {
                 const T ex = ru_ip - ru_i, ey = rv_jp - rv_j, ez = rw_kp - rw_k;
@@ -338,25 +358,25 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                              ru_i * upw6<T>(ru_i, TH[-2], TH[-1], TH[0], TH[1], true, true);
                 const T fy = rv_jp * upw6<T>(rv_jp, TH[-WX], TH[0], TH[WX], TH[2 * WX], true, true) -
                              rv_j * upw6<T>(rv_j, TH[-2 * WX], TH[-WX], TH[0], TH[WX], true, true);
-                const T fz = rw_kp * upw6<T>(rw_kp, zc[0][1], zc[0][2], zc[0][3], zc[0][4], true, okR2) -
-                             rw_k * upw6<T>(rw_k, zc[0][0], zc[0][1], zc[0][2], zc[0][3], true, okR1);
+                fzc[0] = rw_kp * upw6<T>(rw_kp, zc[0][1], zc[0][2], zc[0][3], zc[0][4], true, okR2);
+                const T fz = fzc[0] - zl[0];
                 const T dr = ex * a.rdx + ey * a.rdy + ez * a.rdz;
                 const T dt = (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
-                st(a.out[0], oc, unc[0] - a.cdt * dr);
-                st(a.out[1], oc, unc[1] - a.cdt * dt);
+                st(a.out[0], oc, uc[0] - a.cdt * dr);
+                st(a.out[1], oc, uc[1] - a.cdt * dt);
             }
             // ---- x-face instance
             {
                 const T mxl = h * (ru_im + ru_i), mxh = h * (ru_i + ru_ip);
                 const T myl = h * (RVk[-1] + rv_j), myh = h * (RVk[WX - 1] + rv_jp);
-                const T mzl = h * (RWk[-1] + rw_k), mzh = top ? T(0) : h * (RWp[-1] + rw_kp);
+                const T mzh = top ? T(0) : h * (RWp[-1] + rw_kp);
                 const T fx = mxh * upw6<T>(mxh, UU[-1], UU[0], UU[1], UU[2], true, true) -
                              mxl * upw6<T>(mxl, UU[-2], UU[-1], UU[0], UU[1], true, true);
                 const T fy = myh * upw6<T>(myh, UU[-WX], UU[0], UU[WX], UU[2 * WX], true, true) -
                              myl * upw6<T>(myl, UU[-2 * WX], UU[-WX], UU[0], UU[WX], true, true);
-                const T fz = mzh * upw6<T>(mzh, zc[1][1], zc[1][2], zc[1][3], zc[1][4], true, okR2) -
-                             mzl * upw6<T>(mzl, zc[1][0], zc[1][1], zc[1][2], zc[1][3], true, okR1);
-                const T val = unc[2] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
+                fzc[1] = mzh * upw6<T>(mzh, zc[1][1], zc[1][2], zc[1][3], zc[1][4], true, okR2);
+                const T fz = fzc[1] - zl[1];
+                const T val = uc[2] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
                 st(a.out[2], ou, val);
                 if (i == 0) st(a.out[2], ou + nx, val);
             }
@@ -364,14 +384,14 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             {
                 const T mxl = h * (RUk[-WX] + ru_i), mxh = h * (RUk[1 - WX] + ru_ip);
                 const T myl = h * (rv_jm + rv_j), myh = h * (rv_j + rv_jp);
-                const T mzl = h * (RWk[-WX] + rw_k), mzh = top ? T(0) : h * (RWp[-WX] + rw_kp);
+                const T mzh = top ? T(0) : h * (RWp[-WX] + rw_kp);
                 const T fx = mxh * upw6<T>(mxh, VV[-1], VV[0], VV[1], VV[2], true, true) -
                              mxl * upw6<T>(mxl, VV[-2], VV[-1], VV[0], VV[1], true, true);
                 const T fy = myh * upw6<T>(myh, VV[-WX], VV[0], VV[WX], VV[2 * WX], true, true) -
                              myl * upw6<T>(myl, VV[-2 * WX], VV[-WX], VV[0], VV[WX], true, true);
-                const T fz = mzh * upw6<T>(mzh, zc[2][1], zc[2][2], zc[2][3], zc[2][4], true, okR2) -
-                             mzl * upw6<T>(mzl, zc[2][0], zc[2][1], zc[2][2], zc[2][3], true, okR1);
-                const T val = unc[3] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
+                fzc[2] = mzh * upw6<T>(mzh, zc[2][1], zc[2][2], zc[2][3], zc[2][4], true, okR2);
+                const T fz = fzc[2] - zl[2];
+                const T val = uc[3] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
                 st(a.out[3], ov, val);
                 if (j == 0) st(a.out[3], ov + (uint32_t)ny * nx, val);
             }
@@ -380,15 +400,14 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             {
                 const T mxl = h * (RUm[0] + ru_i), mxh = h * (RUm[1] + ru_ip);
                 const T myl = h * (RVm[0] + rv_j), myh = h * (RVm[WX] + rv_jp);
-                const T mzl = (k != 1) ? h * (RWm[0] + rw_k) : T(0);
                 const T mzh = (k != nz - 1) ? h * (rw_k + rw_kp) : T(0);
                 const T fx = mxh * upw6<T>(mxh, WW[-1], WW[0], WW[1], WW[2], true, true) -
                              mxl * upw6<T>(mxl, WW[-2], WW[-1], WW[0], WW[1], true, true);
                 const T fy = myh * upw6<T>(myh, WW[-WX], WW[0], WW[WX], WW[2 * WX], true, true) -
                              myl * upw6<T>(myl, WW[-2 * WX], WW[-WX], WW[0], WW[WX], true, true);
-                const T fz = mzh * upw6<T>(mzh, zc[3][1], zc[3][2], zc[3][3], zc[3][4], k - 1 >= 1, okR2) -
-                             mzl * upw6<T>(mzl, zc[3][0], zc[3][1], zc[3][2], zc[3][3], k - 2 >= 1, okR1);
-                st(a.out[4], oc, unc[4] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth);
+                fzc[3] = mzh * upw6<T>(mzh, zc[3][1], zc[3][2], zc[3][3], zc[3][4], k - 1 >= 1, okR2);
+                const T fz = fzc[3] - zl[3];
+                st(a.out[4], oc, uc[4] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth);
                 if (k == nz - 1) st(a.out[4], oc + pc, T(0));
             }
         }
@@ -397,9 +416,12 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             m2[q] = m1[q];
             m1[q] = P0[q * 3 * WS];
         }
-#pragma unroll
-        for (int f = 0; f < 5; ++f) unc[f] = unn[f];
+        fetch_un(k + 2, uc);
         __syncthreads();
+    };
+    for (int k = k0; k < z1; k += 2) {
+        step(k, pfA, unA);
+        if (k + 1 < z1) step(k + 1, pfB, unB);
     }
 }
 
@@ -727,11 +749,12 @@ struct Gen {
             RR = at(P.i, P.j, P.k + 1, ci);
         }
         const size_t G = a.v.Ge;
-        a.fh[(0 * 3 + D) * G + g] = beta<0, D>(P) > 0.0 ? fhat<0, D>(LL, L, P, RR, P) : 0.0;
-        a.fh[(1 * 3 + D) * G + g] = beta<0, D>(P) > 0.0 ? fhat<1, D>(LL, L, P, RR, P) : 0.0;
-        a.fh[(2 * 3 + D) * G + g] = beta<1, D>(P) > 0.0 ? fhat<2, D>(LL, L, P, RR, Lx) : 0.0;
-        a.fh[(3 * 3 + D) * G + g] = beta<2, D>(P) > 0.0 ? fhat<3, D>(LL, L, P, RR, Ly) : 0.0;
-        a.fh[(4 * 3 + D) * G + g] = beta<3, D>(P) > 0.0 ? fhat<4, D>(LL, L, P, RR, Lz) : 0.0;
+        const uint32_t ff = P.ff;  // lower faces with fluid (P.k < nz here)
+        a.fh[(0 * 3 + D) * G + g] = (ff & ff_pos(0, D)) ? fhat<0, D>(LL, L, P, RR, P) : 0.0;
+        a.fh[(1 * 3 + D) * G + g] = (ff & ff_pos(0, D)) ? fhat<1, D>(LL, L, P, RR, P) : 0.0;
+        a.fh[(2 * 3 + D) * G + g] = (ff & ff_pos(1, D)) ? fhat<2, D>(LL, L, P, RR, Lx) : 0.0;
+        a.fh[(3 * 3 + D) * G + g] = (ff & ff_pos(2, D)) ? fhat<3, D>(LL, L, P, RR, Ly) : 0.0;
+        a.fh[(4 * 3 + D) * G + g] = (ff & ff_pos(3, D)) ? fhat<4, D>(LL, L, P, RR, Lz) : 0.0;
     }
 };
 
@@ -778,7 +801,8 @@ __global__ void __launch_bounds__(256) k_gen_fhat(GenArgs<T> a) {
     int i, j, k;
     int4 ci;
     face_cell(a.v, g, i, j, k, ci);
-    const Pt P = G.at(i, j, k, ci);
+    Pt P = G.at(i, j, k, ci);
+    P.ff = G.fflags(P);
     // positions below P along x, y, z (the staggering neighbours of instances 1-3)
     const Pt Lx = G.at(G.wx(i - 1), j, k), Ly = G.at(i, G.wy(j - 1), k), Lz = G.at(i, j, k - 1, ci);
     G.template fhat_dir<0>(P, Lx, Ly, Lz, ci, g);

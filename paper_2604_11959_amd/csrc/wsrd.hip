@@ -267,6 +267,12 @@ struct AArgs {
     const double* lc;     // [P][3]
     const double* lev;    // [S][LSQ_MAXEV][3]
     const int8_t* lnev;   // [S]
+    int32_t abase[NINST]; // offset of each instance in the concatenated active list
+    const int32_t* woff;  // [A+1] contributors (neighbourhoods containing the CV), CSR
+    const int32_t* widx;  // [E] general index of the contributing small CV r
+    const double* wgeo;   // [E][4] kappa_r, then (offset + centroid_i - xhat_r) in mesh units
+    const double* aself;  // [A][5] omega, N, centroid_i - xhat_i (mesh units; small CVs)
+    const int8_t* asmall; // [A] 1 if the CV is small with kappa > 0
     int limiter;
     double dv;
 };
@@ -322,50 +328,66 @@ __device__ inline double psi(double delta, double qi, double qmin, double qmax) 
 
 // Limited least-squares gradient of Q-hat for one field (blockIdx.y = field),
 // from the precomputed operator: sigma = sum_s c_s (Q-hat_s - Q-hat_i) with
-// c_s = A^-1 e_s, then the Barth-Jespersen-style limiter.
-__global__ void __launch_bounds__(128) k_grad(AArgs a) {
+// c_s = A^-1 e_s, then the Barth-Jespersen-style limiter.  A group of
+// GRAD_LANES lanes shares one CV: the lanes split its fit points and combine
+// their partial sums and bounds by a butterfly over the group.
+constexpr int GRAD_LANES = 16;
+
+__global__ void __launch_bounds__(256) k_grad(AArgs a) {
     const int f = blockIdx.y;
     const int inst = field_inst(f);
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.ns[inst]) return;
+    const int lane = threadIdx.x % GRAD_LANES;
+    const int t = blockIdx.x * (256 / GRAD_LANES) + threadIdx.x / GRAD_LANES;
+    const bool valid = t < a.ns[inst];
     const GeoView& v = a.v;
-    const int g = a.slist[(size_t)inst * v.G + t];
-    const int e = a.sbase[inst] + t;
-    const int p0 = a.loff[e], p1 = a.loff[e + 1];
+    int g = 0, e = 0, p0 = 0, p1 = 0;
+    if (valid) {
+        g = a.slist[(size_t)inst * v.G + t];
+        e = a.sbase[inst] + t;
+        p0 = a.loff[e];
+        p1 = a.loff[e + 1];
+    }
+    const double* Qh = a.qhat + (size_t)f * v.G;
+    const double* Uh = a.uhat + (size_t)f * v.G;
+    const double qi = valid ? Qh[g] : 0.0;
     double s[3] = {0.0, 0.0, 0.0};
-    if (p1 > p0) {
-        const double* Qh = a.qhat + (size_t)f * v.G;
-        const double* Uh = a.uhat + (size_t)f * v.G;
-        const double qi = Qh[g];
-        double qmin = qi, qmax = qi;
-        for (int p = p0; p < p1; ++p) {
-            const uint32_t id = a.lidx[p];
-            const double qs = (id & LSQ_QHAT) ? Qh[id & ~LSQ_QHAT] : Uh[id];
-            const double dq = qs - qi;
-            s[0] += a.lc[3 * (size_t)p] * dq;
-            s[1] += a.lc[3 * (size_t)p + 1] * dq;
-            s[2] += a.lc[3 * (size_t)p + 2] * dq;
-            qmin = fmin(qmin, qs);
-            qmax = fmax(qmax, qs);
-        }
-        if (a.limiter != EBS_LIM_NONE) {
-            const int nev = a.lnev[e];
-            const double* ev = a.lev + (size_t)e * LSQ_MAXEV * 3;
-            double lam[3] = {1.0, 1.0, 1.0};
-            double lall = 1.0;
-            for (int q = 0; q < nev; ++q) {
-                if (a.limiter == EBS_LIM_BJ_COMPONENT) {
-                    for (int d = 0; d < 3; ++d) lam[d] = fmin(lam[d], psi(s[d] * ev[3 * q + d], qi, qmin, qmax));
-                } else {
-                    lall = fmin(lall, psi(s[0] * ev[3 * q] + s[1] * ev[3 * q + 1] + s[2] * ev[3 * q + 2], qi,
-                                          qmin, qmax));
-                }
-            }
+    double qmin = qi, qmax = qi;
+    for (int p = p0 + lane; p < p1; p += GRAD_LANES) {
+        const uint32_t id = a.lidx[p];
+        const double qs = (id & LSQ_QHAT) ? Qh[id & ~LSQ_QHAT] : Uh[id];
+        const double dq = qs - qi;
+        s[0] += a.lc[3 * (size_t)p] * dq;
+        s[1] += a.lc[3 * (size_t)p + 1] * dq;
+        s[2] += a.lc[3 * (size_t)p + 2] * dq;
+        qmin = fmin(qmin, qs);
+        qmax = fmax(qmax, qs);
+    }
+#pragma unroll
+    for (int m = GRAD_LANES / 2; m >= 1; m >>= 1) {
+        s[0] += __shfl_xor(s[0], m, GRAD_LANES);
+        s[1] += __shfl_xor(s[1], m, GRAD_LANES);
+        s[2] += __shfl_xor(s[2], m, GRAD_LANES);
+        qmin = fmin(qmin, __shfl_xor(qmin, m, GRAD_LANES));
+        qmax = fmax(qmax, __shfl_xor(qmax, m, GRAD_LANES));
+    }
+    if (!valid || lane != 0) return;
+    if (p1 > p0 && a.limiter != EBS_LIM_NONE) {
+        const int nev = a.lnev[e];
+        const double* ev = a.lev + (size_t)e * LSQ_MAXEV * 3;
+        double lam[3] = {1.0, 1.0, 1.0};
+        double lall = 1.0;
+        for (int q = 0; q < nev; ++q) {
             if (a.limiter == EBS_LIM_BJ_COMPONENT) {
-                for (int d = 0; d < 3; ++d) s[d] *= lam[d];
+                for (int d = 0; d < 3; ++d) lam[d] = fmin(lam[d], psi(s[d] * ev[3 * q + d], qi, qmin, qmax));
             } else {
-                for (int d = 0; d < 3; ++d) s[d] *= lall;
+                lall = fmin(lall, psi(s[0] * ev[3 * q] + s[1] * ev[3 * q + 1] + s[2] * ev[3 * q + 2], qi,
+                                      qmin, qmax));
             }
+        }
+        if (a.limiter == EBS_LIM_BJ_COMPONENT) {
+            for (int d = 0; d < 3; ++d) s[d] *= lam[d];
+        } else {
+            for (int d = 0; d < 3; ++d) s[d] *= lall;
         }
     }
     const double del[3] = {v.dx, v.dy, v.dz};
@@ -380,7 +402,8 @@ struct FArgs {
 };
 
 // Final update (Eqs. qrecon, final_update_omega) of one field (blockIdx.y)
-// on the CVs the operator may change, gathered over W.
+// on the CVs the operator may change, gathered over the precomputed list of
+// neighbourhoods containing each CV (W minus itself, fixed order).
 template <typename T>
 __global__ void __launch_bounds__(128) k_final(FArgs<T> F) {
     const AArgs& a = F.a;
@@ -390,35 +413,37 @@ __global__ void __launch_bounds__(128) k_final(FArgs<T> F) {
     if (t >= a.na[inst]) return;
     const GeoView& v = a.v;
     const int g = a.alist[(size_t)inst * v.G + t];
-    int i, j, k;
-    cell_of(v, g, i, j, k);
-    const double om = wv(a, inst, WQ_OMEGA, g), Ni = wv(a, inst, WQ_N, g);
+    const int e = a.abase[inst] + t;
     const double del[3] = {v.dx, v.dy, v.dz};
-    const size_t oi = (size_t)inst * v.G + g;
-    const bool ismall = a.small[oi] && wv(a, inst, WQ_KAPPA, g) > 0.0;
-    const double vc[3] = {gq(v, inst, GQ_VCX, g), gq(v, inst, GQ_VCY, g), gq(v, inst, GQ_VCZ, g)};
     const double* Qh = a.qhat + (size_t)f * v.G;
-    double qi = ismall ? Qh[g] : a.uhat[(size_t)f * v.G + g];
-    if (ismall)
-        for (int d = 0; d < 3; ++d)
-            qi += a.sig[((size_t)f * 3 + d) * v.G + g] * (vc[d] - wv(a, inst, WQ_XHX + d, g)) * del[d];
+    const double* sx = a.sig + ((size_t)f * 3 + 0) * v.G;
+    const double* sy = a.sig + ((size_t)f * 3 + 1) * v.G;
+    const double* sz = a.sig + ((size_t)f * 3 + 2) * v.G;
+    const double* self = a.aself + (size_t)e * 5;
+    const double om = self[0], Ni = self[1];
+    double qi;
+    if (a.asmall[e]) {
+        qi = Qh[g];
+        qi += sx[g] * self[2] * del[0];
+        qi += sy[g] * self[3] * del[1];
+        qi += sz[g] * self[4] * del[2];
+    } else {
+        qi = a.uhat[(size_t)f * v.G + g];
+    }
     double s = 0.0;
-    for (int oz = -1; oz <= 1; ++oz)
-        for (int oy = -1; oy <= 1; ++oy)
-            for (int ox = -1; ox <= 1; ++ox) {
-                if (ox == 0 && oy == 0 && oz == 0) continue;
-                const int gr = nbr(v, inst, i - ox, j - oy, k - oz);
-                if (gr < 0) continue;
-                if (!((a.mask[(size_t)inst * v.G + gr] >> bit_of(ox, oy, oz)) & 1)) continue;
-                const int off[3] = {ox, oy, oz};
-                double qr = Qh[gr];
-                for (int d = 0; d < 3; ++d)
-                    qr += a.sig[((size_t)f * 3 + d) * v.G + gr] *
-                          (off[d] + vc[d] - wv(a, inst, WQ_XHX + d, gr)) * del[d];
-                s += wv(a, inst, WQ_KAPPA, gr) * qr;
-            }
+    for (int q = a.woff[e]; q < a.woff[e + 1]; ++q) {
+        const int gr = a.widx[q];
+        const double* w = a.wgeo + (size_t)q * 4;
+        double qr = Qh[gr];
+        qr += sx[gr] * w[1] * del[0];
+        qr += sy[gr] * w[2] * del[1];
+        qr += sz[gr] * w[3] * del[2];
+        s += w[0] * qr;
+    }
     const double val = om * qi + s / Ni;
     // write into the state layout (with the periodic repeat)
+    int i, j, k;
+    cell_of(v, g, i, j, k);
     const int nx = F.nx, ny = F.ny;
     size_t idx;
     if (f == 2) idx = ((size_t)k * ny + j) * (nx + 1) + i;
@@ -428,6 +453,66 @@ __global__ void __launch_bounds__(128) k_final(FArgs<T> F) {
     o[idx] = (T)val;
     if (f == 2 && i == 0) F.out[2][((size_t)k * ny + j) * (nx + 1) + nx] = (T)val;
     if (f == 3 && j == 0) F.out[3][((size_t)k * (ny + 1) + ny) * nx + i] = (T)val;
+}
+
+// Contributor lists of the final update, built once per geometry: for every
+// CV the operator may change, the small CVs r whose neighbourhood contains it
+// (in the order of the offsets (dz, dy, dx) from -1 to 1), with kappa_r and
+// the offset from r's neighbourhood centroid to this CV's centroid.
+struct WLArgs {
+    GeoView v;
+    const int32_t* mask;
+    const int8_t* small;
+    const double* w;
+    const int32_t* alist;  // [4][G]
+    int32_t na[NINST], abase[NINST];
+    int fill;
+    int32_t* cnt;          // count mode: [A]
+    const int32_t* off;    // fill mode: [A+1]
+    int32_t* idx;
+    double* geo4;
+    double* self;
+    int8_t* smallf;
+};
+
+__global__ void __launch_bounds__(128) k_wlist(WLArgs a) {
+    const int inst = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.na[inst]) return;
+    const GeoView& v = a.v;
+    const int g = a.alist[(size_t)inst * v.G + t];
+    const int e = a.abase[inst] + t;
+    auto W = [&](int q, int gg) { return a.w[((size_t)inst * WQ_COUNT + q) * v.G + gg]; };
+    int i, j, k;
+    cell_of(v, g, i, j, k);
+    const double vc[3] = {gq(v, inst, GQ_VCX, g), gq(v, inst, GQ_VCY, g), gq(v, inst, GQ_VCZ, g)};
+    int n = 0;
+    int q = a.fill ? a.off[e] : 0;
+    for (int oz = -1; oz <= 1; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                if (ox == 0 && oy == 0 && oz == 0) continue;
+                const int gr = nbr(v, inst, i - ox, j - oy, k - oz);
+                if (gr < 0) continue;
+                if (!((a.mask[(size_t)inst * v.G + gr] >> bit_of(ox, oy, oz)) & 1)) continue;
+                ++n;
+                if (!a.fill) continue;
+                const int off[3] = {ox, oy, oz};
+                a.idx[q] = gr;
+                double* o = a.geo4 + (size_t)q * 4;
+                o[0] = W(WQ_KAPPA, gr);
+                for (int d = 0; d < 3; ++d) o[1 + d] = off[d] + vc[d] - W(WQ_XHX + d, gr);
+                ++q;
+            }
+    if (!a.fill) {
+        a.cnt[e] = n;
+        return;
+    }
+    double* sf = a.self + (size_t)e * 5;
+    sf[0] = W(WQ_OMEGA, g);
+    sf[1] = W(WQ_N, g);
+    for (int d = 0; d < 3; ++d) sf[2 + d] = vc[d] - W(WQ_XHX + d, g);
+    a.smallf[e] = (a.small[(size_t)inst * v.G + g] && W(WQ_KAPPA, g) > 0.0) ? 1 : 0;
 }
 
 // ------------------------------------------------ least-squares operators
@@ -708,6 +793,78 @@ ebs_status wsrd_setup(ebs_ctx* cx) {
         EBS_HIP(cx, hipGetLastError());
     }
     EBS_HIP(cx, hipStreamSynchronize(cx->stream));
+    // contributor lists of the final update: count, prefix sum, fill
+    int32_t A = 0, namax = 0;
+    for (int inst = 0; inst < NINST; ++inst) {
+        cx->abase[inst] = A;
+        A += cx->nact[inst];
+        namax = std::max(namax, cx->nact[inst]);
+    }
+    ok = alloc((void**)&cx->d_wl_off, sizeof(int32_t) * (A + 1));
+    ok &= alloc((void**)&cx->d_wl_self, sizeof(double) * 5 * std::max(A, 1));
+    ok &= alloc((void**)&cx->d_wl_small, std::max(A, 1));
+    if (!ok) {
+        cx->err = "device allocation of the redistribution lists failed";
+        return EBS_E_OOM;
+    }
+    WLArgs wl;
+    wl.v = geo_view(cx);
+    wl.mask = cx->d_mask;
+    wl.small = cx->d_small;
+    wl.w = cx->d_w;
+    wl.alist = cx->d_actlist;
+    for (int inst = 0; inst < NINST; ++inst) {
+        wl.na[inst] = cx->nact[inst];
+        wl.abase[inst] = cx->abase[inst];
+    }
+    wl.fill = 0;
+    wl.cnt = cx->d_wl_off;
+    wl.off = nullptr;
+    wl.idx = nullptr;
+    wl.geo4 = nullptr;
+    wl.self = nullptr;
+    wl.smallf = nullptr;
+    const dim3 wgrid((std::max(namax, 1) + 127) / 128, NINST);
+    if (A > 0) {
+        hipLaunchKernelGGL(k_wlist, wgrid, dim3(128), 0, cx->stream, wl);
+        EBS_HIP(cx, hipGetLastError());
+    }
+    std::vector<int32_t> woff(A + 1, 0);
+    if (A > 0)
+        EBS_HIP(cx, hipMemcpyAsync(woff.data(), cx->d_wl_off, sizeof(int32_t) * A, hipMemcpyDeviceToHost,
+                                   cx->stream));
+    EBS_HIP(cx, hipStreamSynchronize(cx->stream));
+    int64_t E = 0;
+    for (int32_t e = 0; e < A; ++e) {
+        const int32_t n = woff[e];
+        woff[e] = (int32_t)E;
+        E += n;
+    }
+    if (E > INT32_MAX / 4) {
+        cx->err = "redistribution lists too large";
+        return EBS_E_UNSUPPORTED;
+    }
+    woff[A] = (int32_t)E;
+    ok = alloc((void**)&cx->d_wl_idx, sizeof(int32_t) * std::max<int64_t>(E, 1));
+    ok &= alloc((void**)&cx->d_wl_geo, sizeof(double) * 4 * std::max<int64_t>(E, 1));
+    if (!ok) {
+        cx->err = "device allocation of the redistribution lists failed";
+        return EBS_E_OOM;
+    }
+    EBS_HIP(cx, hipMemcpyAsync(cx->d_wl_off, woff.data(), sizeof(int32_t) * (A + 1), hipMemcpyHostToDevice,
+                               cx->stream));
+    if (A > 0) {
+        wl.fill = 1;
+        wl.cnt = nullptr;
+        wl.off = cx->d_wl_off;
+        wl.idx = cx->d_wl_idx;
+        wl.geo4 = cx->d_wl_geo;
+        wl.self = cx->d_wl_self;
+        wl.smallf = cx->d_wl_small;
+        hipLaunchKernelGGL(k_wlist, wgrid, dim3(128), 0, cx->stream, wl);
+        EBS_HIP(cx, hipGetLastError());
+    }
+    EBS_HIP(cx, hipStreamSynchronize(cx->stream));
     return EBS_OK;
 }
 
@@ -737,11 +894,18 @@ static ebs_status redistribute_t(ebs_ctx* cx, ebs_state* Uout) {
     a.lc = cx->d_lsq_c;
     a.lev = cx->d_lsq_ev;
     a.lnev = cx->d_lsq_nev;
+    for (int inst = 0; inst < NINST; ++inst) a.abase[inst] = cx->abase[inst];
+    a.woff = cx->d_wl_off;
+    a.widx = cx->d_wl_idx;
+    a.wgeo = cx->d_wl_geo;
+    a.aself = cx->d_wl_self;
+    a.asmall = cx->d_wl_small;
     a.limiter = cx->g.limiter;
     a.dv = cx->g.dx[0] * cx->g.dx[1] * cx->g.dx[2];
     if (nsmax > 0) {
         hipLaunchKernelGGL(k_qhat, dim3((nsmax + 127) / 128, NINST), dim3(128), 0, cx->stream, a);
-        hipLaunchKernelGGL(k_grad, dim3((nsmax + 127) / 128, 5), dim3(128), 0, cx->stream, a);
+        const int per = 256 / GRAD_LANES;
+        hipLaunchKernelGGL(k_grad, dim3((nsmax + per - 1) / per, 5), dim3(256), 0, cx->stream, a);
     }
     if (namax > 0) {
         FArgs<T> F;

@@ -1,0 +1,96 @@
+"""HBM traffic of the regular-region kernel from rocprofv3 counter runs.
+
+    python -m paper_2604_11959_amd.profile_traffic PMC_DIR OUT_JSON --command "..."
+
+PMC_DIR holds the CSV output of four ``rocprofv3 --pmc`` runs (one counter
+each, as the hardware allows): ``fetch`` and ``write`` of the benchmark (one
+RK step, no graph, so every stage is its own dispatch) and ``cfetch`` /
+``cwrite`` of a plain 1 GiB device copy (``bench.py --calib-copy``).  The copy
+reads and writes exactly 2^30 bytes, which fixes the scale factor of each
+counter (FETCH_SIZE counts some request sizes at half width).  The summary
+records the mean calibrated bytes per regular-region launch and a SHA-256 of
+the kernel source, so that a later change of the kernel invalidates it.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "stage.hip")
+COPY_BYTES = 1 << 30
+
+
+def source_sha256(path: str = KERNEL_SOURCE) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _per_dispatch(path: str, counter: str):
+    """{dispatch id: (kernel name, summed value in KiB)} for one counter."""
+    out = {}
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            d = int(r["Dispatch_Id"])
+            name, val = out.get(d, (r["Kernel_Name"], 0.0))
+            out[d] = (name, val + float(r["Counter_Value"]))
+    return out
+
+
+def _copy_kib(path: str, counter: str) -> float:
+    vals = [v for n, v in _per_dispatch(path, counter).values() if "copyBuffer" in n]
+    if not vals:
+        raise SystemExit(f"no copy dispatch in {path}")
+    return max(vals)
+
+
+def summarize(pmc_dir: str, kernel_prefix: str = "k_bulk"):
+    f = lambda name: os.path.join(pmc_dir, f"{name}_counter_collection.csv")
+    fetch = _per_dispatch(f("fetch"), "FETCH_SIZE")
+    write = _per_dispatch(f("write"), "WRITE_SIZE")
+    fscale = COPY_BYTES / (_copy_kib(f("cfetch"), "FETCH_SIZE") * 1024.0)
+    wscale = COPY_BYTES / (_copy_kib(f("cwrite"), "WRITE_SIZE") * 1024.0)
+    pick = lambda d: [v for _, (n, v) in sorted(d.items()) if kernel_prefix in n]
+    fk, wk = pick(fetch), pick(write)
+    if not fk or len(fk) != len(wk):
+        raise SystemExit("fetch / write runs do not hold the same regular-region dispatches")
+    per_launch = [fv * 1024.0 * fscale + wv * 1024.0 * wscale for fv, wv in zip(fk, wk)]
+    return {
+        "kernel": kernel_prefix,
+        "launches": len(per_launch),
+        "fetch_kib_per_launch": fk,
+        "write_kib_per_launch": wk,
+        "fetch_scale": fscale,
+        "write_scale": wscale,
+        "traffic_bytes_per_launch": sum(per_launch) / len(per_launch),
+        "kernel_source_sha256": source_sha256(),
+    }
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("pmc_dir")
+    ap.add_argument("out_json")
+    ap.add_argument("--command", default="", help="the profiling command, recorded verbatim")
+    ap.add_argument("--workload", default="")
+    ap.add_argument("--tile", default="")
+    args = ap.parse_args(argv)
+    s = summarize(args.pmc_dir)
+    s["command"] = args.command
+    s["workload"] = args.workload
+    s["tile"] = [int(v) for v in args.tile.split("x")] if args.tile else None
+    with open(args.out_json, "w") as fo:
+        json.dump(s, fo, indent=1)
+        fo.write("\n")
+    print(json.dumps(s))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
