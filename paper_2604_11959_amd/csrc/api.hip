@@ -84,9 +84,13 @@ ebs_status rk3_enqueue(ebs_ctx* c, ebs_state* U, ebs_state* S, double dt) {
     ebs_state* cur = U;
     ebs_state* outs[3] = {&S[0], &S[1], U};
     for (int s = 0; s < 3; ++s) {
-        ebs_status st = launch_advance(c, U, cur, outs[s], cs[s] * dt);
+        // the redistribution only touches general-range cells, so it runs while
+        // the regular-region kernel of the same stage may still be running
+        ebs_status st = launch_advance(c, U, cur, outs[s], cs[s] * dt, true);
         if (st != EBS_OK) return st;
         st = launch_redistribute(c, outs[s], outs[s]);
+        if (st != EBS_OK) return st;
+        st = join_side(c);
         if (st != EBS_OK) return st;
         cur = outs[s];
     }
@@ -159,6 +163,14 @@ ebs_status ebs_create(const ebs_grid* grid, const ebs_box* boxes, int32_t nbox, 
                 return EBS_E_ARG;
             }
     }
+    // side stream (default priority) and fork / join events for running the
+    // regular-region kernel concurrently with the general range
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        ebs_destroy(c);
+        return EBS_E_HIP;
+    }
     const size_t ncol = c->ncol;
     bool ok = hipMalloc(&c->d_kf, sizeof(int32_t) * NINST * ncol) == hipSuccess;
     ok = ok && hipMalloc(&c->d_kr, sizeof(int32_t) * NINST * ncol) == hipSuccess;
@@ -175,7 +187,11 @@ ebs_status ebs_create(const ebs_grid* grid, const ebs_box* boxes, int32_t nbox, 
 ebs_status ebs_destroy(ebs_ctx* c) {
     if (!c) return EBS_OK;
     drop_graph(c);
+    if (c->side) (void)hipStreamSynchronize(c->side);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->side) (void)hipStreamDestroy(c->side);
     void* ptrs[] = {c->d_kf,   c->d_kr,        c->d_g0,      c->d_g1,   c->d_goff, c->d_gcol,
                     c->d_geo,  c->d_type,      c->d_mask,    c->d_small, c->d_tier, c->d_w,
                     c->d_smalllist, c->d_actlist, c->d_lsq_off, c->d_lsq_idx, c->d_lsq_c, c->d_lsq_ev, c->d_lsq_nev, c->d_wl_off, c->d_wl_idx, c->d_wl_geo, c->d_wl_self, c->d_wl_small, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles, c->d_prim, c->d_fh, c->d_type4, c->d_col, c->d_gcole, c->d_fflag, c->d_cbase, c->d_crec,

@@ -133,6 +133,9 @@ struct ebs_ctx {
     int nx = 0, ny = 0, nz = 0;
     int ncol = 0;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;        // regular-region kernel, concurrent with the general range
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool join_pending = false;
     std::vector<ebs_box> boxes;
     std::string err = "no error";
 
@@ -212,8 +215,11 @@ namespace ebs {
 // geometry (geom.hip)
 ebs_status build_geometry(ebs_ctx* c, const double* d_h);
 // stage kernels (stage.hip)
+// defer_join: leave the regular-region kernel running on the side stream;
+// join_side() makes the context stream wait for it
 ebs_status launch_advance(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uhat,
-                          double cdt);
+                          double cdt, bool defer_join = false);
+ebs_status join_side(ebs_ctx* c);
 ebs_status build_tiles(ebs_ctx* c);
 ebs_status build_cut_faces(ebs_ctx* c);
 size_t bulk_lds_bytes(int tx, int ty, int precision);

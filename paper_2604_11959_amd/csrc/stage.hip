@@ -983,7 +983,17 @@ ebs_status build_tiles(ebs_ctx* cx) {
 
 template <typename T>
 static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uh,
-                            double cdt) {
+                            double cdt, bool defer_join) {
+    // The regular-region kernel and the general-range passes write disjoint
+    // cells and read U_cur (never an output), so the former runs on the side
+    // stream, forked from and joined back into the context stream.
+    const bool fork = cx->side && cx->ntiles > 0 && cx->G > 0;
+    hipStream_t bs = cx->stream;
+    if (fork) {
+        EBS_HIP(cx, hipEventRecord(cx->ev_fork, cx->stream));
+        EBS_HIP(cx, hipStreamWaitEvent(cx->side, cx->ev_fork, 0));
+        bs = cx->side;
+    }
     const void* const un[5] = {Un->rho, Un->rhotheta, Un->rhou, Un->rhov, Un->rhow};
     const void* const cu[5] = {Ucur->rho, Ucur->rhotheta, Ucur->rhou, Ucur->rhov, Ucur->rhow};
     void* const ou[5] = {Uh->rho, Uh->rhotheta, Uh->rhou, Uh->rhov, Uh->rhow};
@@ -1015,7 +1025,7 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
             }
             e0 = cx->ev_pool[cx->ev_used++];
             e1 = cx->ev_pool[cx->ev_used++];
-            EBS_HIP(cx, hipEventRecord(e0, cx->stream));
+            EBS_HIP(cx, hipEventRecord(e0, bs));
         }
         const size_t lds = bulk_lds_bytes(cx->tile_x, cx->tile_y, cx->g.precision);
         a.per_xcd = (cx->ntiles + NXCD - 1) / NXCD;
@@ -1023,7 +1033,7 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
             const dim3 grid(a.per_xcd * NXCD), blk(cx->tile_x, cx->tile_y);
 #define EBS_BULK_CASE(X, Y)                                                                   \
     if (cx->tile_x == X && cx->tile_y == Y) {                                                 \
-        hipLaunchKernelGGL((k_bulk<T, X, Y>), grid, blk, lds, cx->stream, a);                 \
+        hipLaunchKernelGGL((k_bulk<T, X, Y>), grid, blk, lds, bs, a);                         \
     } else
             EBS_BULK_CASE(16, 4) EBS_BULK_CASE(16, 8) EBS_BULK_CASE(16, 16) EBS_BULK_CASE(32, 4)
             EBS_BULK_CASE(32, 8) EBS_BULK_CASE(64, 2) EBS_BULK_CASE(64, 4) {
@@ -1033,7 +1043,8 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
 #undef EBS_BULK_CASE
             EBS_HIP(cx, hipGetLastError());
         }
-        if (cx->timing) EBS_HIP(cx, hipEventRecord(e1, cx->stream));
+        if (cx->timing) EBS_HIP(cx, hipEventRecord(e1, bs));
+        if (fork) EBS_HIP(cx, hipEventRecord(cx->ev_join, bs));
     }
     if (cx->G > 0) {
         GenArgs<T> a;
@@ -1060,13 +1071,22 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
         hipLaunchKernelGGL(k_gen_update<T>, grid, blk, 0, cx->stream, a);
         EBS_HIP(cx, hipGetLastError());
     }
+    cx->join_pending = fork;
+    if (fork && !defer_join) return join_side(cx);
+    return EBS_OK;
+}
+
+ebs_status join_side(ebs_ctx* cx) {
+    if (!cx->join_pending) return EBS_OK;
+    cx->join_pending = false;
+    EBS_HIP(cx, hipStreamWaitEvent(cx->stream, cx->ev_join, 0));
     return EBS_OK;
 }
 
 ebs_status launch_advance(ebs_ctx* cx, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uhat,
-                          double cdt) {
-    if (cx->g.precision == EBS_F32_BULK) return advance_t<float>(cx, Un, Ucur, Uhat, cdt);
-    return advance_t<double>(cx, Un, Ucur, Uhat, cdt);
+                          double cdt, bool defer_join) {
+    if (cx->g.precision == EBS_F32_BULK) return advance_t<float>(cx, Un, Ucur, Uhat, cdt, defer_join);
+    return advance_t<double>(cx, Un, Ucur, Uhat, cdt, defer_join);
 }
 
 }  // namespace ebs
