@@ -9,7 +9,9 @@
 //     g0 = min over instances of kf (below: every instance covered),
 //     g1 = max over instances and over the 7 x 7 neighbouring columns of kr,
 //          plus 3 (above: every CV and every CV within the flux stencil and
-//          the redistribution radius is regular), clamped to nz.
+//          the redistribution radius is regular), clamped to nz; g1 = g0
+//          (empty range) when every CV in that window is regular down to the
+//          bottom wall.
 // General cells are numbered column by column (goff[c] + k - g0[c]); each has
 // a geometry record per instance (structure of arrays, GQ_* quantities) and
 // redistribution data.  Everything above g1 is processed by the regular-region

@@ -400,12 +400,19 @@ __global__ void k_g1(GeomArgs a) {
     if (c >= ncol) return;
     const int i = c % a.nx, j = c / a.nx;
     int m = 0;
+    bool flat = true;  // every CV of every instance in the window is regular
     for (int dj = -GEN_RXY; dj <= GEN_RXY; ++dj)
         for (int di = -GEN_RXY; di <= GEN_RXY; ++di) {
             const int cc = wrapi(j + dj, a.ny) * a.nx + wrapi(i + di, a.nx);
-            for (int inst = 0; inst < 4; ++inst) m = max(m, a.kr[inst * ncol + cc]);
+            for (int inst = 0; inst < 4; ++inst) {
+                const int kr = a.kr[inst * ncol + cc];
+                m = max(m, kr);
+                flat = flat && kr == (inst == 3 ? 1 : 0);
+            }
         }
-    a.g1[c] = min(a.nz, max(m + GEN_RZ, a.g0[c]));
+    // a column whose whole neighbourhood is regular down to the bottom wall
+    // has an empty general range (the regular-region kernel handles the wall)
+    a.g1[c] = flat ? a.g0[c] : min(a.nz, max(m + GEN_RZ, a.g0[c]));
 }
 
 struct RecArgs {
@@ -565,7 +572,8 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
         const int i = c % cx->nx, j = c / cx->nx;
         const int cxm = j * cx->nx + (i == 0 ? cx->nx - 1 : i - 1);
         const int cym = (j == 0 ? cx->ny - 1 : j - 1) * cx->nx + i;
-        g1e[c] = std::min(cx->nz, std::max(cx->h_g1[c] + 1, std::max(cx->h_g1[cxm], cx->h_g1[cym])));
+        const int own = cx->h_g1[c] > cx->h_g0[c] ? cx->h_g1[c] + 1 : cx->h_g0[c];
+        g1e[c] = std::min(cx->nz, std::max(own, std::max(cx->h_g1[cxm], cx->h_g1[cym])));
         goffe[c] = (int32_t)Ge;
         Ge += g1e[c] - cx->h_g0[c];
     }

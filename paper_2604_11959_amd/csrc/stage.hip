@@ -85,7 +85,8 @@ __device__ inline void put_field(const Dims& D, T* const (&out)[5], int f, int i
 // k-1 and k-2 of the advected quantities stay in registers.  Only U^n and the
 // outputs go to HBM directly.  Consecutive blocks are spread so that each XCD
 // receives a contiguous run of neighbouring tiles (shared halos stay in its
-// L2).  Stencil points beyond the top wall are flagged and never loaded.
+// L2).  Stencil points beyond the top and bottom walls are flagged and never
+// loaded.
 template <typename T>
 struct BulkArgs {
     Dims D;
@@ -119,7 +120,7 @@ enum : int { L_RHO = 0, L_RU = 2, L_RV = 6, L_RW = 10, L_PRIM = 14, L_COUNT = 26
 template <typename T>
 __device__ inline void prims_direct(const BulkArgs<T>& a, uint32_t c, uint32_t u, int dxm, int dym, int p,
                                     uint32_t pc, uint32_t pu, uint32_t pv, T* q) {
-    if (p >= a.D.nz) {
+    if (p < 0 || p >= a.D.nz) {  // beyond the walls
         q[0] = q[1] = q[2] = q[3] = T(0);
         return;
     }
@@ -128,7 +129,7 @@ __device__ inline void prims_direct(const BulkArgs<T>& a, uint32_t c, uint32_t u
     q[0] = qdiv<T>(a.cur[1][oc], r);
     q[1] = qdiv<T>(T(2) * a.cur[2][(uint32_t)p * pu + u], a.cur[0][oc + dxm] + r);
     q[2] = qdiv<T>(T(2) * a.cur[3][(uint32_t)p * pv + c], a.cur[0][oc + dym] + r);
-    q[3] = qdiv<T>(T(2) * a.cur[4][oc], a.cur[0][oc - pc] + r);
+    q[3] = p == 0 ? T(0) : qdiv<T>(T(2) * a.cur[4][oc], a.cur[0][oc - pc] + r);  // no w CV at k = 0
 }
 
 // six times the upwind face value (the 1/6 is applied once per CV): branch-free
@@ -193,7 +194,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
     // arithmetic.  rth keeps rho*theta of the committed plane for make_prims.
     T pfA[NPTS][5], pfB[NPTS][5], rth[NPTS];
     auto fetch = [&](int p, T (&pf)[NPTS][5]) {
-        const bool in = p < nz;  // block uniform
+        const bool in = p >= 0 && p < nz;  // block uniform
         const uint32_t oc0 = (uint32_t)p * pc, ou0 = (uint32_t)p * pu;
 #pragma unroll
         for (int q = 0; q < NPTS; ++q) {
@@ -234,7 +235,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
         const T* RV = sm + (L_RV + (p & 3)) * WS;
         const T* RW = sm + (L_RW + (p & 3)) * WS;
         T* P = sm + (L_PRIM + p % 3) * WS;
-        const bool in = p < nz;
+        const bool in = p >= 0 && p < nz;
 #pragma unroll
         for (int q = 0; q < NPTS; ++q) {
             const int r = tid + q * NTHR;
@@ -321,6 +322,9 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
         if (act && k >= ge) {
             const bool top = (k + 1 == nz);
             const bool okR1 = k + 1 <= nz - 1, okR2 = k + 2 <= nz - 1;
+            // far upwind ends of the z stencils of the lower / upper faces inside
+            // the domain (cell-centred and x-, y-face CVs; plane 0 is the bottom)
+            const bool okL1 = k - 2 >= 0, okL0 = k - 1 >= 0;
             T zc[4][5];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -344,11 +348,11 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) zl[q] = fzc[q];
             } else {
-                zl[0] = rw_k * upw6<T>(rw_k, zc[0][0], zc[0][1], zc[0][2], zc[0][3], true, okR1);
+                zl[0] = rw_k * upw6<T>(rw_k, zc[0][0], zc[0][1], zc[0][2], zc[0][3], okL1, okR1);
                 const T m1l = h * (RWk[-1] + rw_k), m2l = h * (RWk[-WX] + rw_k);
                 const T m3l = (k != 1) ? h * (RWm[0] + rw_k) : T(0);
-                zl[1] = m1l * upw6<T>(m1l, zc[1][0], zc[1][1], zc[1][2], zc[1][3], true, okR1);
-                zl[2] = m2l * upw6<T>(m2l, zc[2][0], zc[2][1], zc[2][2], zc[2][3], true, okR1);
+                zl[1] = m1l * upw6<T>(m1l, zc[1][0], zc[1][1], zc[1][2], zc[1][3], okL1, okR1);
+                zl[2] = m2l * upw6<T>(m2l, zc[2][0], zc[2][1], zc[2][2], zc[2][3], okL1, okR1);
                 zl[3] = m3l * upw6<T>(m3l, zc[3][0], zc[3][1], zc[3][2], zc[3][3], k - 2 >= 1, okR1);
             }
             // ---- cell-centred instance
@@ -358,7 +362,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                              ru_i * upw6<T>(ru_i, TH[-2], TH[-1], TH[0], TH[1], true, true);
                 const T fy = rv_jp * upw6<T>(rv_jp, TH[-WX], TH[0], TH[WX], TH[2 * WX], true, true) -
                              rv_j * upw6<T>(rv_j, TH[-2 * WX], TH[-WX], TH[0], TH[WX], true, true);
-                fzc[0] = rw_kp * upw6<T>(rw_kp, zc[0][1], zc[0][2], zc[0][3], zc[0][4], true, okR2);
+                fzc[0] = rw_kp * upw6<T>(rw_kp, zc[0][1], zc[0][2], zc[0][3], zc[0][4], okL0, okR2);
                 const T fz = fzc[0] - zl[0];
                 const T dr = ex * a.rdx + ey * a.rdy + ez * a.rdz;
                 const T dt = (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
@@ -374,7 +378,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                              mxl * upw6<T>(mxl, UU[-2], UU[-1], UU[0], UU[1], true, true);
                 const T fy = myh * upw6<T>(myh, UU[-WX], UU[0], UU[WX], UU[2 * WX], true, true) -
                              myl * upw6<T>(myl, UU[-2 * WX], UU[-WX], UU[0], UU[WX], true, true);
-                fzc[1] = mzh * upw6<T>(mzh, zc[1][1], zc[1][2], zc[1][3], zc[1][4], true, okR2);
+                fzc[1] = mzh * upw6<T>(mzh, zc[1][1], zc[1][2], zc[1][3], zc[1][4], okL0, okR2);
                 const T fz = fzc[1] - zl[1];
                 const T val = uc[2] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
                 st(a.out[2], ou, val);
@@ -389,7 +393,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                              mxl * upw6<T>(mxl, VV[-2], VV[-1], VV[0], VV[1], true, true);
                 const T fy = myh * upw6<T>(myh, VV[-WX], VV[0], VV[WX], VV[2 * WX], true, true) -
                              myl * upw6<T>(myl, VV[-2 * WX], VV[-WX], VV[0], VV[WX], true, true);
-                fzc[2] = mzh * upw6<T>(mzh, zc[2][1], zc[2][2], zc[2][3], zc[2][4], true, okR2);
+                fzc[2] = mzh * upw6<T>(mzh, zc[2][1], zc[2][2], zc[2][3], zc[2][4], okL0, okR2);
                 const T fz = fzc[2] - zl[2];
                 const T val = uc[3] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
                 st(a.out[3], ov, val);
@@ -400,14 +404,17 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             {
                 const T mxl = h * (RUm[0] + ru_i), mxh = h * (RUm[1] + ru_ip);
                 const T myl = h * (RVm[0] + rv_j), myh = h * (RVm[WX] + rv_jp);
-                const T mzh = (k != nz - 1) ? h * (rw_k + rw_kp) : T(0);
+                // (at k = 0 there is no z-face CV: its "upper face" term is the
+                // zero flux of the lower face of the CV at k = 1, carried up)
+                const T mzh = (k != nz - 1 && k != 0) ? h * (rw_k + rw_kp) : T(0);
                 const T fx = mxh * upw6<T>(mxh, WW[-1], WW[0], WW[1], WW[2], true, true) -
                              mxl * upw6<T>(mxl, WW[-2], WW[-1], WW[0], WW[1], true, true);
                 const T fy = myh * upw6<T>(myh, WW[-WX], WW[0], WW[WX], WW[2 * WX], true, true) -
                              myl * upw6<T>(myl, WW[-2 * WX], WW[-WX], WW[0], WW[WX], true, true);
                 fzc[3] = mzh * upw6<T>(mzh, zc[3][1], zc[3][2], zc[3][3], zc[3][4], k - 1 >= 1, okR2);
                 const T fz = fzc[3] - zl[3];
-                st(a.out[4], oc, uc[4] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth);
+                // plane 0 holds the bottom wall face, not a CV
+                st(a.out[4], oc, k == 0 ? T(0) : uc[4] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth);
                 if (k == nz - 1) st(a.out[4], oc + pc, T(0));
             }
         }

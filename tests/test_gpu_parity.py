@@ -190,6 +190,63 @@ def test_stage_parity_random_state_fp64():
     assert max(err.values()) <= 1e-12, err
 
 
+def _hills_with_flat_ground(nz=40):
+    """Two small truncated hills: most columns are flat ground (h = 0), whose
+    whole neighbourhood is regular down to the bottom wall."""
+    g = synth.Grid((48, 40, nz), (78.125, 78.125, 31.25))
+    h = synth.terrain_gaussian_hills(g, 5, 2, hrange=(80.0, 200.0), wrange=(150.0, 250.0))
+    return synth.Workload("hills_flat48", g, h, synth.cfl_dt(g), 5, [((0, 0, 0), g.n)], "atmos")
+
+
+@pytest.mark.parametrize("terrain", ["hills", "flat"])
+@pytest.mark.parametrize("precision,tiles,tol", [
+    (ebs.EBS_F64, ((16, 4, 16), (16, 8, 64)), 1e-12),
+    (ebs.EBS_F32_BULK, ((16, 16, 16), (32, 8, 32)), 2e-5),
+])
+def test_bottom_wall_and_flat_ground(terrain, precision, tiles, tol):
+    """Columns with no cut CV nearby have an empty general range: the
+    regular-region kernel updates them down to the bottom wall (zero flux
+    through k = 0, order reduction of the z stencils next to it, no z-face CV
+    at k = 0).  A random state makes every z flux live; one stage against the
+    oracle, for several tile shapes (tiles starting at the bottom and above)."""
+    w = _hills_with_flat_ground()
+    if terrain == "flat":
+        w = synth.Workload("flat48", w.grid, synth.terrain_flat(w.grid, 0.0), w.dt, 5,
+                           [((0, 0, 0), w.grid.n)], "atmos")
+    # the scenario: many columns whose 7 x 7 neighbourhood is flat ground
+    hn = w.h_nodes
+    hc = np.maximum(np.maximum(hn[:-1, :-1], hn[1:, :-1]), np.maximum(hn[:-1, 1:], hn[1:, 1:])) > 0
+    win = np.zeros_like(hc)
+    for dj in range(-3, 4):
+        for di in range(-3, 4):
+            win |= np.roll(np.roll(hc, dj, 0), di, 1)
+    assert (~win).mean() > (0.3 if terrain == "hills" else 0.99)
+    o = oracle.Oracle(w.grid, w.h_nodes)
+    U0 = synth.state_random(w.grid, 31, amp=2.0)
+    Un = synth.state_random(w.grid, 32, amp=2.0)
+    cdt = 0.3 * w.dt
+    ref = o.redistribute(o.advance(Un, U0, cdt))
+    masks = _fluid_masks(o)
+    boxes = synth.boxes_split(w.grid.n, 9, 12, block=16, unit=8)
+    for tile in tiles:
+        c = _ctx(w, precision=precision, boxes=boxes)
+        c.set_tile(*tile)
+        general = int(c.stats()[0][6])
+        if terrain == "flat":
+            assert general == 0, general
+        Ud, Ucur, Uh = c.new_state(Un), c.new_state(U0), c.new_state()
+        c.advance(Ud, Ucur, Uh, cdt)
+        c.redistribute(Uh, Uh)
+        torch.cuda.synchronize()
+        h = _host(Uh)
+        err = rel_err(h, ref, masks)
+        print(terrain, precision, tile, err, flush=True)
+        assert max(err.values()) <= tol, (tile, err)
+        assert np.all(h["rhow"][0] == 0) and np.all(h["rhow"][-1] == 0)
+        for f in FIELDS:
+            assert np.all(h[f][~masks[f]] == 0.0), f
+
+
 def test_trajectory_parity_c1_ten_stages():
     """Ten consecutive RK3 stages (three steps and the first stage of the
     fourth) on the hill, FP64, compared after every stage; conservation."""
