@@ -1,0 +1,502 @@
+// Regular-region stage kernel: the explicit update of the four instances
+// (Eqs. update-cc / update-fc of Section 3.1 with the advective flux of
+// Section 4.1; Algorithm 1 steps 1-3) on every cell at or above its column's
+// general range.  Every CV and every stencil member there is a full cell, so
+// the update needs no geometry: face fractions are one, no flux is moved to a
+// centroid, and the only special cases are the top and bottom walls.  It runs
+// over a tile list derived from the box list, in the state precision.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "ebs_internal.h"
+#include "stage_common.h"
+
+namespace ebs {
+namespace {
+
+// ------------------------------------------------------------------ bulk
+//
+// 2.5-D z-march.  A block owns an xy tile of TX x TY columns and walks up the
+// tile's z-range.  Every plane of the five fields is read from HBM exactly once
+// per block, over the tile plus a halo (3 cells on the low sides, 2 on the high
+// sides), into LDS rings; the advected quantities (theta, u, v, w) are then
+// computed once per point from LDS.  Rings: rho 2 planes, momenta 4 planes
+// (k-1..k+2), advected quantities 3 planes (k..k+2); the own column's planes
+// k-1 and k-2 of the advected quantities stay in registers.  Only U^n and the
+// outputs go to HBM directly.  Consecutive blocks are spread so that each XCD
+// receives a contiguous run of neighbouring tiles (shared halos stay in its
+// L2).  Stencil points beyond the top and bottom walls are flagged and never
+// loaded.
+template <typename T>
+struct BulkArgs {
+    Dims D;
+    const T* __restrict__ un[5];
+    const T* __restrict__ cur[5];
+    T* out[5];
+    T cdt;
+    T rdx, rdy, rdz;
+    const int32_t* __restrict__ g0;
+    const int32_t* __restrict__ g1;
+    const ebs_tile* __restrict__ tiles;
+    int32_t ntiles;
+    int32_t per_xcd;  // tiles per XCD chunk
+};
+
+template <typename T>
+__device__ inline T qdiv(T a, T b) {
+    return a / b;
+}
+template <>
+__device__ inline float qdiv<float>(float a, float b) {
+    return a * __builtin_amdgcn_rcpf(b);
+}
+
+constexpr int HALO_PTS = 4;  // region points per thread: (TX+5)(TY+5) <= 4 TX TY for TX*TY >= 64
+constexpr int NXCD = 8;
+
+// LDS arrays, each WS entries: rho[2], rhou[4], rhov[4], rhow[4], prim[4 quantities][3]
+enum : int { L_RHO = 0, L_RU = 2, L_RV = 6, L_RW = 10, L_PRIM = 14, L_COUNT = 26 };
+
+template <typename T>
+__device__ inline void prims_direct(const BulkArgs<T>& a, uint32_t c, uint32_t u, int dxm, int dym, int p,
+                                    uint32_t pc, uint32_t pu, uint32_t pv, T* q) {
+    if (p < 0 || p >= a.D.nz) {  // beyond the walls
+        q[0] = q[1] = q[2] = q[3] = T(0);
+        return;
+    }
+    const uint32_t oc = (uint32_t)p * pc + c;
+    const T r = a.cur[0][oc];
+    q[0] = qdiv<T>(a.cur[1][oc], r);
+    q[1] = qdiv<T>(T(2) * a.cur[2][(uint32_t)p * pu + u], a.cur[0][oc + dxm] + r);
+    q[2] = qdiv<T>(T(2) * a.cur[3][(uint32_t)p * pv + c], a.cur[0][oc + dym] + r);
+    q[3] = p == 0 ? T(0) : qdiv<T>(T(2) * a.cur[4][oc], a.cur[0][oc - pc] + r);  // no w CV at k = 0
+}
+
+// six times the upwind face value (the 1/6 is applied once per CV): branch-free
+// third-order upwind, second-order centred when the stencil end is unavailable
+template <typename T>
+__device__ __forceinline__ T upw6(T m, T pLL, T pL, T pR, T pRR, bool okLL, bool okRR) {
+    const bool up = m >= T(0);
+    const T a = up ? pL : pR, b = up ? pR : pL, e = up ? pLL : pRR;
+    const bool ok = up ? okLL : okRR;
+    return ok ? (T(5) * a + T(2) * b - e) : T(3) * (a + b);
+}
+
+// element access with a 32-bit byte offset (every field is below 4 GiB; the
+// context checks it), so the address is a scalar base plus a vector offset
+template <typename T>
+__device__ __forceinline__ T ld(const T* __restrict__ base, uint32_t off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(off * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st(T* base, uint32_t off, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(off * (uint32_t)sizeof(T))) = v;
+}
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
+    constexpr int WX = TX + 5, WS = WX * (TY + 5), NTHR = TX * TY;
+    constexpr int NPTS = (WS + NTHR - 1) / NTHR;
+    static_assert(NPTS <= HALO_PTS, "halo points per thread");
+    extern __shared__ unsigned char smem_raw[];
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    const int nx = a.D.nx, ny = a.D.ny, nz = a.D.nz;
+    const uint32_t pc = (uint32_t)nx * ny, pu = (uint32_t)(nx + 1) * ny, pv = (uint32_t)nx * (ny + 1);
+    const int t = (blockIdx.x % NXCD) * a.per_xcd + blockIdx.x / NXCD;
+    if (t >= a.ntiles) return;
+    const ebs_tile tl = a.tiles[t];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = ty * TX + tx;
+    const bool act = tx < tl.ex && ty < tl.ey;
+    const int i = tl.x0 + (act ? tx : 0), j = tl.y0 + (act ? ty : 0);
+    const int z1 = tl.z0 + tl.ez;
+    int ge = nz;
+    if (act) {
+        const int c = j * nx + i;
+        const int gb = a.g0[c];
+        ge = a.g1[c];
+        for (int k = tl.z0; k < min(gb, z1); ++k)
+            for (int f = 0; f < 5; ++f) put_field<T>(a.D, a.out, f, i, j, k, T(0));
+    }
+    const int k0 = tl.z0 + tl.flags;  // first plane with regular-region work (block uniform)
+    if (k0 >= z1) return;
+    uint32_t rc[NPTS], ru[NPTS];
+#pragma unroll
+    for (int q = 0; q < NPTS; ++q) {
+        const int r = tid + q * NTHR;
+        const int x = wrapi(tl.x0 - 3 + r % WX, nx), y = wrapi(tl.y0 - 3 + r / WX, ny);
+        rc[q] = (uint32_t)(y * nx + x);
+        ru[q] = (uint32_t)(y * (nx + 1) + x);
+    }
+    // Raw values of the next plane to enter the rings are loaded into registers
+    // one z-iteration ahead (fetch) and written to LDS at the top of the next
+    // iteration (commit), so the global-load latency overlaps a whole plane of
+    // arithmetic.  rth keeps rho*theta of the committed plane for make_prims.
+    T pfA[NPTS][5], pfB[NPTS][5], rth[NPTS];
+    auto fetch = [&](int p, T (&pf)[NPTS][5]) {
+        const bool in = p >= 0 && p < nz;  // block uniform
+        const uint32_t oc0 = (uint32_t)p * pc, ou0 = (uint32_t)p * pu;
+#pragma unroll
+        for (int q = 0; q < NPTS; ++q) {
+            const int r = tid + q * NTHR;
+            if (q == NPTS - 1 && r >= WS) break;
+            if (in) {
+                pf[q][0] = ld(a.cur[0], oc0 + rc[q]);
+                pf[q][1] = ld(a.cur[1], oc0 + rc[q]);
+                pf[q][2] = ld(a.cur[2], ou0 + ru[q]);
+                pf[q][3] = ld(a.cur[3], (uint32_t)p * pv + rc[q]);
+                pf[q][4] = ld(a.cur[4], oc0 + rc[q]);
+            } else {
+#pragma unroll
+                for (int f = 0; f < 5; ++f) pf[q][f] = T(0);
+            }
+        }
+    };
+    auto commit = [&](int p, const T (&pf)[NPTS][5]) {
+        T* RHO = sm + (L_RHO + (p & 1)) * WS;
+        T* RU = sm + (L_RU + (p & 3)) * WS;
+        T* RV = sm + (L_RV + (p & 3)) * WS;
+        T* RW = sm + (L_RW + (p & 3)) * WS;
+#pragma unroll
+        for (int q = 0; q < NPTS; ++q) {
+            const int r = tid + q * NTHR;
+            if (q == NPTS - 1 && r >= WS) break;
+            RHO[r] = pf[q][0];
+            rth[q] = pf[q][1];
+            RU[r] = pf[q][2];
+            RV[r] = pf[q][3];
+            RW[r] = pf[q][4];
+        }
+    };
+    auto make_prims = [&](int p) {
+        const T* RHO = sm + (L_RHO + (p & 1)) * WS;
+        const T* RHOm = sm + (L_RHO + ((p + 1) & 1)) * WS;
+        const T* RU = sm + (L_RU + (p & 3)) * WS;
+        const T* RV = sm + (L_RV + (p & 3)) * WS;
+        const T* RW = sm + (L_RW + (p & 3)) * WS;
+        T* P = sm + (L_PRIM + p % 3) * WS;
+        const bool in = p >= 0 && p < nz;
+#pragma unroll
+        for (int q = 0; q < NPTS; ++q) {
+            const int r = tid + q * NTHR;
+            if (q == NPTS - 1 && r >= WS) break;
+            if (r < WX || r % WX == 0) continue;
+            T th = T(0), u = T(0), v = T(0), w = T(0);
+            if (in) {
+                const T rr = RHO[r];
+                th = qdiv<T>(rth[q], rr);
+                u = qdiv<T>(T(2) * RU[r], RHO[r - 1] + rr);
+                v = qdiv<T>(T(2) * RV[r], RHO[r - WX] + rr);
+                w = qdiv<T>(T(2) * RW[r], RHOm[r] + rr);
+            }
+            P[0 * 3 * WS + r] = th;
+            P[1 * 3 * WS + r] = u;
+            P[2 * 3 * WS + r] = v;
+            P[3 * 3 * WS + r] = w;
+        }
+    };
+    const int me = (ty + 3) * WX + (tx + 3);
+    const int dxm = (i == 0) ? nx - 1 : -1;
+    const int dym = (j == 0) ? ny - 1 : -1;
+    const uint32_t c0 = (uint32_t)(j * nx + i), u0 = (uint32_t)(j * (nx + 1) + i);
+    T m2[4], m1[4];
+    prims_direct<T>(a, c0, u0, dxm, dym * nx, k0 - 2, pc, pu, pv, m2);
+    prims_direct<T>(a, c0, u0, dxm, dym * nx, k0 - 1, pc, pu, pv, m1);
+    // Raw planes run two z-iterations ahead in two register sets (pfA, pfB,
+    // alternating), the own-cell Un values likewise (unA, unB).
+    fetch(k0 - 1, pfA);
+    commit(k0 - 1, pfA);
+    fetch(k0, pfA);
+    commit(k0, pfA);
+    fetch(k0 + 1, pfA);
+    __syncthreads();
+    make_prims(k0);
+    __syncthreads();  // the density slot of plane k0 - 1 is reused by plane k0 + 1
+    commit(k0 + 1, pfA);
+    fetch(k0 + 2, pfA);
+    fetch(k0 + 3, pfB);
+    __syncthreads();
+    make_prims(k0 + 1);
+    __syncthreads();  // the density slot of plane k0 is reused by plane k0 + 2
+    const uint32_t ov0 = (uint32_t)(j * nx + i);
+    auto fetch_un = [&](int kk, T (&dst)[5]) {
+        if (act && kk < z1 && kk >= ge) {
+            dst[0] = ld(a.un[0], (uint32_t)kk * pc + c0);
+            dst[1] = ld(a.un[1], (uint32_t)kk * pc + c0);
+            dst[2] = ld(a.un[2], (uint32_t)kk * pu + u0);
+            dst[3] = ld(a.un[3], (uint32_t)kk * pv + ov0);
+            dst[4] = ld(a.un[4], (uint32_t)kk * pc + c0);
+        } else {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) dst[f] = T(0);
+        }
+    };
+    T unA[5], unB[5];
+    T fzc[4] = {T(0), T(0), T(0), T(0)};  // upper z-face flux terms of the last plane
+    fetch_un(k0, unA);
+    fetch_un(k0 + 1, unB);
+    const T sixth = T(1) / T(6);
+    // one z-iteration: plane k is updated; rp holds raw plane k + 2 on entry and
+    // plane k + 4 on exit, uc the Un values of plane k on entry and k + 2 on exit
+    auto step = [&](int k, T (&rp)[NPTS][5], T (&uc)[5]) __attribute__((always_inline)) {
+        commit(k + 2, rp);
+        fetch(k + 4, rp);
+        __syncthreads();
+        make_prims(k + 2);
+        __syncthreads();
+        const int s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
+        const T* P0 = sm + (L_PRIM + s0) * WS + me;  // quantity q at + q * 3 * WS
+        const T* P1 = sm + (L_PRIM + s1) * WS + me;
+        const T* P2 = sm + (L_PRIM + s2) * WS + me;
+        const T* TH = P0;
+        const T* UU = P0 + 3 * WS;
+        const T* VV = P0 + 6 * WS;
+        const T* WW = P0 + 9 * WS;
+        const T* RUk = sm + (L_RU + (k & 3)) * WS + me;
+        const T* RVk = sm + (L_RV + (k & 3)) * WS + me;
+        const T* RUm = sm + (L_RU + ((k + 3) & 3)) * WS + me;  // plane k-1
+        const T* RVm = sm + (L_RV + ((k + 3) & 3)) * WS + me;
+        const T* RWk = sm + (L_RW + (k & 3)) * WS + me;
+        const T* RWp = sm + (L_RW + ((k + 1) & 3)) * WS + me;
+        const T* RWm = sm + (L_RW + ((k + 3) & 3)) * WS + me;
+        if (act && k >= ge) {
+            const bool top = (k + 1 == nz);
+            const bool okR1 = k + 1 <= nz - 1, okR2 = k + 2 <= nz - 1;
+            // far upwind ends of the z stencils of the lower / upper faces inside
+            // the domain (cell-centred and x-, y-face CVs; plane 0 is the bottom)
+            const bool okL1 = k - 2 >= 0, okL0 = k - 1 >= 0;
+            T zc[4][5];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                zc[q][0] = m2[q];
+                zc[q][1] = m1[q];
+                zc[q][2] = P0[q * 3 * WS];
+                zc[q][3] = P1[q * 3 * WS];
+                zc[q][4] = P2[q * 3 * WS];
+            }
+            const uint32_t oc = (uint32_t)k * pc + c0;
+            const uint32_t ou = (uint32_t)k * pu + u0;
+            const uint32_t ov = (uint32_t)k * pv + c0;
+            const T ru_i = RUk[0], ru_ip = RUk[1], ru_im = RUk[-1];
+            const T rv_j = RVk[0], rv_jp = RVk[WX], rv_jm = RVk[-WX];
+            const T rw_k = RWk[0], rw_kp = top ? T(0) : RWp[0];
+            const T h = T(0.5);
+            // lower z-face flux terms: carried from the upper faces of plane k - 1
+            // when this thread updated it (same values, same arithmetic)
+            T zl[4];
+            if (k > k0 && k - 1 >= ge) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) zl[q] = fzc[q];
+            } else {
+                zl[0] = rw_k * upw6<T>(rw_k, zc[0][0], zc[0][1], zc[0][2], zc[0][3], okL1, okR1);
+                const T m1l = h * (RWk[-1] + rw_k), m2l = h * (RWk[-WX] + rw_k);
+                const T m3l = (k != 1) ? h * (RWm[0] + rw_k) : T(0);
+                zl[1] = m1l * upw6<T>(m1l, zc[1][0], zc[1][1], zc[1][2], zc[1][3], okL1, okR1);
+                zl[2] = m2l * upw6<T>(m2l, zc[2][0], zc[2][1], zc[2][2], zc[2][3], okL1, okR1);
+                zl[3] = m3l * upw6<T>(m3l, zc[3][0], zc[3][1], zc[3][2], zc[3][3], k - 2 >= 1, okR1);
+            }
+            // ---- cell-centred instance
+            {
+                const T ex = ru_ip - ru_i, ey = rv_jp - rv_j, ez = rw_kp - rw_k;
+                const T fx = ru_ip * upw6<T>(ru_ip, TH[-1], TH[0], TH[1], TH[2], true, true) -
+                             ru_i * upw6<T>(ru_i, TH[-2], TH[-1], TH[0], TH[1], true, true);
+                const T fy = rv_jp * upw6<T>(rv_jp, TH[-WX], TH[0], TH[WX], TH[2 * WX], true, true) -
+                             rv_j * upw6<T>(rv_j, TH[-2 * WX], TH[-WX], TH[0], TH[WX], true, true);
+                fzc[0] = rw_kp * upw6<T>(rw_kp, zc[0][1], zc[0][2], zc[0][3], zc[0][4], okL0, okR2);
+                const T fz = fzc[0] - zl[0];
+                const T dr = ex * a.rdx + ey * a.rdy + ez * a.rdz;
+                const T dt = (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
+                st(a.out[0], oc, uc[0] - a.cdt * dr);
+                st(a.out[1], oc, uc[1] - a.cdt * dt);
+            }
+            // ---- x-face instance
+            {
+                const T mxl = h * (ru_im + ru_i), mxh = h * (ru_i + ru_ip);
+                const T myl = h * (RVk[-1] + rv_j), myh = h * (RVk[WX - 1] + rv_jp);
+                const T mzh = top ? T(0) : h * (RWp[-1] + rw_kp);
+                const T fx = mxh * upw6<T>(mxh, UU[-1], UU[0], UU[1], UU[2], true, true) -
+                             mxl * upw6<T>(mxl, UU[-2], UU[-1], UU[0], UU[1], true, true);
+                const T fy = myh * upw6<T>(myh, UU[-WX], UU[0], UU[WX], UU[2 * WX], true, true) -
+                             myl * upw6<T>(myl, UU[-2 * WX], UU[-WX], UU[0], UU[WX], true, true);
+                fzc[1] = mzh * upw6<T>(mzh, zc[1][1], zc[1][2], zc[1][3], zc[1][4], okL0, okR2);
+                const T fz = fzc[1] - zl[1];
+                const T val = uc[2] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
+                st(a.out[2], ou, val);
+                if (i == 0) st(a.out[2], ou + nx, val);
+            }
+            // ---- y-face instance
+            {
+                const T mxl = h * (RUk[-WX] + ru_i), mxh = h * (RUk[1 - WX] + ru_ip);
+                const T myl = h * (rv_jm + rv_j), myh = h * (rv_j + rv_jp);
+                const T mzh = top ? T(0) : h * (RWp[-WX] + rw_kp);
+                const T fx = mxh * upw6<T>(mxh, VV[-1], VV[0], VV[1], VV[2], true, true) -
+                             mxl * upw6<T>(mxl, VV[-2], VV[-1], VV[0], VV[1], true, true);
+                const T fy = myh * upw6<T>(myh, VV[-WX], VV[0], VV[WX], VV[2 * WX], true, true) -
+                             myl * upw6<T>(myl, VV[-2 * WX], VV[-WX], VV[0], VV[WX], true, true);
+                fzc[2] = mzh * upw6<T>(mzh, zc[2][1], zc[2][2], zc[2][3], zc[2][4], okL0, okR2);
+                const T fz = fzc[2] - zl[2];
+                const T val = uc[3] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
+                st(a.out[3], ov, val);
+                if (j == 0) st(a.out[3], ov + (uint32_t)ny * nx, val);
+            }
+            // ---- z-face instance (k >= 1 in the regular range); zero flux
+            // through the mid planes of the bottom and top cell layers
+            {
+                const T mxl = h * (RUm[0] + ru_i), mxh = h * (RUm[1] + ru_ip);
+                const T myl = h * (RVm[0] + rv_j), myh = h * (RVm[WX] + rv_jp);
+                // (at k = 0 there is no z-face CV: its "upper face" term is the
+                // zero flux of the lower face of the CV at k = 1, carried up)
+                const T mzh = (k != nz - 1 && k != 0) ? h * (rw_k + rw_kp) : T(0);
+                const T fx = mxh * upw6<T>(mxh, WW[-1], WW[0], WW[1], WW[2], true, true) -
+                             mxl * upw6<T>(mxl, WW[-2], WW[-1], WW[0], WW[1], true, true);
+                const T fy = myh * upw6<T>(myh, WW[-WX], WW[0], WW[WX], WW[2 * WX], true, true) -
+                             myl * upw6<T>(myl, WW[-2 * WX], WW[-WX], WW[0], WW[WX], true, true);
+                fzc[3] = mzh * upw6<T>(mzh, zc[3][1], zc[3][2], zc[3][3], zc[3][4], k - 1 >= 1, okR2);
+                const T fz = fzc[3] - zl[3];
+                // plane 0 holds the bottom wall face, not a CV
+                st(a.out[4], oc, k == 0 ? T(0) : uc[4] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth);
+                if (k == nz - 1) st(a.out[4], oc + pc, T(0));
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            m2[q] = m1[q];
+            m1[q] = P0[q * 3 * WS];
+        }
+        fetch_un(k + 2, uc);
+        __syncthreads();
+    };
+    for (int k = k0; k < z1; k += 2) {
+        step(k, pfA, unA);
+        if (k + 1 < z1) step(k + 1, pfB, unB);
+    }
+}
+
+template <typename T>
+ebs_status launch_bulk_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uh, double cdt,
+                         hipStream_t bs) {
+    const void* const un[5] = {Un->rho, Un->rhotheta, Un->rhou, Un->rhov, Un->rhow};
+    const void* const cu[5] = {Ucur->rho, Ucur->rhotheta, Ucur->rhou, Ucur->rhov, Ucur->rhow};
+    void* const ou[5] = {Uh->rho, Uh->rhotheta, Uh->rhou, Uh->rhov, Uh->rhow};
+    Dims D{cx->nx, cx->ny, cx->nz};
+    {
+        BulkArgs<T> a;
+        a.D = D;
+        for (int f = 0; f < 5; ++f) {
+            a.un[f] = (const T*)un[f];
+            a.cur[f] = (const T*)cu[f];
+            a.out[f] = (T*)ou[f];
+        }
+        a.cdt = (T)cdt;
+        a.rdx = (T)(1.0 / cx->g.dx[0]);
+        a.rdy = (T)(1.0 / cx->g.dx[1]);
+        a.rdz = (T)(1.0 / cx->g.dx[2]);
+        a.g0 = cx->d_g0;
+        a.g1 = cx->d_g1;
+        a.tiles = cx->d_tiles;
+        a.ntiles = cx->ntiles;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (cx->timing) {
+            if (cx->ev_used + 2 > cx->ev_pool.size()) {
+                for (int q = 0; q < 64; ++q) {
+                    hipEvent_t e;
+                    EBS_HIP(cx, hipEventCreate(&e));
+                    cx->ev_pool.push_back(e);
+                }
+            }
+            e0 = cx->ev_pool[cx->ev_used++];
+            e1 = cx->ev_pool[cx->ev_used++];
+            EBS_HIP(cx, hipEventRecord(e0, bs));
+        }
+        const size_t lds = bulk_lds_bytes(cx->tile_x, cx->tile_y, cx->g.precision);
+        a.per_xcd = (cx->ntiles + NXCD - 1) / NXCD;
+        if (cx->ntiles > 0) {
+            const dim3 grid(a.per_xcd * NXCD), blk(cx->tile_x, cx->tile_y);
+#define EBS_BULK_CASE(X, Y)                                                                   \
+    if (cx->tile_x == X && cx->tile_y == Y) {                                                 \
+        hipLaunchKernelGGL((k_bulk<T, X, Y>), grid, blk, lds, bs, a);                         \
+    } else
+            EBS_BULK_CASE(16, 4) EBS_BULK_CASE(16, 8) EBS_BULK_CASE(16, 16) EBS_BULK_CASE(32, 4)
+            EBS_BULK_CASE(32, 8) EBS_BULK_CASE(64, 2) EBS_BULK_CASE(64, 4) {
+                cx->err = "tile shape without a compiled kernel";
+                return EBS_E_UNSUPPORTED;
+            }
+#undef EBS_BULK_CASE
+            EBS_HIP(cx, hipGetLastError());
+        }
+        if (cx->timing) EBS_HIP(cx, hipEventRecord(e1, bs));
+    }
+    return EBS_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- host side
+size_t bulk_lds_bytes(int tx, int ty, int precision) {
+    return (precision == EBS_F32_BULK ? 4 : 8) * (size_t)L_COUNT * (tx + 5) * (ty + 5);
+}
+
+ebs_status build_tiles(ebs_ctx* cx) {
+    cx->h_tiles.clear();
+    const int TX = cx->tile_x, TY = cx->tile_y, TZ = cx->tile_z;
+    for (const ebs_box& b : cx->boxes) {
+        for (int z = b.lo[2]; z < b.hi[2]; z += TZ)
+            for (int y = b.lo[1]; y < b.hi[1]; y += TY)
+                for (int x = b.lo[0]; x < b.hi[0]; x += TX) {
+                    ebs_tile t;
+                    t.x0 = x; t.y0 = y; t.z0 = z;
+                    t.ex = (int16_t)std::min(TX, b.hi[0] - x);
+                    t.ey = (int16_t)std::min(TY, b.hi[1] - y);
+                    t.ez = (int16_t)std::min(TZ, b.hi[2] - z);
+                    // first plane at or above the general range of every column
+                    int kmin = cx->nz;
+                    for (int yy = y; yy < y + t.ey; ++yy)
+                        for (int xx = x; xx < x + t.ex; ++xx)
+                            kmin = std::min(kmin, cx->h_g1.empty() ? 0 : cx->h_g1[yy * cx->nx + xx]);
+                    t.flags = (int16_t)std::min<int>(std::max(kmin - z, 0), t.ez);
+                    cx->h_tiles.push_back(t);
+                }
+    }
+    // Order: z band, then Morton order of the tile origin in 16-cell units.  The
+    // launch hands each XCD a contiguous run of this list, so the blocks resident
+    // on one XCD cover a compact patch at similar heights and share their halo
+    // cache lines in that XCD's L2.
+    auto morton = [](uint32_t x, uint32_t y) {
+        uint64_t m = 0;
+        for (int b = 0; b < 16; ++b) m |= (uint64_t)((x >> b) & 1) << (2 * b) | (uint64_t)((y >> b) & 1) << (2 * b + 1);
+        return m;
+    };
+    std::stable_sort(cx->h_tiles.begin(), cx->h_tiles.end(), [&](const ebs_tile& p, const ebs_tile& q) {
+        const int bp = p.z0 / TZ, bq = q.z0 / TZ;
+        if (bp != bq) return bp < bq;
+        return morton(p.x0 >> 4, p.y0 >> 4) < morton(q.x0 >> 4, q.y0 >> 4);
+    });
+    cx->ntiles = (int32_t)cx->h_tiles.size();
+    if (cx->d_tiles) (void)hipFree(cx->d_tiles);
+    cx->d_tiles = nullptr;
+    if (hipMalloc(&cx->d_tiles, sizeof(ebs_tile) * std::max(1, cx->ntiles)) != hipSuccess) {
+        cx->err = "tile list allocation failed";
+        return EBS_E_OOM;
+    }
+    EBS_HIP(cx, hipMemcpy(cx->d_tiles, cx->h_tiles.data(), sizeof(ebs_tile) * cx->ntiles,
+                          hipMemcpyHostToDevice));
+    // algorithmic bytes of the regular-region kernel: cells at or above g1
+    if (!cx->h_g1.empty()) {
+        double cells = 0;
+        for (int c = 0; c < cx->ncol; ++c) cells += (double)(cx->nz - cx->h_g1[c]);
+        const double es = cx->g.precision == EBS_F32_BULK ? 4.0 : 8.0;
+        cx->alg_bytes[0] = cells * 5 * es * 2;  // read Un (= Ucur), write
+        cx->alg_bytes[1] = cells * 5 * es * 3;  // read Un and Ucur, write
+    }
+    return EBS_OK;
+}
+
+ebs_status launch_bulk(ebs_ctx* cx, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uhat, double cdt,
+                       hipStream_t stream) {
+    if (cx->g.precision == EBS_F32_BULK) return launch_bulk_t<float>(cx, Un, Ucur, Uhat, cdt, stream);
+    return launch_bulk_t<double>(cx, Un, Ucur, Uhat, cdt, stream);
+}
+
+}  // namespace ebs

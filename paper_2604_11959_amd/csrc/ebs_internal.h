@@ -224,6 +224,9 @@ ebs_status launch_advance(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur
 ebs_status join_side(ebs_ctx* c);
 ebs_status build_tiles(ebs_ctx* c);
 ebs_status build_cut_faces(ebs_ctx* c);
+// regular-region kernel (bulk.hip) on the given stream, with its timing events
+ebs_status launch_bulk(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uhat, double cdt,
+                       hipStream_t stream);
 size_t bulk_lds_bytes(int tx, int ty, int precision);
 // redistribution (wsrd.hip)
 ebs_status wsrd_setup(ebs_ctx* c);

@@ -21,13 +21,17 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(HERE, "csrc", "stage.hip")
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", n) for n in ("bulk.hip", "stage_common.h")]
 COPY_BYTES = 1 << 30
 
 
-def source_sha256(path: str = KERNEL_SOURCE) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def source_sha256(paths=None) -> str:
+    """SHA-256 over the regular-region kernel's sources."""
+    h = hashlib.sha256()
+    for path in paths or KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def _per_dispatch(path: str, counter: str):

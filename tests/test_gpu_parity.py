@@ -247,6 +247,98 @@ def test_bottom_wall_and_flat_ground(terrain, precision, tiles, tol):
             assert np.all(h[f][~masks[f]] == 0.0), f
 
 
+
+def _window_state(U, i0, j0, wx, wy):
+    """The state of a window of columns, with the window's periodic face copies."""
+    W = {
+        "rho": U["rho"][:, j0:j0 + wy, i0:i0 + wx].copy(),
+        "rhotheta": U["rhotheta"][:, j0:j0 + wy, i0:i0 + wx].copy(),
+        "rhou": U["rhou"][:, j0:j0 + wy, i0:i0 + wx + 1].copy(),
+        "rhov": U["rhov"][:, j0:j0 + wy + 1, i0:i0 + wx].copy(),
+        "rhow": U["rhow"][:, j0:j0 + wy, i0:i0 + wx].copy(),
+    }
+    W["rhou"][:, :, -1] = W["rhou"][:, :, 0]
+    W["rhov"][:, -1, :] = W["rhov"][:, 0, :]
+    return W
+
+
+def test_full_size_benchmark_configuration_sampled_windows():
+    """The benchmark configuration at full size (512 x 512 x 128, 512 boxes,
+    FP32 bulk, the tile the benchmark uses, RK3 step captured in a HIP graph)
+    against the FP64 oracle on sampled windows.  One RK3 step reaches a few
+    cells per stage (flux stencil and redistribution radius), so the oracle run
+    on a 64 x 64-column window cut from the same terrain and state reproduces
+    the interior of the window (24-column margin) exactly."""
+    import json
+    import os
+
+    w = synth.make_workload(4)
+    n = w.grid.n
+    cache = os.path.join(os.path.dirname(ebs.__file__), "tiles_mi355x.json")
+    key = f"f32bulk_{n[0]}x{n[1]}x{n[2]}_b{len(w.boxes)}"
+    tile = json.load(open(cache))[key]
+    c = _ctx(w, precision=ebs.EBS_F32_BULK, boxes=w.boxes)
+    c.set_tile(*tile)
+    U0 = synth.make_state(w)
+    U = c.new_state(U0)
+    S = [c.new_state(), c.new_state()]
+    c.rk3_step(U, S, w.dt, use_graph=True)
+    torch.cuda.synchronize()
+    got = _host(U)
+    del U, S
+    # reference: one oracle RK3 step on each window
+    wx = wy = 64
+    m = 24
+    hn = w.h_nodes
+    centres = []
+    hc = hn[:-1, :-1]
+    for _ in range(2):  # the two highest hills, then a flat area
+        jj, ii = np.unravel_index(np.argmax(hc), hc.shape)
+        centres.append((ii, jj))
+        hc = hc.copy()
+        hc[max(jj - 64, 0):jj + 64, max(ii - 64, 0):ii + 64] = -1.0
+    flat = np.argwhere(hn[:-1, :-1] == 0.0)
+    centres.append((int(flat[len(flat) // 2][1]), int(flat[len(flat) // 2][0])))
+    for (ci, cj) in centres:
+        i0 = int(min(max(ci - wx // 2, 0), n[0] - wx - 1))
+        j0 = int(min(max(cj - wy // 2, 0), n[1] - wy - 1))
+        ww = synth.window(w, i0, j0, wx, wy, n[2])
+        o = oracle.Oracle(ww.grid, ww.h_nodes)
+        ref = o.rk3_step(_window_state(U0, i0, j0, wx, wy), w.dt)
+        gw = _window_state(got, i0, j0, wx, wy)
+        masks = _fluid_masks(o)
+        for f in FIELDS:
+            inner = np.zeros_like(masks[f])
+            inner[:, m:-m, m:-m] = True
+            masks[f] = masks[f] & inner
+        err = rel_err(gw, ref, masks)
+        print((i0, j0), err, flush=True)
+        assert max(err.values()) <= 2e-5, ((i0, j0), err)
+
+
+def test_terrain_on_a_grid_plane_stage_and_rk3():
+    """Flat terrain exactly on the plane z = 2 dz (faces on the terrain carry no
+    fluid; the first fluid layer is regular), plus the fully flat domain at
+    z = 0 through the RK3 driver and its graph; FP64 against the oracle."""
+    g = synth.Grid((24, 16, 12), (78.125, 78.125, 31.25))
+    for h0 in (2 * 31.25, 0.0):
+        w = synth.Workload("flat_on_plane", g, synth.terrain_flat(g, h0), synth.cfl_dt(g), 3,
+                           [((0, 0, 0), g.n)], "atmos")
+        o = oracle.Oracle(g, w.h_nodes)
+        c = _ctx(w)
+        U0 = synth.state_random(g, 41, amp=1.5)
+        for inst in range(4):
+            assert np.array_equal(c.export(inst, ebs.Q["TYPE"]), o.export_type(inst)), inst
+        ref = o.rk3_step(U0, w.dt)
+        for use_graph in (False, True, True):
+            U = c.new_state(U0)
+            S = [c.new_state(), c.new_state()]
+            c.rk3_step(U, S, w.dt, use_graph=use_graph)
+            torch.cuda.synchronize()
+            err = rel_err(_host(U), ref, _fluid_masks(o))
+            print(h0, use_graph, err, flush=True)
+            assert max(err.values()) <= 1e-12, (h0, use_graph, err)
+
 def test_trajectory_parity_c1_ten_stages():
     """Ten consecutive RK3 stages (three steps and the first stage of the
     fourth) on the hill, FP64, compared after every stage; conservation."""

@@ -41,6 +41,10 @@ def _grid(n=(16, 16, 8), periodic=0x3, vfrac=0.5, prec=0):
     (dict(prec=7), ebs.EBS_E_ARG),
     (dict(periodic=0x1), ebs.EBS_E_UNSUPPORTED),
     (dict(periodic=0x7), ebs.EBS_E_UNSUPPORTED),
+    (dict(n=(16, 16, 32768)), ebs.EBS_E_ARG),                 # nz above 32767
+    (dict(n=(2048, 2048, 513)), ebs.EBS_E_UNSUPPORTED),       # more than 2^31 cells
+    (dict(n=(1024, 1024, 600)), ebs.EBS_E_UNSUPPORTED),       # FP64 fields reach 4 GiB
+    (dict(n=(1024, 1024, 1200), prec=1), ebs.EBS_E_UNSUPPORTED),  # FP32 fields reach 4 GiB
 ])
 def test_create_rejects_bad_grids(kw, status):
     lib = ebs.load()
