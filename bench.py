@@ -40,7 +40,7 @@ def _log(msg):
 
 
 def run_workload(cfg: int, precision: int, steps: int, warmup: int, use_graph: bool,
-                 autotune: bool, timing: bool, tile=None):
+                 autotune: bool, timing: bool, tile=None, overlap: bool = False):
     import torch
 
     import paper_2604_11959_amd as ebs
@@ -53,6 +53,7 @@ def run_workload(cfg: int, precision: int, steps: int, warmup: int, use_graph: b
     t0 = time.time()
     ctx.build_geometry(w.h_nodes)
     _log(f"{w.name}: geometry built in {time.time() - t0:.1f}s")
+    ctx.set_overlap(overlap)
     if tile:
         ctx.set_tile(*tile)
     elif autotune:
@@ -133,9 +134,12 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c4", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--overlap", action="store_true",
+                    help="run the regular-region kernel concurrently with the general range")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--tile", default=None, help="fixed tile shape TXxTY or TXxTYxTZ (skips the autotuner)")
+    ap.add_argument("--tile", default=None,
+                    help="fixed tile TXxTYxTZxSPAN (SPAN 1: tiles cut from the whole domain; skips the autotuner)")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
@@ -162,7 +166,8 @@ def main(argv=None):
     precision = ebs.EBS_F64 if cfg == 2 else ebs.EBS_F32_BULK
     # main timed region: graph replays of the RK3 step
     tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
-    main = run_workload(cfg, precision, args.steps, args.warmup, not args.no_graph, True, False, tile)
+    overlap = args.overlap
+    main = run_workload(cfg, precision, args.steps, args.warmup, not args.no_graph, True, False, tile, overlap)
     w = main["workload"]
     N = w.grid.ncells
     ms_step = main["ms"] / args.steps
@@ -173,7 +178,7 @@ def main(argv=None):
         kt = main
         kt["kern"] = (float("nan"), 1)
     else:
-        kt = run_workload(cfg, precision, args.steps, 1, False, True, True, main["tile"])
+        kt = run_workload(cfg, precision, args.steps, 1, False, True, True, main["tile"], overlap)
     kms, nl = kt["kern"]
     avg_ms = kms / max(nl, 1)
     alg0, alg1 = kt["alg"]
@@ -199,8 +204,10 @@ def main(argv=None):
             "boxes": len(w.boxes),
             "precision": "fp32-bulk (fp64 geometry, cut region, WSRD, sums)"
             if precision == ebs.EBS_F32_BULK else "fp64",
-            "tile": list(main["tile"]) if main["tile"] else None,
+            "tile": list(main["tile"][:3]),
+            "tiling": "domain" if main["tile"][3] else "per box",
             "graph": not args.no_graph,
+            "overlap": overlap,
             "general_region_cells": int(stats[0][6]),
             "cut_cvs": [int(s[0]) for s in stats],
             "small_cvs": [int(s[1]) for s in stats],

@@ -179,13 +179,21 @@ ebs_status ebs_conserved_sums(ebs_ctx* ctx, const ebs_state* U, double hi[5], do
 ebs_status ebs_autotune(ebs_ctx* ctx, const char* cache_json_path);
 
 /* Tile shape of the regular-region kernel: tx x ty columns per block and at
- * most tz planes per tile (a tile never crosses a box boundary).  tx in
- * {16, 32, 64}, ty in {2, 4, 8, 16}, tx*ty in [64, 256], (tx+5)(ty+5) <=
- * 4 tx ty, LDS rings within 64 KiB (26 (tx+5)(ty+5) elements of the state
- * type); tz in {16, 32, 64}, or 0 to keep the current value.  EBS_E_ARG
+ * most tz planes per tile.  tx in {16, 32, 64}, ty in {2, 4, 8, 16}, tx*ty in
+ * [64, 256], (tx+5)(ty+5) <= 4 tx ty, LDS rings within 64 KiB (26 (tx+5)(ty+5)
+ * elements of the state type); tz in {16, 32, 64}, or 0 to keep the current
+ * value.  span = 0: the tiles of every box are cut separately (no tile crosses
+ * a box boundary); span = 1: the whole domain is tiled as one box (the box
+ * list then does not shape the work; results are the same).  EBS_E_ARG
  * otherwise. */
-ebs_status ebs_set_tile(ebs_ctx* ctx, int32_t tx, int32_t ty, int32_t tz);
-ebs_status ebs_get_tile(const ebs_ctx* ctx, int32_t* tx, int32_t* ty, int32_t* tz);
+ebs_status ebs_set_tile(ebs_ctx* ctx, int32_t tx, int32_t ty, int32_t tz, int32_t span);
+ebs_status ebs_get_tile(const ebs_ctx* ctx, int32_t* tx, int32_t* ty, int32_t* tz, int32_t* span);
+
+/* Run the regular-region kernel on a second stream, concurrently with the
+ * general-range passes and (inside ebs_rk3_step) the redistribution of the
+ * same stage (enable != 0), or serially on the context stream (0, the
+ * default).  The results are identical; the captured RK3 graph is rebuilt. */
+ebs_status ebs_set_overlap(ebs_ctx* ctx, int32_t enable);
 
 /* Kernel timing: when enabled, every launch of the regular-region stage
  * kernel is bracketed by HIP events on the context stream; read returns the

@@ -29,7 +29,7 @@ Q = dict(ALPHA=0, BETA_X=1, BETA_Y=2, BETA_Z=3, FX_Y=4, FX_Z=5, FY_X=6, FY_Z=7, 
 # every entry point declared in include/ebstag.h
 SYMBOLS = ("ebs_create", "ebs_build_geometry_terrain", "ebs_geometry_export", "ebs_geometry_stats",
            "ebs_advance_stage", "ebs_redistribute", "ebs_rk3_step", "ebs_conserved_sums",
-           "ebs_autotune", "ebs_set_tile", "ebs_get_tile", "ebs_timing_enable", "ebs_timing_read",
+           "ebs_autotune", "ebs_set_tile", "ebs_get_tile", "ebs_set_overlap", "ebs_timing_enable", "ebs_timing_read",
            "ebs_algorithmic_bytes", "ebs_last_error", "ebs_destroy")
 
 
@@ -76,8 +76,9 @@ def load(path: str = LIB_PATH):
         "ebs_rk3_step": [C.c_void_p, P(State), P(State), C.c_double, C.c_int32],
         "ebs_conserved_sums": [C.c_void_p, P(State), P(C.c_double), P(C.c_double)],
         "ebs_autotune": [C.c_void_p, C.c_char_p],
-        "ebs_set_tile": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32],
-        "ebs_get_tile": [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)],
+        "ebs_set_tile": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
+        "ebs_get_tile": [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)],
+        "ebs_set_overlap": [C.c_void_p, C.c_int32],
         "ebs_timing_enable": [C.c_void_p, C.c_int32],
         "ebs_timing_read": [C.c_void_p, P(C.c_double), P(C.c_int64)],
         "ebs_algorithmic_bytes": [C.c_void_p, P(C.c_double)],
@@ -221,14 +222,20 @@ class Context:
         self._check(self.lib.ebs_autotune(self.h, p), "ebs_autotune")
         return self.get_tile()
 
-    def set_tile(self, tx: int, ty: int, tz: int = 0):
-        """Tile of the regular-region kernel: tx x ty columns, tz planes (0 keeps it)."""
-        self._check(self.lib.ebs_set_tile(self.h, int(tx), int(ty), int(tz)), "ebs_set_tile")
+    def set_tile(self, tx: int, ty: int, tz: int = 0, span: int = 0):
+        """Tile of the regular-region kernel: tx x ty columns, tz planes (0 keeps
+        it); span 1 tiles the whole domain instead of each box."""
+        self._check(self.lib.ebs_set_tile(self.h, int(tx), int(ty), int(tz), int(span)), "ebs_set_tile")
+
+    def set_overlap(self, enable: bool):
+        """Regular-region kernel concurrent with the general range (True) or serial (default)."""
+        self._check(self.lib.ebs_set_overlap(self.h, int(bool(enable))), "ebs_set_overlap")
 
     def get_tile(self):
-        tx, ty, tz = C.c_int32(), C.c_int32(), C.c_int32()
-        self._check(self.lib.ebs_get_tile(self.h, C.byref(tx), C.byref(ty), C.byref(tz)), "ebs_get_tile")
-        return tx.value, ty.value, tz.value
+        tx, ty, tz, sp = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.lib.ebs_get_tile(self.h, C.byref(tx), C.byref(ty), C.byref(tz), C.byref(sp)),
+                    "ebs_get_tile")
+        return tx.value, ty.value, tz.value, sp.value
 
     def timing(self, enable: bool):
         self._check(self.lib.ebs_timing_enable(self.h, int(enable)), "ebs_timing_enable")

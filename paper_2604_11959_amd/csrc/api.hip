@@ -194,7 +194,7 @@ ebs_status ebs_destroy(ebs_ctx* c) {
     if (c->side) (void)hipStreamDestroy(c->side);
     void* ptrs[] = {c->d_kf,   c->d_kr,        c->d_g0,      c->d_g1,   c->d_goff, c->d_gcol,
                     c->d_geo,  c->d_type,      c->d_mask,    c->d_small, c->d_tier, c->d_w,
-                    c->d_smalllist, c->d_actlist, c->d_lsq_off, c->d_lsq_idx, c->d_lsq_c, c->d_lsq_ev, c->d_lsq_nev, c->d_wl_off, c->d_wl_idx, c->d_wl_geo, c->d_wl_self, c->d_wl_small, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles, c->d_prim, c->d_fh, c->d_type4, c->d_col, c->d_gcole, c->d_fflag, c->d_cbase, c->d_crec,
+                    c->d_smalllist, c->d_actlist, c->d_lsq_off, c->d_lsq_idx, c->d_lsq_c, c->d_lsq_ev, c->d_lsq_nev, c->d_wl_off, c->d_wl_idx, c->d_wl_geo, c->d_wl_self, c->d_wl_small, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles, c->d_prim, c->d_fh, c->d_type4, c->d_col, c->d_gcole, c->d_fflag, c->d_cbase, c->d_crec, c->d_bfc,
                     c->d_part, c->d_dummy};
     for (void* p : ptrs) free_ptr(p);
     delete c;
@@ -422,12 +422,13 @@ ebs_status ebs_conserved_sums(ebs_ctx* c, const ebs_state* U, double hi[5], doub
     return conserved_sums(c, U, hi, lo);
 }
 
-ebs_status ebs_set_tile(ebs_ctx* c, int32_t tx, int32_t ty, int32_t tz) {
+ebs_status ebs_set_tile(ebs_ctx* c, int32_t tx, int32_t ty, int32_t tz, int32_t span) {
     if (!c) return EBS_E_ARG;
     if (!(tx == 16 || tx == 32 || tx == 64) || !(ty == 2 || ty == 4 || ty == 8 || ty == 16) ||
         tx * ty < 64 || tx * ty > 256)
         return fail(c, EBS_E_ARG, "unsupported tile shape");
     if (!(tz == 0 || tz == 16 || tz == 32 || tz == 64)) return fail(c, EBS_E_ARG, "unsupported tile height");
+    if (span != 0 && span != 1) return fail(c, EBS_E_ARG, "tile span must be 0 or 1");
     if ((tx + 5) * (ty + 5) > 4 * tx * ty)
         return fail(c, EBS_E_ARG, "tile shape has more halo points than the block covers");
     if (bulk_lds_bytes(tx, ty, c->g.precision) > 64 * 1024)
@@ -435,16 +436,25 @@ ebs_status ebs_set_tile(ebs_ctx* c, int32_t tx, int32_t ty, int32_t tz) {
     c->tile_x = tx;
     c->tile_y = ty;
     if (tz) c->tile_z = tz;
+    c->tile_span = span;
     drop_graph(c);
     if (c->have_geom) return build_tiles(c);
     return EBS_OK;
 }
 
-ebs_status ebs_get_tile(const ebs_ctx* c, int32_t* tx, int32_t* ty, int32_t* tz) {
-    if (!c || !tx || !ty || !tz) return EBS_E_ARG;
+ebs_status ebs_set_overlap(ebs_ctx* c, int32_t enable) {
+    if (!c) return EBS_E_ARG;
+    c->overlap = enable != 0;
+    drop_graph(c);
+    return EBS_OK;
+}
+
+ebs_status ebs_get_tile(const ebs_ctx* c, int32_t* tx, int32_t* ty, int32_t* tz, int32_t* span) {
+    if (!c || !tx || !ty || !tz || !span) return EBS_E_ARG;
     *tx = c->tile_x;
     *ty = c->tile_y;
     *tz = c->tile_z;
+    *span = c->tile_span;
     return EBS_OK;
 }
 
@@ -494,9 +504,9 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
             const std::string pat = std::string("\"") + key + "\": [";
             const size_t p = txt.find(pat);
             if (p != std::string::npos) {
-                int tx = 0, ty = 0, tz = 0;
-                if (std::sscanf(txt.c_str() + p + pat.size(), "%d, %d, %d", &tx, &ty, &tz) == 3 &&
-                    ebs_set_tile(c, tx, ty, tz) == EBS_OK)
+                int tx = 0, ty = 0, tz = 0, sp = 0;
+                if (std::sscanf(txt.c_str() + p + pat.size(), "%d, %d, %d, %d", &tx, &ty, &tz, &sp) == 4 &&
+                    ebs_set_tile(c, tx, ty, tz, sp) == EBS_OK)
                     return EBS_OK;
             }
         }
@@ -523,15 +533,15 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
     const int cxy[][2] = {{16, 4}, {16, 8}, {16, 16}, {32, 4}, {32, 8}, {64, 2}, {64, 4}};
     const int cz[] = {16, 32, 64};
     double best = 1e300;
-    int bx = c->tile_x, by = c->tile_y, bz = c->tile_z;
+    int bx = c->tile_x, by = c->tile_y, bz = c->tile_z, bs = c->tile_span;
     const bool was_timing = c->timing;
     c->timing = false;
     hipEvent_t e0, e1;
     EBS_HIP(c, hipEventCreate(&e0));
     EBS_HIP(c, hipEventCreate(&e1));
-    for (int q = 0; q < (int)(sizeof(cxy) / sizeof(cxy[0]) * 3); ++q) {
-        const int cd[3] = {cxy[q / 3][0], cxy[q / 3][1], cz[q % 3]};
-        if (ebs_set_tile(c, cd[0], cd[1], cd[2]) != EBS_OK) continue;
+    for (int q = 0; q < (int)(sizeof(cxy) / sizeof(cxy[0]) * 6); ++q) {
+        const int cd[4] = {cxy[q / 6][0], cxy[q / 6][1], cz[(q / 2) % 3], q % 2};
+        if (ebs_set_tile(c, cd[0], cd[1], cd[2], cd[3]) != EBS_OK) continue;
         for (int rep = 0; rep < 2; ++rep) (void)launch_advance(c, &st[0], &st[0], &st[1], 0.0);
         (void)hipEventRecord(e0, c->stream);
         const int reps = 5;
@@ -540,14 +550,14 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
         (void)hipEventSynchronize(e1);
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) { best = ms; bx = cd[0]; by = cd[1]; bz = cd[2]; }
+        if (ms < best) { best = ms; bx = cd[0]; by = cd[1]; bz = cd[2]; bs = cd[3]; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->timing = was_timing;
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 5; ++b) free_ptr(buf[a][b]);
-    ebs_status sst = ebs_set_tile(c, bx, by, bz);
+    ebs_status sst = ebs_set_tile(c, bx, by, bz, bs);
     if (sst != EBS_OK) return sst;
     if (cache_json_path) {
         std::string txt;
@@ -562,7 +572,7 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
         // append the entry to a flat JSON object
         const size_t close = txt.rfind('}');
         char ent[256];
-        std::snprintf(ent, sizeof(ent), "\"%s\": [%d, %d, %d]", key, bx, by, bz);
+        std::snprintf(ent, sizeof(ent), "\"%s\": [%d, %d, %d, %d]", key, bx, by, bz, bs);
         if (close == std::string::npos) {
             txt = std::string("{\n  ") + ent + "\n}\n";
         } else {

@@ -441,7 +441,9 @@ size_t bulk_lds_bytes(int tx, int ty, int precision) {
 ebs_status build_tiles(ebs_ctx* cx) {
     cx->h_tiles.clear();
     const int TX = cx->tile_x, TY = cx->tile_y, TZ = cx->tile_z;
-    for (const ebs_box& b : cx->boxes) {
+    const ebs_box whole = {{0, 0, 0}, {cx->nx, cx->ny, cx->nz}};
+    const std::vector<ebs_box> spans(1, whole);
+    for (const ebs_box& b : cx->tile_span ? spans : cx->boxes) {
         for (int z = b.lo[2]; z < b.hi[2]; z += TZ)
             for (int y = b.lo[1]; y < b.hi[1]; y += TY)
                 for (int x = b.lo[0]; x < b.hi[0]; x += TX) {

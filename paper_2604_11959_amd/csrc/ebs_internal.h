@@ -138,6 +138,7 @@ struct ebs_ctx {
     hipStream_t side = nullptr;        // regular-region kernel, concurrent with the general range
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool join_pending = false;
+    bool overlap = false;              // use the side stream (ebs_set_overlap)
     std::vector<ebs_box> boxes;
     std::string err = "no error";
 
@@ -156,6 +157,7 @@ struct ebs_ctx {
     uint32_t* d_fflag = nullptr;     // [G]
     int32_t* d_cbase = nullptr;      // [G] first cut-face record of each general cell
     void* d_crec = nullptr;          // cut-face interpolation records (stage.hip)
+    double* d_bfc = nullptr;         // [2][ncut] interpolated flux per record (per stage)
     int32_t ncut = 0;
     double* d_geo = nullptr;
     int8_t* d_type = nullptr;
@@ -195,6 +197,7 @@ struct ebs_ctx {
 
     // regular-region tiles
     int tile_x = 32, tile_y = 8, tile_z = 64;
+    int tile_span = 0;  // 1: tiles cut from the whole domain instead of per box
     std::vector<ebs_tile> h_tiles;
     ebs_tile* d_tiles = nullptr;
     int32_t ntiles = 0;

@@ -55,6 +55,8 @@ struct GenArgs {
     double* fh;    // [5][3][Ge] provisional flux on the lower faces
     const int32_t* cbase;  // [G] first cut-face record of each general cell
     const struct CutRec* crec;
+    double* bfc;           // [2][ncut] area fraction x interpolated flux per record
+    int32_t ncut;
     double cdt;
     double rdel[3];
     int eb_mode;
@@ -68,6 +70,8 @@ struct GenArgs {
 // consecutive, in the order of (instance, direction) of its partial faces.
 struct CutRec {
     int32_t n[3];
+    int32_t own;  // extended index of the face's own CV
+    int32_t sd;   // instance * 3 + direction
     int32_t pad;
     double b;
     double c[4];
@@ -245,16 +249,13 @@ struct Gen {
         constexpr int s = F < 2 ? 0 : F - 1;
         if (P.k == a.D.nz) return 0.0;  // top wall: zero flux
         if (!(P.ff & ff_pos(s, D))) return 0.0;
-        if (P.ge < 0) F0 = fhat_at<F, D>(P);  // outside the stored face range
+        // (every face read here lies in the stored face range: g1e is at least
+        // the -x and -y neighbours' g1, and g1 + 1 for a non-empty range)
         if (P.ff & ff_full(s, D)) return F0;
+        // partial face: interpolated by the cut-face pass (record order)
         const uint32_t part = (P.ff & 0xFFFu) & ~(P.ff >> 16);
-        const CutRec& r = a.crec[a.cbase[P.g] + __popc(part & (ff_pos(s, D) - 1u))];
-        const double* fhd = a.fh + ((size_t)F * 3 + D) * a.v.Ge;
-        double Fv = r.c[0] * F0;
-        if (r.n[0] >= 0) Fv += r.c[1] * fhd[r.n[0]];
-        if (r.n[1] >= 0) Fv += r.c[2] * fhd[r.n[1]];
-        if (r.n[2] >= 0) Fv += r.c[3] * fhd[r.n[2]];
-        return r.b * Fv;
+        const int r = a.cbase[P.g] + __popc(part & (ff_pos(s, D) - 1u));
+        return a.bfc[(F == 1 ? (size_t)a.ncut : 0) + r];
     }
     // area fraction with a runtime instance (set-up only)
     template <int D>
@@ -275,6 +276,8 @@ struct Gen {
     __device__ bool cut_record(int s, const Pt& P, CutRec& r) const {
         const double b = geo(s, GQ_BX + D, P.g);
         r.n[0] = r.n[1] = r.n[2] = -1;
+        r.own = P.ge;
+        r.sd = s * 3 + D;
         r.pad = 0;
         r.b = b;
         r.c[0] = 1.0;
@@ -492,6 +495,27 @@ __global__ void __launch_bounds__(256) k_gen_update(GenArgs<T> a) {
     G.template update<4>(P, Ux, Uy, Uz, g);
 }
 
+// Area fraction x flux moved to the centroid on every partial face, for the
+// field(s) of the face's instance (slot 1: rho theta of the cell-centred CVs).
+template <typename T>
+__global__ void __launch_bounds__(256) k_gen_cut(GenArgs<T> a) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.ncut) return;
+    const CutRec c = a.crec[r];
+    const int s = c.sd / 3, d = c.sd - 3 * s;
+    const int n0 = max(c.n[0], 0), n1 = max(c.n[1], 0), n2 = max(c.n[2], 0);
+    for (int q = 0; q < (s == 0 ? 2 : 1); ++q) {
+        const int f = s == 0 ? q : s + 1;
+        const double* fhd = a.fh + ((size_t)f * 3 + d) * a.v.Ge;
+        const double F0 = fhd[c.own], F1 = fhd[n0], F2 = fhd[n1], F3 = fhd[n2];
+        double Fv = c.c[0] * F0;
+        if (c.n[0] >= 0) Fv += c.c[1] * F1;
+        if (c.n[1] >= 0) Fv += c.c[2] * F2;
+        if (c.n[2] >= 0) Fv += c.c[3] * F3;
+        a.bfc[(size_t)q * a.ncut + r] = c.b * Fv;
+    }
+}
+
 // number of partial lower faces (area fraction > 0 and not exactly 1) per general cell
 __global__ void __launch_bounds__(256) k_cut_count(GeoView v, int32_t* cnt) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -556,7 +580,10 @@ ebs_status build_cut_faces(ebs_ctx* cx) {
         return EBS_E_UNSUPPORTED;
     }
     cx->ncut = (int32_t)tot;
-    if (hipMalloc(&cx->d_crec, sizeof(CutRec) * std::max<int64_t>(tot, 1)) != hipSuccess) {
+    if (cx->d_bfc) (void)hipFree(cx->d_bfc);
+    cx->d_bfc = nullptr;
+    if (hipMalloc(&cx->d_crec, sizeof(CutRec) * std::max<int64_t>(tot, 1)) != hipSuccess ||
+        hipMalloc(&cx->d_bfc, sizeof(double) * 2 * std::max<int64_t>(tot, 1)) != hipSuccess) {
         (void)hipFree(d_bad);
         cx->err = "cut-face table allocation failed";
         return EBS_E_OOM;
@@ -587,7 +614,7 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
     // The regular-region kernel and the general-range passes write disjoint
     // cells and read U_cur (never an output), so the former runs on the side
     // stream, forked from and joined back into the context stream.
-    const bool fork = cx->side && cx->ntiles > 0 && cx->G > 0;
+    const bool fork = cx->overlap && cx->side && cx->ntiles > 0 && cx->G > 0;
     hipStream_t bs = cx->stream;
     if (fork) {
         EBS_HIP(cx, hipEventRecord(cx->ev_fork, cx->stream));
@@ -617,6 +644,8 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
         a.fh = cx->d_fh;
         a.cbase = cx->d_cbase;
         a.crec = (const CutRec*)cx->d_crec;
+        a.bfc = cx->d_bfc;
+        a.ncut = cx->ncut;
         a.cdt = cdt;
         for (int d = 0; d < 3; ++d) a.rdel[d] = 1.0 / cx->g.dx[d];
         a.eb_mode = cx->g.eb_flux;
@@ -625,6 +654,8 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
         // the output (which may alias U^n, never U_cur)
         hipLaunchKernelGGL(k_gen_prims<T>, grid, blk, 0, cx->stream, a);
         hipLaunchKernelGGL(k_gen_fhat<T>, gride, blk, 0, cx->stream, a);
+        if (cx->ncut > 0)
+            hipLaunchKernelGGL(k_gen_cut<T>, dim3((cx->ncut + 255) / 256), blk, 0, cx->stream, a);
         hipLaunchKernelGGL(k_gen_update<T>, grid, blk, 0, cx->stream, a);
         EBS_HIP(cx, hipGetLastError());
     }

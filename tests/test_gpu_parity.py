@@ -201,7 +201,7 @@ def _hills_with_flat_ground(nz=40):
 @pytest.mark.parametrize("terrain", ["hills", "flat"])
 @pytest.mark.parametrize("precision,tiles,tol", [
     (ebs.EBS_F64, ((16, 4, 16), (16, 8, 64)), 1e-12),
-    (ebs.EBS_F32_BULK, ((16, 16, 16), (32, 8, 32)), 2e-5),
+    (ebs.EBS_F32_BULK, ((16, 16, 16), (32, 8, 32), (32, 8, 64, 1)), 2e-5),
 ])
 def test_bottom_wall_and_flat_ground(terrain, precision, tiles, tol):
     """Columns with no cut CV nearby have an empty general range: the
@@ -427,9 +427,31 @@ def test_free_stream_mode_c2():
         assert np.abs(h[f] - ref)[m[f]].max() <= 1e-12 * scale, f
 
 
+@pytest.mark.parametrize("precision", [ebs.EBS_F64, ebs.EBS_F32_BULK])
+def test_overlap_gives_identical_bits(precision):
+    """The regular-region kernel on a second stream, concurrent with the
+    general range and the redistribution, gives the same bits as the serial
+    order, eagerly and through the captured graph (replayed three times)."""
+    w = synth.make_workload(2)
+    U0 = synth.make_state(w)
+    boxes = synth.boxes_split(w.grid.n, 7, 40, block=32, unit=16)
+    res = []
+    for overlap, use_graph in ((False, False), (True, False), (True, True)):
+        c = _ctx(w, precision=precision, boxes=boxes)
+        c.set_overlap(overlap)
+        U = c.new_state(U0)
+        S = [c.new_state(), c.new_state()]
+        for _ in range(3):
+            c.rk3_step(U, S, w.dt, use_graph=use_graph)
+            torch.cuda.synchronize()
+        res.append(_host(U))
+    for r in res[1:]:
+        for f in FIELDS:
+            assert np.array_equal(r[f], res[0][f]), f
+
 @pytest.mark.parametrize("precision,tiles", [
     (ebs.EBS_F64, ((16, 4), (16, 8))),
-    (ebs.EBS_F32_BULK, ((16, 4), (16, 16), (32, 8), (64, 2))),
+    (ebs.EBS_F32_BULK, ((16, 4), (16, 16), (32, 8), (64, 2), (32, 8, 64, 1), (64, 4, 16, 1))),
 ])
 def test_box_list_and_tiles_do_not_change_results(precision, tiles):
     """Uneven AMR-style boxes and different tile shapes give identical bits."""
