@@ -225,7 +225,7 @@ def main(argv=None):
         },
     }
     if not args.no_fp64 and cfg != 2:
-        r2 = run_workload(2, ebs.EBS_F64, args.steps, args.warmup, not args.no_graph, False, False)
+        r2 = run_workload(2, ebs.EBS_F64, args.steps, args.warmup, not args.no_graph, True, False)
         ms2 = r2["ms"] / args.steps
         out["fp64_single_box"] = {"workload": r2["workload"].name,
                                   "value": round(r2["workload"].grid.ncells * 3 / (ms2 * 1e-3) / 1e6, 1),

@@ -163,6 +163,10 @@ ebs_status ebs_create(const ebs_grid* grid, const ebs_box* boxes, int32_t nbox, 
                 return EBS_E_ARG;
             }
     }
+    // LDS a block may use (the regular-region tiles are checked against it)
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, 0) == hipSuccess && lds_max > 0)
+        c->lds_max = lds_max;
     // side stream (default priority) and fork / join events for running the
     // regular-region kernel concurrently with the general range
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
@@ -425,13 +429,13 @@ ebs_status ebs_conserved_sums(ebs_ctx* c, const ebs_state* U, double hi[5], doub
 ebs_status ebs_set_tile(ebs_ctx* c, int32_t tx, int32_t ty, int32_t tz, int32_t span) {
     if (!c) return EBS_E_ARG;
     if (!(tx == 16 || tx == 32 || tx == 64) || !(ty == 2 || ty == 4 || ty == 8 || ty == 16) ||
-        tx * ty < 64 || tx * ty > 256)
+        tx * ty < 64 || tx * ty > 1024)
         return fail(c, EBS_E_ARG, "unsupported tile shape");
     if (!(tz == 0 || tz == 16 || tz == 32 || tz == 64)) return fail(c, EBS_E_ARG, "unsupported tile height");
     if (span != 0 && span != 1) return fail(c, EBS_E_ARG, "tile span must be 0 or 1");
     if ((tx + 5) * (ty + 5) > 4 * tx * ty)
         return fail(c, EBS_E_ARG, "tile shape has more halo points than the block covers");
-    if (bulk_lds_bytes(tx, ty, c->g.precision) > 64 * 1024)
+    if (bulk_lds_bytes(tx, ty, c->g.precision) > (size_t)c->lds_max)
         return fail(c, EBS_E_ARG, "tile shape needs more LDS than a block may use");
     c->tile_x = tx;
     c->tile_y = ty;
@@ -530,7 +534,7 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
     }
     // timing only: the values (zeros) do not change the work done
     (void)hipStreamSynchronize(c->stream);
-    const int cxy[][2] = {{16, 4}, {16, 8}, {16, 16}, {32, 4}, {32, 8}, {64, 2}, {64, 4}};
+    const int cxy[][2] = {{16, 4}, {16, 8}, {16, 16}, {32, 4}, {32, 8}, {32, 16}, {64, 2}, {64, 4}, {64, 8}, {64, 16}};
     const int cz[] = {16, 32, 64};
     double best = 1e300;
     int bx = c->tile_x, by = c->tile_y, bz = c->tile_z, bs = c->tile_span;

@@ -416,10 +416,14 @@ ebs_status launch_bulk_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* Ucur
             const dim3 grid(a.per_xcd * NXCD), blk(cx->tile_x, cx->tile_y);
 #define EBS_BULK_CASE(X, Y)                                                                   \
     if (cx->tile_x == X && cx->tile_y == Y) {                                                 \
+        if (lds > 64 * 1024)                                                                  \
+            EBS_HIP(cx, hipFuncSetAttribute((const void*)k_bulk<T, X, Y>,                      \
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
         hipLaunchKernelGGL((k_bulk<T, X, Y>), grid, blk, lds, bs, a);                         \
     } else
             EBS_BULK_CASE(16, 4) EBS_BULK_CASE(16, 8) EBS_BULK_CASE(16, 16) EBS_BULK_CASE(32, 4)
-            EBS_BULK_CASE(32, 8) EBS_BULK_CASE(64, 2) EBS_BULK_CASE(64, 4) {
+            EBS_BULK_CASE(32, 8) EBS_BULK_CASE(32, 16) EBS_BULK_CASE(64, 2) EBS_BULK_CASE(64, 4)
+            EBS_BULK_CASE(64, 8) EBS_BULK_CASE(64, 16) {
                 cx->err = "tile shape without a compiled kernel";
                 return EBS_E_UNSUPPORTED;
             }

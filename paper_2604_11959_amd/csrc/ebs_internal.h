@@ -198,6 +198,7 @@ struct ebs_ctx {
     // regular-region tiles
     int tile_x = 32, tile_y = 8, tile_z = 64;
     int tile_span = 0;  // 1: tiles cut from the whole domain instead of per box
+    int lds_max = 64 * 1024;  // LDS per block of the device
     std::vector<ebs_tile> h_tiles;
     ebs_tile* d_tiles = nullptr;
     int32_t ntiles = 0;

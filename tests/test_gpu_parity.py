@@ -201,7 +201,7 @@ def _hills_with_flat_ground(nz=40):
 @pytest.mark.parametrize("terrain", ["hills", "flat"])
 @pytest.mark.parametrize("precision,tiles,tol", [
     (ebs.EBS_F64, ((16, 4, 16), (16, 8, 64)), 1e-12),
-    (ebs.EBS_F32_BULK, ((16, 16, 16), (32, 8, 32), (32, 8, 64, 1)), 2e-5),
+    (ebs.EBS_F32_BULK, ((16, 16, 16), (32, 8, 32), (32, 8, 64, 1), (64, 16, 64, 1)), 2e-5),
 ])
 def test_bottom_wall_and_flat_ground(terrain, precision, tiles, tol):
     """Columns with no cut CV nearby have an empty general range: the
@@ -450,8 +450,9 @@ def test_overlap_gives_identical_bits(precision):
             assert np.array_equal(r[f], res[0][f]), f
 
 @pytest.mark.parametrize("precision,tiles", [
-    (ebs.EBS_F64, ((16, 4), (16, 8))),
-    (ebs.EBS_F32_BULK, ((16, 4), (16, 16), (32, 8), (64, 2), (32, 8, 64, 1), (64, 4, 16, 1))),
+    (ebs.EBS_F64, ((16, 4), (16, 8), (32, 8, 64, 1), (32, 16, 32, 1))),
+    (ebs.EBS_F32_BULK, ((16, 4), (16, 16), (32, 8), (64, 2), (32, 8, 64, 1), (64, 4, 16, 1),
+                        (64, 16, 64, 1), (64, 8, 32, 1), (32, 16, 16, 0))),
 ])
 def test_box_list_and_tiles_do_not_change_results(precision, tiles):
     """Uneven AMR-style boxes and different tile shapes give identical bits."""
