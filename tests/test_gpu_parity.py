@@ -316,6 +316,49 @@ def test_full_size_benchmark_configuration_sampled_windows():
         assert max(err.values()) <= 2e-5, ((i0, j0), err)
 
 
+
+def test_ridges_1024x1024x192_sampled_windows():
+    """The ridge workload at full size (1024 x 1024 x 192, 3072 boxes, steep
+    hipped-roof ridges, FP32 bulk, domain tiles 64 x 16 x 64) against the FP64
+    oracle on windows around the steepest ridges and on flat ground."""
+    w = synth.make_workload(5)
+    n = w.grid.n
+    c = _ctx(w, precision=ebs.EBS_F32_BULK, boxes=w.boxes)
+    c.set_tile(64, 16, 64, 1)
+    U0 = synth.make_state(w)
+    U = c.new_state(U0)
+    S = [c.new_state(), c.new_state()]
+    c.rk3_step(U, S, w.dt, use_graph=True)
+    torch.cuda.synchronize()
+    got = _host(U)
+    del U, S
+    wx = wy = 56
+    m = 22
+    hn = w.h_nodes
+    # steepest node-to-node slope, the highest point, flat ground
+    slope = np.abs(np.diff(hn, axis=1))[:-1, :] + np.abs(np.diff(hn, axis=0))[:, :-1]
+    jj, ii = np.unravel_index(np.argmax(slope), slope.shape)
+    centres = [(ii, jj)]
+    jj, ii = np.unravel_index(np.argmax(hn[:-1, :-1]), (n[1], n[0]))
+    centres.append((ii, jj))
+    flat = np.argwhere(hn[:-1, :-1] == 0.0)
+    centres.append((int(flat[len(flat) // 3][1]), int(flat[len(flat) // 3][0])))
+    for (ci, cj) in centres:
+        i0 = int(min(max(ci - wx // 2, 0), n[0] - wx - 1))
+        j0 = int(min(max(cj - wy // 2, 0), n[1] - wy - 1))
+        ww = synth.window(w, i0, j0, wx, wy, n[2])
+        o = oracle.Oracle(ww.grid, ww.h_nodes)
+        ref = o.rk3_step(_window_state(U0, i0, j0, wx, wy), w.dt)
+        gw = _window_state(got, i0, j0, wx, wy)
+        masks = _fluid_masks(o)
+        for f in FIELDS:
+            inner = np.zeros_like(masks[f])
+            inner[:, m:-m, m:-m] = True
+            masks[f] = masks[f] & inner
+        err = rel_err(gw, ref, masks)
+        print((i0, j0), err, flush=True)
+        assert max(err.values()) <= 2e-5, ((i0, j0), err)
+
 def test_terrain_on_a_grid_plane_stage_and_rk3():
     """Flat terrain exactly on the plane z = 2 dz (faces on the terrain carry no
     fluid; the first fluid layer is regular), plus the fully flat domain at
