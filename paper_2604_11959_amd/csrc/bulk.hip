@@ -95,10 +95,12 @@ __device__ __forceinline__ void st(T* base, uint32_t off, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(off * (uint32_t)sizeof(T))) = v;
 }
 
-template <typename T, int TX, int TY>
+// SAME: U^n and U_cur are the same state (the first stage), so the own-cell
+// values of U^n are taken from the region loads instead of being read again.
+template <typename T, int TX, int TY, bool SAME>
 __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
-    constexpr int WX = TX + 5, WS = WX * (TY + 5), NTHR = TX * TY;
-    constexpr int NPTS = (WS + NTHR - 1) / NTHR;
+    constexpr int WX = TX + 5, WS = WX * (TY + 5), NTHR = TX * TY, NH = WS - NTHR;
+    constexpr int NPTS = 1 + (NH + NTHR - 1) / NTHR;
     static_assert(NPTS <= HALO_PTS, "halo points per thread");
     extern __shared__ unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
@@ -122,11 +124,32 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
     }
     const int k0 = tl.z0 + tl.flags;  // first plane with regular-region work (block uniform)
     if (k0 >= z1) return;
+    // Region points of this thread (row-major index into the (TX+5) x (TY+5)
+    // region): point 0 is its own column's cell; points q >= 1 are the halo
+    // points numbered tid + (q - 1) NTHR (rows 0-2, then the 3 + 2 side points
+    // of each interior row, then the last two rows); lr = -1 past the last.
+    const int me = (ty + 3) * WX + (tx + 3);
+    int lr[NPTS];
     uint32_t rc[NPTS], ru[NPTS];
 #pragma unroll
     for (int q = 0; q < NPTS; ++q) {
-        const int r = tid + q * NTHR;
-        const int x = wrapi(tl.x0 - 3 + r % WX, nx), y = wrapi(tl.y0 - 3 + r / WX, ny);
+        int r = me;
+        if (q > 0) {
+            int h = tid + (q - 1) * NTHR;
+            if (h >= NH) {
+                r = -1;
+            } else if (h < 3 * WX) {
+                r = h;
+            } else if ((h -= 3 * WX) < 5 * TY) {
+                const int c = h % 5;
+                r = (3 + h / 5) * WX + (c < 3 ? c : TX + c);
+            } else {
+                r = (TY + 3) * WX + (h - 5 * TY);
+            }
+        }
+        lr[q] = r;
+        const int rr = max(r, 0);
+        const int x = wrapi(tl.x0 - 3 + rr % WX, nx), y = wrapi(tl.y0 - 3 + rr / WX, ny);
         rc[q] = (uint32_t)(y * nx + x);
         ru[q] = (uint32_t)(y * (nx + 1) + x);
     }
@@ -140,8 +163,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
         const uint32_t oc0 = (uint32_t)p * pc, ou0 = (uint32_t)p * pu;
 #pragma unroll
         for (int q = 0; q < NPTS; ++q) {
-            const int r = tid + q * NTHR;
-            if (q == NPTS - 1 && r >= WS) break;
+            if (q > 0 && lr[q] < 0) break;
             if (in) {
                 pf[q][0] = ld(a.cur[0], oc0 + rc[q]);
                 pf[q][1] = ld(a.cur[1], oc0 + rc[q]);
@@ -161,8 +183,8 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
         T* RW = sm + (L_RW + (p & 3)) * WS;
 #pragma unroll
         for (int q = 0; q < NPTS; ++q) {
-            const int r = tid + q * NTHR;
-            if (q == NPTS - 1 && r >= WS) break;
+            const int r = lr[q];
+            if (q > 0 && r < 0) break;
             RHO[r] = pf[q][0];
             rth[q] = pf[q][1];
             RU[r] = pf[q][2];
@@ -180,8 +202,8 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
         const bool in = p >= 0 && p < nz;
 #pragma unroll
         for (int q = 0; q < NPTS; ++q) {
-            const int r = tid + q * NTHR;
-            if (q == NPTS - 1 && r >= WS) break;
+            const int r = lr[q];
+            if (q > 0 && r < 0) break;
             if (r < WX || r % WX == 0) continue;
             T th = T(0), u = T(0), v = T(0), w = T(0);
             if (in) {
@@ -197,7 +219,6 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             P[3 * 3 * WS + r] = w;
         }
     };
-    const int me = (ty + 3) * WX + (tx + 3);
     const int dxm = (i == 0) ? nx - 1 : -1;
     const int dym = (j == 0) ? ny - 1 : -1;
     const uint32_t c0 = (uint32_t)(j * nx + i), u0 = (uint32_t)(j * (nx + 1) + i);
@@ -205,15 +226,20 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
     prims_direct<T>(a, c0, u0, dxm, dym * nx, k0 - 2, pc, pu, pv, m2);
     prims_direct<T>(a, c0, u0, dxm, dym * nx, k0 - 1, pc, pu, pv, m1);
     // Raw planes run two z-iterations ahead in two register sets (pfA, pfB,
-    // alternating), the own-cell Un values likewise (unA, unB).
+    // alternating), the own-cell Un values likewise (unA, unB).  With SAME,
+    // unA / unB keep rho and rho theta of the own cell from the region loads
+    // (point 0) and the momenta are read from the LDS rings.
+    T unA[5], unB[5];
     fetch(k0 - 1, pfA);
     commit(k0 - 1, pfA);
     fetch(k0, pfA);
+    if (SAME) unA[0] = pfA[0][0], unA[1] = pfA[0][1];
     commit(k0, pfA);
     fetch(k0 + 1, pfA);
     __syncthreads();
     make_prims(k0);
     __syncthreads();  // the density slot of plane k0 - 1 is reused by plane k0 + 1
+    if (SAME) unB[0] = pfA[0][0], unB[1] = pfA[0][1];
     commit(k0 + 1, pfA);
     fetch(k0 + 2, pfA);
     fetch(k0 + 3, pfB);
@@ -233,14 +259,17 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             for (int f = 0; f < 5; ++f) dst[f] = T(0);
         }
     };
-    T unA[5], unB[5];
     T fzc[4] = {T(0), T(0), T(0), T(0)};  // upper z-face flux terms of the last plane
-    fetch_un(k0, unA);
-    fetch_un(k0 + 1, unB);
+    if (!SAME) {
+        fetch_un(k0, unA);
+        fetch_un(k0 + 1, unB);
+    }
     const T sixth = T(1) / T(6);
     // one z-iteration: plane k is updated; rp holds raw plane k + 2 on entry and
     // plane k + 4 on exit, uc the Un values of plane k on entry and k + 2 on exit
     auto step = [&](int k, T (&rp)[NPTS][5], T (&uc)[5]) __attribute__((always_inline)) {
+        T nr0 = T(0), nr1 = T(0);  // SAME: rho, rho theta of the own cell of plane k + 2
+        if (SAME) nr0 = rp[0][0], nr1 = rp[0][1];
         commit(k + 2, rp);
         fetch(k + 4, rp);
         __syncthreads();
@@ -322,7 +351,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                              myl * upw6<T>(myl, UU[-2 * WX], UU[-WX], UU[0], UU[WX], true, true);
                 fzc[1] = mzh * upw6<T>(mzh, zc[1][1], zc[1][2], zc[1][3], zc[1][4], okL0, okR2);
                 const T fz = fzc[1] - zl[1];
-                const T val = uc[2] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
+                const T val = (SAME ? ru_i : uc[2]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
                 st(a.out[2], ou, val);
                 if (i == 0) st(a.out[2], ou + nx, val);
             }
@@ -337,7 +366,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                              myl * upw6<T>(myl, VV[-2 * WX], VV[-WX], VV[0], VV[WX], true, true);
                 fzc[2] = mzh * upw6<T>(mzh, zc[2][1], zc[2][2], zc[2][3], zc[2][4], okL0, okR2);
                 const T fz = fzc[2] - zl[2];
-                const T val = uc[3] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
+                const T val = (SAME ? rv_j : uc[3]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
                 st(a.out[3], ov, val);
                 if (j == 0) st(a.out[3], ov + (uint32_t)ny * nx, val);
             }
@@ -356,7 +385,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                 fzc[3] = mzh * upw6<T>(mzh, zc[3][1], zc[3][2], zc[3][3], zc[3][4], k - 1 >= 1, okR2);
                 const T fz = fzc[3] - zl[3];
                 // plane 0 holds the bottom wall face, not a CV
-                st(a.out[4], oc, k == 0 ? T(0) : uc[4] - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth);
+                st(a.out[4], oc, k == 0 ? T(0) : (SAME ? rw_k : uc[4]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth);
                 if (k == nz - 1) st(a.out[4], oc + pc, T(0));
             }
         }
@@ -365,7 +394,12 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             m2[q] = m1[q];
             m1[q] = P0[q * 3 * WS];
         }
-        fetch_un(k + 2, uc);
+        if (SAME) {
+            uc[0] = nr0;
+            uc[1] = nr1;
+        } else {
+            fetch_un(k + 2, uc);
+        }
         __syncthreads();
     };
     for (int k = k0; k < z1; k += 2) {
@@ -412,14 +446,17 @@ ebs_status launch_bulk_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* Ucur
         }
         const size_t lds = bulk_lds_bytes(cx->tile_x, cx->tile_y, cx->g.precision);
         a.per_xcd = (cx->ntiles + NXCD - 1) / NXCD;
+        bool same = true;
+        for (int f = 0; f < 5; ++f) same = same && un[f] == cu[f];
         if (cx->ntiles > 0) {
             const dim3 grid(a.per_xcd * NXCD), blk(cx->tile_x, cx->tile_y);
 #define EBS_BULK_CASE(X, Y)                                                                   \
     if (cx->tile_x == X && cx->tile_y == Y) {                                                 \
+        auto kf = same ? k_bulk<T, X, Y, true> : k_bulk<T, X, Y, false>;                      \
         if (lds > 64 * 1024)                                                                  \
-            EBS_HIP(cx, hipFuncSetAttribute((const void*)k_bulk<T, X, Y>,                      \
+            EBS_HIP(cx, hipFuncSetAttribute((const void*)kf,                                   \
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
-        hipLaunchKernelGGL((k_bulk<T, X, Y>), grid, blk, lds, bs, a);                         \
+        hipLaunchKernelGGL(kf, grid, blk, lds, bs, a);                                        \
     } else
             EBS_BULK_CASE(16, 4) EBS_BULK_CASE(16, 8) EBS_BULK_CASE(16, 16) EBS_BULK_CASE(32, 4)
             EBS_BULK_CASE(32, 8) EBS_BULK_CASE(32, 16) EBS_BULK_CASE(64, 2) EBS_BULK_CASE(64, 4)

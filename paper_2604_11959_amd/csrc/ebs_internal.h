@@ -162,7 +162,7 @@ struct ebs_ctx {
     double* d_geo = nullptr;
     int8_t* d_type = nullptr;
     uint32_t* d_type4 = nullptr;
-    std::vector<int32_t> h_g0, h_g1, h_goff;
+    std::vector<int32_t> h_g0, h_g1, h_goff, h_g1e;
 
     // redistribution
     int32_t* d_mask = nullptr;
@@ -192,7 +192,11 @@ struct ebs_ctx {
     double* d_uhat = nullptr;  // [5][G] provisional state of the last advance
     double* d_qhat = nullptr;  // [5][G]
     double* d_sig = nullptr;   // [5][3][G]
-    double* d_prim = nullptr;  // [G][4] advected quantities of the general range
+    double* d_prim = nullptr;  // [G + naux][4] advected quantities: general range, then aux positions
+    int32_t naux = 0;          // positions above the general range read by the face-range stencils
+    int2* d_auxcell = nullptr; // [naux] {column, plane} of each aux position
+    uint32_t* d_sten = nullptr; // [10][Ge] stencil table of the face range (see build_stencils)
+    int32_t* d_upd = nullptr;   // [9][G] update table: ge, flags, first record of the +x, +y, +z faces
     double* d_fh = nullptr;    // [5][3][Ge] provisional lower-face fluxes (extended range)
 
     // regular-region tiles
@@ -228,6 +232,7 @@ ebs_status launch_advance(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur
 ebs_status join_side(ebs_ctx* c);
 ebs_status build_tiles(ebs_ctx* c);
 ebs_status build_cut_faces(ebs_ctx* c);
+ebs_status build_stencils(ebs_ctx* c);
 // regular-region kernel (bulk.hip) on the given stream, with its timing events
 ebs_status launch_bulk(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uhat, double cdt,
                        hipStream_t stream);

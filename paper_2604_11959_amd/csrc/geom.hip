@@ -585,6 +585,7 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
     for (int c = 0; c < ncol; ++c)
         for (int k = cx->h_g0[c]; k < g1e[c]; ++k) gcole[goffe[c] + (k - cx->h_g0[c])] = c;
     cx->Ge = (int32_t)Ge;
+    cx->h_g1e = g1e;
     const size_t Ges = (size_t)std::max<int64_t>(Ge, 1);
     auto alloc = [&](void** p, size_t bytes) -> bool {
         if (*p) (void)hipFree(*p);

@@ -7,7 +7,7 @@
 // precision with the full rules: area / volume fractions, covered stencil
 // ends (order reduction), interpolation to the cut-face centroid, walls.  They
 // also keep a double-precision copy of the provisional state there for the
-// redistribution.  The two parts run concurrently on two streams.
+// redistribution.  The two parts may run concurrently on two streams.
 //
 // Readings where the paper is silent: the mass flux advecting momentum on a
 // staggered face is the mean of the two stored face momenta next to it; face
@@ -28,21 +28,23 @@ namespace {
 
 // --------------------------------------------------------------- general
 //
-// The general range is processed in three passes over its cells, in double
-// precision: the advected quantities of every cell (prims), the provisional
-// fluxes on its three lower faces (fhat), and the update, which moves the
-// provisional flux of every cut face to the face centroid (bilinear
-// interpolation of neighbouring provisional fluxes), multiplies by the area
-// fraction and takes the divergence over the six faces.
+// The general range is processed in four passes, in double precision: the
+// advected quantities (prims) of every general cell and of every position
+// above the range that a flux stencil reads; the provisional fluxes on the
+// three lower faces of every cell of the extended face range (fhat); area
+// fraction x flux moved to the centroid on every partial face (cut, from the
+// static cut-face records); and the update, which takes the divergence over
+// the six faces.
 //
-// A stencil position is resolved through its column's range info (loaded once
-// per neighbouring column): general (an index into the range), below the range
-// (no instance is fluid) or above it.  The range's top is chosen so that a
-// position above it has only regular CVs within three cells in x and y and
+// A stencil position is general (an index into the range), below its column's
+// range (no instance is fluid) or above it.  The range's top is chosen so that
+// a position above it has only regular CVs within three cells in x and y and
 // below it; its advected quantities and fluxes therefore follow the plain
 // formulas (every neighbour inside the domain is fluid, faces are full).  Every
 // neighbour a cut-face interpolation reads lies within one cell of a CV that is
-// not regular, hence inside or below its column's range.
+// not regular, hence inside or below its column's range.  Since the geometry
+// is static, the positions the flux and update passes read are resolved once
+// at set-up into two tables (build_stencils), so those passes gather directly.
 template <typename T>
 struct GenArgs {
     Dims D;
@@ -51,7 +53,11 @@ struct GenArgs {
     const T* cur[5];
     T* out[5];
     double* uhat;  // [5][G]
-    double* prim;  // [G][4] theta, u, v, w
+    double* prim;  // [G + naux][4] theta, u, v, w: general cells, then aux positions
+    const uint32_t* sten;  // [10][Ge] stencil table of the face range
+    const int2* auxcell;   // [naux] {column, plane}
+    int32_t naux;
+    const int32_t* upd;    // [9][G] update table: the three upper neighbours' lower faces
     double* fh;    // [5][3][Ge] provisional flux on the lower faces
     const int32_t* cbase;  // [G] first cut-face record of each general cell
     const struct CutRec* crec;
@@ -89,6 +95,19 @@ __device__ inline int finst(int f) { return f < 2 ? 0 : f - 1; }
 struct Pt {
     int i, j, k, g, ge, fl;
     uint32_t ff;
+};
+// a stencil position from the face-range table: wrapped (i, j), plane k, fluid
+// bits per instance, index into the advected-quantity array
+struct SPt {
+    int i, j, k, fl;
+    uint32_t pi;
+};
+// a lower face from the update table: index in the extended face range,
+// lower-face flags of its CV, first cut-face record of that CV
+struct UPt {
+    int ge;
+    uint32_t ff;
+    int rb;
 };
 
 template <typename T>
@@ -156,7 +175,8 @@ struct Gen {
         if (lo_fluid) { s += st(a.cur, 0, i0, j0, k0); ++cnt; }
         if (p.fl & 1) { s += st(a.cur, 0, p.i, p.j, p.k); ++cnt; }
         if (cnt == 0) return 0.0;
-        return st(a.cur, F, p.i, p.j, p.k) / (s / cnt);
+        // the mean over one or two cells: halving is exact, so this equals s / cnt
+        return st(a.cur, F, p.i, p.j, p.k) / (cnt == 2 ? 0.5 * s : s);
     }
     // advected quantity at any stencil position
     template <int F>
@@ -312,12 +332,12 @@ struct Gen {
         if (u12) { r.n[2] = N12.ge; r.c[3] = w1 * w2; ok &= N12.ge >= 0; }
         return ok;
     }
-    template <int F, int D>
+    template <int F, int D, bool EB>
     __device__ __forceinline__ double div_pre(const Pt& P, const Pt& U, int g, double Fp, double Fu) const {
         constexpr int s = F < 2 ? 0 : F - 1;
         const double rd = a.rdel[D];
         double br = (bface_pre<F, D>(U, Fu) - bface_pre<F, D>(P, Fp)) * rd;
-        if (a.eb_mode == 1) {
+        if (EB) {
             const double blo = beta<s, D>(P), bhi = beta<s, D>(U);
             double sm = 0.0;
             int cnt = 0;
@@ -328,7 +348,7 @@ struct Gen {
         }
         return br;
     }
-    template <int F>
+    template <int F, bool EB>
     __device__ __forceinline__ void update(const Pt& P, const Pt& Ux, const Pt& Uy, const Pt& Uz, int g) const {
         constexpr int s = F < 2 ? 0 : F - 1;
         // every load of this field first, from valid indices
@@ -343,21 +363,55 @@ struct Gen {
         const double unv = st(a.un, F, P.i, P.j, P.k);
         double val = 0.0;
         if ((P.fl >> s) & 1) {
-            double br = div_pre<F, 0>(P, Ux, g, Fp0, Fu0);
-            br += div_pre<F, 1>(P, Uy, g, Fp1, Fu1);
-            br += div_pre<F, 2>(P, Uz, g, Fp2, Fu2);
+            double br = div_pre<F, 0, EB>(P, Ux, g, Fp0, Fu0);
+            br += div_pre<F, 1, EB>(P, Uy, g, Fp1, Fu1);
+            br += div_pre<F, 2, EB>(P, Uz, g, Fp2, Fu2);
             val = unv - a.cdt * br / al;
         }
         a.uhat[(size_t)F * a.v.G + g] = val;
         put_field<T>(a.D, a.out, F, P.i, P.j, P.k, (T)val);
     }
-    // advected quantities of a position loaded unconditionally (valid index;
-    // used only where the position is general)
+    // ---- update from the update table (no test-mode EB flux)
+    // area fraction x flux on the lower D-face described by u (zero without
+    // fluid; the stored flux on a full face; the interpolated one otherwise)
+    template <int F, int D>
+    __device__ __forceinline__ double bface_u(const UPt& u, double F0) const {
+        constexpr int s = F < 2 ? 0 : F - 1;
+        if (!(u.ff & ff_pos(s, D))) return 0.0;
+        if (u.ff & ff_full(s, D)) return F0;
+        const uint32_t part = (u.ff & 0xFFFu) & ~(u.ff >> 16);
+        return a.bfc[(F == 1 ? (size_t)a.ncut : 0) + u.rb + __popc(part & (ff_pos(s, D) - 1u))];
+    }
+    template <int F>
+    __device__ __forceinline__ void update_t(int fl, const UPt& P, const UPt (&U)[3], int i, int j, int k,
+                                             int g) const {
+        constexpr int s = F < 2 ? 0 : F - 1;
+        const size_t Ge = a.v.Ge;
+        const double* f0 = a.fh + ((size_t)F * 3 + 0) * Ge;
+        const double* f1 = a.fh + ((size_t)F * 3 + 1) * Ge;
+        const double* f2 = a.fh + ((size_t)F * 3 + 2) * Ge;
+        const double Fp0 = f0[P.ge], Fp1 = f1[P.ge], Fp2 = f2[P.ge];
+        const double Fu0 = f0[U[0].ge], Fu1 = f1[U[1].ge], Fu2 = f2[U[2].ge];
+        const double al = geo(s, GQ_ALPHA, g);
+        const double unv = st(a.un, F, i, j, k);
+        double val = 0.0;
+        if ((fl >> s) & 1) {
+            double br = (bface_u<F, 0>(U[0], Fu0) - bface_u<F, 0>(P, Fp0)) * a.rdel[0];
+            br += (bface_u<F, 1>(U[1], Fu1) - bface_u<F, 1>(P, Fp1)) * a.rdel[1];
+            br += (bface_u<F, 2>(U[2], Fu2) - bface_u<F, 2>(P, Fp2)) * a.rdel[2];
+            val = unv - a.cdt * br / al;
+        }
+        a.uhat[(size_t)F * a.v.G + g] = val;
+        put_field<T>(a.D, a.out, F, i, j, k, (T)val);
+    }
+
+    // ---- provisional fluxes from the stencil table: every advected quantity
+    // a face-range stencil reads is a load from the advected-quantity array
     struct PV {
         double q[4];
     };
-    __device__ __forceinline__ PV loadpv(const Pt& p) const {
-        const double* b = a.prim + 4 * (size_t)max(p.g, 0);
+    __device__ __forceinline__ PV loadpv(const SPt& p) const {
+        const double* b = a.prim + 4 * (size_t)p.pi;
         PV v;
         v.q[0] = b[0];
         v.q[1] = b[1];
@@ -366,19 +420,17 @@ struct Gen {
         return v;
     }
     template <int F>
-    __device__ __forceinline__ double phiv(const Pt& p, const PV& v) const {
-        if (!((p.fl >> finst(F)) & 1)) return 0.0;
-        if (p.g >= 0) return v.q[F - 1];
-        return phi_state<F>(p, true);
+    __device__ __forceinline__ double phit(const SPt& p, const PV& v) const {
+        return ((p.fl >> finst(F)) & 1) ? v.q[F - 1] : 0.0;
     }
     // momentum component D, loaded unconditionally from a clamped plane
     template <int D>
-    __device__ __forceinline__ double momv(const Pt& p) const {
+    __device__ __forceinline__ double momt(const SPt& p) const {
         const double v = st(a.cur, 2 + D, p.i, p.j, min(max(p.k, 0), a.D.nz - 1));
         return ((p.fl >> (D + 1)) & 1) ? v : 0.0;
     }
     template <int F, int D>
-    __device__ __forceinline__ double fhatv(const Pt& LL, const Pt& L, const Pt& P, const Pt& RR,
+    __device__ __forceinline__ double fhatt(const SPt& LL, const SPt& L, const SPt& P, const SPt& RR,
                                             const PV& vLL, const PV& vL, const PV& vP, const PV& vRR,
                                             double m0, double mls) const {
         constexpr int s = F < 2 ? 0 : F - 1;
@@ -388,36 +440,49 @@ struct Gen {
         }
         const double m = s == 0 ? m0 : 0.5 * (mls + m0);
         if (F == 0) return m;
-        return m * upw<double>(m, phiv<F>(LL, vLL), phiv<F>(L, vL), phiv<F>(P, vP), phiv<F>(RR, vRR),
+        return m * upw<double>(m, phit<F>(LL, vLL), phit<F>(L, vL), phit<F>(P, vP), phit<F>(RR, vRR),
                                (LL.fl >> s) & 1, (RR.fl >> s) & 1);
     }
+    // the 15 lower-face fluxes of direction D at table slot set S (slot 0 the
+    // CV, 1 + 3 D .. 3 + 3 D the positions -2, -1, +1 along D)
     template <int D>
-    __device__ __forceinline__ void fhat_dir(const Pt& P, const Pt& Lx, const Pt& Ly, const Pt& Lz,
-                                             const int4& ci, int g, const PV& vP) const {
-        Pt LL, RR;
-        const Pt& L = D == 0 ? Lx : D == 1 ? Ly : Lz;
-        if (D == 0) {
-            LL = at(wx(P.i - 2), P.j, P.k);
-            RR = at(wx(P.i + 1), P.j, P.k);
-        } else if (D == 1) {
-            LL = at(P.i, wy(P.j - 2), P.k);
-            RR = at(P.i, wy(P.j + 1), P.k);
-        } else {
-            LL = at(P.i, P.j, P.k - 2, ci);
-            RR = at(P.i, P.j, P.k + 1, ci);
-        }
+    __device__ __forceinline__ void fhat_dirt(const SPt (&S)[10], const PV& vP, uint32_t ff, int e) const {
+        const SPt& P = S[0];
+        const SPt& LL = S[1 + 3 * D];
+        const SPt& L = S[2 + 3 * D];
+        const SPt& RR = S[3 + 3 * D];
         const size_t G = a.v.Ge;
-        const uint32_t ff = P.ff;  // lower faces with fluid (P.k < nz here)
         const PV vLL = loadpv(LL), vL = loadpv(L), vRR = loadpv(RR);
         // mass fluxes: component D at P and below P along x, y, z
-        const double m0 = momv<D>(P), mx = momv<D>(Lx), my = momv<D>(Ly), mz = momv<D>(Lz);
-        a.fh[(0 * 3 + D) * G + g] = (ff & ff_pos(0, D)) ? fhatv<0, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, m0) : 0.0;
-        a.fh[(1 * 3 + D) * G + g] = (ff & ff_pos(0, D)) ? fhatv<1, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, m0) : 0.0;
-        a.fh[(2 * 3 + D) * G + g] = (ff & ff_pos(1, D)) ? fhatv<2, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, mx) : 0.0;
-        a.fh[(3 * 3 + D) * G + g] = (ff & ff_pos(2, D)) ? fhatv<3, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, my) : 0.0;
-        a.fh[(4 * 3 + D) * G + g] = (ff & ff_pos(3, D)) ? fhatv<4, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, mz) : 0.0;
+        const double m0 = momt<D>(P), mx = momt<D>(S[2]), my = momt<D>(S[5]), mz = momt<D>(S[8]);
+        a.fh[(0 * 3 + D) * G + e] = (ff & ff_pos(0, D)) ? fhatt<0, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, m0) : 0.0;
+        a.fh[(1 * 3 + D) * G + e] = (ff & ff_pos(0, D)) ? fhatt<1, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, m0) : 0.0;
+        a.fh[(2 * 3 + D) * G + e] = (ff & ff_pos(1, D)) ? fhatt<2, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, mx) : 0.0;
+        a.fh[(3 * 3 + D) * G + e] = (ff & ff_pos(2, D)) ? fhatt<3, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, my) : 0.0;
+        a.fh[(4 * 3 + D) * G + e] = (ff & ff_pos(3, D)) ? fhatt<4, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, mz) : 0.0;
+    }
+    // table code of a stencil position (set-up): index into the
+    // advected-quantity array | fluid bits << 28; 0 where no instance is
+    // fluid (below the range, beyond the walls).  ok is cleared when an aux
+    // position beyond its column's aux range is needed.
+    __device__ uint32_t sten_code(int i, int j, int k, const int32_t* gp, const int32_t* aoff, bool& ok) const {
+        if (k < 0 || k >= a.D.nz) return 0u;
+        const int c = j * a.D.nx + i;
+        const int4 ci = a.v.col[c];
+        const Pt p = at(i, j, k, ci);
+        if (p.g >= 0) return (uint32_t)p.g | ((uint32_t)p.fl << 28);
+        if (p.g == -2) return 0u;
+        if (k >= gp[c]) {
+            ok = false;
+            return 0u;
+        }
+        return (uint32_t)(a.v.G + aoff[c] + (k - col_g1(ci))) | ((uint32_t)p.fl << 28);
     }
 };
+
+// slot offsets of the stencil table: the CV, then -2, -1, +1 along x, y, z
+constexpr int8_t kStenOff[10][3] = {{0, 0, 0},  {-2, 0, 0}, {-1, 0, 0}, {1, 0, 0},  {0, -2, 0},
+                                             {0, -1, 0}, {0, 1, 0},  {0, 0, -2}, {0, 0, -1}, {0, 0, 1}};
 
 __device__ inline void gen_cell(const GeoView& v, int g, int& i, int& j, int& k, int4& ci) {
     const int c = v.gcol[g];
@@ -438,8 +503,21 @@ __device__ inline void face_cell(const GeoView& v, int e, int& i, int& j, int& k
 template <typename T>
 __global__ void __launch_bounds__(256) k_gen_prims(GenArgs<T> a) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.v.G) return;
+    if (g >= a.v.G + a.naux) return;
     const Gen<T> G(a);
+    double* o = a.prim + 4 * (size_t)g;
+    if (g >= a.v.G) {
+        // aux position above the general range: every CV there and below it
+        // is fluid, so the face densities average over both sides
+        const int2 ck = a.auxcell[g - a.v.G];
+        const int i = ck.x % a.v.nx, j = ck.x / a.v.nx;
+        const Pt P = G.at(i, j, ck.y, a.v.col[ck.x]);
+        o[0] = (P.fl & 1) ? G.template phi_state<1>(P, true) : 0.0;
+        o[1] = (P.fl & 2) ? G.template phi_state<2>(P, true) : 0.0;
+        o[2] = (P.fl & 4) ? G.template phi_state<3>(P, true) : 0.0;
+        o[3] = (P.fl & 8) ? G.template phi_state<4>(P, true) : 0.0;
+        return;
+    }
     int i, j, k;
     int4 ci;
     gen_cell(a.v, g, i, j, k, ci);
@@ -447,7 +525,6 @@ __global__ void __launch_bounds__(256) k_gen_prims(GenArgs<T> a) {
     const bool lx = G.at(G.wx(i - 1), j, k).fl & 1;
     const bool ly = G.at(i, G.wy(j - 1), k).fl & 1;
     const bool lz = G.at(i, j, k - 1, ci).fl & 1;
-    double* o = a.prim + 4 * (size_t)g;
     o[0] = (P.fl & 1) ? G.template phi_state<1>(P, false) : 0.0;
     o[1] = (P.fl & 2) ? G.template phi_state<2>(P, lx) : 0.0;
     o[2] = (P.fl & 4) ? G.template phi_state<3>(P, ly) : 0.0;
@@ -456,24 +533,37 @@ __global__ void __launch_bounds__(256) k_gen_prims(GenArgs<T> a) {
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_gen_fhat(GenArgs<T> a) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;  // extended face range
-    if (g >= a.v.Ge) return;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;  // extended face range
+    if (e >= a.v.Ge) return;
     const Gen<T> G(a);
     int i, j, k;
     int4 ci;
-    face_cell(a.v, g, i, j, k, ci);
-    Pt P = G.at(i, j, k, ci);
-    P.ff = G.fflags(P);
-    // positions below P along x, y, z (the staggering neighbours of instances 1-3)
-    const Pt Lx = G.at(G.wx(i - 1), j, k), Ly = G.at(i, G.wy(j - 1), k), Lz = G.at(i, j, k - 1, ci);
-    const auto vP = G.loadpv(P);
-    G.template fhat_dir<0>(P, Lx, Ly, Lz, ci, g, vP);
-    G.template fhat_dir<1>(P, Lx, Ly, Lz, ci, g, vP);
-    G.template fhat_dir<2>(P, Lx, Ly, Lz, ci, g, vP);
+    face_cell(a.v, e, i, j, k, ci);
+    SPt S[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+        const uint32_t cd = a.sten[(size_t)q * a.v.Ge + e];
+        S[q].i = G.wx(i + kStenOff[q][0]);
+        S[q].j = G.wy(j + kStenOff[q][1]);
+        S[q].k = k + kStenOff[q][2];
+        S[q].fl = (int)(cd >> 28);
+        S[q].pi = cd & 0x0FFFFFFFu;
+    }
+    // lower-face flags of the CV (stored in the general range; above it every
+    // face of a plane holding CVs is full)
+    Pt P = G.atf(i, j, k, ci);
+    const uint32_t ff = G.fflags(P);
+    const auto vP = G.loadpv(S[0]);
+    G.template fhat_dirt<0>(S, vP, ff, e);
+    G.template fhat_dirt<1>(S, vP, ff, e);
+    G.template fhat_dirt<2>(S, vP, ff, e);
 }
 
+// update with the test-mode embedded-boundary flux (positions resolved from
+// the column ranges; the production update below reads the update table)
 template <typename T>
-__global__ void __launch_bounds__(256) k_gen_update(GenArgs<T> a) {
+__global__ void __launch_bounds__(256) k_gen_update_eb(GenArgs<T> a) {
+    constexpr bool EB = true;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.v.G) return;
     const Gen<T> G(a);
@@ -488,11 +578,37 @@ __global__ void __launch_bounds__(256) k_gen_update(GenArgs<T> a) {
     Ux.ff = G.fflags(Ux);
     Uy.ff = G.fflags(Uy);
     Uz.ff = G.fflags(Uz);
-    G.template update<0>(P, Ux, Uy, Uz, g);
-    G.template update<1>(P, Ux, Uy, Uz, g);
-    G.template update<2>(P, Ux, Uy, Uz, g);
-    G.template update<3>(P, Ux, Uy, Uz, g);
-    G.template update<4>(P, Ux, Uy, Uz, g);
+    G.template update<0, EB>(P, Ux, Uy, Uz, g);
+    G.template update<1, EB>(P, Ux, Uy, Uz, g);
+    G.template update<2, EB>(P, Ux, Uy, Uz, g);
+    G.template update<3, EB>(P, Ux, Uy, Uz, g);
+    G.template update<4, EB>(P, Ux, Uy, Uz, g);
+}
+
+// the update (EB flux zero), from the update table
+template <typename T>
+__global__ void __launch_bounds__(256) k_gen_update(GenArgs<T> a) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.v.G) return;
+    const Gen<T> G(a);
+    const int Gn = a.v.G;
+    UPt U[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        U[d].ge = a.upd[(size_t)d * Gn + g];
+        U[d].ff = (uint32_t)a.upd[(size_t)(3 + d) * Gn + g];
+        U[d].rb = a.upd[(size_t)(6 + d) * Gn + g];
+    }
+    int i, j, k;
+    int4 ci;
+    gen_cell(a.v, g, i, j, k, ci);
+    const Pt Q = G.at(i, j, k, ci);
+    const UPt P{ci.w + (k - col_g0(ci)), a.v.fflag[g], a.cbase[g]};
+    G.template update_t<0>(Q.fl, P, U, i, j, k, g);
+    G.template update_t<1>(Q.fl, P, U, i, j, k, g);
+    G.template update_t<2>(Q.fl, P, U, i, j, k, g);
+    G.template update_t<3>(Q.fl, P, U, i, j, k, g);
+    G.template update_t<4>(Q.fl, P, U, i, j, k, g);
 }
 
 // Area fraction x flux moved to the centroid on every partial face, for the
@@ -540,6 +656,47 @@ __global__ void __launch_bounds__(128) k_cut_fill(GenArgs<double> a, CutRec* rec
         if (part & ff_pos(s, 0)) ok &= G.template cut_record<0>(s, P, rec[r++]);
         if (part & ff_pos(s, 1)) ok &= G.template cut_record<1>(s, P, rec[r++]);
         if (part & ff_pos(s, 2)) ok &= G.template cut_record<2>(s, P, rec[r++]);
+    }
+    if (!ok) atomicAdd(bad, 1);
+}
+
+// stencil table of the face range (set-up)
+__global__ void __launch_bounds__(256) k_sten_fill(GenArgs<double> a, const int32_t* gp, const int32_t* aoff,
+                                                   uint32_t* sten, int32_t* bad) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.v.Ge) return;
+    const Gen<double> G(a);
+    int i, j, k;
+    int4 ci;
+    face_cell(a.v, e, i, j, k, ci);
+    bool ok = true;
+    for (int q = 0; q < 10; ++q)
+        sten[(size_t)q * a.v.Ge + e] =
+            G.sten_code(G.wx(i + kStenOff[q][0]), G.wy(j + kStenOff[q][1]), k + kStenOff[q][2], gp, aoff, ok);
+    if (!ok) atomicAdd(bad, 1);
+}
+
+// update table (set-up): for each general cell, the lower faces of its +x, +y
+// and +z neighbours (its own upper faces)
+__global__ void __launch_bounds__(256) k_upd_fill(GenArgs<double> a, int32_t* upd, int32_t* bad) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.v.G) return;
+    const Gen<double> G(a);
+    int i, j, k;
+    int4 ci;
+    gen_cell(a.v, g, i, j, k, ci);
+    const int ip = G.wx(i + 1), jp = G.wy(j + 1);
+    const Pt U[3] = {G.atf(ip, j, k, G.colinfo(ip, j)), G.atf(i, jp, k, G.colinfo(i, jp)),
+                     G.atf(i, j, k + 1, ci)};
+    const size_t Gn = a.v.G;
+    bool ok = true;
+    for (int d = 0; d < 3; ++d) {
+        const uint32_t ff = G.fflags(U[d]);
+        // a face with fluid must lie in the stored face range
+        if (ff != 0u && U[d].ge < 0) ok = false;
+        upd[d * Gn + g] = max(U[d].ge, 0);
+        upd[(3 + d) * Gn + g] = (int32_t)ff;
+        upd[(6 + d) * Gn + g] = U[d].g >= 0 ? a.cbase[U[d].g] : 0;
     }
     if (!ok) atomicAdd(bad, 1);
 }
@@ -608,6 +765,104 @@ ebs_status build_cut_faces(ebs_ctx* cx) {
     return EBS_OK;
 }
 
+// Stencil and update tables.  Every position a provisional-flux stencil
+// of the face range reads (the CV and -2, -1, +1 along each axis) is resolved
+// once: general cells by their index, positions above their column's general
+// range by an index in a list of aux positions appended to the general range
+// (whose advected quantities the prims pass computes as well), and positions
+// with no fluid CV by code 0.  The aux range of a column is [g1, gp), gp the
+// highest plane any face-range stencil reads there, plus one.  The update
+// table holds, for each general cell, the lower faces of its +x, +y and +z
+// neighbours: their index in the face range, their flags and the first
+// cut-face record of their CV.
+ebs_status build_stencils(ebs_ctx* cx) {
+    if (cx->d_auxcell) (void)hipFree(cx->d_auxcell);
+    if (cx->d_sten) (void)hipFree(cx->d_sten);
+    if (cx->d_upd) (void)hipFree(cx->d_upd);
+    cx->d_auxcell = nullptr;
+    cx->d_sten = nullptr;
+    cx->d_upd = nullptr;
+    cx->naux = 0;
+    const int nx = cx->nx, ny = cx->ny, nz = cx->nz, ncol = nx * ny;
+    const int32_t G = cx->G, Ge = cx->Ge;
+    const std::vector<int32_t>& g0 = cx->h_g0;
+    const std::vector<int32_t>& g1 = cx->h_g1;
+    const std::vector<int32_t>& g1e = cx->h_g1e;
+    std::vector<int32_t> gp(g1);
+    auto cid = [&](int i, int j) { return ((j % ny + ny) % ny) * nx + ((i % nx + nx) % nx); };
+    for (int c = 0; c < ncol; ++c) {
+        if (g1e[c] <= g0[c]) continue;  // empty face range: reads nothing
+        const int i = c % nx, j = c / nx;
+        gp[c] = std::max(gp[c], std::min(nz, g1e[c] + 1));
+        for (int d : {-2, -1, 1}) {
+            int& a = gp[cid(i + d, j)];
+            a = std::max(a, g1e[c]);
+            int& b = gp[cid(i, j + d)];
+            b = std::max(b, g1e[c]);
+        }
+    }
+    std::vector<int32_t> aoff(ncol);
+    int64_t A = 0;
+    for (int c = 0; c < ncol; ++c) {
+        aoff[c] = (int32_t)A;
+        A += gp[c] - g1[c];
+    }
+    if ((int64_t)G + A >= (int64_t)1 << 28) {
+        cx->err = "general region too large for the stencil table";
+        return EBS_E_UNSUPPORTED;
+    }
+    std::vector<int2> aux((size_t)std::max<int64_t>(A, 1));
+    for (int c = 0; c < ncol; ++c)
+        for (int k = g1[c]; k < gp[c]; ++k) aux[aoff[c] + (k - g1[c])] = make_int2(c, k);
+    cx->naux = (int32_t)A;
+    const size_t P = (size_t)std::max<int64_t>(G + A, 1);
+    if (cx->d_prim) (void)hipFree(cx->d_prim);
+    cx->d_prim = nullptr;
+    int32_t *d_gp = nullptr, *d_aoff = nullptr, *d_bad = nullptr;
+    bool ok = hipMalloc(&cx->d_prim, sizeof(double) * 4 * P) == hipSuccess;
+    ok = ok && hipMalloc(&cx->d_auxcell, sizeof(int2) * aux.size()) == hipSuccess;
+    ok = ok && hipMalloc(&cx->d_sten, sizeof(uint32_t) * 10 * (size_t)std::max(Ge, 1)) == hipSuccess;
+    ok = ok && hipMalloc(&cx->d_upd, sizeof(int32_t) * 9 * (size_t)std::max(G, 1)) == hipSuccess;
+    ok = ok && hipMalloc(&d_gp, sizeof(int32_t) * ncol) == hipSuccess;
+    ok = ok && hipMalloc(&d_aoff, sizeof(int32_t) * ncol) == hipSuccess;
+    ok = ok && hipMalloc(&d_bad, sizeof(int32_t)) == hipSuccess;
+    auto release = [&]() {
+        if (d_gp) (void)hipFree(d_gp);
+        if (d_aoff) (void)hipFree(d_aoff);
+        if (d_bad) (void)hipFree(d_bad);
+    };
+    if (!ok) {
+        release();
+        cx->err = "stencil table allocation failed";
+        return EBS_E_OOM;
+    }
+    EBS_HIP(cx, hipMemcpyAsync(cx->d_auxcell, aux.data(), sizeof(int2) * aux.size(), hipMemcpyHostToDevice,
+                               cx->stream));
+    EBS_HIP(cx, hipMemcpyAsync(d_gp, gp.data(), sizeof(int32_t) * ncol, hipMemcpyHostToDevice, cx->stream));
+    EBS_HIP(cx, hipMemcpyAsync(d_aoff, aoff.data(), sizeof(int32_t) * ncol, hipMemcpyHostToDevice, cx->stream));
+    EBS_HIP(cx, hipMemsetAsync(d_bad, 0, sizeof(int32_t), cx->stream));
+    int32_t bad = 0;
+    if (Ge > 0) {
+        GenArgs<double> a{};
+        a.D = Dims{nx, ny, nz};
+        a.v = geo_view(cx);
+        a.cbase = cx->d_cbase;
+        hipLaunchKernelGGL(k_sten_fill, dim3((Ge + 255) / 256), dim3(256), 0, cx->stream, a, d_gp, d_aoff,
+                           cx->d_sten, d_bad);
+        if (G > 0)
+            hipLaunchKernelGGL(k_upd_fill, dim3((G + 255) / 256), dim3(256), 0, cx->stream, a, cx->d_upd, d_bad);
+        EBS_HIP(cx, hipGetLastError());
+        EBS_HIP(cx, hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, cx->stream));
+    }
+    EBS_HIP(cx, hipStreamSynchronize(cx->stream));
+    release();
+    if (bad != 0) {
+        cx->err = "a face-range stencil reads a position outside the stored ranges";
+        return EBS_E_UNSUPPORTED;
+    }
+    return EBS_OK;
+}
+
 template <typename T>
 static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uh,
                             double cdt, bool defer_join) {
@@ -641,6 +896,10 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
         }
         a.uhat = cx->d_uhat;
         a.prim = cx->d_prim;
+        a.sten = cx->d_sten;
+        a.auxcell = cx->d_auxcell;
+        a.naux = cx->naux;
+        a.upd = cx->d_upd;
         a.fh = cx->d_fh;
         a.cbase = cx->d_cbase;
         a.crec = (const CutRec*)cx->d_crec;
@@ -652,11 +911,14 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
         const dim3 grid((cx->G + 255) / 256), gride((cx->Ge + 255) / 256), blk(256);
         // the first two passes only read the input state; the update writes
         // the output (which may alias U^n, never U_cur)
-        hipLaunchKernelGGL(k_gen_prims<T>, grid, blk, 0, cx->stream, a);
+        hipLaunchKernelGGL(k_gen_prims<T>, dim3((cx->G + cx->naux + 255) / 256), blk, 0, cx->stream, a);
         hipLaunchKernelGGL(k_gen_fhat<T>, gride, blk, 0, cx->stream, a);
         if (cx->ncut > 0)
             hipLaunchKernelGGL(k_gen_cut<T>, dim3((cx->ncut + 255) / 256), blk, 0, cx->stream, a);
-        hipLaunchKernelGGL(k_gen_update<T>, grid, blk, 0, cx->stream, a);
+        if (a.eb_mode == 1)
+            hipLaunchKernelGGL(k_gen_update_eb<T>, grid, blk, 0, cx->stream, a);
+        else
+            hipLaunchKernelGGL(k_gen_update<T>, grid, blk, 0, cx->stream, a);
         EBS_HIP(cx, hipGetLastError());
     }
     cx->join_pending = fork;
