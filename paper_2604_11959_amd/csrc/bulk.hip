@@ -502,19 +502,18 @@ ebs_status build_tiles(ebs_ctx* cx) {
                     cx->h_tiles.push_back(t);
                 }
     }
-    // Order: z band, then Morton order of the tile origin in 16-cell units.  The
-    // launch hands each XCD a contiguous run of this list, so the blocks resident
-    // on one XCD cover a compact patch at similar heights and share their halo
-    // cache lines in that XCD's L2.
-    auto morton = [](uint32_t x, uint32_t y) {
-        uint64_t m = 0;
-        for (int b = 0; b < 16; ++b) m |= (uint64_t)((x >> b) & 1) << (2 * b) | (uint64_t)((y >> b) & 1) << (2 * b + 1);
-        return m;
-    };
+    // Order: y slab (one per XCD), z band, then row-major.  The launch hands
+    // each XCD a contiguous run of this list, so the blocks resident on one
+    // XCD cover whole rows of tiles at similar heights: neighbouring tiles
+    // share their halo cache lines in that XCD's L2, and in x (periodic) no
+    // halo line is fetched by two XCDs.
     std::stable_sort(cx->h_tiles.begin(), cx->h_tiles.end(), [&](const ebs_tile& p, const ebs_tile& q) {
+        const int sp = (int)((int64_t)p.y0 * NXCD / cx->ny), sq = (int)((int64_t)q.y0 * NXCD / cx->ny);
+        if (sp != sq) return sp < sq;
         const int bp = p.z0 / TZ, bq = q.z0 / TZ;
         if (bp != bq) return bp < bq;
-        return morton(p.x0 >> 4, p.y0 >> 4) < morton(q.x0 >> 4, q.y0 >> 4);
+        if (p.y0 != q.y0) return p.y0 < q.y0;
+        return p.x0 < q.x0;
     });
     cx->ntiles = (int32_t)cx->h_tiles.size();
     if (cx->d_tiles) (void)hipFree(cx->d_tiles);

@@ -187,6 +187,10 @@ struct ebs_ctx {
     double* d_wl_geo = nullptr;       // [E][4] kappa_r and the centroid offset
     double* d_wl_self = nullptr;      // [A][5] omega, N and the own centroid offset
     int8_t* d_wl_small = nullptr;     // [A]
+    int32_t* d_q_idx = nullptr;       // [nlsq][8] Q-hat operator: the CV, then its members
+    double* d_q_w = nullptr;          // [nlsq][8] its weights
+    double* d_q_den = nullptr;        // [nlsq] V-hat
+    int8_t* d_q_n = nullptr;          // [nlsq] entries used
 
     // per-stage buffers (cut region, double)
     double* d_uhat = nullptr;  // [5][G] provisional state of the last advance
@@ -194,7 +198,9 @@ struct ebs_ctx {
     double* d_sig = nullptr;   // [5][3][G]
     double* d_prim = nullptr;  // [G + naux][4] advected quantities: general range, then aux positions
     int32_t naux = 0;          // positions above the general range read by the face-range stencils
-    int2* d_auxcell = nullptr; // [naux] {column, plane} of each aux position
+    int4* d_ptab = nullptr;    // [G + naux] cell table of the prims pass
+    int4* d_ftab = nullptr;    // [Ge] cell table of the flux pass
+    int4* d_utab = nullptr;    // [G] cell table of the update pass
     uint32_t* d_sten = nullptr; // [10][Ge] stencil table of the face range (see build_stencils)
     int32_t* d_upd = nullptr;   // [9][G] update table: ge, flags, first record of the +x, +y, +z faces
     double* d_fh = nullptr;    // [5][3][Ge] provisional lower-face fluxes (extended range)

@@ -55,8 +55,10 @@ struct GenArgs {
     double* uhat;  // [5][G]
     double* prim;  // [G + naux][4] theta, u, v, w: general cells, then aux positions
     const uint32_t* sten;  // [10][Ge] stencil table of the face range
-    const int2* auxcell;   // [naux] {column, plane}
     int32_t naux;
+    const int4* ptab;      // [G + naux] {i, j, k, fluid bits | lower-neighbour fluid bits << 4}
+    const int4* ftab;      // [Ge] {i, j, k, lower-face flags} of the face range
+    const int4* utab;      // [G] {i, j, k | fluid bits << 16, index in the face range}
     const int32_t* upd;    // [9][G] update table: the three upper neighbours' lower faces
     double* fh;    // [5][3][Ge] provisional flux on the lower faces
     const int32_t* cbase;  // [G] first cut-face record of each general cell
@@ -502,33 +504,22 @@ __device__ inline void face_cell(const GeoView& v, int e, int& i, int& j, int& k
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_gen_prims(GenArgs<T> a) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.v.G + a.naux) return;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.v.G + a.naux) return;
     const Gen<T> G(a);
-    double* o = a.prim + 4 * (size_t)g;
-    if (g >= a.v.G) {
-        // aux position above the general range: every CV there and below it
-        // is fluid, so the face densities average over both sides
-        const int2 ck = a.auxcell[g - a.v.G];
-        const int i = ck.x % a.v.nx, j = ck.x / a.v.nx;
-        const Pt P = G.at(i, j, ck.y, a.v.col[ck.x]);
-        o[0] = (P.fl & 1) ? G.template phi_state<1>(P, true) : 0.0;
-        o[1] = (P.fl & 2) ? G.template phi_state<2>(P, true) : 0.0;
-        o[2] = (P.fl & 4) ? G.template phi_state<3>(P, true) : 0.0;
-        o[3] = (P.fl & 8) ? G.template phi_state<4>(P, true) : 0.0;
-        return;
-    }
-    int i, j, k;
-    int4 ci;
-    gen_cell(a.v, g, i, j, k, ci);
-    const Pt P = G.at(i, j, k, ci);
-    const bool lx = G.at(G.wx(i - 1), j, k).fl & 1;
-    const bool ly = G.at(i, G.wy(j - 1), k).fl & 1;
-    const bool lz = G.at(i, j, k - 1, ci).fl & 1;
+    const int4 t = a.ptab[p];
+    Pt P;
+    P.i = t.x;
+    P.j = t.y;
+    P.k = t.z;
+    P.g = P.ge = 0;
+    P.fl = t.w & 0xF;
+    P.ff = 0;
+    double* o = a.prim + 4 * (size_t)p;
     o[0] = (P.fl & 1) ? G.template phi_state<1>(P, false) : 0.0;
-    o[1] = (P.fl & 2) ? G.template phi_state<2>(P, lx) : 0.0;
-    o[2] = (P.fl & 4) ? G.template phi_state<3>(P, ly) : 0.0;
-    o[3] = (P.fl & 8) ? G.template phi_state<4>(P, lz) : 0.0;
+    o[1] = (P.fl & 2) ? G.template phi_state<2>(P, (t.w >> 4) & 1) : 0.0;
+    o[2] = (P.fl & 4) ? G.template phi_state<3>(P, (t.w >> 5) & 1) : 0.0;
+    o[3] = (P.fl & 8) ? G.template phi_state<4>(P, (t.w >> 6) & 1) : 0.0;
 }
 
 template <typename T>
@@ -536,9 +527,9 @@ __global__ void __launch_bounds__(256) k_gen_fhat(GenArgs<T> a) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;  // extended face range
     if (e >= a.v.Ge) return;
     const Gen<T> G(a);
-    int i, j, k;
-    int4 ci;
-    face_cell(a.v, e, i, j, k, ci);
+    const int4 t = a.ftab[e];
+    const int i = t.x, j = t.y, k = t.z;
+    const uint32_t ff = (uint32_t)t.w;  // lower-face flags of the CV
     SPt S[10];
 #pragma unroll
     for (int q = 0; q < 10; ++q) {
@@ -549,10 +540,6 @@ __global__ void __launch_bounds__(256) k_gen_fhat(GenArgs<T> a) {
         S[q].fl = (int)(cd >> 28);
         S[q].pi = cd & 0x0FFFFFFFu;
     }
-    // lower-face flags of the CV (stored in the general range; above it every
-    // face of a plane holding CVs is full)
-    Pt P = G.atf(i, j, k, ci);
-    const uint32_t ff = G.fflags(P);
     const auto vP = G.loadpv(S[0]);
     G.template fhat_dirt<0>(S, vP, ff, e);
     G.template fhat_dirt<1>(S, vP, ff, e);
@@ -599,16 +586,14 @@ __global__ void __launch_bounds__(256) k_gen_update(GenArgs<T> a) {
         U[d].ff = (uint32_t)a.upd[(size_t)(3 + d) * Gn + g];
         U[d].rb = a.upd[(size_t)(6 + d) * Gn + g];
     }
-    int i, j, k;
-    int4 ci;
-    gen_cell(a.v, g, i, j, k, ci);
-    const Pt Q = G.at(i, j, k, ci);
-    const UPt P{ci.w + (k - col_g0(ci)), a.v.fflag[g], a.cbase[g]};
-    G.template update_t<0>(Q.fl, P, U, i, j, k, g);
-    G.template update_t<1>(Q.fl, P, U, i, j, k, g);
-    G.template update_t<2>(Q.fl, P, U, i, j, k, g);
-    G.template update_t<3>(Q.fl, P, U, i, j, k, g);
-    G.template update_t<4>(Q.fl, P, U, i, j, k, g);
+    const int4 t = a.utab[g];
+    const int i = t.x, j = t.y, k = t.z & 0xFFFF, fl = t.z >> 16;
+    const UPt P{t.w, a.v.fflag[g], a.cbase[g]};
+    G.template update_t<0>(fl, P, U, i, j, k, g);
+    G.template update_t<1>(fl, P, U, i, j, k, g);
+    G.template update_t<2>(fl, P, U, i, j, k, g);
+    G.template update_t<3>(fl, P, U, i, j, k, g);
+    G.template update_t<4>(fl, P, U, i, j, k, g);
 }
 
 // Area fraction x flux moved to the centroid on every partial face, for the
@@ -662,13 +647,16 @@ __global__ void __launch_bounds__(128) k_cut_fill(GenArgs<double> a, CutRec* rec
 
 // stencil table of the face range (set-up)
 __global__ void __launch_bounds__(256) k_sten_fill(GenArgs<double> a, const int32_t* gp, const int32_t* aoff,
-                                                   uint32_t* sten, int32_t* bad) {
+                                                   uint32_t* sten, int4* ftab, int32_t* bad) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= a.v.Ge) return;
     const Gen<double> G(a);
     int i, j, k;
     int4 ci;
     face_cell(a.v, e, i, j, k, ci);
+    // lower-face flags (stored in the general range; above it every face of a
+    // plane holding CVs is full)
+    ftab[e] = make_int4(i, j, k, (int)G.fflags(G.atf(i, j, k, ci)));
     bool ok = true;
     for (int q = 0; q < 10; ++q)
         sten[(size_t)q * a.v.Ge + e] =
@@ -678,13 +666,14 @@ __global__ void __launch_bounds__(256) k_sten_fill(GenArgs<double> a, const int3
 
 // update table (set-up): for each general cell, the lower faces of its +x, +y
 // and +z neighbours (its own upper faces)
-__global__ void __launch_bounds__(256) k_upd_fill(GenArgs<double> a, int32_t* upd, int32_t* bad) {
+__global__ void __launch_bounds__(256) k_upd_fill(GenArgs<double> a, int32_t* upd, int4* utab, int32_t* bad) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.v.G) return;
     const Gen<double> G(a);
     int i, j, k;
     int4 ci;
     gen_cell(a.v, g, i, j, k, ci);
+    utab[g] = make_int4(i, j, k | (G.at(i, j, k, ci).fl << 16), ci.w + (k - col_g0(ci)));
     const int ip = G.wx(i + 1), jp = G.wy(j + 1);
     const Pt U[3] = {G.atf(ip, j, k, G.colinfo(ip, j)), G.atf(i, jp, k, G.colinfo(i, jp)),
                      G.atf(i, j, k + 1, ci)};
@@ -699,6 +688,30 @@ __global__ void __launch_bounds__(256) k_upd_fill(GenArgs<double> a, int32_t* up
         upd[(6 + d) * Gn + g] = U[d].g >= 0 ? a.cbase[U[d].g] : 0;
     }
     if (!ok) atomicAdd(bad, 1);
+}
+
+// cell table of the prims pass (set-up): general cells, then aux positions
+__global__ void __launch_bounds__(256) k_ptab_fill(GenArgs<double> a, const int2* aux, int4* ptab) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.v.G + a.naux) return;
+    const Gen<double> G(a);
+    int i, j, k, bits;
+    if (p < a.v.G) {
+        int4 ci;
+        gen_cell(a.v, p, i, j, k, ci);
+        const int lx = G.at(G.wx(i - 1), j, k).fl & 1;
+        const int ly = G.at(i, G.wy(j - 1), k).fl & 1;
+        const int lz = G.at(i, j, k - 1, ci).fl & 1;
+        bits = G.at(i, j, k, ci).fl | lx << 4 | ly << 5 | lz << 6;
+    } else {
+        // above the general range: every CV there and below it is fluid
+        const int2 ck = aux[p - a.v.G];
+        i = ck.x % a.v.nx;
+        j = ck.x / a.v.nx;
+        k = ck.y;
+        bits = G.at(i, j, k, a.v.col[ck.x]).fl | 0x70;
+    }
+    ptab[p] = make_int4(i, j, k, bits);
 }
 
 }  // namespace
@@ -776,12 +789,11 @@ ebs_status build_cut_faces(ebs_ctx* cx) {
 // neighbours: their index in the face range, their flags and the first
 // cut-face record of their CV.
 ebs_status build_stencils(ebs_ctx* cx) {
-    if (cx->d_auxcell) (void)hipFree(cx->d_auxcell);
-    if (cx->d_sten) (void)hipFree(cx->d_sten);
-    if (cx->d_upd) (void)hipFree(cx->d_upd);
-    cx->d_auxcell = nullptr;
-    cx->d_sten = nullptr;
-    cx->d_upd = nullptr;
+    for (void** q : {(void**)&cx->d_sten, (void**)&cx->d_upd, (void**)&cx->d_ptab, (void**)&cx->d_ftab,
+                     (void**)&cx->d_utab}) {
+        if (*q) (void)hipFree(*q);
+        *q = nullptr;
+    }
     cx->naux = 0;
     const int nx = cx->nx, ny = cx->ny, nz = cx->nz, ncol = nx * ny;
     const int32_t G = cx->G, Ge = cx->Ge;
@@ -816,46 +828,59 @@ ebs_status build_stencils(ebs_ctx* cx) {
         for (int k = g1[c]; k < gp[c]; ++k) aux[aoff[c] + (k - g1[c])] = make_int2(c, k);
     cx->naux = (int32_t)A;
     const size_t P = (size_t)std::max<int64_t>(G + A, 1);
+    const size_t Gs = (size_t)std::max(G, 1), Ges = (size_t)std::max(Ge, 1);
     if (cx->d_prim) (void)hipFree(cx->d_prim);
     cx->d_prim = nullptr;
     int32_t *d_gp = nullptr, *d_aoff = nullptr, *d_bad = nullptr;
+    int2* d_aux = nullptr;
     bool ok = hipMalloc(&cx->d_prim, sizeof(double) * 4 * P) == hipSuccess;
-    ok = ok && hipMalloc(&cx->d_auxcell, sizeof(int2) * aux.size()) == hipSuccess;
-    ok = ok && hipMalloc(&cx->d_sten, sizeof(uint32_t) * 10 * (size_t)std::max(Ge, 1)) == hipSuccess;
-    ok = ok && hipMalloc(&cx->d_upd, sizeof(int32_t) * 9 * (size_t)std::max(G, 1)) == hipSuccess;
+    ok = ok && hipMalloc(&cx->d_ptab, sizeof(int4) * P) == hipSuccess;
+    ok = ok && hipMalloc(&cx->d_sten, sizeof(uint32_t) * 10 * Ges) == hipSuccess;
+    ok = ok && hipMalloc(&cx->d_ftab, sizeof(int4) * Ges) == hipSuccess;
+    ok = ok && hipMalloc(&cx->d_upd, sizeof(int32_t) * 9 * Gs) == hipSuccess;
+    ok = ok && hipMalloc(&cx->d_utab, sizeof(int4) * Gs) == hipSuccess;
+    ok = ok && hipMalloc(&d_aux, sizeof(int2) * aux.size()) == hipSuccess;
     ok = ok && hipMalloc(&d_gp, sizeof(int32_t) * ncol) == hipSuccess;
     ok = ok && hipMalloc(&d_aoff, sizeof(int32_t) * ncol) == hipSuccess;
     ok = ok && hipMalloc(&d_bad, sizeof(int32_t)) == hipSuccess;
-    auto release = [&]() {
-        if (d_gp) (void)hipFree(d_gp);
-        if (d_aoff) (void)hipFree(d_aoff);
-        if (d_bad) (void)hipFree(d_bad);
-    };
-    if (!ok) {
-        release();
-        cx->err = "stencil table allocation failed";
-        return EBS_E_OOM;
-    }
-    EBS_HIP(cx, hipMemcpyAsync(cx->d_auxcell, aux.data(), sizeof(int2) * aux.size(), hipMemcpyHostToDevice,
-                               cx->stream));
-    EBS_HIP(cx, hipMemcpyAsync(d_gp, gp.data(), sizeof(int32_t) * ncol, hipMemcpyHostToDevice, cx->stream));
-    EBS_HIP(cx, hipMemcpyAsync(d_aoff, aoff.data(), sizeof(int32_t) * ncol, hipMemcpyHostToDevice, cx->stream));
-    EBS_HIP(cx, hipMemsetAsync(d_bad, 0, sizeof(int32_t), cx->stream));
     int32_t bad = 0;
-    if (Ge > 0) {
+    hipError_t e = ok ? hipSuccess : hipErrorOutOfMemory;
+    auto chk = [&](hipError_t r) {
+        if (e == hipSuccess) e = r;
+    };
+    if (ok) {
+        chk(hipMemcpyAsync(d_aux, aux.data(), sizeof(int2) * aux.size(), hipMemcpyHostToDevice, cx->stream));
+        chk(hipMemcpyAsync(d_gp, gp.data(), sizeof(int32_t) * ncol, hipMemcpyHostToDevice, cx->stream));
+        chk(hipMemcpyAsync(d_aoff, aoff.data(), sizeof(int32_t) * ncol, hipMemcpyHostToDevice, cx->stream));
+        chk(hipMemsetAsync(d_bad, 0, sizeof(int32_t), cx->stream));
         GenArgs<double> a{};
         a.D = Dims{nx, ny, nz};
         a.v = geo_view(cx);
         a.cbase = cx->d_cbase;
-        hipLaunchKernelGGL(k_sten_fill, dim3((Ge + 255) / 256), dim3(256), 0, cx->stream, a, d_gp, d_aoff,
-                           cx->d_sten, d_bad);
+        a.naux = cx->naux;
+        if (G + A > 0)
+            hipLaunchKernelGGL(k_ptab_fill, dim3((unsigned)((G + A + 255) / 256)), dim3(256), 0, cx->stream, a,
+                               d_aux, cx->d_ptab);
+        if (Ge > 0)
+            hipLaunchKernelGGL(k_sten_fill, dim3((Ge + 255) / 256), dim3(256), 0, cx->stream, a, d_gp, d_aoff,
+                               cx->d_sten, cx->d_ftab, d_bad);
         if (G > 0)
-            hipLaunchKernelGGL(k_upd_fill, dim3((G + 255) / 256), dim3(256), 0, cx->stream, a, cx->d_upd, d_bad);
-        EBS_HIP(cx, hipGetLastError());
-        EBS_HIP(cx, hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, cx->stream));
+            hipLaunchKernelGGL(k_upd_fill, dim3((G + 255) / 256), dim3(256), 0, cx->stream, a, cx->d_upd,
+                               cx->d_utab, d_bad);
+        chk(hipGetLastError());
+        chk(hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, cx->stream));
+        chk(hipStreamSynchronize(cx->stream));
     }
-    EBS_HIP(cx, hipStreamSynchronize(cx->stream));
-    release();
+    for (void* q : {(void*)d_aux, (void*)d_gp, (void*)d_aoff, (void*)d_bad})
+        if (q) (void)hipFree(q);
+    if (!ok) {
+        cx->err = "stencil table allocation failed";
+        return EBS_E_OOM;
+    }
+    if (e != hipSuccess) {
+        cx->err = std::string("stencil tables: ") + hipGetErrorString(e);
+        return EBS_E_HIP;
+    }
     if (bad != 0) {
         cx->err = "a face-range stencil reads a position outside the stored ranges";
         return EBS_E_UNSUPPORTED;
@@ -897,7 +922,9 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
         a.uhat = cx->d_uhat;
         a.prim = cx->d_prim;
         a.sten = cx->d_sten;
-        a.auxcell = cx->d_auxcell;
+        a.ptab = cx->d_ptab;
+        a.ftab = cx->d_ftab;
+        a.utab = cx->d_utab;
         a.naux = cx->naux;
         a.upd = cx->d_upd;
         a.fh = cx->d_fh;

@@ -273,6 +273,10 @@ struct AArgs {
     const double* wgeo;   // [E][4] kappa_r, then (offset + centroid_i - xhat_r) in mesh units
     const double* aself;  // [A][5] omega, N, centroid_i - xhat_i (mesh units; small CVs)
     const int8_t* asmall; // [A] 1 if the CV is small with kappa > 0
+    const int32_t* qidx;  // [S][LSQ_MAXEV] Q-hat operator: the CV, then its members
+    const double* qw;     // [S][LSQ_MAXEV] weights: omega V, then kappa alpha_r V / N_r
+    const double* qden;   // [S] V-hat
+    const int8_t* qn;     // [S] entries used
     int limiter;
     double dv;
 };
@@ -281,42 +285,71 @@ __device__ inline double wv(const AArgs& a, int inst, int q, int g) {
     return a.w[((size_t)inst * WQ_COUNT + q) * a.v.G + g];
 }
 
-// Q-hat (Eq. qhat_omega) of the small CVs with kappa > 0; all instances in one
-// launch (blockIdx.y = instance)
-__global__ void __launch_bounds__(128) k_qhat(AArgs a) {
+// Q-hat operator of the small CVs with kappa > 0 (Eq. qhat_omega), built once
+// per geometry: Q-hat_i = (omega_i V_i U_i + sum over the members r of
+// kappa_i alpha_r V / N_r U_r) / V-hat_i, members in the order of the offsets
+// (dz, dy, dx) from -1 to 1.  Every member lies in the general range: its
+// margin exceeds the merge radius.
+__global__ void __launch_bounds__(128) k_qtab(AArgs a, int32_t* qidx, double* qw, double* qden, int8_t* qn) {
     const int inst = blockIdx.y;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.ns[inst]) return;
     const int g = a.slist[(size_t)inst * a.v.G + t];
+    const size_t e = (size_t)a.sbase[inst] + t;
     const GeoView& v = a.v;
     int i, j, k;
     cell_of(v, g, i, j, k);
     const double V = gq(v, inst, GQ_ALPHA, g) * a.dv;
     const double om = wv(a, inst, WQ_OMEGA, g), kap = wv(a, inst, WQ_KAPPA, g);
-    const double den = wv(a, inst, WQ_VHAT, g) * a.dv;
     const int32_t m = a.mask[(size_t)inst * v.G + g];
-    // members (every member of a small CV's neighbourhood lies in the general
-    // range: its margin exceeds the merge radius)
-    int gm[LSQ_MAXEV - 1];
-    double wm[LSQ_MAXEV - 1];
-    int nm = 0;
+    int32_t* id = qidx + e * LSQ_MAXEV;
+    double* w = qw + e * LSQ_MAXEV;
+    id[0] = g;
+    w[0] = om * V;
+    int n = 1;
     for (int oz = -1; oz <= 1; ++oz)
         for (int oy = -1; oy <= 1; ++oy)
             for (int ox = -1; ox <= 1; ++ox) {
                 if (ox == 0 && oy == 0 && oz == 0) continue;
                 if (!((m >> bit_of(ox, oy, oz)) & 1)) continue;
                 const int gr = nbr(v, inst, i + ox, j + oy, k + oz);
-                if (gr < 0 || nm >= LSQ_MAXEV - 1) continue;
-                gm[nm] = gr;
-                wm[nm] = kap * gq(v, inst, GQ_ALPHA, gr) * a.dv / wv(a, inst, WQ_N, gr);
-                ++nm;
+                if (gr < 0 || n >= LSQ_MAXEV) continue;
+                id[n] = gr;
+                w[n] = kap * gq(v, inst, GQ_ALPHA, gr) * a.dv / wv(a, inst, WQ_N, gr);
+                ++n;
             }
+    for (int q = n; q < LSQ_MAXEV; ++q) {
+        id[q] = g;
+        w[q] = 0.0;
+    }
+    qn[e] = (int8_t)n;
+    qden[e] = wv(a, inst, WQ_VHAT, g) * a.dv;
+}
+
+// Q-hat of the small CVs with kappa > 0, from the operator table; all
+// instances in one launch (blockIdx.y = instance)
+__global__ void __launch_bounds__(128) k_qhat(AArgs a) {
+    const int inst = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.ns[inst]) return;
+    const size_t e = (size_t)a.sbase[inst] + t;
+    int32_t id[LSQ_MAXEV];
+    double w[LSQ_MAXEV];
+#pragma unroll
+    for (int q = 0; q < LSQ_MAXEV; ++q) {
+        id[q] = a.qidx[e * LSQ_MAXEV + q];
+        w[q] = a.qw[e * LSQ_MAXEV + q];
+    }
+    const int n = a.qn[e];
+    const double den = a.qden[e];
     const int f0 = inst_f0(inst), nf = inst_nf(inst);
     for (int f = f0; f < f0 + nf; ++f) {
-        const double* U = a.uhat + (size_t)f * v.G;
-        double s = om * V * U[g];
-        for (int q = 0; q < nm; ++q) s += wm[q] * U[gm[q]];
-        a.qhat[(size_t)f * v.G + g] = s / den;
+        const double* U = a.uhat + (size_t)f * a.v.G;
+        double s = w[0] * U[id[0]];
+#pragma unroll
+        for (int q = 1; q < LSQ_MAXEV; ++q)
+            if (q < n) s += w[q] * U[id[q]];
+        a.qhat[(size_t)f * a.v.G + id[0]] = s / den;
     }
 }
 
@@ -332,6 +365,7 @@ __device__ inline double psi(double delta, double qi, double qmin, double qmax) 
 // GRAD_LANES lanes shares one CV: the lanes split its fit points and combine
 // their partial sums and bounds by a butterfly over the group.
 constexpr int GRAD_LANES = 16;
+static_assert(LSQ_MAXEV <= GRAD_LANES, "one limiter evaluation point per lane");
 
 __global__ void __launch_bounds__(256) k_grad(AArgs a) {
     const int f = blockIdx.y;
@@ -370,26 +404,25 @@ __global__ void __launch_bounds__(256) k_grad(AArgs a) {
         qmin = fmin(qmin, __shfl_xor(qmin, m, GRAD_LANES));
         qmax = fmax(qmax, __shfl_xor(qmax, m, GRAD_LANES));
     }
-    if (!valid || lane != 0) return;
-    if (p1 > p0 && a.limiter != EBS_LIM_NONE) {
-        const int nev = a.lnev[e];
-        const double* ev = a.lev + (size_t)e * LSQ_MAXEV * 3;
-        double lam[3] = {1.0, 1.0, 1.0};
-        double lall = 1.0;
-        for (int q = 0; q < nev; ++q) {
-            if (a.limiter == EBS_LIM_BJ_COMPONENT) {
-                for (int d = 0; d < 3; ++d) lam[d] = fmin(lam[d], psi(s[d] * ev[3 * q + d], qi, qmin, qmax));
-            } else {
-                lall = fmin(lall, psi(s[0] * ev[3 * q] + s[1] * ev[3 * q + 1] + s[2] * ev[3 * q + 2], qi,
-                                      qmin, qmax));
-            }
-        }
+    // limiter: lane q of the group evaluates point q (at most LSQ_MAXEV <=
+    // GRAD_LANES); the factors are combined by a min-butterfly (min is exact,
+    // so the result does not depend on the order)
+    const bool lim = valid && p1 > p0 && a.limiter != EBS_LIM_NONE;
+    double lam[3] = {1.0, 1.0, 1.0};
+    if (lim && lane < a.lnev[e]) {
+        const double* ev = a.lev + ((size_t)e * LSQ_MAXEV + lane) * 3;
         if (a.limiter == EBS_LIM_BJ_COMPONENT) {
-            for (int d = 0; d < 3; ++d) s[d] *= lam[d];
+            for (int d = 0; d < 3; ++d) lam[d] = psi(s[d] * ev[d], qi, qmin, qmax);
         } else {
-            for (int d = 0; d < 3; ++d) s[d] *= lall;
+            lam[0] = lam[1] = lam[2] = psi(s[0] * ev[0] + s[1] * ev[1] + s[2] * ev[2], qi, qmin, qmax);
         }
     }
+#pragma unroll
+    for (int m = GRAD_LANES / 2; m >= 1; m >>= 1)
+        for (int d = 0; d < 3; ++d) lam[d] = fmin(lam[d], __shfl_xor(lam[d], m, GRAD_LANES));
+    if (!valid || lane != 0) return;
+    if (lim)
+        for (int d = 0; d < 3; ++d) s[d] *= lam[d];
     const double del[3] = {v.dx, v.dy, v.dz};
     for (int d = 0; d < 3; ++d) a.sig[((size_t)f * 3 + d) * v.G + g] = s[d] / del[d];
 }
@@ -730,9 +763,30 @@ ebs_status wsrd_setup(ebs_ctx* cx) {
     bool ok = alloc((void**)&cx->d_lsq_off, sizeof(int32_t) * (S + 1));
     ok &= alloc((void**)&cx->d_lsq_ev, sizeof(double) * 3 * LSQ_MAXEV * std::max(S, 1));
     ok &= alloc((void**)&cx->d_lsq_nev, std::max(S, 1));
+    ok &= alloc((void**)&cx->d_q_idx, sizeof(int32_t) * LSQ_MAXEV * std::max(S, 1));
+    ok &= alloc((void**)&cx->d_q_w, sizeof(double) * LSQ_MAXEV * std::max(S, 1));
+    ok &= alloc((void**)&cx->d_q_den, sizeof(double) * std::max(S, 1));
+    ok &= alloc((void**)&cx->d_q_n, std::max(S, 1));
     if (!ok) {
         cx->err = "device allocation of the least-squares tables failed";
         return EBS_E_OOM;
+    }
+    // Q-hat operators
+    if (S > 0) {
+        AArgs q{};
+        q.v = geo_view(cx);
+        q.mask = cx->d_mask;
+        q.small = cx->d_small;
+        q.w = cx->d_w;
+        q.slist = cx->d_smalllist;
+        for (int inst = 0; inst < NINST; ++inst) {
+            q.ns[inst] = cx->nsmall[inst];
+            q.sbase[inst] = cx->sbase[inst];
+        }
+        q.dv = cx->g.dx[0] * cx->g.dx[1] * cx->g.dx[2];
+        hipLaunchKernelGGL(k_qtab, dim3((nsmax + 127) / 128, NINST), dim3(128), 0, cx->stream, q, cx->d_q_idx,
+                           cx->d_q_w, cx->d_q_den, cx->d_q_n);
+        EBS_HIP(cx, hipGetLastError());
     }
     LArgs L;
     L.v = geo_view(cx);
@@ -900,6 +954,10 @@ static ebs_status redistribute_t(ebs_ctx* cx, ebs_state* Uout) {
     a.wgeo = cx->d_wl_geo;
     a.aself = cx->d_wl_self;
     a.asmall = cx->d_wl_small;
+    a.qidx = cx->d_q_idx;
+    a.qw = cx->d_q_w;
+    a.qden = cx->d_q_den;
+    a.qn = cx->d_q_n;
     a.limiter = cx->g.limiter;
     a.dv = cx->g.dx[0] * cx->g.dx[1] * cx->g.dx[2];
     if (nsmax > 0) {
