@@ -135,8 +135,14 @@ ebs_status ebs_create(const ebs_grid* grid, const ebs_box* boxes, int32_t nbox, 
 /* Build the four geometry instances and the redistribution tables from nodal
  * terrain heights (Section 3.2; Section 5.1 precomputation).  h_nodes has
  * (nx+1)*(ny+1) doubles, x fastest, on the host (on_device = 0) or device.
+ * Besides the geometry, the context then holds the static operators the
+ * stage and the redistribution read: cut-face interpolation records,
+ * stencil, update and cell tables of the general range, the Q-hat,
+ * least-squares and contributor operators (about 2 KB per general cell).
  * Synchronous.  Errors: EBS_E_ARG (non-finite heights, non-periodic node rows,
- * terrain reaching the top cell layer). */
+ * terrain reaching the top cell layer), EBS_E_OOM (device tables),
+ * EBS_E_UNSUPPORTED (general range or its tables beyond the sizes the
+ * tables index: 2^28 general cells and stencil positions), EBS_E_HIP. */
 ebs_status ebs_build_geometry_terrain(ebs_ctx* ctx, const double* h_nodes, int32_t on_device);
 
 /* Copy one quantity (EBS_Q_*) of instance inst (0 cell, 1 x-face, 2 y-face,
