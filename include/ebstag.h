@@ -180,8 +180,11 @@ ebs_status ebs_conserved_sums(ebs_ctx* ctx, const ebs_state* U, double hi[5], do
 
 /* Time the candidate tile shapes of the regular-region kernel on this
  * context's grid and keep the fastest; the choice is cached in the JSON file
- * (created if missing, keyed by precision and grid size; NULL = no cache).
- * Synchronous; scratch states are allocated and freed internally. */
+ * (created if missing, keyed by precision, grid size and box count; NULL = no
+ * cache).  Each candidate is timed on the three stages of a step (the first
+ * with U^n = U_cur), regular-region kernel and general passes together.
+ * Synchronous; three scratch states are allocated and freed internally
+ * (EBS_E_OOM if they do not fit). */
 ebs_status ebs_autotune(ebs_ctx* ctx, const char* cache_json_path);
 
 /* Tile shape of the regular-region kernel: tx x ty columns per block and at

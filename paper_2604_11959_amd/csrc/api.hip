@@ -521,12 +521,12 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
     const size_t es = c->g.precision == EBS_F32_BULK ? 4 : 8;
     const size_t nx = c->nx, ny = c->ny, nz = c->nz;
     const size_t cnt[5] = {nx * ny * nz, nx * ny * nz, (nx + 1) * ny * nz, nx * (ny + 1) * nz, nx * ny * (nz + 1)};
-    void* buf[2][5] = {{nullptr}};
-    ebs_state st[2];
-    for (int s = 0; s < 2; ++s) {
+    void* buf[3][5] = {{nullptr}};
+    ebs_state st[3];
+    for (int s = 0; s < 3; ++s) {
         for (int f = 0; f < 5; ++f) {
             if (hipMalloc(&buf[s][f], es * cnt[f]) != hipSuccess) {
-                for (int a = 0; a < 2; ++a)
+                for (int a = 0; a < 3; ++a)
                     for (int b = 0; b < 5; ++b) free_ptr(buf[a][b]);
                 return fail(c, EBS_E_OOM, "autotune scratch");
             }
@@ -534,8 +534,15 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
         }
         st[s] = {buf[s][0], buf[s][1], buf[s][2], buf[s][3], buf[s][4]};
     }
-    // timing only: the values (zeros) do not change the work done
+    // timing only: the values (zeros) do not change the work done.  Each
+    // repetition is the three stages of a step: U^n = U_cur once, then twice
+    // with separate U^n and U_cur.
     (void)hipStreamSynchronize(c->stream);
+    auto three = [&]() {
+        (void)launch_advance(c, &st[0], &st[0], &st[1], 0.0);
+        (void)launch_advance(c, &st[0], &st[1], &st[2], 0.0);
+        (void)launch_advance(c, &st[0], &st[2], &st[1], 0.0);
+    };
     const int cxy[][2] = {{16, 4}, {16, 8}, {16, 16}, {32, 4}, {32, 8}, {32, 16}, {64, 2}, {64, 4}, {64, 8}, {64, 16}};
     const int cz[] = {16, 32, 64};
     double best = 1e300;
@@ -548,10 +555,10 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
     for (int q = 0; q < (int)(sizeof(cxy) / sizeof(cxy[0]) * 6); ++q) {
         const int cd[4] = {cxy[q / 6][0], cxy[q / 6][1], cz[(q / 2) % 3], q % 2};
         if (ebs_set_tile(c, cd[0], cd[1], cd[2], cd[3]) != EBS_OK) continue;
-        for (int rep = 0; rep < 2; ++rep) (void)launch_advance(c, &st[0], &st[0], &st[1], 0.0);
+        three();
         (void)hipEventRecord(e0, c->stream);
-        const int reps = 5;
-        for (int rep = 0; rep < reps; ++rep) (void)launch_advance(c, &st[0], &st[0], &st[1], 0.0);
+        const int reps = 3;
+        for (int rep = 0; rep < reps; ++rep) three();
         (void)hipEventRecord(e1, c->stream);
         (void)hipEventSynchronize(e1);
         float ms = 0.f;
@@ -561,7 +568,7 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->timing = was_timing;
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 5; ++b) free_ptr(buf[a][b]);
     ebs_status sst = ebs_set_tile(c, bx, by, bz, bs);
     if (sst != EBS_OK) return sst;
