@@ -84,6 +84,14 @@ __device__ __forceinline__ T upw6(T m, T pLL, T pL, T pR, T pRR, bool okLL, bool
     return ok ? (T(5) * a + T(2) * b - e) : T(3) * (a + b);
 }
 
+// the same for z-faces, whose wall flags are uniform over the block: the
+// common case (both stencil ends inside the domain) takes a branch-free path
+template <typename T>
+__device__ __forceinline__ T upw6z(T m, T pLL, T pL, T pR, T pRR, bool okLL, bool okRR) {
+    if (okLL && okRR) return upw6<T>(m, pLL, pL, pR, pRR, true, true);
+    return upw6<T>(m, pLL, pL, pR, pRR, okLL, okRR);
+}
+
 // element access with a 32-bit byte offset (every field is below 4 GiB; the
 // context checks it), so the address is a scalar base plus a vector offset
 template <typename T>
@@ -311,7 +319,11 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             const T ru_i = RUk[0], ru_ip = RUk[1], ru_im = RUk[-1];
             const T rv_j = RVk[0], rv_jp = RVk[WX], rv_jm = RVk[-WX];
             const T rw_k = RWk[0], rw_kp = top ? T(0) : RWp[0];
-            const T h = T(0.5);
+            // The staggered instances' mass fluxes are the means of two stored
+            // momenta; their factor 1/2 is applied once, with the 1/6 of the
+            // upwind values (scaling by 1/2 is exact, so every rounding is the
+            // same as with the factor inside).
+            const T hs = T(0.5) * sixth;
             // lower z-face flux terms: carried from the upper faces of plane k - 1
             // when this thread updated it (same values, same arithmetic)
             T zl[4];
@@ -319,12 +331,12 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) zl[q] = fzc[q];
             } else {
-                zl[0] = rw_k * upw6<T>(rw_k, zc[0][0], zc[0][1], zc[0][2], zc[0][3], okL1, okR1);
-                const T m1l = h * (RWk[-1] + rw_k), m2l = h * (RWk[-WX] + rw_k);
-                const T m3l = (k != 1) ? h * (RWm[0] + rw_k) : T(0);
-                zl[1] = m1l * upw6<T>(m1l, zc[1][0], zc[1][1], zc[1][2], zc[1][3], okL1, okR1);
-                zl[2] = m2l * upw6<T>(m2l, zc[2][0], zc[2][1], zc[2][2], zc[2][3], okL1, okR1);
-                zl[3] = m3l * upw6<T>(m3l, zc[3][0], zc[3][1], zc[3][2], zc[3][3], k - 2 >= 1, okR1);
+                zl[0] = rw_k * upw6z<T>(rw_k, zc[0][0], zc[0][1], zc[0][2], zc[0][3], okL1, okR1);
+                const T m1l = RWk[-1] + rw_k, m2l = RWk[-WX] + rw_k;
+                const T m3l = (k != 1) ? RWm[0] + rw_k : T(0);
+                zl[1] = m1l * upw6z<T>(m1l, zc[1][0], zc[1][1], zc[1][2], zc[1][3], okL1, okR1);
+                zl[2] = m2l * upw6z<T>(m2l, zc[2][0], zc[2][1], zc[2][2], zc[2][3], okL1, okR1);
+                zl[3] = m3l * upw6z<T>(m3l, zc[3][0], zc[3][1], zc[3][2], zc[3][3], k - 2 >= 1, okR1);
             }
             // ---- cell-centred instance
             {
@@ -333,7 +345,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                              ru_i * upw6<T>(ru_i, TH[-2], TH[-1], TH[0], TH[1], true, true);
                 const T fy = rv_jp * upw6<T>(rv_jp, TH[-WX], TH[0], TH[WX], TH[2 * WX], true, true) -
                              rv_j * upw6<T>(rv_j, TH[-2 * WX], TH[-WX], TH[0], TH[WX], true, true);
-                fzc[0] = rw_kp * upw6<T>(rw_kp, zc[0][1], zc[0][2], zc[0][3], zc[0][4], okL0, okR2);
+                fzc[0] = rw_kp * upw6z<T>(rw_kp, zc[0][1], zc[0][2], zc[0][3], zc[0][4], okL0, okR2);
                 const T fz = fzc[0] - zl[0];
                 const T dr = ex * a.rdx + ey * a.rdy + ez * a.rdz;
                 const T dt = (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
@@ -342,50 +354,50 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             }
             // ---- x-face instance
             {
-                const T mxl = h * (ru_im + ru_i), mxh = h * (ru_i + ru_ip);
-                const T myl = h * (RVk[-1] + rv_j), myh = h * (RVk[WX - 1] + rv_jp);
-                const T mzh = top ? T(0) : h * (RWp[-1] + rw_kp);
+                const T mxl = ru_im + ru_i, mxh = ru_i + ru_ip;
+                const T myl = RVk[-1] + rv_j, myh = RVk[WX - 1] + rv_jp;
+                const T mzh = top ? T(0) : RWp[-1] + rw_kp;
                 const T fx = mxh * upw6<T>(mxh, UU[-1], UU[0], UU[1], UU[2], true, true) -
                              mxl * upw6<T>(mxl, UU[-2], UU[-1], UU[0], UU[1], true, true);
                 const T fy = myh * upw6<T>(myh, UU[-WX], UU[0], UU[WX], UU[2 * WX], true, true) -
                              myl * upw6<T>(myl, UU[-2 * WX], UU[-WX], UU[0], UU[WX], true, true);
-                fzc[1] = mzh * upw6<T>(mzh, zc[1][1], zc[1][2], zc[1][3], zc[1][4], okL0, okR2);
+                fzc[1] = mzh * upw6z<T>(mzh, zc[1][1], zc[1][2], zc[1][3], zc[1][4], okL0, okR2);
                 const T fz = fzc[1] - zl[1];
-                const T val = (SAME ? ru_i : uc[2]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
+                const T val = (SAME ? ru_i : uc[2]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * hs;
                 st(a.out[2], ou, val);
                 if (i == 0) st(a.out[2], ou + nx, val);
             }
             // ---- y-face instance
             {
-                const T mxl = h * (RUk[-WX] + ru_i), mxh = h * (RUk[1 - WX] + ru_ip);
-                const T myl = h * (rv_jm + rv_j), myh = h * (rv_j + rv_jp);
-                const T mzh = top ? T(0) : h * (RWp[-WX] + rw_kp);
+                const T mxl = RUk[-WX] + ru_i, mxh = RUk[1 - WX] + ru_ip;
+                const T myl = rv_jm + rv_j, myh = rv_j + rv_jp;
+                const T mzh = top ? T(0) : RWp[-WX] + rw_kp;
                 const T fx = mxh * upw6<T>(mxh, VV[-1], VV[0], VV[1], VV[2], true, true) -
                              mxl * upw6<T>(mxl, VV[-2], VV[-1], VV[0], VV[1], true, true);
                 const T fy = myh * upw6<T>(myh, VV[-WX], VV[0], VV[WX], VV[2 * WX], true, true) -
                              myl * upw6<T>(myl, VV[-2 * WX], VV[-WX], VV[0], VV[WX], true, true);
-                fzc[2] = mzh * upw6<T>(mzh, zc[2][1], zc[2][2], zc[2][3], zc[2][4], okL0, okR2);
+                fzc[2] = mzh * upw6z<T>(mzh, zc[2][1], zc[2][2], zc[2][3], zc[2][4], okL0, okR2);
                 const T fz = fzc[2] - zl[2];
-                const T val = (SAME ? rv_j : uc[3]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth;
+                const T val = (SAME ? rv_j : uc[3]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * hs;
                 st(a.out[3], ov, val);
                 if (j == 0) st(a.out[3], ov + (uint32_t)ny * nx, val);
             }
             // ---- z-face instance (k >= 1 in the regular range); zero flux
             // through the mid planes of the bottom and top cell layers
             {
-                const T mxl = h * (RUm[0] + ru_i), mxh = h * (RUm[1] + ru_ip);
-                const T myl = h * (RVm[0] + rv_j), myh = h * (RVm[WX] + rv_jp);
+                const T mxl = RUm[0] + ru_i, mxh = RUm[1] + ru_ip;
+                const T myl = RVm[0] + rv_j, myh = RVm[WX] + rv_jp;
                 // (at k = 0 there is no z-face CV: its "upper face" term is the
                 // zero flux of the lower face of the CV at k = 1, carried up)
-                const T mzh = (k != nz - 1 && k != 0) ? h * (rw_k + rw_kp) : T(0);
+                const T mzh = (k != nz - 1 && k != 0) ? rw_k + rw_kp : T(0);
                 const T fx = mxh * upw6<T>(mxh, WW[-1], WW[0], WW[1], WW[2], true, true) -
                              mxl * upw6<T>(mxl, WW[-2], WW[-1], WW[0], WW[1], true, true);
                 const T fy = myh * upw6<T>(myh, WW[-WX], WW[0], WW[WX], WW[2 * WX], true, true) -
                              myl * upw6<T>(myl, WW[-2 * WX], WW[-WX], WW[0], WW[WX], true, true);
-                fzc[3] = mzh * upw6<T>(mzh, zc[3][1], zc[3][2], zc[3][3], zc[3][4], k - 1 >= 1, okR2);
+                fzc[3] = mzh * upw6z<T>(mzh, zc[3][1], zc[3][2], zc[3][3], zc[3][4], k - 1 >= 1, okR2);
                 const T fz = fzc[3] - zl[3];
                 // plane 0 holds the bottom wall face, not a CV
-                st(a.out[4], oc, k == 0 ? T(0) : (SAME ? rw_k : uc[4]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * sixth);
+                st(a.out[4], oc, k == 0 ? T(0) : (SAME ? rw_k : uc[4]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * hs);
                 if (k == nz - 1) st(a.out[4], oc + pc, T(0));
             }
         }
