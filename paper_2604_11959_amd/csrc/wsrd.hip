@@ -364,8 +364,7 @@ __device__ inline double psi(double delta, double qi, double qmin, double qmax) 
 // c_s = A^-1 e_s, then the Barth-Jespersen-style limiter.  A group of
 // GRAD_LANES lanes shares one CV: the lanes split its fit points and combine
 // their partial sums and bounds by a butterfly over the group.
-constexpr int GRAD_LANES = 16;
-static_assert(LSQ_MAXEV <= GRAD_LANES, "one limiter evaluation point per lane");
+constexpr int GRAD_LANES = 8;
 
 __global__ void __launch_bounds__(256) k_grad(AArgs a) {
     const int f = blockIdx.y;
@@ -404,17 +403,19 @@ __global__ void __launch_bounds__(256) k_grad(AArgs a) {
         qmin = fmin(qmin, __shfl_xor(qmin, m, GRAD_LANES));
         qmax = fmax(qmax, __shfl_xor(qmax, m, GRAD_LANES));
     }
-    // limiter: lane q of the group evaluates point q (at most LSQ_MAXEV <=
-    // GRAD_LANES); the factors are combined by a min-butterfly (min is exact,
+    // limiter: the lanes of the group split the evaluation points (at most
+    // LSQ_MAXEV); the factors are combined by a min-butterfly (min is exact,
     // so the result does not depend on the order)
     const bool lim = valid && p1 > p0 && a.limiter != EBS_LIM_NONE;
     double lam[3] = {1.0, 1.0, 1.0};
-    if (lim && lane < a.lnev[e]) {
-        const double* ev = a.lev + ((size_t)e * LSQ_MAXEV + lane) * 3;
+    const int nev = lim ? a.lnev[e] : 0;
+    for (int q = lane; q < nev; q += GRAD_LANES) {
+        const double* ev = a.lev + ((size_t)e * LSQ_MAXEV + q) * 3;
         if (a.limiter == EBS_LIM_BJ_COMPONENT) {
-            for (int d = 0; d < 3; ++d) lam[d] = psi(s[d] * ev[d], qi, qmin, qmax);
+            for (int d = 0; d < 3; ++d) lam[d] = fmin(lam[d], psi(s[d] * ev[d], qi, qmin, qmax));
         } else {
-            lam[0] = lam[1] = lam[2] = psi(s[0] * ev[0] + s[1] * ev[1] + s[2] * ev[2], qi, qmin, qmax);
+            const double l = psi(s[0] * ev[0] + s[1] * ev[1] + s[2] * ev[2], qi, qmin, qmax);
+            for (int d = 0; d < 3; ++d) lam[d] = fmin(lam[d], l);
         }
     }
 #pragma unroll
