@@ -428,6 +428,8 @@ __global__ void __launch_bounds__(256) k_grad(AArgs a) {
     for (int d = 0; d < 3; ++d) a.sig[((size_t)f * 3 + d) * v.G + g] = s[d] / del[d];
 }
 
+constexpr int FINAL_LANES = 4;
+
 template <typename T>
 struct FArgs {
     AArgs a;
@@ -443,16 +445,33 @@ __global__ void __launch_bounds__(128) k_final(FArgs<T> F) {
     const AArgs& a = F.a;
     const int f = blockIdx.y;
     const int inst = field_inst(f);
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.na[inst]) return;
+    // FINAL_LANES lanes per CV split its contributors and add their partial
+    // sums by a butterfly over the group
+    const int lane = threadIdx.x % FINAL_LANES;
+    const int t = (blockIdx.x * blockDim.x + threadIdx.x) / FINAL_LANES;
+    const bool valid = t < a.na[inst];
     const GeoView& v = a.v;
-    const int g = a.alist[(size_t)inst * v.G + t];
-    const int e = a.abase[inst] + t;
+    const int g = valid ? a.alist[(size_t)inst * v.G + t] : 0;
+    const int e = valid ? a.abase[inst] + t : 0;
     const double del[3] = {v.dx, v.dy, v.dz};
     const double* Qh = a.qhat + (size_t)f * v.G;
     const double* sx = a.sig + ((size_t)f * 3 + 0) * v.G;
     const double* sy = a.sig + ((size_t)f * 3 + 1) * v.G;
     const double* sz = a.sig + ((size_t)f * 3 + 2) * v.G;
+    double s = 0.0;
+    const int q1 = valid ? a.woff[e + 1] : 0;
+    for (int q = (valid ? a.woff[e] : 0) + lane; q < q1; q += FINAL_LANES) {
+        const int gr = a.widx[q];
+        const double* w = a.wgeo + (size_t)q * 4;
+        double qr = Qh[gr];
+        qr += sx[gr] * w[1] * del[0];
+        qr += sy[gr] * w[2] * del[1];
+        qr += sz[gr] * w[3] * del[2];
+        s += w[0] * qr;
+    }
+#pragma unroll
+    for (int m = FINAL_LANES / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, FINAL_LANES);
+    if (!valid || lane != 0) return;
     const double* self = a.aself + (size_t)e * 5;
     const double om = self[0], Ni = self[1];
     double qi;
@@ -463,16 +482,6 @@ __global__ void __launch_bounds__(128) k_final(FArgs<T> F) {
         qi += sz[g] * self[4] * del[2];
     } else {
         qi = a.uhat[(size_t)f * v.G + g];
-    }
-    double s = 0.0;
-    for (int q = a.woff[e]; q < a.woff[e + 1]; ++q) {
-        const int gr = a.widx[q];
-        const double* w = a.wgeo + (size_t)q * 4;
-        double qr = Qh[gr];
-        qr += sx[gr] * w[1] * del[0];
-        qr += sy[gr] * w[2] * del[1];
-        qr += sz[gr] * w[3] * del[2];
-        s += w[0] * qr;
     }
     const double val = om * qi + s / Ni;
     // write into the state layout (with the periodic repeat)
@@ -973,7 +982,7 @@ static ebs_status redistribute_t(ebs_ctx* cx, ebs_state* Uout) {
         F.ny = cx->ny;
         F.nz = cx->nz;
         for (int f = 0; f < 5; ++f) F.out[f] = (T*)ou[f];
-        hipLaunchKernelGGL(k_final<T>, dim3((namax + 127) / 128, 5), dim3(128), 0, cx->stream, F);
+        hipLaunchKernelGGL(k_final<T>, dim3((namax * FINAL_LANES + 127) / 128, 5), dim3(128), 0, cx->stream, F);
     }
     EBS_HIP(cx, hipGetLastError());
     return EBS_OK;
