@@ -89,10 +89,10 @@ def run_workload(cfg: int, precision: int, steps: int, warmup: int, use_graph: b
     return res
 
 
-def measured_traffic(tile, workload_name):
+def measured_traffic(tile, workload_name, alg_bytes):
     """Calibrated HBM bytes per regular-region launch from the committed counter
-    summary, or None when it was taken for another kernel source, tile or
-    workload."""
+    summary, or None when it was taken for another kernel source, tile,
+    workload or regular region (algorithmic bytes per launch)."""
     from paper_2604_11959_amd import profile_traffic
 
     try:
@@ -103,6 +103,8 @@ def measured_traffic(tile, workload_name):
     if s.get("kernel_source_sha256") != profile_traffic.source_sha256():
         return None
     if list(s.get("tile") or []) != list(tile) or s.get("workload") != workload_name:
+        return None
+    if s.get("alg_bytes_per_launch") != alg_bytes:
         return None
     return float(s["traffic_bytes_per_launch"])
 
@@ -219,7 +221,7 @@ def main(argv=None):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(main["tile"], w.name),
+            "traffic": measured_traffic(main["tile"], w.name, bytes_per_launch),
             "avg_launch_ms": round(avg_ms, 4),
             "alg_bytes_per_launch": bytes_per_launch,
         },

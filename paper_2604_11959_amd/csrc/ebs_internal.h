@@ -37,9 +37,12 @@ enum : int {
 // redistribution tables per general cell and instance (doubles)
 enum : int { WQ_N = 0, WQ_KAPPA, WQ_OMEGA, WQ_VHAT, WQ_XHX, WQ_XHY, WQ_XHZ, WQ_COUNT };
 
-// margins of the general region around the cut band (cells)
+// reach of the regular-region stencils (cells, laterally and downwards) and of
+// the redistribution footprint of a small CV (neighbourhood, fit points)
 constexpr int GEN_RXY = 3;
 constexpr int GEN_RZ = 3;
+constexpr int WSRD_RXY = 2;
+constexpr int WSRD_RZ = 2;
 // tie / threshold tolerance of the discrete redistribution decisions
 constexpr double TIE = 1e-12;
 

@@ -394,25 +394,40 @@ __global__ void k_classify(GeomArgs a) {
     a.g0[c] = gmin;
 }
 
+// Top g1 of the general range of a column.  At and above it the
+// regular-region kernel applies the plain formulas, which needs (a) every CV
+// of the cell regular (full faces, no cut-face interpolation), (b) every CV
+// its stencils read, up to GEN_RXY columns away and GEN_RZ cells below, fluid
+// (no order reduction; face densities average both sides), and (c) the cell
+// outside the redistribution footprint of every small CV (neighbourhood
+// members and least-squares fit points reach WSRD_RXY columns and WSRD_RZ
+// cells above a cut CV).  A column whose whole neighbourhood is regular down
+// to the bottom wall has an empty range.
 __global__ void k_g1(GeomArgs a) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int ncol = a.nx * a.ny;
     if (c >= ncol) return;
     const int i = c % a.nx, j = c / a.nx;
-    int m = 0;
-    bool flat = true;  // every CV of every instance in the window is regular
+    int own = 0;         // (a): first level where every instance is regular
+    int kfw = 0, kfx = 0;  // (b): highest first fluid level, and above the lowest CV level
+    int wsrd = 0;        // (c)
+    bool flat = true;    // every CV of every instance in the window is regular
     for (int dj = -GEN_RXY; dj <= GEN_RXY; ++dj)
         for (int di = -GEN_RXY; di <= GEN_RXY; ++di) {
             const int cc = wrapi(j + dj, a.ny) * a.nx + wrapi(i + di, a.nx);
+            const bool near = abs(di) <= WSRD_RXY && abs(dj) <= WSRD_RXY;
             for (int inst = 0; inst < 4; ++inst) {
-                const int kr = a.kr[inst * ncol + cc];
-                m = max(m, kr);
-                flat = flat && kr == (inst == 3 ? 1 : 0);
+                const int low = inst == 3 ? 1 : 0;  // lowest CV level of the instance
+                const int kr = a.kr[inst * ncol + cc], kf = a.kf[inst * ncol + cc];
+                flat = flat && kr == low;
+                kfw = max(kfw, kf);
+                kfx = max(kfx, kf - low);
+                if (near && kr > low) wsrd = max(wsrd, kr + WSRD_RZ);
+                if (di == 0 && dj == 0) own = max(own, kr);
             }
         }
-    // a column whose whole neighbourhood is regular down to the bottom wall
-    // has an empty general range (the regular-region kernel handles the wall)
-    a.g1[c] = flat ? a.g0[c] : min(a.nz, max(m + GEN_RZ, a.g0[c]));
+    const int fluid = kfx > 0 ? kfw + GEN_RZ : 0;
+    a.g1[c] = flat ? a.g0[c] : min(a.nz, max(max(own, fluid), max(wsrd, a.g0[c])));
 }
 
 struct RecArgs {

@@ -8,8 +8,9 @@ RK step, no graph, so every stage is its own dispatch) and ``cfetch`` /
 ``cwrite`` of a plain 1 GiB device copy (``bench.py --calib-copy``).  The copy
 reads and writes exactly 2^30 bytes, which fixes the scale factor of each
 counter (FETCH_SIZE counts some request sizes at half width).  The summary
-records the mean calibrated bytes per regular-region launch and a SHA-256 of
-the kernel source, so that a later change of the kernel invalidates it.
+records the mean calibrated bytes per regular-region launch, a SHA-256 of
+the kernel source and the algorithmic bytes of one launch (which fix the
+regular region it covered), so that a later change of either invalidates it.
 """
 from __future__ import annotations
 
@@ -84,8 +85,16 @@ def main(argv=None) -> int:
     ap.add_argument("--command", default="", help="the profiling command, recorded verbatim")
     ap.add_argument("--workload", default="")
     ap.add_argument("--tile", default="")
+    ap.add_argument("--bench-log", default="",
+                    help="output of the profiled bench run; its algorithmic bytes per launch are recorded")
     args = ap.parse_args(argv)
     s = summarize(args.pmc_dir)
+    s["alg_bytes_per_launch"] = None
+    if args.bench_log:
+        with open(args.bench_log) as f:
+            for line in f:
+                if line.startswith("{") and '"roofline"' in line:
+                    s["alg_bytes_per_launch"] = json.loads(line)["roofline"]["alg_bytes_per_launch"]
     s["command"] = args.command
     s["workload"] = args.workload
     s["tile"] = [int(v) for v in args.tile.split("x")] if args.tile else None
