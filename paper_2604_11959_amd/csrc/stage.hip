@@ -38,9 +38,9 @@ namespace {
 //
 // A stencil position is general (an index into the range), below its column's
 // range (no instance is fluid) or above it.  The range's top is chosen so that
-// a position above it has only regular CVs within three cells in x and y and
-// below it; its advected quantities and fluxes therefore follow the plain
-// formulas (every neighbour inside the domain is fluid, faces are full).  Every
+// a position above it is regular and every CV within three cells in x and y
+// and three below it is fluid; its advected quantities and fluxes therefore
+// follow the plain formulas (two-sided face densities, full faces).  Every
 // neighbour a cut-face interpolation reads lies within one cell of a CV that is
 // not regular, hence inside or below its column's range.  Since the geometry
 // is static, the positions the flux and update passes read are resolved once
