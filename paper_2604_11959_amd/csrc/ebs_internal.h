@@ -194,6 +194,7 @@ struct ebs_ctx {
     double* d_q_w = nullptr;          // [nlsq][8] its weights
     double* d_q_den = nullptr;        // [nlsq] V-hat
     int8_t* d_q_n = nullptr;          // [nlsq] entries used
+    int32_t* d_chk = nullptr;         // set-up check counter
 
     // per-stage buffers (cut region, double)
     double* d_uhat = nullptr;  // [5][G] provisional state of the last advance

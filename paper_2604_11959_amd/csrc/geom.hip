@@ -319,6 +319,7 @@ struct GeomArgs {
     int32_t* kr;
     int32_t* g0;
     int32_t* g1;
+    const int32_t* stop;  // [ncol] highest level of a small CV, -1 if none (null: not yet known)
 };
 
 __device__ inline Heights cell_heights(const double* h, int nx, int ny, int i, int j) {
@@ -401,8 +402,11 @@ __global__ void k_classify(GeomArgs a) {
 // (no order reduction; face densities average both sides), and (c) the cell
 // outside the redistribution footprint of every small CV (neighbourhood
 // members and least-squares fit points reach WSRD_RXY columns and WSRD_RZ
-// cells above a cut CV).  A column whose whole neighbourhood is regular down
-// to the bottom wall has an empty range.
+// cells above a small CV).  Before the volume fractions are known, every CV
+// below kr counts as possibly small; once they are (a.stop), the footprint
+// of the actual small CVs is used, together with the reach of the cut-face
+// interpolation.  A column whose whole neighbourhood is regular down to the
+// bottom wall has an empty range.
 __global__ void k_g1(GeomArgs a) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int ncol = a.nx * a.ny;
@@ -422,9 +426,14 @@ __global__ void k_g1(GeomArgs a) {
                 flat = flat && kr == low;
                 kfw = max(kfw, kf);
                 kfx = max(kfx, kf - low);
-                if (near && kr > low) wsrd = max(wsrd, kr + WSRD_RZ);
+                if (near && !a.stop && kr > low) wsrd = max(wsrd, kr + WSRD_RZ);
+                // the cut-face interpolation of a cut CV reads the faces of
+                // its neighbours one column away and one level up: they must
+                // lie in the stored face range (at least one above g1)
+                if (abs(di) <= 1 && abs(dj) <= 1 && a.stop && kr > low) wsrd = max(wsrd, kr);
                 if (di == 0 && dj == 0) own = max(own, kr);
             }
+            if (near && a.stop && a.stop[cc] >= 0) wsrd = max(wsrd, a.stop[cc] + WSRD_RZ + 1);
         }
     const int fluid = kfx > 0 ? kfw + GEN_RZ : 0;
     a.g1[c] = flat ? a.g0[c] : min(a.nz, max(max(own, fluid), max(wsrd, a.g0[c])));
@@ -542,7 +551,25 @@ __global__ void k_records(RecArgs r) {
     put(r, inst, GQ_AREA, g, o.area / (DX * DY));
 }
 
+// highest level of a small CV (0 < volume fraction < vfrac, any instance) per
+// column of the general range
+__global__ void k_small_top(RecArgs r, double vfrac, int32_t* stop) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= r.G) return;
+    bool small = false;
+    for (int s = 0; s < NINST; ++s) {
+        const double al = r.geo[((size_t)s * GQ_N + GQ_ALPHA) * r.G + g];
+        small = small || (al > 0.0 && al < vfrac);
+    }
+    if (!small) return;
+    const int c = r.gcol[g];
+    const int k = r.a.g0[c] + (g - r.goff[c]);
+    atomicMax(&stop[c], k);
+}
+
 }  // namespace
+
+static ebs_status build_range(ebs_ctx* cx, const GeomArgs& a);
 
 ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
     const int ncol = cx->ncol;
@@ -552,11 +579,55 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
     a.lo_z = cx->g.lo[2];
     a.h = d_h;
     a.kf = cx->d_kf; a.kr = cx->d_kr; a.g0 = cx->d_g0; a.g1 = cx->d_g1;
+    a.stop = nullptr;
     const int tb = 256;
     hipLaunchKernelGGL(k_classify, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
     EBS_HIP(cx, hipGetLastError());
+    // pass 1: every CV below kr may be small
     hipLaunchKernelGGL(k_g1, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
     EBS_HIP(cx, hipGetLastError());
+    ebs_status st = build_range(cx, a);
+    if (st != EBS_OK || cx->G == 0) return st;
+    // pass 2: the footprint of the small CVs found in pass 1 (they all lie in
+    // its range); the range can only shrink
+    int32_t* d_stop = nullptr;
+    if (hipMalloc(&d_stop, sizeof(int32_t) * ncol) != hipSuccess) {
+        cx->err = "device allocation of geometry tables failed";
+        return EBS_E_OOM;
+    }
+    std::vector<int32_t> g1_first = cx->h_g1;
+    hipError_t e = hipMemsetAsync(d_stop, 0xFF, sizeof(int32_t) * ncol, cx->stream);
+    if (e == hipSuccess) {
+        RecArgs r;
+        r.a = a;
+        r.goff = cx->d_goff;
+        r.gcol = cx->d_gcol;
+        r.G = cx->G;
+        r.geo = cx->d_geo;
+        r.type = cx->d_type;
+        hipLaunchKernelGGL(k_small_top, dim3((cx->G + 255) / 256), dim3(256), 0, cx->stream, r,
+                           cx->g.small_vfrac, d_stop);
+        a.stop = d_stop;
+        hipLaunchKernelGGL(k_g1, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(cx->h_g1.data(), cx->d_g1, sizeof(int32_t) * ncol,
+                                            hipMemcpyDeviceToHost, cx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(cx->stream);
+    (void)hipFree(d_stop);
+    if (e != hipSuccess) {
+        cx->err = std::string("general range: ") + hipGetErrorString(e);
+        return EBS_E_HIP;
+    }
+    a.stop = nullptr;
+    if (cx->h_g1 == g1_first) return EBS_OK;
+    return build_range(cx, a);
+}
+
+// the general range from the column ranges in d_g0 / d_g1: index tables, per
+// cell allocations, geometry records, packed types and face flags
+static ebs_status build_range(ebs_ctx* cx, const GeomArgs& a) {
+    const int ncol = cx->ncol;
     cx->h_g0.assign(ncol, 0);
     cx->h_g1.assign(ncol, 0);
     EBS_HIP(cx, hipMemcpyAsync(cx->h_g0.data(), cx->d_g0, sizeof(int32_t) * ncol,

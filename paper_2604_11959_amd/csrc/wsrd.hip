@@ -47,6 +47,7 @@ struct WArgs {
     double* w;      // [4][WQ_COUNT][G]
     double vfrac;   // small_vfrac
     double dv;
+    int32_t* bad;   // counts neighbourhood members above the general range
 };
 
 __device__ inline double& wq(const WArgs& a, int inst, int q, int g) {
@@ -125,6 +126,9 @@ __global__ void k_merge(WArgs a) {
                     if ((mask >> bt) & 1) continue;
                     const int gn = nbr(v, inst, i + off[0], j + off[1], k + off[2]);
                     if (gn == -2) continue;
+                    // members must lie in the general range (its top covers the
+                    // footprint of every small CV); checked, not assumed
+                    if (gn == -1) atomicAdd(a.bad, 1);
                     mask |= 1 << bt;
                     vsum += alpha_of(v, inst, gn) * dv;
                 }
@@ -581,6 +585,7 @@ struct LArgs {
     double* c;
     double* ev;
     int8_t* nev;
+    int32_t* bad;          // counts fit points above the general range
 };
 
 __global__ void __launch_bounds__(64) k_lsq(LArgs a) {
@@ -605,7 +610,10 @@ __global__ void __launch_bounds__(64) k_lsq(LArgs a) {
                 for (int ox = -wd[0]; ox <= wd[0]; ++ox) {
                     if (ox == 0 && oy == 0 && oz == 0) continue;
                     const int gs = nbr(v, inst, i + ox, j + oy, k + oz);
-                    if (gs < 0) continue;  // not fluid (regular CVs lie outside the fit radius)
+                    // a fluid CV above the general range would be a missing fit
+                    // point: the range's top excludes it, and this checks it
+                    if (gs == -1 && !a.fill) atomicAdd(a.bad, 1);
+                    if (gs < 0) continue;  // not fluid
                     const int o[3] = {ox, oy, oz};
                     for (int d = 0; d < 3; ++d) spread[d] = fmax(spread[d], fabs(o[d] + W(WQ_XHX + d, gs) - xh[d]));
                     ++npts;
@@ -714,6 +722,11 @@ WsrdView wsrd_view(const ebs_ctx* c) {
 
 ebs_status wsrd_setup(ebs_ctx* cx) {
     if (cx->G == 0) return EBS_OK;
+    if (!cx->d_chk && hipMalloc(&cx->d_chk, sizeof(int32_t)) != hipSuccess) {
+        cx->err = "device allocation of the redistribution tables failed";
+        return EBS_E_OOM;
+    }
+    EBS_HIP(cx, hipMemsetAsync(cx->d_chk, 0, sizeof(int32_t), cx->stream));
     WArgs a;
     a.v = geo_view(cx);
     a.mask = cx->d_mask;
@@ -722,6 +735,7 @@ ebs_status wsrd_setup(ebs_ctx* cx) {
     a.w = cx->d_w;
     a.vfrac = cx->g.small_vfrac;
     a.dv = cx->g.dx[0] * cx->g.dx[1] * cx->g.dx[2];
+    a.bad = cx->d_chk;
     const dim3 grid((cx->G + 127) / 128, NINST), blk(128);
     hipLaunchKernelGGL(k_merge, grid, blk, 0, cx->stream, a);
     hipLaunchKernelGGL(k_count, grid, blk, 0, cx->stream, a);
@@ -799,6 +813,7 @@ ebs_status wsrd_setup(ebs_ctx* cx) {
         EBS_HIP(cx, hipGetLastError());
     }
     LArgs L;
+    L.bad = cx->d_chk;
     L.v = geo_view(cx);
     L.mask = cx->d_mask;
     L.small = cx->d_small;
@@ -824,7 +839,13 @@ ebs_status wsrd_setup(ebs_ctx* cx) {
     if (S > 0)
         EBS_HIP(cx, hipMemcpyAsync(off.data(), cx->d_lsq_off, sizeof(int32_t) * S, hipMemcpyDeviceToHost,
                                    cx->stream));
+    int32_t outside = 0;
+    EBS_HIP(cx, hipMemcpyAsync(&outside, cx->d_chk, sizeof(int32_t), hipMemcpyDeviceToHost, cx->stream));
     EBS_HIP(cx, hipStreamSynchronize(cx->stream));
+    if (outside != 0) {
+        cx->err = "a redistribution neighbourhood member or fit point lies above the general range";
+        return EBS_E_UNSUPPORTED;
+    }
     int64_t P = 0;
     for (int32_t e = 0; e < S; ++e) {
         const int32_t n = off[e];
