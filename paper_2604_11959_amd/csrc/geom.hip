@@ -396,47 +396,62 @@ __global__ void k_classify(GeomArgs a) {
 }
 
 // Top g1 of the general range of a column.  At and above it the
-// regular-region kernel applies the plain formulas, which needs (a) every CV
-// of the cell regular (full faces, no cut-face interpolation), (b) every CV
-// its stencils read, up to GEN_RXY columns away and GEN_RZ cells below, fluid
-// (no order reduction; face densities average both sides), and (c) the cell
-// outside the redistribution footprint of every small CV (neighbourhood
-// members and least-squares fit points reach WSRD_RXY columns and WSRD_RZ
-// cells above a small CV).  Before the volume fractions are known, every CV
-// below kr counts as possibly small; once they are (a.stop), the footprint
-// of the actual small CVs is used, together with the reach of the cut-face
-// interpolation.  A column whose whole neighbourhood is regular down to the
-// bottom wall has an empty range.
+// regular-region kernel applies the plain formulas, which needs
+//  (a) every CV of the cell regular (full faces, no cut-face interpolation);
+//  (b) every CV its stencils read fluid (no order reduction; face densities
+//      average both sides).  At the cell's own level they lie from GEN_RXY
+//      columns below to GEN_RXY - 1 above in x and y (a staggered velocity
+//      reads the densities on both sides of its face), and a vertical
+//      velocity there reads the density one cell lower; in the own column
+//      they reach GEN_RZ - 1 cells down, where the vertical velocity reads the
+//      density GEN_RZ down and the horizontal ones the densities of the -x
+//      and -y neighbours;
+//  (c) the cell outside the redistribution footprint of every small CV
+//      (neighbourhood members and least-squares fit points reach WSRD_RXY
+//      columns and WSRD_RZ cells above a small CV).
+// Before the volume fractions are known, every CV below kr counts as
+// possibly small; once they are (a.stop), the footprint of the actual small
+// CVs is used, together with the reach of the cut-face interpolation (the
+// faces one column away and one level up from a cut CV must lie in the
+// stored face range, which extends at least one above g1).  A column whose
+// whole neighbourhood is regular down to the bottom wall has an empty range.
+// "Fluid from level e" uses e = 0 for an instance that is fluid from its
+// lowest CV level (nothing to require there).
 __global__ void k_g1(GeomArgs a) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int ncol = a.nx * a.ny;
     if (c >= ncol) return;
     const int i = c % a.nx, j = c / a.nx;
-    int own = 0;         // (a): first level where every instance is regular
-    int kfw = 0, kfx = 0;  // (b): highest first fluid level, and above the lowest CV level
-    int wsrd = 0;        // (c)
-    bool flat = true;    // every CV of every instance in the window is regular
+    auto eff = [&](int s, int cc) {
+        const int kf = a.kf[s * ncol + cc];
+        return kf == (s == 3 ? 1 : 0) ? 0 : kf;
+    };
+    auto eff_all = [&](int cc) { return max(max(eff(0, cc), eff(1, cc)), max(eff(2, cc), eff(3, cc))); };
+    auto need = [](int e, int d) { return e > 0 ? e + d : 0; };
+    int own = 0;   // (a)
+    int fl = 0;    // (b)
+    int wsrd = 0;  // (c)
+    bool flat = true;  // every CV of every instance in the window is regular
     for (int dj = -GEN_RXY; dj <= GEN_RXY; ++dj)
         for (int di = -GEN_RXY; di <= GEN_RXY; ++di) {
             const int cc = wrapi(j + dj, a.ny) * a.nx + wrapi(i + di, a.nx);
             const bool near = abs(di) <= WSRD_RXY && abs(dj) <= WSRD_RXY;
+            if (di < GEN_RXY && dj < GEN_RXY) fl = max(fl, need(eff_all(cc), 1));
             for (int inst = 0; inst < 4; ++inst) {
                 const int low = inst == 3 ? 1 : 0;  // lowest CV level of the instance
-                const int kr = a.kr[inst * ncol + cc], kf = a.kf[inst * ncol + cc];
+                const int kr = a.kr[inst * ncol + cc];
                 flat = flat && kr == low;
-                kfw = max(kfw, kf);
-                kfx = max(kfx, kf - low);
                 if (near && !a.stop && kr > low) wsrd = max(wsrd, kr + WSRD_RZ);
-                // the cut-face interpolation of a cut CV reads the faces of
-                // its neighbours one column away and one level up: they must
-                // lie in the stored face range (at least one above g1)
                 if (abs(di) <= 1 && abs(dj) <= 1 && a.stop && kr > low) wsrd = max(wsrd, kr);
                 if (di == 0 && dj == 0) own = max(own, kr);
             }
             if (near && a.stop && a.stop[cc] >= 0) wsrd = max(wsrd, a.stop[cc] + WSRD_RZ + 1);
         }
-    const int fluid = kfx > 0 ? kfw + GEN_RZ : 0;
-    a.g1[c] = flat ? a.g0[c] : min(a.nz, max(max(own, fluid), max(wsrd, a.g0[c])));
+    // own column, and the -x / -y neighbours at the depth of the z stencils
+    fl = max(fl, max(need(eff_all(c), GEN_RZ - 1), need(eff(0, c), GEN_RZ)));
+    fl = max(fl, need(eff(0, j * a.nx + wrapi(i - 1, a.nx)), GEN_RZ - 1));
+    fl = max(fl, need(eff(0, wrapi(j - 1, a.ny) * a.nx + i), GEN_RZ - 1));
+    a.g1[c] = flat ? a.g0[c] : min(a.nz, max(max(own, fl), max(wsrd, a.g0[c])));
 }
 
 struct RecArgs {
