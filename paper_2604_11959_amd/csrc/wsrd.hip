@@ -363,18 +363,17 @@ __device__ inline double psi(double delta, double qi, double qmin, double qmax) 
     return 1.0;
 }
 
-// Limited least-squares gradient of Q-hat for one field (blockIdx.y = field),
-// from the precomputed operator: sigma = sum_s c_s (Q-hat_s - Q-hat_i) with
+// Limited least-squares gradient of Q-hat, per small CV and field of its
+// instance, from the precomputed operator: sigma = sum_s c_s (Q-hat_s - Q-hat_i) with
 // c_s = A^-1 e_s, then the Barth-Jespersen-style limiter.  A group of
 // GRAD_LANES lanes shares one CV: the lanes split its fit points and combine
 // their partial sums and bounds by a butterfly over the group.
 constexpr int GRAD_LANES = 8;
 
-__global__ void __launch_bounds__(256) k_grad(AArgs a) {
-    const int f = blockIdx.y;
-    const int inst = field_inst(f);
-    const int lane = threadIdx.x % GRAD_LANES;
-    const int t = blockIdx.x * (256 / GRAD_LANES) + threadIdx.x / GRAD_LANES;
+// NF fields of one instance (the cell-centred instance carries rho and rho
+// theta) share the group's operator loads
+template <int NF>
+__device__ __forceinline__ void grad_group(const AArgs& a, int inst, int f0, int lane, int t) {
     const bool valid = t < a.ns[inst];
     const GeoView& v = a.v;
     int g = 0, e = 0, p0 = 0, p1 = 0;
@@ -384,52 +383,83 @@ __global__ void __launch_bounds__(256) k_grad(AArgs a) {
         p0 = a.loff[e];
         p1 = a.loff[e + 1];
     }
-    const double* Qh = a.qhat + (size_t)f * v.G;
-    const double* Uh = a.uhat + (size_t)f * v.G;
-    const double qi = valid ? Qh[g] : 0.0;
-    double s[3] = {0.0, 0.0, 0.0};
-    double qmin = qi, qmax = qi;
+    double qi[NF], s[NF][3], qmin[NF], qmax[NF];
+#pragma unroll
+    for (int n = 0; n < NF; ++n) {
+        qi[n] = valid ? a.qhat[(size_t)(f0 + n) * v.G + g] : 0.0;
+        s[n][0] = s[n][1] = s[n][2] = 0.0;
+        qmin[n] = qmax[n] = qi[n];
+    }
     for (int p = p0 + lane; p < p1; p += GRAD_LANES) {
         const uint32_t id = a.lidx[p];
-        const double qs = (id & LSQ_QHAT) ? Qh[id & ~LSQ_QHAT] : Uh[id];
-        const double dq = qs - qi;
-        s[0] += a.lc[3 * (size_t)p] * dq;
-        s[1] += a.lc[3 * (size_t)p + 1] * dq;
-        s[2] += a.lc[3 * (size_t)p + 2] * dq;
-        qmin = fmin(qmin, qs);
-        qmax = fmax(qmax, qs);
-    }
+        const double c0 = a.lc[3 * (size_t)p], c1 = a.lc[3 * (size_t)p + 1], c2 = a.lc[3 * (size_t)p + 2];
 #pragma unroll
-    for (int m = GRAD_LANES / 2; m >= 1; m >>= 1) {
-        s[0] += __shfl_xor(s[0], m, GRAD_LANES);
-        s[1] += __shfl_xor(s[1], m, GRAD_LANES);
-        s[2] += __shfl_xor(s[2], m, GRAD_LANES);
-        qmin = fmin(qmin, __shfl_xor(qmin, m, GRAD_LANES));
-        qmax = fmax(qmax, __shfl_xor(qmax, m, GRAD_LANES));
-    }
-    // limiter: the lanes of the group split the evaluation points (at most
-    // LSQ_MAXEV); the factors are combined by a min-butterfly (min is exact,
-    // so the result does not depend on the order)
-    const bool lim = valid && p1 > p0 && a.limiter != EBS_LIM_NONE;
-    double lam[3] = {1.0, 1.0, 1.0};
-    const int nev = lim ? a.lnev[e] : 0;
-    for (int q = lane; q < nev; q += GRAD_LANES) {
-        const double* ev = a.lev + ((size_t)e * LSQ_MAXEV + q) * 3;
-        if (a.limiter == EBS_LIM_BJ_COMPONENT) {
-            for (int d = 0; d < 3; ++d) lam[d] = fmin(lam[d], psi(s[d] * ev[d], qi, qmin, qmax));
-        } else {
-            const double l = psi(s[0] * ev[0] + s[1] * ev[1] + s[2] * ev[2], qi, qmin, qmax);
-            for (int d = 0; d < 3; ++d) lam[d] = fmin(lam[d], l);
+        for (int n = 0; n < NF; ++n) {
+            const size_t fo = (size_t)(f0 + n) * v.G;
+            const double qs = (id & LSQ_QHAT) ? a.qhat[fo + (id & ~LSQ_QHAT)] : a.uhat[fo + id];
+            const double dq = qs - qi[n];
+            s[n][0] += c0 * dq;
+            s[n][1] += c1 * dq;
+            s[n][2] += c2 * dq;
+            qmin[n] = fmin(qmin[n], qs);
+            qmax[n] = fmax(qmax[n], qs);
         }
     }
 #pragma unroll
     for (int m = GRAD_LANES / 2; m >= 1; m >>= 1)
-        for (int d = 0; d < 3; ++d) lam[d] = fmin(lam[d], __shfl_xor(lam[d], m, GRAD_LANES));
+#pragma unroll
+        for (int n = 0; n < NF; ++n) {
+            s[n][0] += __shfl_xor(s[n][0], m, GRAD_LANES);
+            s[n][1] += __shfl_xor(s[n][1], m, GRAD_LANES);
+            s[n][2] += __shfl_xor(s[n][2], m, GRAD_LANES);
+            qmin[n] = fmin(qmin[n], __shfl_xor(qmin[n], m, GRAD_LANES));
+            qmax[n] = fmax(qmax[n], __shfl_xor(qmax[n], m, GRAD_LANES));
+        }
+    // limiter: the lanes of the group split the evaluation points (at most
+    // LSQ_MAXEV); the factors are combined by a min-butterfly (min is exact,
+    // so the result does not depend on the order)
+    const bool lim = valid && p1 > p0 && a.limiter != EBS_LIM_NONE;
+    double lam[NF][3];
+#pragma unroll
+    for (int n = 0; n < NF; ++n) lam[n][0] = lam[n][1] = lam[n][2] = 1.0;
+    const int nev = lim ? a.lnev[e] : 0;
+    for (int q = lane; q < nev; q += GRAD_LANES) {
+        const double* ev = a.lev + ((size_t)e * LSQ_MAXEV + q) * 3;
+#pragma unroll
+        for (int n = 0; n < NF; ++n) {
+            if (a.limiter == EBS_LIM_BJ_COMPONENT) {
+                for (int d = 0; d < 3; ++d)
+                    lam[n][d] = fmin(lam[n][d], psi(s[n][d] * ev[d], qi[n], qmin[n], qmax[n]));
+            } else {
+                const double l = psi(s[n][0] * ev[0] + s[n][1] * ev[1] + s[n][2] * ev[2], qi[n], qmin[n], qmax[n]);
+                for (int d = 0; d < 3; ++d) lam[n][d] = fmin(lam[n][d], l);
+            }
+        }
+    }
+#pragma unroll
+    for (int m = GRAD_LANES / 2; m >= 1; m >>= 1)
+#pragma unroll
+        for (int n = 0; n < NF; ++n)
+            for (int d = 0; d < 3; ++d) lam[n][d] = fmin(lam[n][d], __shfl_xor(lam[n][d], m, GRAD_LANES));
     if (!valid || lane != 0) return;
-    if (lim)
-        for (int d = 0; d < 3; ++d) s[d] *= lam[d];
     const double del[3] = {v.dx, v.dy, v.dz};
-    for (int d = 0; d < 3; ++d) a.sig[((size_t)f * 3 + d) * v.G + g] = s[d] / del[d];
+#pragma unroll
+    for (int n = 0; n < NF; ++n) {
+        if (lim)
+            for (int d = 0; d < 3; ++d) s[n][d] *= lam[n][d];
+        for (int d = 0; d < 3; ++d) a.sig[((size_t)(f0 + n) * 3 + d) * v.G + g] = s[n][d] / del[d];
+    }
+}
+
+// one launch for all instances (blockIdx.y = instance)
+__global__ void __launch_bounds__(256) k_grad(AArgs a) {
+    const int inst = blockIdx.y;
+    const int lane = threadIdx.x % GRAD_LANES;
+    const int t = blockIdx.x * (256 / GRAD_LANES) + threadIdx.x / GRAD_LANES;
+    if (inst == 0)
+        grad_group<2>(a, 0, 0, lane, t);
+    else
+        grad_group<1>(a, inst, inst + 1, lane, t);
 }
 
 constexpr int FINAL_LANES = 4;
@@ -441,65 +471,83 @@ struct FArgs {
     T* out[5];
 };
 
-// Final update (Eqs. qrecon, final_update_omega) of one field (blockIdx.y)
-// on the CVs the operator may change, gathered over the precomputed list of
-// neighbourhoods containing each CV (W minus itself, fixed order).
-template <typename T>
-__global__ void __launch_bounds__(128) k_final(FArgs<T> F) {
+// Final update (Eqs. qrecon, final_update_omega) of the NF fields of one
+// instance on the CVs the operator may change, gathered over the precomputed
+// list of neighbourhoods containing each CV (W minus itself, fixed order).
+template <typename T, int NF>
+__device__ __forceinline__ void final_group(const FArgs<T>& F, int inst, int f0, int lane, int t) {
     const AArgs& a = F.a;
-    const int f = blockIdx.y;
-    const int inst = field_inst(f);
-    // FINAL_LANES lanes per CV split its contributors and add their partial
-    // sums by a butterfly over the group
-    const int lane = threadIdx.x % FINAL_LANES;
-    const int t = (blockIdx.x * blockDim.x + threadIdx.x) / FINAL_LANES;
     const bool valid = t < a.na[inst];
     const GeoView& v = a.v;
     const int g = valid ? a.alist[(size_t)inst * v.G + t] : 0;
     const int e = valid ? a.abase[inst] + t : 0;
     const double del[3] = {v.dx, v.dy, v.dz};
-    const double* Qh = a.qhat + (size_t)f * v.G;
-    const double* sx = a.sig + ((size_t)f * 3 + 0) * v.G;
-    const double* sy = a.sig + ((size_t)f * 3 + 1) * v.G;
-    const double* sz = a.sig + ((size_t)f * 3 + 2) * v.G;
-    double s = 0.0;
+    double s[NF];
+#pragma unroll
+    for (int n = 0; n < NF; ++n) s[n] = 0.0;
     const int q1 = valid ? a.woff[e + 1] : 0;
     for (int q = (valid ? a.woff[e] : 0) + lane; q < q1; q += FINAL_LANES) {
         const int gr = a.widx[q];
         const double* w = a.wgeo + (size_t)q * 4;
-        double qr = Qh[gr];
-        qr += sx[gr] * w[1] * del[0];
-        qr += sy[gr] * w[2] * del[1];
-        qr += sz[gr] * w[3] * del[2];
-        s += w[0] * qr;
+        const double w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3];
+#pragma unroll
+        for (int n = 0; n < NF; ++n) {
+            const size_t f = f0 + n;
+            double qr = a.qhat[f * v.G + gr];
+            qr += a.sig[(f * 3 + 0) * v.G + gr] * w1 * del[0];
+            qr += a.sig[(f * 3 + 1) * v.G + gr] * w2 * del[1];
+            qr += a.sig[(f * 3 + 2) * v.G + gr] * w3 * del[2];
+            s[n] += w0 * qr;
+        }
     }
 #pragma unroll
-    for (int m = FINAL_LANES / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, FINAL_LANES);
+    for (int m = FINAL_LANES / 2; m >= 1; m >>= 1)
+#pragma unroll
+        for (int n = 0; n < NF; ++n) s[n] += __shfl_xor(s[n], m, FINAL_LANES);
     if (!valid || lane != 0) return;
     const double* self = a.aself + (size_t)e * 5;
     const double om = self[0], Ni = self[1];
-    double qi;
-    if (a.asmall[e]) {
-        qi = Qh[g];
-        qi += sx[g] * self[2] * del[0];
-        qi += sy[g] * self[3] * del[1];
-        qi += sz[g] * self[4] * del[2];
-    } else {
-        qi = a.uhat[(size_t)f * v.G + g];
-    }
-    const double val = om * qi + s / Ni;
+    const bool sm = a.asmall[e];
     // write into the state layout (with the periodic repeat)
     int i, j, k;
     cell_of(v, g, i, j, k);
     const int nx = F.nx, ny = F.ny;
-    size_t idx;
-    if (f == 2) idx = ((size_t)k * ny + j) * (nx + 1) + i;
-    else if (f == 3) idx = ((size_t)k * (ny + 1) + j) * nx + i;
-    else idx = ((size_t)k * ny + j) * nx + i;
-    T* o = f == 0 ? F.out[0] : f == 1 ? F.out[1] : f == 2 ? F.out[2] : f == 3 ? F.out[3] : F.out[4];
-    o[idx] = (T)val;
-    if (f == 2 && i == 0) F.out[2][((size_t)k * ny + j) * (nx + 1) + nx] = (T)val;
-    if (f == 3 && j == 0) F.out[3][((size_t)k * (ny + 1) + ny) * nx + i] = (T)val;
+#pragma unroll
+    for (int n = 0; n < NF; ++n) {
+        const int f = f0 + n;
+        double qi;
+        if (sm) {
+            qi = a.qhat[(size_t)f * v.G + g];
+            qi += a.sig[((size_t)f * 3 + 0) * v.G + g] * self[2] * del[0];
+            qi += a.sig[((size_t)f * 3 + 1) * v.G + g] * self[3] * del[1];
+            qi += a.sig[((size_t)f * 3 + 2) * v.G + g] * self[4] * del[2];
+        } else {
+            qi = a.uhat[(size_t)f * v.G + g];
+        }
+        const double val = om * qi + s[n] / Ni;
+        size_t idx;
+        if (f == 2) idx = ((size_t)k * ny + j) * (nx + 1) + i;
+        else if (f == 3) idx = ((size_t)k * (ny + 1) + j) * nx + i;
+        else idx = ((size_t)k * ny + j) * nx + i;
+        T* o = f == 0 ? F.out[0] : f == 1 ? F.out[1] : f == 2 ? F.out[2] : f == 3 ? F.out[3] : F.out[4];
+        o[idx] = (T)val;
+        if (f == 2 && i == 0) F.out[2][((size_t)k * ny + j) * (nx + 1) + nx] = (T)val;
+        if (f == 3 && j == 0) F.out[3][((size_t)k * (ny + 1) + ny) * nx + i] = (T)val;
+    }
+}
+
+// FINAL_LANES lanes per CV split its contributors and add their partial sums
+// by a butterfly over the group; the fields of one instance share the
+// contributor loads (blockIdx.y = instance)
+template <typename T>
+__global__ void __launch_bounds__(128) k_final(FArgs<T> F) {
+    const int inst = blockIdx.y;
+    const int lane = threadIdx.x % FINAL_LANES;
+    const int t = (blockIdx.x * blockDim.x + threadIdx.x) / FINAL_LANES;
+    if (inst == 0)
+        final_group<T, 2>(F, 0, 0, lane, t);
+    else
+        final_group<T, 1>(F, inst, inst + 1, lane, t);
 }
 
 // Contributor lists of the final update, built once per geometry: for every
@@ -994,7 +1042,7 @@ static ebs_status redistribute_t(ebs_ctx* cx, ebs_state* Uout) {
     if (nsmax > 0) {
         hipLaunchKernelGGL(k_qhat, dim3((nsmax + 127) / 128, NINST), dim3(128), 0, cx->stream, a);
         const int per = 256 / GRAD_LANES;
-        hipLaunchKernelGGL(k_grad, dim3((nsmax + per - 1) / per, 5), dim3(256), 0, cx->stream, a);
+        hipLaunchKernelGGL(k_grad, dim3((nsmax + per - 1) / per, NINST), dim3(256), 0, cx->stream, a);
     }
     if (namax > 0) {
         FArgs<T> F;
@@ -1003,7 +1051,7 @@ static ebs_status redistribute_t(ebs_ctx* cx, ebs_state* Uout) {
         F.ny = cx->ny;
         F.nz = cx->nz;
         for (int f = 0; f < 5; ++f) F.out[f] = (T*)ou[f];
-        hipLaunchKernelGGL(k_final<T>, dim3((namax * FINAL_LANES + 127) / 128, 5), dim3(128), 0, cx->stream, F);
+        hipLaunchKernelGGL(k_final<T>, dim3((namax * FINAL_LANES + 127) / 128, NINST), dim3(128), 0, cx->stream, F);
     }
     EBS_HIP(cx, hipGetLastError());
     return EBS_OK;
