@@ -231,15 +231,21 @@ ebs_status ebs_build_geometry_terrain(ebs_ctx* c, const double* h_nodes, int32_t
         (void)hipFree(d_h);
         return hip_fail(c, e, "terrain upload");
     }
-    ebs_status st = build_geometry(c, d_h);
-    (void)hipStreamSynchronize(c->stream);
+    // The tight general range rests on the small CVs found in a first, looser
+    // range; the set-up steps check that every stencil, interpolation and
+    // redistribution read stays inside it.  If one of them fails, the
+    // geometry is rebuilt with the looser range.
+    ebs_status st = EBS_OK;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        c->tight_range = attempt == 0;
+        st = build_geometry(c, d_h);
+        (void)hipStreamSynchronize(c->stream);
+        if (st == EBS_OK) st = build_cut_faces(c);
+        if (st == EBS_OK) st = build_stencils(c);
+        if (st == EBS_OK) st = wsrd_setup(c);
+        if (st != EBS_E_UNSUPPORTED) break;
+    }
     (void)hipFree(d_h);
-    if (st != EBS_OK) return st;
-    st = build_cut_faces(c);
-    if (st != EBS_OK) return st;
-    st = build_stencils(c);
-    if (st != EBS_OK) return st;
-    st = wsrd_setup(c);
     if (st != EBS_OK) return st;
     st = build_tiles(c);
     if (st != EBS_OK) return st;

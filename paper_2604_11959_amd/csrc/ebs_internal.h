@@ -166,6 +166,7 @@ struct ebs_ctx {
     int8_t* d_type = nullptr;
     uint32_t* d_type4 = nullptr;
     std::vector<int32_t> h_g0, h_g1, h_goff, h_g1e;
+    bool tight_range = true;  // second pass of the general range (small-CV footprint)
 
     // redistribution
     int32_t* d_mask = nullptr;

@@ -602,7 +602,7 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
     hipLaunchKernelGGL(k_g1, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
     EBS_HIP(cx, hipGetLastError());
     ebs_status st = build_range(cx, a);
-    if (st != EBS_OK || cx->G == 0) return st;
+    if (st != EBS_OK || cx->G == 0 || !cx->tight_range) return st;
     // pass 2: the footprint of the small CVs found in pass 1 (they all lie in
     // its range); the range can only shrink
     int32_t* d_stop = nullptr;
