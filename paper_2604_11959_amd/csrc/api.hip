@@ -231,20 +231,32 @@ ebs_status ebs_build_geometry_terrain(ebs_ctx* c, const double* h_nodes, int32_t
         (void)hipFree(d_h);
         return hip_fail(c, e, "terrain upload");
     }
-    // The tight general range rests on the small CVs found in a first, looser
-    // range; the set-up steps check that every stencil, interpolation and
-    // redistribution read stays inside it.  If one of them fails, the
-    // geometry is rebuilt with the looser range.
-    ebs_status st = EBS_OK;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        c->tight_range = attempt == 0;
-        st = build_geometry(c, d_h);
+    // The general range is built three times at most: with the footprint of
+    // the small CVs (mode 1), then with the cells the resulting redistribution
+    // tables actually touch (mode 2).  The set-up steps check that every
+    // stencil, interpolation and redistribution read stays inside the range;
+    // a check that fails falls back to the previous mode (mode 0 takes every
+    // CV below kr as possibly small).
+    auto build_all = [&](int mode) -> ebs_status {
+        c->range_mode = mode;
+        ebs_status r = build_geometry(c, d_h);
         (void)hipStreamSynchronize(c->stream);
-        if (st == EBS_OK) st = build_cut_faces(c);
-        if (st == EBS_OK) st = build_stencils(c);
-        if (st == EBS_OK) st = wsrd_setup(c);
-        if (st != EBS_E_UNSUPPORTED) break;
+        if (r == EBS_OK) r = build_cut_faces(c);
+        if (r == EBS_OK) r = build_stencils(c);
+        if (r == EBS_OK) r = wsrd_setup(c);
+        return r;
+    };
+    ebs_status st = build_all(1);
+    if (st == EBS_OK) {
+        std::vector<int32_t> ftop;
+        st = redistribution_tops(c, ftop);
+        if (st == EBS_OK) {
+            c->h_ftop.swap(ftop);
+            st = build_all(2);
+            if (st == EBS_E_UNSUPPORTED) st = build_all(1);
+        }
     }
+    if (st == EBS_E_UNSUPPORTED) st = build_all(0);
     (void)hipFree(d_h);
     if (st != EBS_OK) return st;
     st = build_tiles(c);

@@ -166,7 +166,11 @@ struct ebs_ctx {
     int8_t* d_type = nullptr;
     uint32_t* d_type4 = nullptr;
     std::vector<int32_t> h_g0, h_g1, h_goff, h_g1e;
-    bool tight_range = true;  // second pass of the general range (small-CV footprint)
+    // general range rule: 0 loose (every CV below kr possibly small), 1 tight
+    // (footprint window of the small CVs), 2 exact (the cells the
+    // redistribution reads or writes, h_ftop, per column)
+    int range_mode = 1;
+    std::vector<int32_t> h_ftop;  // [ncol] highest level the redistribution touches, -1 if none
 
     // redistribution
     int32_t* d_mask = nullptr;
@@ -244,6 +248,9 @@ ebs_status join_side(ebs_ctx* c);
 ebs_status build_tiles(ebs_ctx* c);
 ebs_status build_cut_faces(ebs_ctx* c);
 ebs_status build_stencils(ebs_ctx* c);
+// per column the highest level the redistribution reads or writes (its
+// active CVs and least-squares fit points), from the current tables
+ebs_status redistribution_tops(ebs_ctx* c, std::vector<int32_t>& ftop);
 // regular-region kernel (bulk.hip) on the given stream, with its timing events
 ebs_status launch_bulk(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uhat, double cdt,
                        hipStream_t stream);

@@ -320,6 +320,7 @@ struct GeomArgs {
     int32_t* g0;
     int32_t* g1;
     const int32_t* stop;  // [ncol] highest level of a small CV, -1 if none (null: not yet known)
+    const int32_t* ftop;  // [ncol] highest level the redistribution touches, -1 if none (null: unknown)
 };
 
 __device__ inline Heights cell_heights(const double* h, int nx, int ny, int i, int j) {
@@ -413,7 +414,9 @@ __global__ void k_classify(GeomArgs a) {
 // possibly small; once they are (a.stop), the footprint of the actual small
 // CVs is used, together with the reach of the cut-face interpolation (the
 // faces one column away and one level up from a cut CV must lie in the
-// stored face range, which extends at least one above g1).  A column whose
+// stored face range, which extends at least one above g1).  Once the
+// redistribution tables exist (a.ftop), the range only has to contain the
+// cells they read or write in its own column.  A column whose
 // whole neighbourhood is regular down to the bottom wall has an empty range.
 // "Fluid from level e" uses e = 0 for an instance that is fluid from its
 // lowest CV level (nothing to require there).
@@ -441,12 +444,13 @@ __global__ void k_g1(GeomArgs a) {
                 const int low = inst == 3 ? 1 : 0;  // lowest CV level of the instance
                 const int kr = a.kr[inst * ncol + cc];
                 flat = flat && kr == low;
-                if (near && !a.stop && kr > low) wsrd = max(wsrd, kr + WSRD_RZ);
-                if (abs(di) <= 1 && abs(dj) <= 1 && a.stop && kr > low) wsrd = max(wsrd, kr);
+                if (near && !a.stop && !a.ftop && kr > low) wsrd = max(wsrd, kr + WSRD_RZ);
+                if (abs(di) <= 1 && abs(dj) <= 1 && (a.stop || a.ftop) && kr > low) wsrd = max(wsrd, kr);
                 if (di == 0 && dj == 0) own = max(own, kr);
             }
             if (near && a.stop && a.stop[cc] >= 0) wsrd = max(wsrd, a.stop[cc] + WSRD_RZ + 1);
         }
+    if (a.ftop && a.ftop[c] >= 0) wsrd = max(wsrd, a.ftop[c] + 1);
     // own column, and the -x / -y neighbours at the depth of the z stencils
     fl = max(fl, max(need(eff_all(c), GEN_RZ - 1), need(eff(0, c), GEN_RZ)));
     fl = max(fl, need(eff(0, j * a.nx + wrapi(i - 1, a.nx)), GEN_RZ - 1));
@@ -595,14 +599,38 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
     a.h = d_h;
     a.kf = cx->d_kf; a.kr = cx->d_kr; a.g0 = cx->d_g0; a.g1 = cx->d_g1;
     a.stop = nullptr;
+    a.ftop = nullptr;
     const int tb = 256;
     hipLaunchKernelGGL(k_classify, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
     EBS_HIP(cx, hipGetLastError());
+    if (cx->range_mode == 2) {
+        // one pass with the redistribution footprint of an earlier build
+        int32_t* d_ftop = nullptr;
+        if ((int)cx->h_ftop.size() != ncol || hipMalloc(&d_ftop, sizeof(int32_t) * ncol) != hipSuccess) {
+            cx->err = "general range: no redistribution footprint";
+            return EBS_E_UNSUPPORTED;
+        }
+        hipError_t e = hipMemcpyAsync(d_ftop, cx->h_ftop.data(), sizeof(int32_t) * ncol, hipMemcpyHostToDevice,
+                                      cx->stream);
+        a.ftop = d_ftop;
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_g1, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(cx->stream);
+        (void)hipFree(d_ftop);
+        if (e != hipSuccess) {
+            cx->err = std::string("general range: ") + hipGetErrorString(e);
+            return EBS_E_HIP;
+        }
+        a.ftop = nullptr;
+        return build_range(cx, a);
+    }
     // pass 1: every CV below kr may be small
     hipLaunchKernelGGL(k_g1, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
     EBS_HIP(cx, hipGetLastError());
     ebs_status st = build_range(cx, a);
-    if (st != EBS_OK || cx->G == 0 || !cx->tight_range) return st;
+    if (st != EBS_OK || cx->G == 0 || cx->range_mode == 0) return st;
     // pass 2: the footprint of the small CVs found in pass 1 (they all lie in
     // its range); the range can only shrink
     int32_t* d_stop = nullptr;

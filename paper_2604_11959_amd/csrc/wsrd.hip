@@ -1001,6 +1001,62 @@ ebs_status wsrd_setup(ebs_ctx* cx) {
     return EBS_OK;
 }
 
+namespace {
+
+// the level of general cell g raised into its column's footprint top
+__device__ inline void raise_top(const GeoView& v, int g, int32_t* ftop) {
+    const int c = v.gcol[g];
+    atomicMax(&ftop[c], col_g0(v.col[c]) + (g - v.col[c].z));
+}
+
+// every CV the redistribution writes (active lists) or reads beyond them
+// (least-squares fit points)
+__global__ void __launch_bounds__(256) k_tops(GeoView v, const int32_t* alist, int32_t na0, int32_t na1,
+                                              int32_t na2, int32_t na3, const uint32_t* lidx, int64_t npts,
+                                              int32_t* ftop) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t na[4] = {na0, na1, na2, na3};
+    int64_t r = t;
+    for (int inst = 0; inst < NINST; ++inst) {
+        if (r < na[inst]) {
+            raise_top(v, alist[(size_t)inst * v.G + r], ftop);
+            return;
+        }
+        r -= na[inst];
+    }
+    if (r < npts) raise_top(v, (int)(lidx[r] & ~LSQ_QHAT), ftop);
+}
+
+}  // namespace
+
+ebs_status redistribution_tops(ebs_ctx* cx, std::vector<int32_t>& ftop) {
+    ftop.assign(cx->ncol, -1);
+    if (cx->G == 0) return EBS_OK;
+    int32_t* d = nullptr;
+    if (hipMalloc(&d, sizeof(int32_t) * cx->ncol) != hipSuccess) {
+        cx->err = "device allocation of the redistribution footprint failed";
+        return EBS_E_OOM;
+    }
+    int64_t n = cx->nlsq_pts;
+    for (int inst = 0; inst < NINST; ++inst) n += cx->nact[inst];
+    hipError_t e = hipMemsetAsync(d, 0xFF, sizeof(int32_t) * cx->ncol, cx->stream);
+    if (e == hipSuccess && n > 0) {
+        hipLaunchKernelGGL(k_tops, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, cx->stream, geo_view(cx),
+                           cx->d_actlist, cx->nact[0], cx->nact[1], cx->nact[2], cx->nact[3], cx->d_lsq_idx,
+                           cx->nlsq_pts, d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ftop.data(), d, sizeof(int32_t) * cx->ncol, hipMemcpyDeviceToHost, cx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(cx->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) {
+        cx->err = std::string("redistribution footprint: ") + hipGetErrorString(e);
+        return EBS_E_HIP;
+    }
+    return EBS_OK;
+}
+
 template <typename T>
 static ebs_status redistribute_t(ebs_ctx* cx, ebs_state* Uout) {
     void* const ou[5] = {Uout->rho, Uout->rhotheta, Uout->rhou, Uout->rhov, Uout->rhow};
