@@ -412,9 +412,8 @@ __global__ void k_classify(GeomArgs a) {
 //      columns and WSRD_RZ cells above a small CV).
 // Before the volume fractions are known, every CV below kr counts as
 // possibly small; once they are (a.stop), the footprint of the actual small
-// CVs is used, together with the reach of the cut-face interpolation (the
-// faces one column away and one level up from a cut CV must lie in the
-// stored face range, which extends at least one above g1).  Once the
+// CVs is used (the reach of the cut-face interpolation is covered by the
+// face range, see build_range).  Once the
 // redistribution tables exist (a.ftop), the range only has to contain the
 // cells they read or write in its own column.  A column whose
 // whole neighbourhood is regular down to the bottom wall has an empty range.
@@ -445,7 +444,6 @@ __global__ void k_g1(GeomArgs a) {
                 const int kr = a.kr[inst * ncol + cc];
                 flat = flat && kr == low;
                 if (near && !a.stop && !a.ftop && kr > low) wsrd = max(wsrd, kr + WSRD_RZ);
-                if (abs(di) <= 1 && abs(dj) <= 1 && (a.stop || a.ftop) && kr > low) wsrd = max(wsrd, kr);
                 if (di == 0 && dj == 0) own = max(own, kr);
             }
             if (near && a.stop && a.stop[cc] >= 0) wsrd = max(wsrd, a.stop[cc] + WSRD_RZ + 1);
@@ -694,7 +692,17 @@ static ebs_status build_range(ebs_ctx* cx, const GeomArgs& a) {
     cx->G = (int32_t)G;
     const size_t Gs = (size_t)std::max<int64_t>(G, 1);
     // extended face range: the lower faces of every CV whose face bounds a
-    // general CV from above (+x, +y neighbours and the cell above the range)
+    // general CV from above (+x, +y neighbours and the cell above the range).
+    // It also holds the faces a cut-face interpolation reads: one column away
+    // and up to one level above a cut CV, i.e. up to level kr of every cut
+    // column in the 3 x 3 neighbourhood.
+    std::vector<int32_t> h_kr((size_t)NINST * ncol), krcut(ncol, 0);
+    EBS_HIP(cx, hipMemcpy(h_kr.data(), cx->d_kr, sizeof(int32_t) * NINST * ncol, hipMemcpyDeviceToHost));
+    for (int c = 0; c < ncol; ++c)
+        for (int s = 0; s < NINST; ++s) {
+            const int kr = h_kr[(size_t)s * ncol + c];
+            if (kr > (s == 3 ? 1 : 0)) krcut[c] = std::max(krcut[c], kr + 1);
+        }
     std::vector<int32_t> g1e(ncol), goffe(ncol);
     int64_t Ge = 0;
     for (int c = 0; c < ncol; ++c) {
@@ -702,7 +710,13 @@ static ebs_status build_range(ebs_ctx* cx, const GeomArgs& a) {
         const int cxm = j * cx->nx + (i == 0 ? cx->nx - 1 : i - 1);
         const int cym = (j == 0 ? cx->ny - 1 : j - 1) * cx->nx + i;
         const int own = cx->h_g1[c] > cx->h_g0[c] ? cx->h_g1[c] + 1 : cx->h_g0[c];
-        g1e[c] = std::min(cx->nz, std::max(own, std::max(cx->h_g1[cxm], cx->h_g1[cym])));
+        int interp = 0;
+        for (int dj = -1; dj <= 1; ++dj)
+            for (int di = -1; di <= 1; ++di) {
+                const int ii = (i + di + cx->nx) % cx->nx, jj = (j + dj + cx->ny) % cx->ny;
+                interp = std::max(interp, krcut[jj * cx->nx + ii]);
+            }
+        g1e[c] = std::min(cx->nz, std::max(std::max(own, interp), std::max(cx->h_g1[cxm], cx->h_g1[cym])));
         goffe[c] = (int32_t)Ge;
         Ge += g1e[c] - cx->h_g0[c];
     }
