@@ -206,6 +206,16 @@ ebs_status ebs_get_tile(const ebs_ctx* ctx, int32_t* tx, int32_t* ty, int32_t* t
  * default).  The results are identical; the captured RK3 graph is rebuilt. */
 ebs_status ebs_set_overlap(ebs_ctx* ctx, int32_t enable);
 
+/* Rule for the top of each column's general range (the cells the FP64 cut
+ * passes update; above it the regular-region kernel applies the plain
+ * formulas), used by the next ebs_build_geometry_terrain.  rule 0: every CV
+ * below the first regular level counts as possibly small; 1: the footprint
+ * of the actual small CVs; 2 (default): the cells the redistribution tables
+ * actually read or write.  A stricter rule gives fewer general cells and the
+ * same results up to rounding; if one of its set-up checks fails, the build
+ * falls back to the next looser rule.  EBS_E_ARG for another value. */
+ebs_status ebs_set_range_rule(ebs_ctx* ctx, int32_t rule);
+
 /* Kernel timing: when enabled, every launch of the regular-region stage
  * kernel is bracketed by HIP events on the context stream; read returns the
  * summed duration (ms) and launch count since the last reset and resets. */

@@ -29,7 +29,7 @@ Q = dict(ALPHA=0, BETA_X=1, BETA_Y=2, BETA_Z=3, FX_Y=4, FX_Z=5, FY_X=6, FY_Z=7, 
 # every entry point declared in include/ebstag.h
 SYMBOLS = ("ebs_create", "ebs_build_geometry_terrain", "ebs_geometry_export", "ebs_geometry_stats",
            "ebs_advance_stage", "ebs_redistribute", "ebs_rk3_step", "ebs_conserved_sums",
-           "ebs_autotune", "ebs_set_tile", "ebs_get_tile", "ebs_set_overlap", "ebs_timing_enable", "ebs_timing_read",
+           "ebs_autotune", "ebs_set_tile", "ebs_get_tile", "ebs_set_overlap", "ebs_set_range_rule", "ebs_timing_enable", "ebs_timing_read",
            "ebs_algorithmic_bytes", "ebs_last_error", "ebs_destroy")
 
 
@@ -79,6 +79,7 @@ def load(path: str = LIB_PATH):
         "ebs_set_tile": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
         "ebs_get_tile": [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)],
         "ebs_set_overlap": [C.c_void_p, C.c_int32],
+        "ebs_set_range_rule": [C.c_void_p, C.c_int32],
         "ebs_timing_enable": [C.c_void_p, C.c_int32],
         "ebs_timing_read": [C.c_void_p, P(C.c_double), P(C.c_int64)],
         "ebs_algorithmic_bytes": [C.c_void_p, P(C.c_double)],
@@ -230,6 +231,12 @@ class Context:
     def set_overlap(self, enable: bool):
         """Regular-region kernel concurrent with the general range (True) or serial (default)."""
         self._check(self.lib.ebs_set_overlap(self.h, int(bool(enable))), "ebs_set_overlap")
+
+    def set_range_rule(self, rule: int):
+        """Rule for the top of the general range used by the next geometry build:
+        0 loose, 1 small-CV footprint, 2 (default) the cells the redistribution
+        touches."""
+        self._check(self.lib.ebs_set_range_rule(self.h, int(rule)), "ebs_set_range_rule")
 
     def get_tile(self):
         tx, ty, tz, sp = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()

@@ -236,7 +236,8 @@ ebs_status ebs_build_geometry_terrain(ebs_ctx* c, const double* h_nodes, int32_t
     // tables actually touch (mode 2).  The set-up steps check that every
     // stencil, interpolation and redistribution read stays inside the range;
     // a check that fails falls back to the previous mode (mode 0 takes every
-    // CV below kr as possibly small).
+    // CV below kr as possibly small).  ebs_set_range_rule caps the strictest
+    // mode tried.
     auto build_all = [&](int mode) -> ebs_status {
         c->range_mode = mode;
         ebs_status r = build_geometry(c, d_h);
@@ -246,8 +247,8 @@ ebs_status ebs_build_geometry_terrain(ebs_ctx* c, const double* h_nodes, int32_t
         if (r == EBS_OK) r = wsrd_setup(c);
         return r;
     };
-    ebs_status st = build_all(1);
-    if (st == EBS_OK) {
+    ebs_status st = build_all(std::min(c->range_rule, 1));
+    if (st == EBS_OK && c->range_rule == 2) {
         std::vector<int32_t> ftop;
         st = redistribution_tops(c, ftop);
         if (st == EBS_OK) {
@@ -256,7 +257,7 @@ ebs_status ebs_build_geometry_terrain(ebs_ctx* c, const double* h_nodes, int32_t
             if (st == EBS_E_UNSUPPORTED) st = build_all(1);
         }
     }
-    if (st == EBS_E_UNSUPPORTED) st = build_all(0);
+    if (st == EBS_E_UNSUPPORTED && c->range_mode != 0) st = build_all(0);
     (void)hipFree(d_h);
     if (st != EBS_OK) return st;
     st = build_tiles(c);
@@ -463,6 +464,13 @@ ebs_status ebs_set_tile(ebs_ctx* c, int32_t tx, int32_t ty, int32_t tz, int32_t 
     c->tile_span = span;
     drop_graph(c);
     if (c->have_geom) return build_tiles(c);
+    return EBS_OK;
+}
+
+ebs_status ebs_set_range_rule(ebs_ctx* c, int32_t rule) {
+    if (!c) return EBS_E_ARG;
+    if (rule < 0 || rule > 2) return fail(c, EBS_E_ARG, "range rule must be 0, 1 or 2");
+    c->range_rule = rule;
     return EBS_OK;
 }
 

@@ -170,6 +170,7 @@ struct ebs_ctx {
     // (footprint window of the small CVs), 2 exact (the cells the
     // redistribution reads or writes, h_ftop, per column)
     int range_mode = 1;
+    int range_rule = 2;  // the strictest mode the geometry build tries (ebs_set_range_rule)
     std::vector<int32_t> h_ftop;  // [ncol] highest level the redistribution touches, -1 if none
 
     // redistribution

@@ -190,6 +190,35 @@ def test_stage_parity_random_state_fp64():
     assert max(err.values()) <= 1e-12, err
 
 
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_general_range_rules(cfg):
+    """Each rule for the top of the general range (0 loose, 1 small-CV
+    footprint, 2 the cells the redistribution touches) gives the oracle's
+    stage within the FP64 bar; a stricter rule never keeps more general cells."""
+    w, o = _oracle(cfg)
+    U0 = synth.state_random(w.grid, 31, amp=1.0) if cfg == 1 else synth.make_state(w)
+    cdt = w.dt / 3
+    ref = o.stage(U0, U0, cdt)
+    m = _fluid_masks(o)
+    general = []
+    for rule in (0, 1, 2):
+        print(f"[range rule] cfg={cfg} rule={rule}", flush=True)
+        c = ebs.Context(w.grid.n, w.grid.dx, w.grid.lo, precision=ebs.EBS_F64)
+        c.set_range_rule(rule)
+        c.build_geometry(w.h_nodes)
+        general.append(int(c.stats()[0][6]))
+        Ud, Uh = c.new_state(U0), c.new_state()
+        c.advance(Ud, Ud, Uh, cdt)
+        c.redistribute(Uh, Uh)
+        torch.cuda.synchronize()
+        err = rel_err(_host(Uh), ref, m)
+        assert max(err.values()) <= 1e-12, (rule, err)
+    print("general cells per rule", general)
+    assert general[0] >= general[1] >= general[2] > 0, general
+    with pytest.raises(ebs.EbsError):
+        c.set_range_rule(3)
+
+
 def _hills_with_flat_ground(nz=40):
     """Two small truncated hills: most columns are flat ground (h = 0), whose
     whole neighbourhood is regular down to the bottom wall."""
