@@ -23,7 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = ["geom.c", "flux.c", "wsrd.c"]
+_SRC = ["geom.c", "flux.c", "wsrd.c", "source.c"]
 
 # geometry quantity indices (mirror oracle.h)
 OQ = dict(ALPHA=0, BX=1, BY=2, BZ=3, FX1=4, FX2=5, FY1=6, FY2=7, FZ1=8, FZ2=9,
@@ -52,6 +52,10 @@ def build(force: bool = False) -> str:
     return _SO
 
 
+class _Src(C.Structure):
+    _fields_ = [("P00", C.c_double), ("R", C.c_double), ("gamma", C.c_double), ("g", C.c_double)]
+
+
 class _Grid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("dx", C.c_double * 3), ("lo", C.c_double * 3),
                 ("small_vfrac", C.c_double), ("limiter", C.c_int32), ("eb_flux", C.c_int32)]
@@ -75,6 +79,7 @@ def _load():
         lib.orc_redistribute.argtypes = [P(_Grid), dpp, dpp, dpp, dpp]
         lib.orc_redistribute_sig.argtypes = [P(_Grid), dpp, dpp, dpp, dpp, dpp]
         lib.orc_face_fluxes.argtypes = [P(_Grid), dpp, dpp, C.c_int, dpp, dpp]
+        lib.orc_sources.argtypes = [P(_Grid), dpp, dpp, P(_Src), dp, dp, dpp]
         lib.orc_box_moments.argtypes = [P(_Grid), dp, C.c_int, C.c_int, dp, C.c_double,
                                         C.c_double, C.c_int, dp]
         _lib = lib
@@ -179,10 +184,37 @@ class Oracle:
             self.g.eb_flux = eb_flux
 
     # ------------------------------------------------------------- operators
-    def advance_dense(self, Un: list, Ucur: list, cdt: float) -> list:
+    def sources_dense(self, Ucur: list, ref) -> list:
+        """Momentum sources (perturbation pressure gradient, buoyancy) of a
+        dense state for the reference state ``ref`` (attributes P00, R,
+        gamma, g, p0[nz], rho0[nz]): three dense arrays, instances 1-3."""
+        nz = self.n[2]
+        p0 = np.ascontiguousarray(ref.p0, dtype=np.float64)
+        r0 = np.ascontiguousarray(ref.rho0, dtype=np.float64)
+        assert p0.shape == (nz,) and r0.shape == (nz,)
+        S = [np.zeros_like(Ucur[0]) for _ in range(3)]
+        prm = _Src(float(ref.P00), float(ref.R), float(ref.gamma), float(ref.g))
+        _load().orc_sources(C.byref(self.g), _dpp(self.geo), _dpp(Ucur), C.byref(prm), _dptr(p0),
+                            _dptr(r0), _dpp(S))
+        return S
+
+    def sources(self, U: dict, ref) -> dict:
+        """Intensive momentum sources in the public layout (rhou, rhov, rhow)."""
+        S = self.sources_dense(to_dense(U, self.n), ref)
+        zero = [np.zeros_like(S[0]), np.zeros_like(S[0])]
+        out = from_dense(zero + S, self.n)
+        return {k: out[k] for k in ("rhou", "rhov", "rhow")}
+
+    def advance_dense(self, Un: list, Ucur: list, cdt: float, ref=None) -> list:
+        """Uhat = Un + cdt dU(Ucur); with a reference state, plus cdt times the
+        momentum sources of Ucur on every fluid CV."""
         out = [np.zeros_like(Un[0]) for _ in range(5)]
         _load().orc_advance(C.byref(self.g), _dpp(self.geo), _dpp(Un), _dpp(Ucur), _dpp(out),
                             float(cdt))
+        if ref is not None:
+            S = self.sources_dense(Ucur, ref)
+            for d in range(3):
+                out[2 + d] = out[2 + d] + float(cdt) * S[d]
         return out
 
     def redistribute_dense(self, Uhat: list) -> list:
@@ -201,25 +233,25 @@ class Oracle:
                                      _dpp(out), _dpp(sig))
         return from_dense(out, self.n), sig
 
-    def advance(self, Un: dict, Ucur: dict, cdt: float) -> dict:
-        return from_dense(self.advance_dense(to_dense(Un, self.n), to_dense(Ucur, self.n), cdt),
+    def advance(self, Un: dict, Ucur: dict, cdt: float, ref=None) -> dict:
+        return from_dense(self.advance_dense(to_dense(Un, self.n), to_dense(Ucur, self.n), cdt, ref),
                           self.n)
 
     def redistribute(self, Uhat: dict) -> dict:
         return from_dense(self.redistribute_dense(to_dense(Uhat, self.n)), self.n)
 
-    def stage(self, Un: dict, Ucur: dict, cdt: float) -> dict:
+    def stage(self, Un: dict, Ucur: dict, cdt: float, ref=None) -> dict:
         """Algorithm 1 steps (1)-(4) for one stage: U^s = R(U^n + c dt dU(U^{s-1}))."""
         d_n = to_dense(Un, self.n)
         d_c = d_n if Ucur is Un else to_dense(Ucur, self.n)
-        return from_dense(self.redistribute_dense(self.advance_dense(d_n, d_c, cdt)), self.n)
+        return from_dense(self.redistribute_dense(self.advance_dense(d_n, d_c, cdt, ref)), self.n)
 
-    def rk3_step(self, U: dict, dt: float) -> dict:
+    def rk3_step(self, U: dict, dt: float, ref=None) -> dict:
         """Low-storage three-stage Runge-Kutta (Wicker-Skamarock form)."""
         d_n = to_dense(U, self.n)
         cur = d_n
         for c in RK3_C:
-            cur = self.redistribute_dense(self.advance_dense(d_n, cur, c * dt))
+            cur = self.redistribute_dense(self.advance_dense(d_n, cur, c * dt, ref))
         return from_dense(cur, self.n)
 
     def face_fluxes(self, U: dict, field: int):

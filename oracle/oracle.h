@@ -88,6 +88,19 @@ int orc_redistribute_sig(const orc_grid* g, double* const geo[4], double* const 
 int orc_face_fluxes(const orc_grid* g, double* const geo[4], const double* const U[5],
                     int field, double* const F[3], double* const Fhat[3]);
 
+/* Constants of the equation of state p = P00 (R rho theta / P00)^gamma and
+ * gravity (acting along -z), Section 2.1. */
+typedef struct {
+    double P00, R, gamma, g;
+} orc_src;
+
+/* Momentum sources of Ucur (perturbation pressure gradient, buoyancy on the
+ * z-face CVs), intensive, per CV: S[d] receives instance d+1 in dense storage,
+ * zero where not a fluid CV.  p0, rho0: reference pressure and density at the
+ * cell-centre height of each level (nz entries). */
+int orc_sources(const orc_grid* g, double* const geo[4], const double* const U[5], const orc_src* s,
+                const double* p0, const double* rho0, double* const S[3]);
+
 /* Moments of the fluid part {z > terrain} of an axis-aligned box inside the
  * xy-cell (ci,cj): exposed so tests can check the clipper against closed forms.
  * out: [vol, mx, my, mz, area vector x,y,z, eb area, 6 face areas] with moments

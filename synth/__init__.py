@@ -254,6 +254,60 @@ def state_random(grid: Grid, seed: int, amp: float = 1.0) -> dict:
     return U
 
 
+# ------------------------------------------------------------ reference state
+
+@dataclass
+class Reference:
+    """Hydrostatic reference state at the cell-centre height of every level,
+    with the constants of the equation of state and gravity."""
+    p0: np.ndarray      # (nz,) Pa
+    rho0: np.ndarray    # (nz,) kg/m^3
+    theta0: float = 300.0
+    P00: float = 1.0e5
+    R: float = 287.0
+    gamma: float = 1.4
+    g: float = 9.81
+
+
+def reference_isentropic(grid: Grid, theta0: float = 300.0, P00: float = 1.0e5, R: float = 287.0,
+                         gamma: float = 1.4, g: float = 9.81) -> Reference:
+    """Dry atmosphere of constant potential temperature theta0 in hydrostatic
+    balance (textbook form): Exner function pi(z) = 1 - g z / (cp theta0),
+    cp = gamma R / (gamma - 1), p0 = P00 pi^(cp / R), rho0 = p0 / (R theta0 pi),
+    taken at z = lo_z + (k + 1/2) dz."""
+    nz = grid.n[2]
+    z = grid.lo[2] + (np.arange(nz, dtype=np.float64) + 0.5) * grid.dx[2]
+    cp = gamma * R / (gamma - 1.0)
+    pi = 1.0 - g * z / (cp * theta0)
+    p0 = P00 * pi ** (cp / R)
+    rho0 = p0 / (R * theta0 * pi)
+    return Reference(p0, rho0, theta0, P00, R, gamma, g)
+
+
+def state_reference(grid: Grid, ref: Reference, seed: int, rho_noise: float = 1e-3,
+                    theta_noise: float = 0.5, u0: float = 10.0, w_amp: float = 0.5) -> dict:
+    """Perturbed reference state: rho = rho0 (1 + rho_noise N(0,1)),
+    theta = theta0 + theta_noise N(0,1), rho u = rho0 (u0 + N(0,1)),
+    rho v, rho w = rho0 w_amp N(0,1) (walls 0).  rho_noise = theta_noise =
+    u0 = w_amp = 0 gives the reference state at rest."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = grid.n
+    sh = field_shapes(grid.n)
+    r0 = ref.rho0[:, None, None]
+    rho = r0 * (1.0 + rho_noise * rng.standard_normal(sh["rho"]))
+    theta = ref.theta0 + theta_noise * rng.standard_normal(sh["rho"])
+    rhou = np.empty(sh["rhou"])
+    rhou[:, :, :nx] = r0 * (u0 + (1.0 if u0 else 0.0) * rng.standard_normal((nz, ny, nx)))
+    rhov = np.empty(sh["rhov"])
+    rhov[:, :ny, :] = r0 * w_amp * rng.standard_normal((nz, ny, nx))
+    _dup_periodic(rhou, rhov)
+    r0w = np.concatenate([ref.rho0[:1], ref.rho0])[:, None, None]
+    rhow = r0w * w_amp * rng.standard_normal(sh["rhow"])
+    rhow[0] = 0.0
+    rhow[-1] = 0.0
+    return {"rho": rho, "rhotheta": rho * theta, "rhou": rhou, "rhov": rhov, "rhow": rhow}
+
+
 # ------------------------------------------------------------------------ boxes
 
 def boxes_split(n, seed: int, target: int, block: int = 64, unit: int = 16):
