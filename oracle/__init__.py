@@ -187,9 +187,9 @@ class Oracle:
     def sources_dense(self, Ucur: list, ref) -> list:
         """Momentum sources (perturbation pressure gradient, buoyancy) of a
         dense state for the reference state ``ref`` (attributes P00, R,
-        gamma, g, p0[nz], rho0[nz]): three dense arrays, instances 1-3."""
+        gamma, g, rhotheta0[nz], rho0[nz]): three dense arrays, instances 1-3."""
         nz = self.n[2]
-        p0 = np.ascontiguousarray(ref.p0, dtype=np.float64)
+        p0 = np.ascontiguousarray(ref.rhotheta0, dtype=np.float64)
         r0 = np.ascontiguousarray(ref.rho0, dtype=np.float64)
         assert p0.shape == (nz,) and r0.shape == (nz,)
         S = [np.zeros_like(Ucur[0]) for _ in range(3)]

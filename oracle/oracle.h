@@ -96,10 +96,11 @@ typedef struct {
 
 /* Momentum sources of Ucur (perturbation pressure gradient, buoyancy on the
  * z-face CVs), intensive, per CV: S[d] receives instance d+1 in dense storage,
- * zero where not a fluid CV.  p0, rho0: reference pressure and density at the
- * cell-centre height of each level (nz entries). */
+ * zero where not a fluid CV.  rt0, rho0: reference rho theta and density at
+ * the cell-centre height of each level (nz entries); the reference pressure is
+ * their equation-of-state value. */
 int orc_sources(const orc_grid* g, double* const geo[4], const double* const U[5], const orc_src* s,
-                const double* p0, const double* rho0, double* const S[3]);
+                const double* rt0, const double* rho0, double* const S[3]);
 
 /* Moments of the fluid part {z > terrain} of an axis-aligned box inside the
  * xy-cell (ci,cj): exposed so tests can check the clipper against closed forms.

@@ -7,9 +7,14 @@
  * adds the pressure gradient to the right-hand side as a source term
  * (Section 4.1) and states no discretisation for it; the readings here (also
  * listed in the design notes) are:
- *  - p' and rho' live on fluid cells: p' = P00 (R rho theta / P00)^gamma
- *    - p0(k), rho' = rho - rho0(k), with the reference values taken at the
- *    cell-centre height of level k;
+ *  - the reference state is given per level (cell-centre height of level k)
+ *    as rho theta0(k) and rho0(k); it satisfies the equation of state, so
+ *    p0(k) = P00 (R rho theta0(k) / P00)^gamma;
+ *  - p' and rho' live on fluid cells: p' = p - p0(k), rho' = rho - rho0(k).
+ *    p' is evaluated as p0 ((rho theta / rho theta0)^gamma - 1) =
+ *    p0 expm1(gamma log1p((rho theta - rho theta0) / rho theta0)), which is
+ *    p - p0 in exact arithmetic; the plain difference of two values near
+ *    1e5 Pa would lose about three of FP64's digits to cancellation;
  *  - the source of the momentum CV around the lower d-face of cell c is
  *    intensive: -(p'(c) - p'(c - e_d)) / dx_d when both cells are fluid,
  *    zero otherwise;
@@ -25,8 +30,14 @@
 
 static int wrapi(int i, int n) { return ((i % n) + n) % n; }
 
+/* perturbation pressure of a cell of level k with the given rho theta */
+static double pprime(const orc_src* s, const double* rt0, int k, double rt) {
+    const double p0 = s->P00 * pow(s->R * rt0[k] / s->P00, s->gamma);
+    return p0 * expm1(s->gamma * log1p((rt - rt0[k]) / rt0[k]));
+}
+
 int orc_sources(const orc_grid* g, double* const geo[4], const double* const U[5], const orc_src* s,
-                const double* p0, const double* rho0, double* const S[3]) {
+                const double* rt0, const double* rho0, double* const S[3]) {
     const int nx = g->n[0], ny = g->n[1], nz = g->n[2];
     const size_t NI = (size_t)(nz + 1) * ny * nx;
 #define ID(i, j, k) (((size_t)(k) * ny + wrapi((j), ny)) * nx + wrapi((i), nx))
@@ -45,8 +56,8 @@ int orc_sources(const orc_grid* g, double* const geo[4], const double* const U[5
                     const int fa = FLUID(i, j, k), fb = FLUID(il, jl, kl);
                     double src = 0.0;
                     if (fa && fb) {
-                        const double pa = s->P00 * pow(s->R * U[1][ID(i, j, k)] / s->P00, s->gamma) - p0[k];
-                        const double pb = s->P00 * pow(s->R * U[1][ID(il, jl, kl)] / s->P00, s->gamma) - p0[kl];
+                        const double pa = pprime(s, rt0, k, U[1][ID(i, j, k)]);
+                        const double pb = pprime(s, rt0, kl, U[1][ID(il, jl, kl)]);
                         src = -(pa - pb) / g->dx[d];
                     }
                     if (d == 2) {

@@ -259,9 +259,12 @@ def state_random(grid: Grid, seed: int, amp: float = 1.0) -> dict:
 @dataclass
 class Reference:
     """Hydrostatic reference state at the cell-centre height of every level,
-    with the constants of the equation of state and gravity."""
-    p0: np.ndarray      # (nz,) Pa
-    rho0: np.ndarray    # (nz,) kg/m^3
+    with the constants of the equation of state and gravity.  rhotheta0 and
+    rho0 define it; p0 is the pressure the recipe started from (equal to the
+    equation-of-state value of rhotheta0 up to rounding)."""
+    p0: np.ndarray         # (nz,) Pa
+    rho0: np.ndarray       # (nz,) kg/m^3
+    rhotheta0: np.ndarray  # (nz,) kg K/m^3
     theta0: float = 300.0
     P00: float = 1.0e5
     R: float = 287.0
@@ -281,7 +284,7 @@ def reference_isentropic(grid: Grid, theta0: float = 300.0, P00: float = 1.0e5, 
     pi = 1.0 - g * z / (cp * theta0)
     p0 = P00 * pi ** (cp / R)
     rho0 = p0 / (R * theta0 * pi)
-    return Reference(p0, rho0, theta0, P00, R, gamma, g)
+    return Reference(p0, rho0, rho0 * theta0, theta0, P00, R, gamma, g)
 
 
 def state_reference(grid: Grid, ref: Reference, seed: int, rho_noise: float = 1e-3,

@@ -3,8 +3,10 @@ perturbation pressure gradient from the equation of state, buoyancy -rho' g)
 against closed forms and invariants.  CPU only.
 
 The reference state comes from the textbook isentropic atmosphere (Exner
-function), written independently of the oracle's equation of state, so the
-state at rest pins the EOS, its constants and the level indexing of p0/rho0.
+function), written independently of the oracle's equation of state; the
+state at rest pins the level indexing of rho theta0 / rho0, and the
+perturbation pressure of single cells is checked against the plain
+difference of two EOS pressures in extended precision.
 Linear perturbation pressures pin sign, index direction and spacing of the
 gradient on every momentum instance; a uniform density excess pins the
 buoyancy; CVs next to covered cells pin the treatment of the terrain."""
@@ -26,6 +28,10 @@ def _terrain_case():
 def _rhotheta_for(ref, p):
     """rho theta whose EOS pressure is p (inverse of p = P00 (R rho theta / P00)^gamma)."""
     return ref.P00 / ref.R * (p / ref.P00) ** (1.0 / ref.gamma)
+
+
+def _p0_eos(ref):
+    return ref.P00 * (ref.R * ref.rhotheta0 / ref.P00) ** ref.gamma
 
 
 def _fluid_cv(o, inst):
@@ -58,6 +64,38 @@ def test_reference_state_at_rest_has_no_source(case):
         assert np.abs(S[d]).max() <= 1e-12 * scale, d
 
 
+def test_perturbation_pressure_against_extended_precision(case):
+    """p' of single perturbed cells (their lower x-neighbours at rest, p' = 0
+    there, so S = -p' / dx) against P00 (R rho theta / P00)^gamma - p0
+    evaluated in x87 extended precision (absolute error about 1e-14 Pa).
+    Departures of about 1e-6 give |p'| up to about 0.5 Pa; the plain FP64
+    difference of two pressures near 1e5 Pa would be off by about 1e-11 Pa,
+    the cancellation-free form by about 1e-16 |p'|: the bound is 1e-13 Pa."""
+    g, h, o, ref = case
+    nx, ny, nz = g.n
+    U = synth.state_reference(g, ref, 0, rho_noise=0.0, theta_noise=0.0, u0=0.0, w_amp=0.0)
+    rng = np.random.default_rng(7)
+    pert = np.zeros((nz, ny, nx), dtype=bool)
+    pert[:, :, 1::2] = True
+    rt = U["rhotheta"].copy()
+    rt[pert] *= 1.0 + 1e-6 * rng.standard_normal(int(pert.sum()))
+    U["rhotheta"] = rt
+    S = o.sources_dense(oracle.to_dense(U, o.n), ref)[0][:nz]
+    fc = (o.alpha(0) > 0)[:nz]
+    cv = (o.alpha(1) > 0)[:nz]
+    sel = cv & fc & np.roll(fc, 1, axis=2) & pert
+    assert sel.sum() > 1000
+    L = np.longdouble
+    P00, R, gam = L(ref.P00), L(ref.R), L(ref.gamma)
+    p_ld = P00 * (R * rt.astype(L) / P00) ** gam
+    p0_ld = P00 * (R * ref.rhotheta0.astype(L) / P00) ** gam
+    pp_ld = p_ld - p0_ld[:, None, None]
+    got = -S * g.dx[0]
+    err = np.abs(got[sel] - pp_ld[sel].astype(np.float64))
+    assert 0.05 < np.abs(pp_ld[sel]).max() < 1.0
+    assert err.max() <= 1e-13, err.max()
+
+
 @pytest.mark.parametrize("d", [0, 1, 2])
 def test_linear_perturbation_pressure(case, d):
     """p' = a * (cell-centre coordinate along d): the source of a momentum CV
@@ -69,7 +107,7 @@ def test_linear_perturbation_pressure(case, d):
     a = 0.37 if d < 2 else -0.8
     idx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     coord = (idx[2 - d] + 0.5) * g.dx[d]
-    p = ref.p0[:, None, None] + a * coord
+    p = _p0_eos(ref)[:, None, None] + a * coord
     U = synth.state_reference(g, ref, 0, rho_noise=0.0, theta_noise=0.0, u0=0.0, w_amp=0.0)
     U["rhotheta"] = _rhotheta_for(ref, p)
     S = o.sources_dense(oracle.to_dense(U, o.n), ref)[d]
