@@ -216,6 +216,40 @@ ebs_status ebs_set_overlap(ebs_ctx* ctx, int32_t enable);
  * falls back to the next looser rule.  EBS_E_ARG for another value. */
 ebs_status ebs_set_range_rule(ebs_ctx* ctx, int32_t rule);
 
+/* Momentum sources of the compressible model (Section 2.1, Eq. mom-comp):
+ * the perturbation pressure gradient -grad p' and the buoyancy -rho' g (g
+ * acting along -z), with p = P00 (R rho theta / P00)^gamma (the equation of
+ * state of Section 2.1), p' = p - p0(z) and rho' = rho - rho0(z).  The
+ * reference state satisfies the equation of state, so it is given by rho
+ * theta0 and rho0, and p0 = P00 (R rho theta0 / P00)^gamma; p' is evaluated
+ * as p0 expm1(gamma log1p((rho theta - rho theta0) / rho theta0)), equal to
+ * p - p0 but free of the cancellation of two values near P00.  The paper
+ * adds them to the right-hand side as a source (Section 4.1) without giving
+ * a cut-cell form; this library uses: p' and rho' on fluid cells with the
+ * reference values of the cell's level; the momentum CV around the lower
+ * d-face of cell c gets -(p'(c) - p'(c - e_d)) / dx_d when both cells are
+ * fluid (else no pressure force), and the z-face CVs add -g times the mean
+ * rho' of their fluid cells.  Every later ebs_advance_stage / ebs_rk3_step
+ * adds c dt times these (evaluated on Ucur) to the provisional momenta of
+ * every fluid CV, before the redistribution.
+ *   prm:  constants (P00 > 0, R > 0, gamma > 1, g >= 0), or NULL to switch
+ *         the sources off.
+ *   rhotheta0, rho0: host arrays of nz doubles, the reference rho theta
+ *         (kg K / m^3) and density (kg / m^3) at the cell-centre height of
+ *         each level (positive, finite); copied, the caller keeps ownership.
+ *         The state must keep rho theta > 0 on fluid cells.
+ * Errors: EBS_E_ARG for invalid values; EBS_E_UNSUPPORTED with the
+ * free-stream EB closure, or when the current tile shape leaves no LDS for
+ * the pressure planes (choose another with ebs_set_tile); EBS_E_OOM, EBS_E_HIP. */
+typedef struct {
+    double P00;    /* reference pressure of the equation of state, Pa (1e5) */
+    double R;      /* gas constant of dry air, J / (kg K) */
+    double gamma;  /* ratio of specific heats cp / cv */
+    double g;      /* gravitational acceleration, m / s^2 */
+} ebs_source_params;
+ebs_status ebs_set_sources(ebs_ctx* ctx, const ebs_source_params* prm, const double* rhotheta0,
+                           const double* rho0);
+
 /* Kernel timing: when enabled, every launch of the regular-region stage
  * kernel is bracketed by HIP events on the context stream; read returns the
  * summed duration (ms) and launch count since the last reset and resets. */

@@ -29,7 +29,7 @@ Q = dict(ALPHA=0, BETA_X=1, BETA_Y=2, BETA_Z=3, FX_Y=4, FX_Z=5, FY_X=6, FY_Z=7, 
 # every entry point declared in include/ebstag.h
 SYMBOLS = ("ebs_create", "ebs_build_geometry_terrain", "ebs_geometry_export", "ebs_geometry_stats",
            "ebs_advance_stage", "ebs_redistribute", "ebs_rk3_step", "ebs_conserved_sums",
-           "ebs_autotune", "ebs_set_tile", "ebs_get_tile", "ebs_set_overlap", "ebs_set_range_rule", "ebs_timing_enable", "ebs_timing_read",
+           "ebs_autotune", "ebs_set_tile", "ebs_get_tile", "ebs_set_overlap", "ebs_set_range_rule", "ebs_set_sources", "ebs_timing_enable", "ebs_timing_read",
            "ebs_algorithmic_bytes", "ebs_last_error", "ebs_destroy")
 
 
@@ -47,6 +47,10 @@ class Grid(C.Structure):
 
 class Box(C.Structure):
     _fields_ = [("lo", C.c_int32 * 3), ("hi", C.c_int32 * 3)]
+
+
+class SourceParams(C.Structure):
+    _fields_ = [("P00", C.c_double), ("R", C.c_double), ("gamma", C.c_double), ("g", C.c_double)]
 
 
 class State(C.Structure):
@@ -80,6 +84,7 @@ def load(path: str = LIB_PATH):
         "ebs_get_tile": [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)],
         "ebs_set_overlap": [C.c_void_p, C.c_int32],
         "ebs_set_range_rule": [C.c_void_p, C.c_int32],
+        "ebs_set_sources": [C.c_void_p, P(SourceParams), P(C.c_double), P(C.c_double)],
         "ebs_timing_enable": [C.c_void_p, C.c_int32],
         "ebs_timing_read": [C.c_void_p, P(C.c_double), P(C.c_int64)],
         "ebs_algorithmic_bytes": [C.c_void_p, P(C.c_double)],
@@ -237,6 +242,25 @@ class Context:
         0 loose, 1 small-CV footprint, 2 (default) the cells the redistribution
         touches."""
         self._check(self.lib.ebs_set_range_rule(self.h, int(rule)), "ebs_set_range_rule")
+
+    def set_sources(self, ref=None):
+        """Switch the momentum sources (perturbation pressure gradient and
+        buoyancy) on for a reference state ``ref`` with attributes P00, R,
+        gamma, g and per-level arrays rhotheta0, rho0 (nz values each), or off
+        with None."""
+        import numpy as np
+
+        if ref is None:
+            self._check(self.lib.ebs_set_sources(self.h, None, None, None), "ebs_set_sources")
+            return
+        p0 = np.ascontiguousarray(ref.rhotheta0, dtype=np.float64)
+        r0 = np.ascontiguousarray(ref.rho0, dtype=np.float64)
+        if p0.shape != (self.n[2],) or r0.shape != (self.n[2],):
+            raise ValueError("p0 and rho0 need one value per level")
+        prm = SourceParams(float(ref.P00), float(ref.R), float(ref.gamma), float(ref.g))
+        dp = C.POINTER(C.c_double)
+        self._check(self.lib.ebs_set_sources(self.h, C.byref(prm), p0.ctypes.data_as(dp), r0.ctypes.data_as(dp)),
+                    "ebs_set_sources")
 
     def get_tile(self):
         tx, ty, tz, sp = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()

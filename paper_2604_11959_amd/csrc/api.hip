@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -199,7 +200,8 @@ ebs_status ebs_destroy(ebs_ctx* c) {
     void* ptrs[] = {c->d_kf,   c->d_kr,        c->d_g0,      c->d_g1,   c->d_goff, c->d_gcol,
                     c->d_geo,  c->d_type,      c->d_mask,    c->d_small, c->d_tier, c->d_w,
                     c->d_smalllist, c->d_actlist, c->d_lsq_off, c->d_lsq_idx, c->d_lsq_c, c->d_lsq_ev, c->d_lsq_nev, c->d_wl_off, c->d_wl_idx, c->d_wl_geo, c->d_wl_self, c->d_wl_small, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles, c->d_prim, c->d_fh, c->d_type4, c->d_col, c->d_gcole, c->d_fflag, c->d_cbase, c->d_crec, c->d_bfc,
-                    c->d_ptab, c->d_ftab, c->d_utab, c->d_sten, c->d_upd, c->d_q_idx, c->d_q_w, c->d_q_den, c->d_q_n, c->d_chk, c->d_part, c->d_dummy};
+                    c->d_ptab, c->d_ftab, c->d_utab, c->d_sten, c->d_upd, c->d_q_idx, c->d_q_w, c->d_q_den, c->d_q_n, c->d_chk, c->d_part, c->d_dummy,
+                    c->d_srcf, c->d_srcd, c->d_srcv};
     for (void* p : ptrs) free_ptr(p);
     delete c;
     return EBS_OK;
@@ -456,7 +458,7 @@ ebs_status ebs_set_tile(ebs_ctx* c, int32_t tx, int32_t ty, int32_t tz, int32_t 
     if (span != 0 && span != 1) return fail(c, EBS_E_ARG, "tile span must be 0 or 1");
     if ((tx + 5) * (ty + 5) > 4 * tx * ty)
         return fail(c, EBS_E_ARG, "tile shape has more halo points than the block covers");
-    if (bulk_lds_bytes(tx, ty, c->g.precision) > (size_t)c->lds_max)
+    if (bulk_lds_bytes(tx, ty, c->g.precision, c->src_on) > (size_t)c->lds_max)
         return fail(c, EBS_E_ARG, "tile shape needs more LDS than a block may use");
     c->tile_x = tx;
     c->tile_y = ty;
@@ -464,6 +466,55 @@ ebs_status ebs_set_tile(ebs_ctx* c, int32_t tx, int32_t ty, int32_t tz, int32_t 
     c->tile_span = span;
     drop_graph(c);
     if (c->have_geom) return build_tiles(c);
+    return EBS_OK;
+}
+
+ebs_status ebs_set_sources(ebs_ctx* c, const ebs_source_params* prm, const double* rt0, const double* rho0) {
+    if (!c) return EBS_E_ARG;
+    if (!prm) {
+        if (c->src_on) drop_graph(c);
+        c->src_on = false;
+        return EBS_OK;
+    }
+    if (!rt0 || !rho0) return fail(c, EBS_E_ARG, "null reference-state array");
+    const ebs_source_params q = *prm;
+    if (!(q.P00 > 0 && std::isfinite(q.P00)) || !(q.R > 0 && std::isfinite(q.R)) ||
+        !(q.gamma > 1 && std::isfinite(q.gamma)) || !(q.g >= 0 && std::isfinite(q.g)))
+        return fail(c, EBS_E_ARG, "source constants out of range");
+    if (c->g.eb_flux != EBS_EB_WALL) return fail(c, EBS_E_UNSUPPORTED, "sources need the no-flux EB closure");
+    if (bulk_lds_bytes(c->tile_x, c->tile_y, c->g.precision, true) > (size_t)c->lds_max)
+        return fail(c, EBS_E_UNSUPPORTED, "the tile shape leaves no LDS for the pressure planes");
+    const int nz = c->nz;
+    // per level: p0 (the equation-of-state pressure of rho theta0), rho
+    // theta0 (split into a part exact in the state precision and the rest),
+    // 1 / rho theta0, rho0; p' = p0 ((rho theta / rho theta0)^gamma - 1)
+    std::vector<double> td((size_t)5 * nz);
+    std::vector<float> tf((size_t)5 * nz);
+    for (int k = 0; k < nz; ++k) {
+        if (!(rt0[k] > 0 && std::isfinite(rt0[k])) || !(rho0[k] > 0 && std::isfinite(rho0[k])))
+            return fail(c, EBS_E_ARG, "reference state must be positive and finite");
+        const double p0 = q.P00 * std::pow(q.R * rt0[k] / q.P00, q.gamma);
+        td[0 * nz + k] = p0;
+        td[1 * nz + k] = rt0[k];
+        td[2 * nz + k] = 0.0;
+        td[3 * nz + k] = 1.0 / rt0[k];
+        td[4 * nz + k] = rho0[k];
+        const float hi = (float)rt0[k];
+        tf[0 * nz + k] = (float)p0;
+        tf[1 * nz + k] = hi;
+        tf[2 * nz + k] = (float)(rt0[k] - (double)hi);
+        tf[3 * nz + k] = (float)(1.0 / rt0[k]);
+        tf[4 * nz + k] = (float)rho0[k];
+    }
+    if (!c->d_srcd) {
+        if (hipMalloc(&c->d_srcd, sizeof(double) * 5 * nz) != hipSuccess) return fail(c, EBS_E_OOM, "source tables");
+        if (hipMalloc(&c->d_srcf, sizeof(float) * 5 * nz) != hipSuccess) return fail(c, EBS_E_OOM, "source tables");
+    }
+    EBS_HIP(c, hipMemcpy(c->d_srcd, td.data(), sizeof(double) * 5 * nz, hipMemcpyHostToDevice));
+    EBS_HIP(c, hipMemcpy(c->d_srcf, tf.data(), sizeof(float) * 5 * nz, hipMemcpyHostToDevice));
+    c->src = q;
+    c->src_on = true;
+    drop_graph(c);
     return EBS_OK;
 }
 
@@ -525,7 +576,8 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
     if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
     const char* prec = c->g.precision == EBS_F32_BULK ? "f32bulk" : "f64";
     char key[160];
-    std::snprintf(key, sizeof(key), "%s_%dx%dx%d_b%zu", prec, c->nx, c->ny, c->nz, c->boxes.size());
+    std::snprintf(key, sizeof(key), "%s_%dx%dx%d_b%zu%s", prec, c->nx, c->ny, c->nz, c->boxes.size(),
+                  c->src_on ? "_src" : "");
     // cached choice
     if (cache_json_path) {
         std::ifstream in(cache_json_path);

@@ -29,6 +29,12 @@ namespace {
 // receives a contiguous run of neighbouring tiles (shared halos stay in its
 // L2).  Stencil points beyond the top and bottom walls are flagged and never
 // loaded.
+//
+// With the momentum sources (SRC), the perturbation pressure of every plane
+// is evaluated once per point from the raw rho theta of the region loads, for
+// the own cells and the -x column and -y row next to the tile, into a
+// two-plane LDS ring; the own column's p' and rho of the plane below stay in
+// registers.
 template <typename T>
 struct BulkArgs {
     Dims D;
@@ -42,7 +48,31 @@ struct BulkArgs {
     const ebs_tile* __restrict__ tiles;
     int32_t ntiles;
     int32_t per_xcd;  // tiles per XCD chunk
+    // sources: per-level table [5][nz] (p0, rho theta0 high and low part,
+    // 1 / rho theta0, rho0), gravity, gamma
+    const T* __restrict__ sref;
+    T sg, sgam;
 };
+
+__device__ __forceinline__ float log1p_t(float x) { return log1pf(x); }
+__device__ __forceinline__ double log1p_t(double x) { return log1p(x); }
+__device__ __forceinline__ float expm1_t(float x) { return expm1f(x); }
+__device__ __forceinline__ double expm1_t(double x) { return expm1(x); }
+
+// perturbation pressure of a cell of level k from its rho theta:
+// p - p0 = p0 ((rho theta / rho theta0)^gamma - 1), evaluated from the
+// relative departure (rho theta - rho theta0) / rho theta0 so that the small
+// difference keeps the state precision's relative accuracy (FP32: rho theta0
+// as a float pair, so the departure is exact up to one rounding)
+template <typename T>
+__device__ __forceinline__ T pprime(const T* __restrict__ sref, int nz, T gam, T rt, int k) {
+    T x;
+    if constexpr (sizeof(T) == 8)
+        x = (rt - sref[nz + k]) / sref[nz + k];
+    else
+        x = ((rt - sref[nz + k]) - sref[2 * nz + k]) * sref[3 * nz + k];
+    return sref[k] * expm1_t(gam * log1p_t(x));
+}
 
 template <typename T>
 __device__ inline T qdiv(T a, T b) {
@@ -105,9 +135,10 @@ __device__ __forceinline__ void st(T* base, uint32_t off, T v) {
 
 // SAME: U^n and U_cur are the same state (the first stage), so the own-cell
 // values of U^n are taken from the region loads instead of being read again.
-template <typename T, int TX, int TY, bool SAME>
+template <typename T, int TX, int TY, bool SAME, bool SRC>
 __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
     constexpr int WX = TX + 5, WS = WX * (TY + 5), NTHR = TX * TY, NH = WS - NTHR;
+    constexpr int PW = TX + 1, PS = PW * (TY + 1);  // pressure plane: own cells, -x column, -y row
     constexpr int NPTS = 1 + (NH + NTHR - 1) / NTHR;
     static_assert(NPTS <= HALO_PTS, "halo points per thread");
     extern __shared__ unsigned char smem_raw[];
@@ -137,7 +168,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
     // points numbered tid + (q - 1) NTHR (rows 0-2, then the 3 + 2 side points
     // of each interior row, then the last two rows); lr = -1 past the last.
     const int me = (ty + 3) * WX + (tx + 3);
-    int lr[NPTS];
+    int lr[NPTS], lp[NPTS];
     uint32_t rc[NPTS], ru[NPTS];
 #pragma unroll
     for (int q = 0; q < NPTS; ++q) {
@@ -156,6 +187,11 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             }
         }
         lr[q] = r;
+        if (SRC) {
+            const int rx = r % WX, ry = r / WX;
+            const bool win = r >= 0 && rx >= 2 && rx <= TX + 2 && ry >= 2 && ry <= TY + 2 && (rx > 2 || ry > 2);
+            lp[q] = win ? (ry - 2) * PW + (rx - 2) : -1;
+        }
         const int rr = max(r, 0);
         const int x = wrapi(tl.x0 - 3 + rr % WX, nx), y = wrapi(tl.y0 - 3 + rr / WX, ny);
         rc[q] = (uint32_t)(y * nx + x);
@@ -227,6 +263,24 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             P[3 * 3 * WS + r] = w;
         }
     };
+    // SRC: p' of plane p at this thread's points in the pressure window, from
+    // the raw rho theta of the last commit (rth); returns the own cell's value
+    T* const PPB = sm + L_COUNT * WS;
+    auto write_pp = [&](int p) -> T {
+        T own = T(0);
+        if (p < 0 || p >= nz) return own;  // block uniform
+        T* PP = PPB + (p & 1) * PS;
+#pragma unroll
+        for (int q = 0; q < NPTS; ++q) {
+            if (q > 0 && lr[q] < 0) break;
+            if (lp[q] < 0) continue;
+            const T v = pprime<T>(a.sref, nz, a.sgam, rth[q], p);
+            PP[lp[q]] = v;
+            if (q == 0) own = v;
+        }
+        return own;
+    };
+    auto own_rho = [&](int p) -> T { return sm[(L_RHO + (p & 1)) * WS + me]; };
     const int dxm = (i == 0) ? nx - 1 : -1;
     const int dym = (j == 0) ? ny - 1 : -1;
     const uint32_t c0 = (uint32_t)(j * nx + i), u0 = (uint32_t)(j * (nx + 1) + i);
@@ -238,8 +292,14 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
     // unA / unB keep rho and rho theta of the own cell from the region loads
     // (point 0) and the momenta are read from the LDS rings.
     T unA[5], unB[5];
+    // SRC: own p' of planes k - 1, k, k + 1 and own rho of planes k - 1, k
+    T ppm = T(0), pc0 = T(0), pc1 = T(0), rkm = T(0), rk = T(0);
     fetch(k0 - 1, pfA);
     commit(k0 - 1, pfA);
+    if (SRC) {
+        ppm = (k0 >= 1) ? pprime<T>(a.sref, nz, a.sgam, rth[0], k0 - 1) : T(0);
+        rkm = own_rho(k0 - 1);
+    }
     fetch(k0, pfA);
     if (SAME) unA[0] = pfA[0][0], unA[1] = pfA[0][1];
     commit(k0, pfA);
@@ -248,6 +308,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
     make_prims(k0);
     __syncthreads();  // the density slot of plane k0 - 1 is reused by plane k0 + 1
     if (SAME) unB[0] = pfA[0][0], unB[1] = pfA[0][1];
+    if (SRC) pc0 = write_pp(k0);
     commit(k0 + 1, pfA);
     fetch(k0 + 2, pfA);
     fetch(k0 + 3, pfB);
@@ -278,6 +339,10 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
     auto step = [&](int k, T (&rp)[NPTS][5], T (&uc)[5]) __attribute__((always_inline)) {
         T nr0 = T(0), nr1 = T(0);  // SAME: rho, rho theta of the own cell of plane k + 2
         if (SAME) nr0 = rp[0][0], nr1 = rp[0][1];
+        if (SRC) {
+            rk = own_rho(k);  // plane k leaves the density ring with this commit
+            pc1 = write_pp(k + 1);
+        }
         commit(k + 2, rp);
         fetch(k + 4, rp);
         __syncthreads();
@@ -338,6 +403,17 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                 zl[2] = m2l * upw6z<T>(m2l, zc[2][0], zc[2][1], zc[2][2], zc[2][3], okL1, okR1);
                 zl[3] = m3l * upw6z<T>(m3l, zc[3][0], zc[3][1], zc[3][2], zc[3][3], k - 2 >= 1, okR1);
             }
+            // sources of the three momentum CVs of this cell (p' of the own
+            // cell and of its -x, -y, -z neighbours, all fluid here)
+            T sx = T(0), sy = T(0), sz = T(0);
+            if (SRC) {
+                const T* PPk = PPB + (k & 1) * PS + (ty + 1) * PW + (tx + 1);
+                sx = -(pc0 - PPk[-1]) * a.rdx;
+                sy = -(pc0 - PPk[-PW]) * a.rdy;
+                if (k >= 1)
+                    sz = -(pc0 - ppm) * a.rdz -
+                         a.sg * T(0.5) * ((rk - a.sref[4 * nz + k]) + (rkm - a.sref[4 * nz + k - 1]));
+            }
             // ---- cell-centred instance
             {
                 const T ex = ru_ip - ru_i, ey = rv_jp - rv_j, ez = rw_kp - rw_k;
@@ -363,7 +439,8 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                              myl * upw6<T>(myl, UU[-2 * WX], UU[-WX], UU[0], UU[WX], true, true);
                 fzc[1] = mzh * upw6z<T>(mzh, zc[1][1], zc[1][2], zc[1][3], zc[1][4], okL0, okR2);
                 const T fz = fzc[1] - zl[1];
-                const T val = (SAME ? ru_i : uc[2]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * hs;
+                T val = (SAME ? ru_i : uc[2]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * hs;
+                if (SRC) val += a.cdt * sx;
                 st(a.out[2], ou, val);
                 if (i == 0) st(a.out[2], ou + nx, val);
             }
@@ -378,7 +455,8 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                              myl * upw6<T>(myl, VV[-2 * WX], VV[-WX], VV[0], VV[WX], true, true);
                 fzc[2] = mzh * upw6z<T>(mzh, zc[2][1], zc[2][2], zc[2][3], zc[2][4], okL0, okR2);
                 const T fz = fzc[2] - zl[2];
-                const T val = (SAME ? rv_j : uc[3]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * hs;
+                T val = (SAME ? rv_j : uc[3]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * hs;
+                if (SRC) val += a.cdt * sy;
                 st(a.out[3], ov, val);
                 if (j == 0) st(a.out[3], ov + (uint32_t)ny * nx, val);
             }
@@ -397,7 +475,9 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                 fzc[3] = mzh * upw6z<T>(mzh, zc[3][1], zc[3][2], zc[3][3], zc[3][4], k - 1 >= 1, okR2);
                 const T fz = fzc[3] - zl[3];
                 // plane 0 holds the bottom wall face, not a CV
-                st(a.out[4], oc, k == 0 ? T(0) : (SAME ? rw_k : uc[4]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * hs);
+                T val = (SAME ? rw_k : uc[4]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * hs;
+                if (SRC) val += a.cdt * sz;
+                st(a.out[4], oc, k == 0 ? T(0) : val);
                 if (k == nz - 1) st(a.out[4], oc + pc, T(0));
             }
         }
@@ -411,6 +491,11 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
             uc[1] = nr1;
         } else {
             fetch_un(k + 2, uc);
+        }
+        if (SRC) {
+            ppm = pc0;
+            pc0 = pc1;
+            rkm = rk;
         }
         __syncthreads();
     };
@@ -456,7 +541,16 @@ ebs_status launch_bulk_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* Ucur
             e1 = cx->ev_pool[cx->ev_used++];
             EBS_HIP(cx, hipEventRecord(e0, bs));
         }
-        const size_t lds = bulk_lds_bytes(cx->tile_x, cx->tile_y, cx->g.precision);
+        const bool src = cx->src_on;
+        const size_t lds = bulk_lds_bytes(cx->tile_x, cx->tile_y, cx->g.precision, src);
+        a.sref = nullptr;
+        a.sg = a.sgam = T(0);
+        if (src) {
+            a.sref = cx->g.precision == EBS_F32_BULK ? (const T*)(const void*)cx->d_srcf
+                                                     : (const T*)(const void*)cx->d_srcd;
+            a.sg = (T)cx->src.g;
+            a.sgam = (T)cx->src.gamma;
+        }
         a.per_xcd = (cx->ntiles + NXCD - 1) / NXCD;
         bool same = true;
         for (int f = 0; f < 5; ++f) same = same && un[f] == cu[f];
@@ -464,7 +558,8 @@ ebs_status launch_bulk_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* Ucur
             const dim3 grid(a.per_xcd * NXCD), blk(cx->tile_x, cx->tile_y);
 #define EBS_BULK_CASE(X, Y)                                                                   \
     if (cx->tile_x == X && cx->tile_y == Y) {                                                 \
-        auto kf = same ? k_bulk<T, X, Y, true> : k_bulk<T, X, Y, false>;                      \
+        auto kf = src ? (same ? k_bulk<T, X, Y, true, true> : k_bulk<T, X, Y, false, true>)    \
+                      : (same ? k_bulk<T, X, Y, true, false> : k_bulk<T, X, Y, false, false>); \
         if (lds > 64 * 1024)                                                                  \
             EBS_HIP(cx, hipFuncSetAttribute((const void*)kf,                                   \
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
@@ -487,8 +582,9 @@ ebs_status launch_bulk_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* Ucur
 }  // namespace
 
 // ------------------------------------------------------------- host side
-size_t bulk_lds_bytes(int tx, int ty, int precision) {
-    return (precision == EBS_F32_BULK ? 4 : 8) * (size_t)L_COUNT * (tx + 5) * (ty + 5);
+size_t bulk_lds_bytes(int tx, int ty, int precision, bool sources) {
+    const size_t es = precision == EBS_F32_BULK ? 4 : 8;
+    return es * ((size_t)L_COUNT * (tx + 5) * (ty + 5) + (sources ? (size_t)2 * (tx + 1) * (ty + 1) : 0));
 }
 
 ebs_status build_tiles(ebs_ctx* cx) {

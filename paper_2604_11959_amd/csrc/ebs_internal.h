@@ -170,7 +170,15 @@ struct ebs_ctx {
     // (footprint window of the small CVs), 2 exact (the cells the
     // redistribution reads or writes, h_ftop, per column)
     int range_mode = 1;
-    int range_rule = 2;  // the strictest mode the geometry build tries (ebs_set_range_rule)
+    int range_rule = 2;
+    // momentum sources (ebs_set_sources): per-level tables [5][nz] of p0,
+    // rho theta0 (high, low part), 1 / rho theta0, rho0 in the state precision
+    // and in FP64; per position of the prims pass {p', rho'} (FP64)
+    bool src_on = false;
+    ebs_source_params src{};
+    float* d_srcf = nullptr;
+    double* d_srcd = nullptr;
+    double* d_srcv = nullptr;  // the strictest mode the geometry build tries (ebs_set_range_rule)
     std::vector<int32_t> h_ftop;  // [ncol] highest level the redistribution touches, -1 if none
 
     // redistribution
@@ -255,7 +263,7 @@ ebs_status redistribution_tops(ebs_ctx* c, std::vector<int32_t>& ftop);
 // regular-region kernel (bulk.hip) on the given stream, with its timing events
 ebs_status launch_bulk(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uhat, double cdt,
                        hipStream_t stream);
-size_t bulk_lds_bytes(int tx, int ty, int precision);
+size_t bulk_lds_bytes(int tx, int ty, int precision, bool sources);
 // redistribution (wsrd.hip)
 ebs_status wsrd_setup(ebs_ctx* c);
 ebs_status launch_redistribute(ebs_ctx* c, const ebs_state* Uhat, ebs_state* Uout);

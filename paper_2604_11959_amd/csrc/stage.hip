@@ -68,6 +68,12 @@ struct GenArgs {
     double cdt;
     double rdel[3];
     int eb_mode;
+    // momentum sources (null when off): {p', rho'} per position of the prims
+    // pass, the FP64 per-level table [5][nz] (p0, rho theta0, -, -, rho0) and
+    // the equation-of-state constants
+    double* srcv;
+    const double* sref;
+    double sP00, sR, sgam, sg;
 };
 
 // Interpolation of the flux on one cut face (area fraction b in (0, 1), or not
@@ -386,7 +392,7 @@ struct Gen {
     }
     template <int F>
     __device__ __forceinline__ void update_t(int fl, const UPt& P, const UPt (&U)[3], int i, int j, int k,
-                                             int g) const {
+                                             int g, double src = 0.0) const {
         constexpr int s = F < 2 ? 0 : F - 1;
         const size_t Ge = a.v.Ge;
         const double* f0 = a.fh + ((size_t)F * 3 + 0) * Ge;
@@ -402,6 +408,7 @@ struct Gen {
             br += (bface_u<F, 1>(U[1], Fu1) - bface_u<F, 1>(P, Fp1)) * a.rdel[1];
             br += (bface_u<F, 2>(U[2], Fu2) - bface_u<F, 2>(P, Fp2)) * a.rdel[2];
             val = unv - a.cdt * br / al;
+            if (F >= 2 && a.srcv) val += a.cdt * src;
         }
         a.uhat[(size_t)F * a.v.G + g] = val;
         put_field<T>(a.D, a.out, F, i, j, k, (T)val);
@@ -560,6 +567,18 @@ __global__ void __launch_bounds__(256) k_gen_prims(GenArgs<T> a) {
         o[1] = (fl & 2) ? vel(v.mu, v.rx, 4) : 0.0;
         o[2] = (fl & 4) ? vel(v.mv, v.ry, 5) : 0.0;
         o[3] = (fl & 8) ? vel(v.mw, v.rz, 6) : 0.0;
+        if (a.srcv) {
+            // perturbation pressure (equation of state) and density of a fluid cell
+            double pp = 0.0, rp = 0.0;
+            if (fl & 1) {
+                const int k = t[u].z;
+                const double rt0 = a.sref[a.D.nz + k];
+                pp = a.sref[k] * expm1(a.sgam * log1p((v.rt - rt0) / rt0));
+                rp = v.r - a.sref[4 * a.D.nz + k];
+            }
+            a.srcv[2 * (size_t)p] = pp;
+            a.srcv[2 * (size_t)p + 1] = rp;
+        }
     }
 }
 
@@ -630,11 +649,28 @@ __global__ void __launch_bounds__(256) k_gen_update(GenArgs<T> a) {
     const int4 t = a.utab[g];
     const int i = t.x, j = t.y, k = t.z & 0xFFFF, fl = t.z >> 16;
     const UPt P{t.w, a.v.fflag[g], a.cbase[g]};
+    // momentum sources: p' and rho' of this cell and of its lower neighbours
+    // along x, y, z (stencil-table slots 2, 5, 8 name their positions and
+    // whether they are fluid cells)
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    if (a.srcv) {
+        const size_t Ge = a.v.Ge;
+        const uint32_t cx = a.sten[2 * Ge + t.w], cy = a.sten[5 * Ge + t.w], cz = a.sten[8 * Ge + t.w];
+        const bool fo = fl & 1, fx = (cx >> 28) & 1u, fy = (cy >> 28) & 1u, fz = (cz >> 28) & 1u;
+        const double po = fo ? a.srcv[2 * (size_t)g] : 0.0, ro = fo ? a.srcv[2 * (size_t)g + 1] : 0.0;
+        const double pz = fz ? a.srcv[2 * (size_t)(cz & 0x0FFFFFFFu)] : 0.0;
+        const double rz = fz ? a.srcv[2 * (size_t)(cz & 0x0FFFFFFFu) + 1] : 0.0;
+        if (fo && fx) sx = -(po - a.srcv[2 * (size_t)(cx & 0x0FFFFFFFu)]) * a.rdel[0];
+        if (fo && fy) sy = -(po - a.srcv[2 * (size_t)(cy & 0x0FFFFFFFu)]) * a.rdel[1];
+        if (fo && fz) sz = -(po - pz) * a.rdel[2];
+        const int cnt = (int)fo + (int)fz;
+        if (cnt) sz -= a.sg * ((ro + rz) / cnt);
+    }
     G.template update_t<0>(fl, P, U, i, j, k, g);
     G.template update_t<1>(fl, P, U, i, j, k, g);
-    G.template update_t<2>(fl, P, U, i, j, k, g);
-    G.template update_t<3>(fl, P, U, i, j, k, g);
-    G.template update_t<4>(fl, P, U, i, j, k, g);
+    G.template update_t<2>(fl, P, U, i, j, k, g, sx);
+    G.template update_t<3>(fl, P, U, i, j, k, g, sy);
+    G.template update_t<4>(fl, P, U, i, j, k, g, sz);
 }
 
 // Area fraction x flux moved to the centroid on every partial face, for the
@@ -872,9 +908,12 @@ ebs_status build_stencils(ebs_ctx* cx) {
     const size_t Gs = (size_t)std::max(G, 1), Ges = (size_t)std::max(Ge, 1);
     if (cx->d_prim) (void)hipFree(cx->d_prim);
     cx->d_prim = nullptr;
+    if (cx->d_srcv) (void)hipFree(cx->d_srcv);
+    cx->d_srcv = nullptr;
     int32_t *d_gp = nullptr, *d_aoff = nullptr, *d_bad = nullptr;
     int2* d_aux = nullptr;
     bool ok = hipMalloc(&cx->d_prim, sizeof(double) * 4 * P) == hipSuccess;
+    ok = ok && hipMalloc(&cx->d_srcv, sizeof(double) * 2 * P) == hipSuccess;
     ok = ok && hipMalloc(&cx->d_ptab, sizeof(int4) * P) == hipSuccess;
     ok = ok && hipMalloc(&cx->d_sten, sizeof(uint32_t) * 10 * Ges) == hipSuccess;
     ok = ok && hipMalloc(&cx->d_ftab, sizeof(int4) * Ges) == hipSuccess;
@@ -976,6 +1015,12 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
         a.cdt = cdt;
         for (int d = 0; d < 3; ++d) a.rdel[d] = 1.0 / cx->g.dx[d];
         a.eb_mode = cx->g.eb_flux;
+        a.srcv = cx->src_on ? cx->d_srcv : nullptr;
+        a.sref = cx->d_srcd;
+        a.sP00 = cx->src.P00;
+        a.sR = cx->src.R;
+        a.sgam = cx->src.gamma;
+        a.sg = cx->src.g;
         const dim3 grid((cx->G + 255) / 256), gride((cx->Ge + 255) / 256), blk(256);
         // the first two passes only read the input state; the update writes
         // the output (which may alias U^n, never U_cur)

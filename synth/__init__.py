@@ -287,18 +287,26 @@ def reference_isentropic(grid: Grid, theta0: float = 300.0, P00: float = 1.0e5, 
     return Reference(p0, rho0, rho0 * theta0, theta0, P00, R, gamma, g)
 
 
-def state_reference(grid: Grid, ref: Reference, seed: int, rho_noise: float = 1e-3,
-                    theta_noise: float = 0.5, u0: float = 10.0, w_amp: float = 0.5) -> dict:
-    """Perturbed reference state: rho = rho0 (1 + rho_noise N(0,1)),
-    theta = theta0 + theta_noise N(0,1), rho u = rho0 (u0 + N(0,1)),
-    rho v, rho w = rho0 w_amp N(0,1) (walls 0).  rho_noise = theta_noise =
-    u0 = w_amp = 0 gives the reference state at rest."""
+def state_reference(grid: Grid, ref: Reference, seed: int, rho_noise: float = 1e-4,
+                    theta_noise: float = 1e-3, theta_amp: float = 1.0, u0: float = 10.0,
+                    w_amp: float = 0.5) -> dict:
+    """Perturbed reference state: a smooth potential-temperature anomaly plus
+    small cell noise, theta = theta0 + theta_amp cos(2 pi x / Lx) cos(2 pi y /
+    Ly) sin(pi z / Lz) + theta_noise N(0,1), rho = rho0 (1 + rho_noise
+    N(0,1)), rho u = rho0 (u0 + N(0,1)), rho v, rho w = rho0 w_amp N(0,1)
+    (walls 0).  All amplitudes 0 give the reference state at rest."""
     rng = np.random.default_rng(seed)
     nx, ny, nz = grid.n
     sh = field_shapes(grid.n)
     r0 = ref.rho0[:, None, None]
     rho = r0 * (1.0 + rho_noise * rng.standard_normal(sh["rho"]))
-    theta = ref.theta0 + theta_noise * rng.standard_normal(sh["rho"])
+    L = grid.length
+    xc = (np.arange(nx) + 0.5) * grid.dx[0]
+    yc = (np.arange(ny) + 0.5) * grid.dx[1]
+    zc = (np.arange(nz) + 0.5) * grid.dx[2]
+    bump = (np.sin(np.pi * zc / L[2])[:, None, None] * np.cos(2 * np.pi * yc / L[1])[None, :, None]
+            * np.cos(2 * np.pi * xc / L[0])[None, None, :])
+    theta = ref.theta0 + theta_amp * bump + theta_noise * rng.standard_normal(sh["rho"])
     rhou = np.empty(sh["rhou"])
     rhou[:, :, :nx] = r0 * (u0 + (1.0 if u0 else 0.0) * rng.standard_normal((nz, ny, nx)))
     rhov = np.empty(sh["rhov"])

@@ -57,7 +57,7 @@ def test_reference_state_at_rest_has_no_source(case):
     """The hydrostatic reference state at rest is an exact steady state of the
     sources: p' = 0 and rho' = 0 on every fluid cell (well-balanced form)."""
     g, h, o, ref = case
-    U = synth.state_reference(g, ref, 0, rho_noise=0.0, theta_noise=0.0, u0=0.0, w_amp=0.0)
+    U = synth.state_reference(g, ref, 0, rho_noise=0.0, theta_noise=0.0, theta_amp=0.0, u0=0.0, w_amp=0.0)
     S = o.sources_dense(oracle.to_dense(U, o.n), ref)
     scale = ref.g * ref.rho0.max()
     for d in range(3):
@@ -73,7 +73,7 @@ def test_perturbation_pressure_against_extended_precision(case):
     the cancellation-free form by about 1e-16 |p'|: the bound is 1e-13 Pa."""
     g, h, o, ref = case
     nx, ny, nz = g.n
-    U = synth.state_reference(g, ref, 0, rho_noise=0.0, theta_noise=0.0, u0=0.0, w_amp=0.0)
+    U = synth.state_reference(g, ref, 0, rho_noise=0.0, theta_noise=0.0, theta_amp=0.0, u0=0.0, w_amp=0.0)
     rng = np.random.default_rng(7)
     pert = np.zeros((nz, ny, nx), dtype=bool)
     pert[:, :, 1::2] = True
@@ -108,7 +108,7 @@ def test_linear_perturbation_pressure(case, d):
     idx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     coord = (idx[2 - d] + 0.5) * g.dx[d]
     p = _p0_eos(ref)[:, None, None] + a * coord
-    U = synth.state_reference(g, ref, 0, rho_noise=0.0, theta_noise=0.0, u0=0.0, w_amp=0.0)
+    U = synth.state_reference(g, ref, 0, rho_noise=0.0, theta_noise=0.0, theta_amp=0.0, u0=0.0, w_amp=0.0)
     U["rhotheta"] = _rhotheta_for(ref, p)
     S = o.sources_dense(oracle.to_dense(U, o.n), ref)[d]
     fc = _cell_fluid_dense(o)
@@ -135,7 +135,7 @@ def test_buoyancy_of_uniform_density_excess(case):
     gets -g c, whether one or both of its cells are fluid; x and y sources vanish."""
     g, h, o, ref = case
     c = 0.013
-    U = synth.state_reference(g, ref, 0, rho_noise=0.0, theta_noise=0.0, u0=0.0, w_amp=0.0)
+    U = synth.state_reference(g, ref, 0, rho_noise=0.0, theta_noise=0.0, theta_amp=0.0, u0=0.0, w_amp=0.0)
     rt = U["rhotheta"].copy()
     U["rho"] = U["rho"] + c
     U["rhotheta"] = rt
@@ -154,7 +154,7 @@ def test_buoyancy_averages_the_two_cells(case):
     g, h, o, ref = case
     nz = g.n[2]
     c = 0.01 * (1.0 + np.arange(nz, dtype=np.float64))
-    U = synth.state_reference(g, ref, 0, rho_noise=0.0, theta_noise=0.0, u0=0.0, w_amp=0.0)
+    U = synth.state_reference(g, ref, 0, rho_noise=0.0, theta_noise=0.0, theta_amp=0.0, u0=0.0, w_amp=0.0)
     rt = U["rhotheta"].copy()
     U["rho"] = U["rho"] + c[:, None, None]
     U["rhotheta"] = rt
