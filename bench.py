@@ -11,8 +11,10 @@ Default workload: 512 x 512 x 128 cells tiled by 512 uneven AMR-style boxes
 (16^3..64^3) over seeded multi-hill terrain, FP32-bulk state (geometry, cut
 region, redistribution and sums in FP64), tile shape chosen by the autotuner,
 RK3 step captured in a HIP graph.  Besides the main line it reports the plain
-FP64 single-box case (128 x 128 x 64 Witch of Agnesi hill), the regular-region
-kernel against the HBM roofline, and the FP64 oracle timed on the host.
+FP64 single-box case (128 x 128 x 64 Witch of Agnesi hill), the same workload
+with the momentum sources (perturbation pressure gradient and buoyancy over an
+isentropic reference atmosphere), the regular-region kernel against the HBM
+roofline, and the FP64 oracle timed on the host.
 
 Prints ONE JSON line.
 """
@@ -40,7 +42,7 @@ def _log(msg):
 
 
 def run_workload(cfg: int, precision: int, steps: int, warmup: int, use_graph: bool,
-                 autotune: bool, timing: bool, tile=None, overlap: bool = False):
+                 autotune: bool, timing: bool, tile=None, overlap: bool = False, sources: bool = False):
     import torch
 
     import paper_2604_11959_amd as ebs
@@ -54,13 +56,17 @@ def run_workload(cfg: int, precision: int, steps: int, warmup: int, use_graph: b
     ctx.build_geometry(w.h_nodes)
     _log(f"{w.name}: geometry built in {time.time() - t0:.1f}s")
     ctx.set_overlap(overlap)
+    ref = None
+    if sources:
+        ref = synth.reference_isentropic(w.grid)
+        ctx.set_sources(ref)
     if tile:
         ctx.set_tile(*tile)
     elif autotune:
         tile = ctx.autotune(os.environ.get("EBS_TILE_CACHE", TILE_CACHE))
         _log(f"{w.name}: tile {tile}")
     tile = ctx.get_tile()
-    U = ctx.new_state(synth.make_state(w))
+    U = ctx.new_state(synth.state_reference(w.grid, ref, 1000 + w.seed) if sources else synth.make_state(w))
     S = [ctx.new_state(), ctx.new_state()]
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
@@ -140,6 +146,8 @@ def main(argv=None):
                     help="run the regular-region kernel concurrently with the general range")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-sources", action="store_true",
+                    help="skip the leg with the momentum sources (pressure gradient, buoyancy)")
     ap.add_argument("--tile", default=None,
                     help="fixed tile TXxTYxTZxSPAN (SPAN 1: tiles cut from the whole domain; skips the autotuner)")
     ap.add_argument("--no-kernel-timing", action="store_true")
@@ -232,6 +240,27 @@ def main(argv=None):
         out["fp64_single_box"] = {"workload": r2["workload"].name,
                                   "value": round(r2["workload"].grid.ncells * 3 / (ms2 * 1e-3) / 1e6, 1),
                                   "ms_per_step": round(ms2, 4)}
+    if not args.no_sources:
+        # the same workload with the momentum sources of the compressible
+        # model (perturbation pressure gradient, buoyancy) switched on
+        rs = run_workload(cfg, precision, args.steps, args.warmup, not args.no_graph, True, False, None, overlap,
+                          sources=True)
+        ms3 = rs["ms"] / args.steps
+        leg = {"workload": rs["workload"].name + " + sources",
+               "value": round(N * 3 / (ms3 * 1e-3) / 1e6, 1),
+               "ms_per_step": round(ms3, 4),
+               "tile": list(rs["tile"][:3]),
+               "tiling": "domain" if rs["tile"][3] else "per box"}
+        if not args.no_kernel_timing:
+            ks = run_workload(cfg, precision, args.steps, 1, False, True, True, rs["tile"], overlap, sources=True)
+            kms3, nl3 = ks["kern"]
+            a3 = kms3 / max(nl3, 1)
+            b3 = (ks["alg"][0] + 2 * ks["alg"][1]) / 3.0
+            leg["k_bulk_avg_launch_ms"] = round(a3, 4)
+            leg["k_bulk_achieved_GBs"] = round(b3 / (a3 * 1e-3) / 1e9, 1)
+            leg["k_bulk_frac_of_hbm_peak"] = round(b3 / (a3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        _log(f"sources: {ms3:.3f} ms/step")
+        out["with_sources"] = leg
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
