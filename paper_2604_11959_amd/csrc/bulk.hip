@@ -52,6 +52,7 @@ struct BulkArgs {
     // 1 / rho theta0, rho0), gravity, gamma
     const T* __restrict__ sref;
     T sg, sgam;
+    T bc[8];  // FP32: binomial coefficients C(gamma, n), n = 1..8
 };
 
 __device__ __forceinline__ float log1p_t(float x) { return log1pf(x); }
@@ -64,14 +65,30 @@ __device__ __forceinline__ double expm1_t(double x) { return expm1(x); }
 // relative departure (rho theta - rho theta0) / rho theta0 so that the small
 // difference keeps the state precision's relative accuracy (FP32: rho theta0
 // as a float pair, so the departure is exact up to one rounding)
+//
+// FP32: (1 + x)^gamma - 1 from the binomial series sum_{n=1..8} C(gamma, n) x^n
+// for |x| < 1/8 (truncation below 1e-9 relative; coefficients in bc[]), and
+// from the hardware base-2 exponential and logarithm beyond, where the result
+// is at least 0.15 and no cancellation occurs.  FP64: log1p and expm1.
+constexpr int PP_DEG = 8;
 template <typename T>
-__device__ __forceinline__ T pprime(const T* __restrict__ sref, int nz, T gam, T rt, int k) {
-    T x;
-    if constexpr (sizeof(T) == 8)
-        x = (rt - sref[nz + k]) / sref[nz + k];
-    else
-        x = ((rt - sref[nz + k]) - sref[2 * nz + k]) * sref[3 * nz + k];
-    return sref[k] * expm1_t(gam * log1p_t(x));
+__device__ __forceinline__ T pprime(const T* __restrict__ sref, int nz, T gam, const T* bc, T rt, int k) {
+    if constexpr (sizeof(T) == 8) {
+        const T x = (rt - sref[nz + k]) / sref[nz + k];
+        return sref[k] * expm1_t(gam * log1p_t(x));
+    } else {
+        const float x = ((rt - sref[nz + k]) - sref[2 * nz + k]) * sref[3 * nz + k];
+        float e;
+        if (fabsf(x) < 0.125f) {
+            e = bc[PP_DEG - 1];
+#pragma unroll
+            for (int n = PP_DEG - 2; n >= 0; --n) e = e * x + bc[n];
+            e *= x;
+        } else {
+            e = __builtin_amdgcn_exp2f(gam * __builtin_amdgcn_logf(1.0f + x)) - 1.0f;
+        }
+        return sref[k] * e;
+    }
 }
 
 template <typename T>
@@ -274,7 +291,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
         for (int q = 0; q < NPTS; ++q) {
             if (q > 0 && lr[q] < 0) break;
             if (lp[q] < 0) continue;
-            const T v = pprime<T>(a.sref, nz, a.sgam, rth[q], p);
+            const T v = pprime<T>(a.sref, nz, a.sgam, a.bc, rth[q], p);
             PP[lp[q]] = v;
             if (q == 0) own = v;
         }
@@ -297,7 +314,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
     fetch(k0 - 1, pfA);
     commit(k0 - 1, pfA);
     if (SRC) {
-        ppm = (k0 >= 1) ? pprime<T>(a.sref, nz, a.sgam, rth[0], k0 - 1) : T(0);
+        ppm = (k0 >= 1) ? pprime<T>(a.sref, nz, a.sgam, a.bc, rth[0], k0 - 1) : T(0);
         rkm = own_rho(k0 - 1);
     }
     fetch(k0, pfA);
@@ -329,7 +346,9 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
         }
     };
     T fzc[4] = {T(0), T(0), T(0), T(0)};  // upper z-face flux terms of the last plane
-    if (!SAME) {
+    // (with the sources, whose extra registers would not fit beside two
+    // planes of U^n, U^n is loaded at the top of its own z-iteration)
+    if (!SAME && !SRC) {
         fetch_un(k0, unA);
         fetch_un(k0 + 1, unB);
     }
@@ -340,6 +359,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
         T nr0 = T(0), nr1 = T(0);  // SAME: rho, rho theta of the own cell of plane k + 2
         if (SAME) nr0 = rp[0][0], nr1 = rp[0][1];
         if (SRC) {
+            if (!SAME) fetch_un(k, uc);
             rk = own_rho(k);  // plane k leaves the density ring with this commit
             pc1 = write_pp(k + 1);
         }
@@ -404,16 +424,9 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                 zl[3] = m3l * upw6z<T>(m3l, zc[3][0], zc[3][1], zc[3][2], zc[3][3], k - 2 >= 1, okR1);
             }
             // sources of the three momentum CVs of this cell (p' of the own
-            // cell and of its -x, -y, -z neighbours, all fluid here)
-            T sx = T(0), sy = T(0), sz = T(0);
-            if (SRC) {
-                const T* PPk = PPB + (k & 1) * PS + (ty + 1) * PW + (tx + 1);
-                sx = -(pc0 - PPk[-1]) * a.rdx;
-                sy = -(pc0 - PPk[-PW]) * a.rdy;
-                if (k >= 1)
-                    sz = -(pc0 - ppm) * a.rdz -
-                         a.sg * T(0.5) * ((rk - a.sref[4 * nz + k]) + (rkm - a.sref[4 * nz + k - 1]));
-            }
+            // cell and of its -x, -y, -z neighbours, all fluid here), each
+            // evaluated next to its use
+            const T* PPk = PPB + (k & 1) * PS + (ty + 1) * PW + (tx + 1);
             // ---- cell-centred instance
             {
                 const T ex = ru_ip - ru_i, ey = rv_jp - rv_j, ez = rw_kp - rw_k;
@@ -440,7 +453,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                 fzc[1] = mzh * upw6z<T>(mzh, zc[1][1], zc[1][2], zc[1][3], zc[1][4], okL0, okR2);
                 const T fz = fzc[1] - zl[1];
                 T val = (SAME ? ru_i : uc[2]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * hs;
-                if (SRC) val += a.cdt * sx;
+                if (SRC) val += a.cdt * (-(pc0 - PPk[-1]) * a.rdx);
                 st(a.out[2], ou, val);
                 if (i == 0) st(a.out[2], ou + nx, val);
             }
@@ -456,7 +469,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                 fzc[2] = mzh * upw6z<T>(mzh, zc[2][1], zc[2][2], zc[2][3], zc[2][4], okL0, okR2);
                 const T fz = fzc[2] - zl[2];
                 T val = (SAME ? rv_j : uc[3]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * hs;
-                if (SRC) val += a.cdt * sy;
+                if (SRC) val += a.cdt * (-(pc0 - PPk[-PW]) * a.rdy);
                 st(a.out[3], ov, val);
                 if (j == 0) st(a.out[3], ov + (uint32_t)ny * nx, val);
             }
@@ -476,7 +489,9 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
                 const T fz = fzc[3] - zl[3];
                 // plane 0 holds the bottom wall face, not a CV
                 T val = (SAME ? rw_k : uc[4]) - a.cdt * (fx * a.rdx + fy * a.rdy + fz * a.rdz) * hs;
-                if (SRC) val += a.cdt * sz;
+                if (SRC && k >= 1)
+                    val += a.cdt * (-(pc0 - ppm) * a.rdz -
+                                    a.sg * T(0.5) * ((rk - a.sref[4 * nz + k]) + (rkm - a.sref[4 * nz + k - 1])));
                 st(a.out[4], oc, k == 0 ? T(0) : val);
                 if (k == nz - 1) st(a.out[4], oc + pc, T(0));
             }
@@ -489,7 +504,7 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
         if (SAME) {
             uc[0] = nr0;
             uc[1] = nr1;
-        } else {
+        } else if (!SRC) {
             fetch_un(k + 2, uc);
         }
         if (SRC) {
@@ -550,6 +565,11 @@ ebs_status launch_bulk_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* Ucur
                                                      : (const T*)(const void*)cx->d_srcd;
             a.sg = (T)cx->src.g;
             a.sgam = (T)cx->src.gamma;
+            double cn = 1.0;
+            for (int q = 0; q < 8; ++q) {  // C(gamma, q + 1)
+                cn *= (cx->src.gamma - q) / (q + 1);
+                a.bc[q] = (T)cn;
+            }
         }
         a.per_xcd = (cx->ntiles + NXCD - 1) / NXCD;
         bool same = true;
