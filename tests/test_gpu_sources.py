@@ -316,3 +316,45 @@ def test_sources_full_size_sampled_windows():
         tol = 2e-5 + _storage_bound(w, ref, [w.dt / 2, w.dt], mom)
         print((i0, j0), err, "tol", tol, flush=True)
         assert max(err.values()) <= tol, ((i0, j0), err, tol)
+
+
+@pytest.mark.parametrize("terrain", ["hills", "flat"])
+@pytest.mark.parametrize("precision,tiles,tol", [
+    (ebs.EBS_F64, ((16, 4, 16), (16, 8, 64)), 1e-12),
+    (ebs.EBS_F32_BULK, ((16, 16, 16), (32, 8, 32), (64, 16, 64, 1)), 2e-5),
+])
+def test_sources_down_to_the_bottom_wall(terrain, precision, tiles, tol):
+    """Columns over flat ground have an empty general range, so the
+    regular-region kernel applies the sources down to the bottom wall: no
+    z-face CV at k = 0, the pressure difference and the buoyancy of the CV at
+    k = 1 reach the bottom cell layer, and tiles start at the bottom or above
+    it (their first plane takes p' and rho of the plane below from a direct
+    evaluation).  Distinct U^n and U_cur, one stage against the oracle; FP32
+    inputs are FP32-representable."""
+    g = synth.Grid((48, 40, 40), (78.125, 78.125, 31.25))
+    if terrain == "flat":
+        h = synth.terrain_flat(g, 0.0)
+    else:
+        h = synth.terrain_gaussian_hills(g, 5, 2, hrange=(80.0, 200.0), wrange=(150.0, 250.0))
+    w = synth.Workload("src_" + terrain + "48", g, h, synth.cfl_dt(g), 5, [((0, 0, 0), g.n)], "atmos")
+    ref = synth.reference_isentropic(g)
+    o = oracle.Oracle(g, h)
+    Un = synth.state_reference(g, ref, 71)
+    U0 = synth.state_reference(g, ref, 72, theta_noise=0.05)
+    if precision == ebs.EBS_F32_BULK:
+        Un, U0 = _f32(Un), _f32(U0)
+    cdt = 0.5 * w.dt
+    want = o.redistribute(o.advance(Un, U0, cdt, ref))
+    boxes = synth.boxes_split(g.n, 9, 12, block=16, unit=8)
+    for tile in tiles:
+        c = _ctx(w, ref, precision=precision, boxes=boxes)
+        c.set_tile(*tile)
+        if terrain == "flat":
+            assert int(c.stats()[0][6]) == 0
+        Ud, Uc, Uh = c.new_state(Un), c.new_state(U0), c.new_state()
+        c.advance(Ud, Uc, Uh, cdt)
+        c.redistribute(Uh, Uh)
+        torch.cuda.synchronize()
+        err, _ = rel_err(_host(Uh), want, _masks(o))
+        print(terrain, precision, tile, err, flush=True)
+        assert max(err.values()) <= tol, (tile, err)
