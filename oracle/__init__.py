@@ -23,7 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = ["geom.c", "flux.c", "wsrd.c", "source.c"]
+_SRC = ["geom.c", "flux.c", "wsrd.c", "source.c", "restrict.c"]
 
 # geometry quantity indices (mirror oracle.h)
 OQ = dict(ALPHA=0, BX=1, BY=2, BZ=3, FX1=4, FX2=5, FY1=6, FY2=7, FZ1=8, FZ2=9,
@@ -80,6 +80,8 @@ def _load():
         lib.orc_redistribute_sig.argtypes = [P(_Grid), dpp, dpp, dpp, dpp, dpp]
         lib.orc_face_fluxes.argtypes = [P(_Grid), dpp, dpp, C.c_int, dpp, dpp]
         lib.orc_sources.argtypes = [P(_Grid), dpp, dpp, P(_Src), dp, dp, dpp]
+        lib.orc_coarsen_geometry.argtypes = [P(_Grid), dpp, dp, dpp]
+        lib.orc_restrict.argtypes = [P(_Grid), dpp, dpp, dpp]
         lib.orc_box_moments.argtypes = [P(_Grid), dp, C.c_int, C.c_int, dp, C.c_double,
                                         C.c_double, C.c_int, dp]
         _lib = lib
@@ -253,6 +255,28 @@ class Oracle:
         for c in RK3_C:
             cur = self.redistribute_dense(self.advance_dense(d_n, cur, c * dt, ref))
         return from_dense(cur, self.n)
+
+    # ------------------------------------------------------------ two levels
+    def coarsened_geometry(self):
+        """alpha and lower-face area fractions (x, y, z) of the grid coarsened
+        by 2, each (nz/2, ny/2, nx/2)."""
+        nx, ny, nz = self.n
+        sh = (nz // 2, ny // 2, nx // 2)
+        a = np.zeros(sh)
+        b = [np.zeros(sh) for _ in range(3)]
+        if _load().orc_coarsen_geometry(C.byref(self.g), _dpp(self.geo), _dptr(a), _dpp(b)) != 0:
+            raise ValueError("odd grid size")
+        return a, b
+
+    def restrict(self, U: dict) -> dict:
+        """Restriction of a fine state onto the grid coarsened by 2 (public layout)."""
+        nx, ny, nz = self.n
+        D = to_dense(U, self.n)
+        cn = (nx // 2, ny // 2, nz // 2)
+        out = [np.zeros((cn[2] + 1, cn[1], cn[0])) for _ in range(5)]
+        if _load().orc_restrict(C.byref(self.g), _dpp(self.geo), _dpp(D), _dpp(out)) != 0:
+            raise ValueError("odd grid size")
+        return from_dense(out, cn)
 
     def face_fluxes(self, U: dict, field: int):
         F = [np.zeros(self.NI).reshape(self.n[2] + 1, self.n[1], self.n[0]) for _ in range(3)]
