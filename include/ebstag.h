@@ -250,6 +250,33 @@ typedef struct {
 ebs_status ebs_set_sources(ebs_ctx* ctx, const ebs_source_params* prm, const double* rhotheta0,
                            const double* rho0);
 
+/* Restriction (averaging down) of a state of this context's grid onto the
+ * grid coarsened by 2 in every direction (Section 3.3: static two-level
+ * refinement with ratio 2; the coarse geometry is merged from the fine
+ * subcells, cell-centred variables are averaged with volume-fraction weights
+ * and face-centred ones with area-fraction weights, which keeps the mass of
+ * every coarse cell and the mass flux through every coarse face).  Coarse
+ * cell (I, J, K) covers fine cells (2I + a, 2J + b, 2K + c), a, b, c in {0, 1}.
+ *   Ufine:   device state of this context (layout of ebs_advance_stage).
+ *   Ucoarse: caller-owned device state of the coarse grid, same precision:
+ *            rho, rhotheta (nz/2, ny/2, nx/2), rhou (nz/2, ny/2, nx/2 + 1),
+ *            rhov (nz/2, ny/2 + 1, nx/2), rhow (nz/2 + 1, ny/2, nx/2), x
+ *            fastest; every entry is written (periodic repeats copied, walls
+ *            and covered cells 0).  Must not overlap Ufine.
+ * A coarse momentum is the area-weighted mean over the four fine faces on
+ * its face; where that face has no open area, the mean weighted by the
+ * volume fractions of the four fine staggered CVs; 0 if both vanish.
+ * Asynchronous on the context stream.  Errors: EBS_E_ARG (null pointers),
+ * EBS_E_ORDER (no geometry), EBS_E_UNSUPPORTED (an odd grid size). */
+ebs_status ebs_restrict(ebs_ctx* ctx, const ebs_state* Ufine, ebs_state* Ucoarse);
+
+/* The merged geometry of the coarse grid (Section 3.3): volume fraction of
+ * every coarse cell (mean of its eight children) and area fractions of its
+ * lower x, y, z faces (means of the four fine faces on each); host arrays of
+ * (nz/2)(ny/2)(nx/2) doubles each, x fastest.  Synchronous; allocates and
+ * frees a device buffer.  Errors as ebs_restrict, EBS_E_OOM, EBS_E_HIP. */
+ebs_status ebs_coarsened_geometry(ebs_ctx* ctx, double* alpha, double* beta_x, double* beta_y, double* beta_z);
+
 /* Kernel timing: when enabled, every launch of the regular-region stage
  * kernel is bracketed by HIP events on the context stream; read returns the
  * summed duration (ms) and launch count since the last reset and resets. */

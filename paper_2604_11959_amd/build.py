@@ -20,7 +20,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libebstag.so")
-SOURCES = ["api.hip", "geom.hip", "bulk.hip", "stage.hip", "wsrd.hip", "reduce.hip"]
+SOURCES = ["api.hip", "geom.hip", "bulk.hip", "stage.hip", "wsrd.hip", "reduce.hip", "restrict.hip"]
 ARCH = "gfx950"
 
 COMMON = [

@@ -518,6 +518,33 @@ ebs_status ebs_set_sources(ebs_ctx* c, const ebs_source_params* prm, const doubl
     return EBS_OK;
 }
 
+ebs_status ebs_restrict(ebs_ctx* c, const ebs_state* Uf, ebs_state* Uc) {
+    if (!c) return EBS_E_ARG;
+    if (!state_ok(Uf) || !state_ok(Uc)) return fail(c, EBS_E_ARG, "null state pointer");
+    if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
+    if ((c->nx | c->ny | c->nz) & 1) return fail(c, EBS_E_UNSUPPORTED, "restriction needs even grid sizes");
+    return launch_restrict(c, Uf, Uc, nullptr);
+}
+
+ebs_status ebs_coarsened_geometry(ebs_ctx* c, double* alpha, double* bx, double* by, double* bz) {
+    if (!c) return EBS_E_ARG;
+    if (!alpha || !bx || !by || !bz) return fail(c, EBS_E_ARG, "null output array");
+    if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
+    if ((c->nx | c->ny | c->nz) & 1) return fail(c, EBS_E_UNSUPPORTED, "restriction needs even grid sizes");
+    const size_t NC = (size_t)(c->nx / 2) * (c->ny / 2) * (c->nz / 2);
+    double* d = nullptr;
+    if (hipMalloc(&d, sizeof(double) * 4 * NC) != hipSuccess) return fail(c, EBS_E_OOM, "coarse geometry buffer");
+    ebs_status st = launch_restrict(c, nullptr, nullptr, d);
+    hipError_t e = st == EBS_OK ? hipStreamSynchronize(c->stream) : hipSuccess;
+    double* const dst[4] = {alpha, bx, by, bz};
+    for (int q = 0; q < 4 && st == EBS_OK && e == hipSuccess; ++q)
+        e = hipMemcpy(dst[q], d + q * NC, sizeof(double) * NC, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (st != EBS_OK) return st;
+    if (e != hipSuccess) return hip_fail(c, e, "coarse geometry");
+    return EBS_OK;
+}
+
 ebs_status ebs_set_range_rule(ebs_ctx* c, int32_t rule) {
     if (!c) return EBS_E_ARG;
     if (rule < 0 || rule > 2) return fail(c, EBS_E_ARG, "range rule must be 0, 1 or 2");

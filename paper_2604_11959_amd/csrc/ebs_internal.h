@@ -264,6 +264,7 @@ ebs_status redistribution_tops(ebs_ctx* c, std::vector<int32_t>& ftop);
 ebs_status launch_bulk(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uhat, double cdt,
                        hipStream_t stream);
 size_t bulk_lds_bytes(int tx, int ty, int precision, bool sources);
+ebs_status launch_restrict(ebs_ctx* cx, const ebs_state* Uf, ebs_state* Uc, double* geo_out);
 // redistribution (wsrd.hip)
 ebs_status wsrd_setup(ebs_ctx* c);
 ebs_status launch_redistribute(ebs_ctx* c, const ebs_state* Uhat, ebs_state* Uout);

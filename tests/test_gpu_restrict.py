@@ -1,0 +1,177 @@
+"""GPU parity of the two-level restriction (Section 3.3: merged geometry,
+volume- and area-weighted averaging down) through the C ABI against the
+FP64 oracle.
+
+Bars: merged geometry <= 1e-13 absolute (fractions); FP64 coarse state
+<= 1e-12 relative per field (max |dU| over the coarse grid / max |U_ref| of
+the field); FP32 bulk <= 2e-5 from FP32-representable inputs; conservation
+<= 1e-13 relative.  States are smooth: a coarse cell whose fluid is a few
+slivers weights its children by volume fractions of order 1e-7, whose last
+digits differ between two correct geometry builders, so a state with O(1)
+jumps between children would measure the geometry's rounding, not the
+restriction."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2604_11959_amd as ebs  # noqa: E402
+
+FIELDS = ebs.FIELDS
+_cache = {}
+
+
+def _oracle(cfg):
+    if cfg not in _cache:
+        w = synth.make_workload(cfg)
+        _cache[cfg] = (w, oracle.Oracle(w.grid, w.h_nodes))
+    return _cache[cfg]
+
+
+def _ctx(w, precision=ebs.EBS_F64, boxes=None):
+    print(f"[ctx] {w.name} precision={precision}", flush=True)
+    c = ebs.Context(w.grid.n, w.grid.dx, w.grid.lo, boxes=boxes, precision=precision)
+    c.build_geometry(w.h_nodes)
+    return c
+
+
+def _host(U):
+    return {k: v.double().cpu().numpy() for k, v in U.items()}
+
+
+def _smooth_state(w):
+    """The workload's state with smooth, non-zero v and w (the stored state has
+    v = w = 0): rho v = rho (1 + 0.5 sin 2 pi x / Lx), rho w = rho 0.3 cos 2 pi y / Ly
+    (walls 0)."""
+    U = synth.make_state(w)
+    nx, ny, nz = w.grid.n
+    L = w.grid.length
+    x = (np.arange(nx) + 0.5) * w.grid.dx[0]
+    y = (np.arange(ny) + 0.5) * w.grid.dx[1]
+    r = U["rho"]
+    rv = np.empty((nz, ny + 1, nx))
+    rv[:, :ny, :] = r * (1.0 + 0.5 * np.sin(2 * np.pi * x / L[0]))[None, None, :]
+    rv[:, ny, :] = rv[:, 0, :]
+    rw = np.zeros((nz + 1, ny, nx))
+    rw[1:nz] = r[1:] * 0.3 * np.cos(2 * np.pi * y / L[1])[None, :, None]
+    U["rhov"], U["rhow"] = rv, rw
+    return U
+
+
+def _rel(got, ref):
+    return {f: float(np.abs(got[f] - ref[f]).max() / max(np.abs(ref[f]).max(), 1e-300)) for f in FIELDS}
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_coarsened_geometry(cfg):
+    w, o = _oracle(cfg)
+    c = _ctx(w)
+    a, b = c.coarsened_geometry()
+    ra, rb = o.coarsened_geometry()
+    assert np.abs(a - ra).max() <= 1e-13
+    for d in range(3):
+        assert np.abs(b[d] - rb[d]).max() <= 1e-13, d
+    assert ((a > 0) & (a < 1)).any() and (a == 0).any() and (a == 1).any()
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_restrict_fp64(cfg):
+    w, o = _oracle(cfg)
+    U = _smooth_state(w)
+    want = o.restrict(U)
+    c = _ctx(w)
+    got = _host(c.restrict(c.new_state(U)))
+    torch.cuda.synchronize()
+    err = _rel(got, want)
+    print(err)
+    assert max(err.values()) <= 1e-12, err
+    # every entry written: walls, periodic repeats
+    assert np.all(got["rhow"][0] == 0) and np.all(got["rhow"][-1] == 0)
+    assert np.array_equal(got["rhou"][:, :, -1], got["rhou"][:, :, 0])
+    assert np.array_equal(got["rhov"][:, -1, :], got["rhov"][:, 0, :])
+
+
+def test_restrict_conserves_mass_on_the_gpu_geometry():
+    """With the GPU's own merged geometry and fine volume fractions: the mass
+    and rho theta of every coarse cell equal those of its children."""
+    w, o = _oracle(2)
+    U = _smooth_state(w)
+    c = _ctx(w)
+    got = _host(c.restrict(c.new_state(U)))
+    a, _ = c.coarsened_geometry()
+    nx, ny, nz = w.grid.n
+    af = c.export(0, oracle.OQ["ALPHA"])[:nz]
+    for f in ("rho", "rhotheta"):
+        fine = (af * U[f]).reshape(nz // 2, 2, ny // 2, 2, nx // 2, 2).sum(axis=(1, 3, 5))
+        coarse = 8.0 * a * got[f]
+        assert np.abs(coarse - fine).max() <= 1e-13 * np.abs(fine).max(), f
+
+
+def test_restrict_f32_bulk():
+    w, o = _oracle(2)
+    U = {k: v.astype(np.float32).astype(np.float64) for k, v in _smooth_state(w).items()}
+    want = o.restrict(U)
+    c = _ctx(w, precision=ebs.EBS_F32_BULK)
+    got = _host(c.restrict(c.new_state(U)))
+    err = _rel(got, want)
+    print(err)
+    assert max(err.values()) <= 2e-5, err
+
+
+def test_restrict_full_size_windows():
+    """The 512 x 512 x 128 multi-hill configuration (FP32 bulk, 512 boxes): the
+    restricted state on 64 x 64-column windows (two highest hills, flat
+    ground) against the oracle run on the same windows; the window's outer
+    two coarse columns are dropped (its terrain is made periodic there)."""
+    w = synth.make_workload(4)
+    n = w.grid.n
+    U = {k: v.astype(np.float32).astype(np.float64) for k, v in _smooth_state(w).items()}
+    c = _ctx(w, precision=ebs.EBS_F32_BULK, boxes=w.boxes)
+    got = _host(c.restrict(c.new_state(U)))
+    hn = w.h_nodes
+    hc = hn[:-1, :-1].copy()
+    centres = []
+    for _ in range(2):
+        jj, ii = np.unravel_index(np.argmax(hc), hc.shape)
+        centres.append((ii, jj))
+        hc[max(jj - 64, 0):jj + 64, max(ii - 64, 0):ii + 64] = -1.0
+    flat = np.argwhere(hn[:-1, :-1] == 0.0)
+    centres.append((int(flat[len(flat) // 2][1]), int(flat[len(flat) // 2][0])))
+    wx = wy = 64
+    for (ci, cj) in centres:
+        i0 = int(min(max(ci - wx // 2, 0), n[0] - wx - 1)) & ~1
+        j0 = int(min(max(cj - wy // 2, 0), n[1] - wy - 1)) & ~1
+        ww = synth.window(w, i0, j0, wx, wy, n[2])
+        o = oracle.Oracle(ww.grid, ww.h_nodes)
+        Uw = {
+            "rho": U["rho"][:, j0:j0 + wy, i0:i0 + wx], "rhotheta": U["rhotheta"][:, j0:j0 + wy, i0:i0 + wx],
+            "rhou": U["rhou"][:, j0:j0 + wy, i0:i0 + wx + 1], "rhov": U["rhov"][:, j0:j0 + wy + 1, i0:i0 + wx],
+            "rhow": U["rhow"][:, j0:j0 + wy, i0:i0 + wx],
+        }
+        want = o.restrict({k: np.ascontiguousarray(v) for k, v in Uw.items()})
+        I0, J0, m = i0 // 2, j0 // 2, 2
+        err = {}
+        for f in FIELDS:
+            g = got[f][:, J0 + m:J0 + wy // 2 - m, I0 + m:I0 + wx // 2 - m]
+            r = want[f][:, m:wy // 2 - m, m:wx // 2 - m]
+            err[f] = float(np.abs(g - r).max() / np.abs(r).max())
+        print((i0, j0), err, flush=True)
+        assert max(err.values()) <= 2e-5, ((i0, j0), err)
+
+
+def test_restrict_errors():
+    g = synth.Grid((16, 16, 9), (50.0, 50.0, 25.0))
+    c = ebs.Context(g.n, g.dx, g.lo, precision=ebs.EBS_F64)
+    U = c.new_state()
+    with pytest.raises(ebs.EbsError):
+        c.restrict(U, out=c.new_state())  # no geometry yet
+    c.build_geometry(synth.terrain_flat(g, 10.0))
+    with pytest.raises(ebs.EbsError):
+        c.restrict(U, out=c.new_state())  # odd nz
