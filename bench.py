@@ -13,8 +13,9 @@ region, redistribution and sums in FP64), tile shape chosen by the autotuner,
 RK3 step captured in a HIP graph.  Besides the main line it reports the plain
 FP64 single-box case (128 x 128 x 64 Witch of Agnesi hill), the same workload
 with the momentum sources (perturbation pressure gradient and buoyancy over an
-isentropic reference atmosphere), the regular-region kernel against the HBM
-roofline, and the FP64 oracle timed on the host.
+isentropic reference atmosphere), the restriction of the state onto the grid
+coarsened by 2, the regular-region kernel against the HBM roofline, and the
+FP64 oracle timed on the host.
 
 Prints ONE JSON line.
 """
@@ -115,6 +116,43 @@ def measured_traffic(tile, workload_name, alg_bytes):
     return float(s["traffic_bytes_per_launch"])
 
 
+def restriction_leg(cfg: int, precision: int, launches: int):
+    """Restriction of the workload's state onto the grid coarsened by 2,
+    timed with HIP events over ``launches`` calls, against the HBM roofline.
+    Algorithmic bytes per coarse cell: the eight children of rho and rho
+    theta, the four fine faces of each momentum, and the five coarse values
+    written (33 state elements)."""
+    import torch
+
+    import paper_2604_11959_amd as ebs
+    import synth
+
+    w = synth.make_workload(cfg)
+    ctx = ebs.Context(w.grid.n, w.grid.dx, w.grid.lo, boxes=w.boxes, precision=precision)
+    ctx.build_geometry(w.h_nodes)
+    U = ctx.new_state(synth.make_state(w))
+    Uc = ctx.restrict(U)
+    for _ in range(2):
+        ctx.restrict(U, Uc)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(launches):
+        ctx.restrict(U, Uc)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / launches
+    nc = (w.grid.n[0] // 2) * (w.grid.n[1] // 2) * (w.grid.n[2] // 2)
+    es = 4 if precision == ebs.EBS_F32_BULK else 8
+    alg = 33 * es * nc
+    gbs = alg / (ms * 1e-3) / 1e9
+    return {"workload": f"{w.name} -> {w.grid.n[0] // 2}x{w.grid.n[1] // 2}x{w.grid.n[2] // 2}",
+            "kernel": "k_restrict", "avg_launch_ms": round(ms, 4), "alg_bytes_per_launch": alg,
+            "achieved_GBs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "coarse_cells_per_s": round(nc / (ms * 1e-3), 1)}
+
+
 def cpu_baseline(seconds_budget: float = 30.0):
     """The FP64 oracle (single thread) on a 128 x 128 x 64 window of the
     default workload's terrain: one stage (update + redistribution)."""
@@ -148,6 +186,8 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-sources", action="store_true",
                     help="skip the leg with the momentum sources (pressure gradient, buoyancy)")
+    ap.add_argument("--no-restrict", action="store_true",
+                    help="skip the leg that restricts the state onto the grid coarsened by 2")
     ap.add_argument("--tile", default=None,
                     help="fixed tile TXxTYxTZxSPAN (SPAN 1: tiles cut from the whole domain; skips the autotuner)")
     ap.add_argument("--no-kernel-timing", action="store_true")
@@ -261,6 +301,8 @@ def main(argv=None):
             leg["k_bulk_frac_of_hbm_peak"] = round(b3 / (a3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         _log(f"sources: {ms3:.3f} ms/step")
         out["with_sources"] = leg
+    if not args.no_restrict:
+        out["restriction"] = restriction_leg(cfg, precision, args.steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
