@@ -257,7 +257,8 @@ ebs_status ebs_set_sources(ebs_ctx* ctx, const ebs_source_params* prm, const dou
  * and face-centred ones with area-fraction weights, which keeps the mass of
  * every coarse cell and the mass flux through every coarse face).  Coarse
  * cell (I, J, K) covers fine cells (2I + a, 2J + b, 2K + c), a, b, c in {0, 1}.
- *   Ufine:   device state of this context (layout of ebs_advance_stage).
+ *   Ufine:   device state of this context (layout of ebs_advance_stage),
+ *            each array aligned to two elements (8 bytes FP32, 16 FP64).
  *   Ucoarse: caller-owned device state of the coarse grid, same precision:
  *            rho, rhotheta (nz/2, ny/2, nx/2), rhou (nz/2, ny/2, nx/2 + 1),
  *            rhov (nz/2, ny/2 + 1, nx/2), rhow (nz/2 + 1, ny/2, nx/2), x
@@ -266,8 +267,9 @@ ebs_status ebs_set_sources(ebs_ctx* ctx, const ebs_source_params* prm, const dou
  * A coarse momentum is the area-weighted mean over the four fine faces on
  * its face; where that face has no open area, the mean weighted by the
  * volume fractions of the four fine staggered CVs; 0 if both vanish.
- * Asynchronous on the context stream.  Errors: EBS_E_ARG (null pointers),
- * EBS_E_ORDER (no geometry), EBS_E_UNSUPPORTED (an odd grid size). */
+ * Asynchronous on the context stream.  Errors: EBS_E_ARG (null or
+ * misaligned pointers), EBS_E_ORDER (no geometry), EBS_E_UNSUPPORTED (an odd
+ * grid size). */
 ebs_status ebs_restrict(ebs_ctx* ctx, const ebs_state* Ufine, ebs_state* Ucoarse);
 
 /* The merged geometry of the coarse grid (Section 3.3): volume fraction of

@@ -523,6 +523,11 @@ ebs_status ebs_restrict(ebs_ctx* c, const ebs_state* Uf, ebs_state* Uc) {
     if (!state_ok(Uf) || !state_ok(Uc)) return fail(c, EBS_E_ARG, "null state pointer");
     if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
     if ((c->nx | c->ny | c->nz) & 1) return fail(c, EBS_E_UNSUPPORTED, "restriction needs even grid sizes");
+    // the fine state is read in pairs of x-neighbours (one 2-element load)
+    const uintptr_t al = c->g.precision == EBS_F32_BULK ? 8 : 16;
+    const void* const fine[5] = {Uf->rho, Uf->rhotheta, Uf->rhou, Uf->rhov, Uf->rhow};
+    for (const void* p : fine)
+        if ((uintptr_t)p % al) return fail(c, EBS_E_ARG, "fine state arrays must be aligned to two elements");
     return launch_restrict(c, Uf, Uc, nullptr);
 }
 

@@ -175,3 +175,16 @@ def test_restrict_errors():
     c.build_geometry(synth.terrain_flat(g, 10.0))
     with pytest.raises(ebs.EbsError):
         c.restrict(U, out=c.new_state())  # odd nz
+
+
+def test_restrict_rejects_misaligned_fine_arrays():
+    """The fine state is read in pairs of x-neighbours: an array that starts
+    one element past an aligned address is rejected before any launch."""
+    w, o = _oracle(1)
+    c = _ctx(w)
+    U = c.new_state(synth.make_state(w))
+    n = U["rho"].numel()
+    big = torch.zeros(n + 1, dtype=U["rho"].dtype, device="cuda")
+    U["rho"] = big[1:].view(U["rho"].shape)
+    with pytest.raises(ebs.EbsError):
+        c.restrict(U)
