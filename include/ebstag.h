@@ -180,8 +180,8 @@ ebs_status ebs_conserved_sums(ebs_ctx* ctx, const ebs_state* U, double hi[5], do
 
 /* Time the candidate tile shapes of the regular-region kernel on this
  * context's grid and keep the fastest; the choice is cached in the JSON file
- * (created if missing, keyed by precision, grid size and box count; NULL = no
- * cache).  Each candidate is timed on the three stages of a step (the first
+ * (created if missing, keyed by precision, grid size, box count and whether
+ * the momentum sources are on; NULL = no cache).  Each candidate is timed on the three stages of a step (the first
  * with U^n = U_cur), regular-region kernel and general passes together.
  * Synchronous; three scratch states are allocated and freed internally
  * (EBS_E_OOM if they do not fit). */
@@ -190,10 +190,10 @@ ebs_status ebs_autotune(ebs_ctx* ctx, const char* cache_json_path);
 /* Tile shape of the regular-region kernel: tx x ty columns per block and at
  * most tz planes per tile.  tx in {16, 32, 64}, ty in {2, 4, 8, 16}, tx*ty in
  * [64, 1024], (tx+5)(ty+5) <= 4 tx ty, LDS rings (26 (tx+5)(ty+5) elements of
- * the state type) within the device's LDS per block, and a compiled shape
- * (16x4, 16x8, 16x16, 32x4, 32x8, 32x16, 64x2, 64x4, 64x8, 64x16; other
- * shapes give EBS_E_UNSUPPORTED at launch); tz in {16, 32, 64}, or 0 to keep the current
- * value.  span = 0: the tiles of every box are cut separately (no tile crosses
+ * the state type, plus 2 (tx+1)(ty+1) with the momentum sources) within the
+ * device's LDS per block, and a compiled shape (16x4, 16x8, 16x16, 32x4, 32x8,
+ * 32x16, 64x2, 64x4, 64x8, 64x16; other shapes give EBS_E_UNSUPPORTED at
+ * launch); tz in {16, 32, 64, 128, 256}, or 0 to keep the current value.  span = 0: the tiles of every box are cut separately (no tile crosses
  * a box boundary); span = 1: the whole domain is tiled as one box (the box
  * list then does not shape the work; results are the same).  EBS_E_ARG
  * otherwise. */

@@ -454,7 +454,8 @@ ebs_status ebs_set_tile(ebs_ctx* c, int32_t tx, int32_t ty, int32_t tz, int32_t 
     if (!(tx == 16 || tx == 32 || tx == 64) || !(ty == 2 || ty == 4 || ty == 8 || ty == 16) ||
         tx * ty < 64 || tx * ty > 1024)
         return fail(c, EBS_E_ARG, "unsupported tile shape");
-    if (!(tz == 0 || tz == 16 || tz == 32 || tz == 64)) return fail(c, EBS_E_ARG, "unsupported tile height");
+    if (!(tz == 0 || tz == 16 || tz == 32 || tz == 64 || tz == 128 || tz == 256))
+        return fail(c, EBS_E_ARG, "unsupported tile height");
     if (span != 0 && span != 1) return fail(c, EBS_E_ARG, "tile span must be 0 or 1");
     if ((tx + 5) * (ty + 5) > 4 * tx * ty)
         return fail(c, EBS_E_ARG, "tile shape has more halo points than the block covers");
@@ -654,7 +655,7 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
         (void)launch_advance(c, &st[0], &st[2], &st[1], 0.0);
     };
     const int cxy[][2] = {{16, 4}, {16, 8}, {16, 16}, {32, 4}, {32, 8}, {32, 16}, {64, 2}, {64, 4}, {64, 8}, {64, 16}};
-    const int cz[] = {16, 32, 64};
+    const int cz[] = {16, 32, 64, 128};
     double best = 1e300;
     int bx = c->tile_x, by = c->tile_y, bz = c->tile_z, bs = c->tile_span;
     const bool was_timing = c->timing;
@@ -662,8 +663,9 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
     hipEvent_t e0, e1;
     EBS_HIP(c, hipEventCreate(&e0));
     EBS_HIP(c, hipEventCreate(&e1));
-    for (int q = 0; q < (int)(sizeof(cxy) / sizeof(cxy[0]) * 6); ++q) {
-        const int cd[4] = {cxy[q / 6][0], cxy[q / 6][1], cz[(q / 2) % 3], q % 2};
+    constexpr int NZ = (int)(sizeof(cz) / sizeof(cz[0]));
+    for (int q = 0; q < (int)(sizeof(cxy) / sizeof(cxy[0])) * NZ * 2; ++q) {
+        const int cd[4] = {cxy[q / (2 * NZ)][0], cxy[q / (2 * NZ)][1], cz[(q / 2) % NZ], q % 2};
         if (ebs_set_tile(c, cd[0], cd[1], cd[2], cd[3]) != EBS_OK) continue;
         three();
         (void)hipEventRecord(e0, c->stream);
