@@ -522,9 +522,10 @@ def test_overlap_gives_identical_bits(precision):
             assert np.array_equal(r[f], res[0][f]), f
 
 @pytest.mark.parametrize("precision,tiles", [
-    (ebs.EBS_F64, ((16, 4), (16, 8), (32, 8, 64, 1), (32, 16, 32, 1))),
+    (ebs.EBS_F64, ((16, 4), (16, 8), (32, 8, 64, 1), (32, 16, 32, 1), (16, 8, 128, 1))),
     (ebs.EBS_F32_BULK, ((16, 4), (16, 16), (32, 8), (64, 2), (32, 8, 64, 1), (64, 4, 16, 1),
-                        (64, 16, 64, 1), (64, 8, 32, 1), (32, 16, 16, 0))),
+                        (64, 16, 64, 1), (64, 8, 32, 1), (32, 16, 16, 0), (64, 16, 128, 1),
+                        (32, 8, 256, 0))),
 ])
 def test_box_list_and_tiles_do_not_change_results(precision, tiles):
     """Uneven AMR-style boxes and different tile shapes give identical bits."""
