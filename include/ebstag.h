@@ -251,7 +251,7 @@ ebs_status ebs_set_sources(ebs_ctx* ctx, const ebs_source_params* prm, const dou
                            const double* rho0);
 
 /* Restriction (averaging down) of a state of this context's grid onto the
- * grid coarsened by 2 in every direction (Section 3.3: static two-level
+ * grid coarsened by 2 in every direction (Section 4.3: static two-level
  * refinement with ratio 2; the coarse geometry is merged from the fine
  * subcells, cell-centred variables are averaged with volume-fraction weights
  * and face-centred ones with area-fraction weights, which keeps the mass of
@@ -272,7 +272,7 @@ ebs_status ebs_set_sources(ebs_ctx* ctx, const ebs_source_params* prm, const dou
  * grid size). */
 ebs_status ebs_restrict(ebs_ctx* ctx, const ebs_state* Ufine, ebs_state* Ucoarse);
 
-/* The merged geometry of the coarse grid (Section 3.3): volume fraction of
+/* The merged geometry of the coarse grid (Section 4.3): volume fraction of
  * every coarse cell (mean of its eight children) and area fractions of its
  * lower x, y, z faces (means of the four fine faces on each); host arrays of
  * (nz/2)(ny/2)(nx/2) doubles each, x fastest.  Synchronous; allocates and

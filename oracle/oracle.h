@@ -102,7 +102,7 @@ typedef struct {
 int orc_sources(const orc_grid* g, double* const geo[4], const double* const U[5], const orc_src* s,
                 const double* rt0, const double* rho0, double* const S[3]);
 
-/* Geometry of the grid coarsened by 2 (Section 3.3, merged subcells):
+/* Geometry of the grid coarsened by 2 (Section 4.3, merged subcells):
  * alpha and the area fractions of the lower x, y, z faces of every coarse
  * cell, (nz/2) x (ny/2) x (nx/2) arrays, x fastest.  1 if a size is odd. */
 int orc_coarsen_geometry(const orc_grid* g, double* const geo[4], double* alpha, double* const beta[3]);

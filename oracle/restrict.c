@@ -1,7 +1,7 @@
 /*
  * Oracle restriction (averaging down) between two levels of a static
  * block-structured hierarchy with refinement ratio 2 (TEST INFRASTRUCTURE
- * ONLY; see oracle.h).  Follows Section 3.3: the geometry of the coarse level
+ * ONLY; see oracle.h).  Follows Section 4.3: the geometry of the coarse level
  * is built from the fine one by merging subcells, so that volume and area
  * fractions are preserved; cell-centred variables are averaged with volume
  * weights (volume fractions), face-centred ones with area weights (area

@@ -1,5 +1,5 @@
 // Restriction (averaging down) of a state onto the grid coarsened by 2, and
-// the merged geometry of that grid (Section 3.3: coarse volume and area
+// the merged geometry of that grid (Section 4.3: coarse volume and area
 // fractions from the fine subcells; cell-centred variables averaged with
 // volume weights, face-centred ones with area weights, so that the mass of
 // every coarse cell and the mass flux through every coarse face are those of

@@ -1,4 +1,4 @@
-"""GPU parity of the two-level restriction (Section 3.3: merged geometry,
+"""GPU parity of the two-level restriction (Section 4.3: merged geometry,
 volume- and area-weighted averaging down) through the C ABI against the
 FP64 oracle.
 

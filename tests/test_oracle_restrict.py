@@ -1,5 +1,5 @@
 """Pins of the oracle restriction between two levels (refinement ratio 2,
-Section 3.3): merged geometry and conservative averaging.  CPU only.
+Section 4.3): merged geometry and conservative averaging.  CPU only.
 
 - terrains that both resolutions represent exactly (flat, tilted plane): the
   merged fine geometry equals the geometry built directly on the coarse grid;
