@@ -204,8 +204,8 @@ def main(argv=None):
         print(json.dumps({"calib_copy_bytes_read": x.numel() * 4, "calib_copy_bytes_written": y.numel() * 4}))
         return 0
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU decomposition is described in the design notes but not built.",
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the decomposition over several GPUs is not implemented.",
               file=sys.stderr)
         return 2
     import torch

@@ -51,7 +51,7 @@ typedef enum {
     EBS_E_OOM = 2,         /* device or host allocation failed               */
     EBS_E_HIP = 3,         /* a HIP runtime call failed                      */
     EBS_E_ORDER = 4,       /* call made before the geometry was built        */
-    EBS_E_UNSUPPORTED = 5  /* valid request outside what this build supports */
+    EBS_E_UNSUPPORTED = 5  /* valid request outside what the library supports */
 } ebs_status;
 
 typedef enum {
