@@ -273,16 +273,20 @@ def _window_state(U, i0, j0, wx, wy):
 
 
 def test_sources_full_size_sampled_windows():
-    """The 512 x 512 x 128 multi-hill configuration (512 boxes, FP32 bulk,
-    64 x 8 x 32 domain tiles, RK3 step in a HIP graph) with the sources, against
-    the oracle on 64 x 64-column windows (24-column margin) around the two
-    highest hills and on flat ground."""
+    """The 512 x 512 x 128 multi-hill configuration (512 boxes, FP32 bulk, the
+    tile the benchmark's source leg uses, RK3 step in a HIP graph) with the
+    sources, against the oracle on 64 x 64-column windows (24-column margin)
+    around the two highest hills and on flat ground."""
+    import json
+    import os
+
     w = synth.make_workload(4)
     n = w.grid.n
     ref = synth.reference_isentropic(w.grid)
     U0 = _f32(synth.state_reference(w.grid, ref, 65))
     c = _ctx(w, ref, precision=ebs.EBS_F32_BULK, boxes=w.boxes)
-    c.set_tile(64, 8, 32, 1)
+    cache = os.path.join(os.path.dirname(ebs.__file__), "tiles_mi355x.json")
+    c.set_tile(*json.load(open(cache))[f"f32bulk_{n[0]}x{n[1]}x{n[2]}_b{len(w.boxes)}_src"])
     U = c.new_state(U0)
     S = [c.new_state(), c.new_state()]
     c.rk3_step(U, S, w.dt, use_graph=True)
