@@ -507,9 +507,13 @@ ebs_status ebs_set_sources(ebs_ctx* c, const ebs_source_params* prm, const doubl
         tf[3 * nz + k] = (float)(1.0 / rt0[k]);
         tf[4 * nz + k] = (float)rho0[k];
     }
-    if (!c->d_srcd) {
-        if (hipMalloc(&c->d_srcd, sizeof(double) * 5 * nz) != hipSuccess) return fail(c, EBS_E_OOM, "source tables");
-        if (hipMalloc(&c->d_srcf, sizeof(float) * 5 * nz) != hipSuccess) return fail(c, EBS_E_OOM, "source tables");
+    if (!c->d_srcd && hipMalloc(&c->d_srcd, sizeof(double) * 5 * nz) != hipSuccess) {
+        c->d_srcd = nullptr;
+        return fail(c, EBS_E_OOM, "source tables");
+    }
+    if (!c->d_srcf && hipMalloc(&c->d_srcf, sizeof(float) * 5 * nz) != hipSuccess) {
+        c->d_srcf = nullptr;
+        return fail(c, EBS_E_OOM, "source tables");
     }
     EBS_HIP(c, hipMemcpy(c->d_srcd, td.data(), sizeof(double) * 5 * nz, hipMemcpyHostToDevice));
     EBS_HIP(c, hipMemcpy(c->d_srcf, tf.data(), sizeof(float) * 5 * nz, hipMemcpyHostToDevice));
