@@ -238,9 +238,11 @@ ebs_status ebs_set_range_rule(ebs_ctx* ctx, int32_t rule);
  *         (kg K / m^3) and density (kg / m^3) at the cell-centre height of
  *         each level (positive, finite); copied, the caller keeps ownership.
  *         The state must keep rho theta > 0 on fluid cells.
- * Errors: EBS_E_ARG for invalid values; EBS_E_UNSUPPORTED with the
- * free-stream EB closure, or when the current tile shape leaves no LDS for
- * the pressure planes (choose another with ebs_set_tile); EBS_E_OOM, EBS_E_HIP. */
+ * Synchronous: waits for the work queued on the context stream before it
+ * replaces the tables.  Errors: EBS_E_ARG for invalid values;
+ * EBS_E_UNSUPPORTED with the free-stream EB closure, or when the current tile
+ * shape leaves no LDS for the pressure planes (choose another with
+ * ebs_set_tile); EBS_E_OOM, EBS_E_HIP. */
 typedef struct {
     double P00;    /* reference pressure of the equation of state, Pa (1e5) */
     double R;      /* gas constant of dry air, J / (kg K) */

@@ -515,6 +515,8 @@ ebs_status ebs_set_sources(ebs_ctx* c, const ebs_source_params* prm, const doubl
         c->d_srcf = nullptr;
         return fail(c, EBS_E_OOM, "source tables");
     }
+    // stages already queued on the context stream may still read the tables
+    EBS_HIP(c, hipStreamSynchronize(c->stream));
     EBS_HIP(c, hipMemcpy(c->d_srcd, td.data(), sizeof(double) * 5 * nz, hipMemcpyHostToDevice));
     EBS_HIP(c, hipMemcpy(c->d_srcf, tf.data(), sizeof(float) * 5 * nz, hipMemcpyHostToDevice));
     c->src = q;
