@@ -38,14 +38,15 @@ RK3_C = (1.0 / 3.0, 0.5, 1.0)
 
 
 def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (plain -O2, no FMA contraction)."""
+    """Compile liboracle.so with gcc (plain -O2, no FMA contraction, OpenMP
+    over the planes of every loop nest)."""
     srcs = [os.path.join(_HERE, s) for s in _SRC]
     if not force and os.path.exists(_SO):
         so_t = os.path.getmtime(_SO)
         if all(os.path.getmtime(s) <= so_t for s in srcs + [os.path.join(_HERE, "oracle.h")]):
             return _SO
     tmp = _SO + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-Wall",
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp", "-Wall",
            "-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _SO)
@@ -78,14 +79,23 @@ def _load():
         lib.orc_advance.argtypes = [P(_Grid), dpp, dpp, dpp, dpp, C.c_double]
         lib.orc_redistribute.argtypes = [P(_Grid), dpp, dpp, dpp, dpp]
         lib.orc_redistribute_sig.argtypes = [P(_Grid), dpp, dpp, dpp, dpp, dpp]
+        lib.orc_redistribute_diag.argtypes = [P(_Grid), dpp, dpp, dpp, dpp, dpp, dpp]
         lib.orc_face_fluxes.argtypes = [P(_Grid), dpp, dpp, C.c_int, dpp, dpp]
         lib.orc_sources.argtypes = [P(_Grid), dpp, dpp, P(_Src), dp, dp, dpp]
         lib.orc_coarsen_geometry.argtypes = [P(_Grid), dpp, dp, dpp]
         lib.orc_restrict.argtypes = [P(_Grid), dpp, dpp, dpp]
         lib.orc_box_moments.argtypes = [P(_Grid), dp, C.c_int, C.c_int, dp, C.c_double,
                                         C.c_double, C.c_int, dp]
+        lib.orc_set_threads.argtypes = [C.c_int]
+        lib.orc_set_threads.restype = C.c_int
         _lib = lib
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's plane loops (n > 0 sets them); returns the
+    count in use.  Results do not depend on it."""
+    return int(_load().orc_set_threads(int(n)))
 
 
 def _dptr(a: np.ndarray):
@@ -234,6 +244,18 @@ class Oracle:
         _load().orc_redistribute_sig(C.byref(self.g), _dpp(self.geo), _dpp(self.w), _dpp(D),
                                      _dpp(out), _dpp(sig))
         return from_dense(out, self.n), sig
+
+    def redistribute_diag(self, Uhat: dict):
+        """Redistribution plus, per field in dense instance storage, the
+        limited gradient sigma (nz+1, ny, nx, 3; physical units) and Q-hat
+        (nz+1, ny, nx) of every CV."""
+        D = to_dense(Uhat, self.n)
+        out = [np.zeros_like(D[0]) for _ in range(5)]
+        sig = [np.zeros(D[0].shape + (3,)) for _ in range(5)]
+        qh = [np.zeros_like(D[0]) for _ in range(5)]
+        _load().orc_redistribute_diag(C.byref(self.g), _dpp(self.geo), _dpp(self.w), _dpp(D),
+                                      _dpp(out), _dpp(sig), _dpp(qh))
+        return from_dense(out, self.n), sig, qh
 
     def advance(self, Un: dict, Ucur: dict, cdt: float, ref=None) -> dict:
         return from_dense(self.advance_dense(to_dense(Un, self.n), to_dense(Ucur, self.n), cdt, ref),

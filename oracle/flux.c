@@ -32,6 +32,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -81,6 +82,7 @@ static const int FIELD_INST[5] = {0, 0, 1, 2, 3};
 /* Diagnostics: theta on cells, velocities on faces (zero where not fluid). */
 static void diagnostics(const FCtx* c, const double* const U[5], double* th, double* vel[3]) {
     const int nx = c->nx, ny = c->ny, nz = c->nz;
+#pragma omp parallel for schedule(static)
     for (int k = 0; k <= nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -237,6 +239,7 @@ int orc_advance(const orc_grid* g, double* const geo[4], const double* const Un[
     const double del[3] = {g->dx[0], g->dx[1], g->dx[2]};
     for (int field = 0; field < 5; ++field) {
         const int inst = FIELD_INST[field];
+#pragma omp parallel for schedule(dynamic, 1)
         for (int k = 0; k <= c.nz; ++k)
             for (int j = 0; j < c.ny; ++j)
                 for (int i = 0; i < c.nx; ++i) {
@@ -302,4 +305,12 @@ int orc_face_fluxes(const orc_grid* g, double* const geo[4], const double* const
     free(th);
     for (int d = 0; d < 3; ++d) free(vel[d]);
     return 0;
+}
+
+/* Threads of the parallel plane loops (n > 0 sets them); returns the number
+ * in use.  Every loop writes only the entries of its own plane, so results
+ * do not depend on the count. */
+int orc_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }

@@ -479,6 +479,8 @@ int orc_geometry(const orc_grid* g, const double* h, double* const geo[4], int8_
         memset(ctype[q], 0, NI);
     }
     (void)node_h;
+    /* every iteration writes only its own entries: planes run in parallel */
+#pragma omp parallel for schedule(dynamic, 1)
     for (int k = 0; k <= nz; ++k) {
         for (int j = 0; j < ny; ++j) {
             for (int i = 0; i < nx; ++i) {

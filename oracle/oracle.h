@@ -82,6 +82,12 @@ int orc_redistribute_sig(const orc_grid* g, double* const geo[4], double* const 
                          const double* const Uhat[5], double* const Uout[5],
                          double* const sig[5]);
 
+/* Same, also returning Q-hat of every CV (Eq. qhat_omega; U-hat where the
+ * neighbourhood is the CV alone): qhat[f] points at (nz+1)*ny*nx doubles. */
+int orc_redistribute_diag(const orc_grid* g, double* const geo[4], double* const w[4],
+                          const double* const Uhat[5], double* const Uout[5], double* const sig[5],
+                          double* const qhat[5]);
+
 /* Raw face fluxes, exposed for the telescoping and polynomial-exactness pins:
  * F[d] receives the flux used in the divergence on the lower d-face of every
  * CV of instance inst for field f (0 rho, 1 rhotheta, 2 rhou, 3 rhov, 4 rhow). */
@@ -117,5 +123,11 @@ int orc_restrict(const orc_grid* g, double* const geo[4], const double* const Uf
  * relative to the box corner. */
 int orc_box_moments(const orc_grid* g, const double* h_nodes, int ci, int cj,
                     const double rect[4], double za, double zb, int bottom, double* out);
+
+/* Threads used by the plane loops of the geometry, stage and redistribution
+ * (n > 0 sets the count; returns the count in use).  Each loop iteration
+ * writes only its own plane's entries, so results are bitwise independent
+ * of the count. */
+int orc_set_threads(int n);
 
 #endif

@@ -150,6 +150,7 @@ int orc_wsrd_setup(const orc_grid* g, double* const geo[4], double* const w[4]) 
     for (int inst = 0; inst < 4; ++inst) {
         memset(w[inst], 0, sizeof(double) * OW_N * c.NI);
         /* small flags and neighbourhoods M */
+#pragma omp parallel for schedule(dynamic, 1)
         for (int k = 0; k <= c.nz; ++k)
             for (int j = 0; j < c.ny; ++j)
                 for (int i = 0; i < c.nx; ++i) {
@@ -164,6 +165,7 @@ int orc_wsrd_setup(const orc_grid* g, double* const geo[4], double* const w[4]) 
                     }
                 }
         /* N = |W| */
+#pragma omp parallel for schedule(dynamic, 1)
         for (int k = 0; k <= c.nz; ++k)
             for (int j = 0; j < c.ny; ++j)
                 for (int i = 0; i < c.nx; ++i) {
@@ -179,6 +181,7 @@ int orc_wsrd_setup(const orc_grid* g, double* const geo[4], double* const w[4]) 
                     WSET(&c, inst, OW_NCOUNT, i, j, k, (double)cnt);
                 }
         /* kappa */
+#pragma omp parallel for schedule(dynamic, 1)
         for (int k = 0; k <= c.nz; ++k)
             for (int j = 0; j < c.ny; ++j)
                 for (int i = 0; i < c.nx; ++i) {
@@ -200,6 +203,7 @@ int orc_wsrd_setup(const orc_grid* g, double* const geo[4], double* const w[4]) 
                     WSET(&c, inst, OW_KAPPA, i, j, k, kap);
                 }
         /* omega, V-hat, x-hat */
+#pragma omp parallel for schedule(dynamic, 1)
         for (int k = 0; k <= c.nz; ++k)
             for (int j = 0; j < c.ny; ++j)
                 for (int i = 0; i < c.nx; ++i) {
@@ -218,6 +222,7 @@ int orc_wsrd_setup(const orc_grid* g, double* const geo[4], double* const w[4]) 
                     const double om = 1.0 - ks / Ni;
                     WSET(&c, inst, OW_OMEGA, i, j, k, om);
                 }
+#pragma omp parallel for schedule(dynamic, 1)
         for (int k = 0; k <= c.nz; ++k)
             for (int j = 0; j < c.ny; ++j)
                 for (int i = 0; i < c.nx; ++i) {
@@ -393,7 +398,7 @@ static void gradient(const WCtx* c, int inst, const double* Qh, int i, int j, in
 
 static int redistribute_impl(const orc_grid* g, double* const geo[4], double* const w[4],
                              const double* const Uhat[5], double* const Uout[5],
-                             double* const sig_out[5]) {
+                             double* const sig_out[5], double* const qhat_out[5]) {
     static const int FI[5] = {0, 0, 1, 2, 3};
     WCtx c = {g, geo, w, 0, g->n[0], g->n[1], g->n[2]};
     c.NI = (size_t)(c.nz + 1) * c.ny * c.nx;
@@ -405,6 +410,7 @@ static int redistribute_impl(const orc_grid* g, double* const geo[4], double* co
         const int inst = FI[f];
         const double* U = Uhat[f];
         /* Q-hat */
+#pragma omp parallel for schedule(dynamic, 1)
         for (int k = 0; k <= c.nz; ++k)
             for (int j = 0; j < c.ny; ++j)
                 for (int i = 0; i < c.nx; ++i) {
@@ -433,6 +439,7 @@ static int redistribute_impl(const orc_grid* g, double* const geo[4], double* co
                     Qh[id] = s / (WQ(&c, inst, OW_VHAT, i, j, k) * dv);
                 }
         /* gradients of small CVs with |M| >= 2 */
+#pragma omp parallel for schedule(dynamic, 1)
         for (int k = 0; k <= c.nz; ++k)
             for (int j = 0; j < c.ny; ++j)
                 for (int i = 0; i < c.nx; ++i) {
@@ -445,6 +452,7 @@ static int redistribute_impl(const orc_grid* g, double* const geo[4], double* co
                     gradient(&c, inst, Qh, i, j, k, &sg[3 * id]);
                 }
         /* final update */
+#pragma omp parallel for schedule(dynamic, 1)
         for (int k = 0; k <= c.nz; ++k)
             for (int j = 0; j < c.ny; ++j)
                 for (int i = 0; i < c.nx; ++i) {
@@ -482,6 +490,7 @@ static int redistribute_impl(const orc_grid* g, double* const geo[4], double* co
                     Uout[f][id] = om * qi + s / Ni;
                 }
         if (sig_out && sig_out[f]) memcpy(sig_out[f], sg, sizeof(double) * 3 * c.NI);
+        if (qhat_out && qhat_out[f]) memcpy(qhat_out[f], Qh, sizeof(double) * c.NI);
     }
     free(Qh);
     free(sg);
@@ -490,11 +499,17 @@ static int redistribute_impl(const orc_grid* g, double* const geo[4], double* co
 
 int orc_redistribute(const orc_grid* g, double* const geo[4], double* const w[4],
                      const double* const Uhat[5], double* const Uout[5]) {
-    return redistribute_impl(g, geo, w, Uhat, Uout, NULL);
+    return redistribute_impl(g, geo, w, Uhat, Uout, NULL, NULL);
 }
 
 int orc_redistribute_sig(const orc_grid* g, double* const geo[4], double* const w[4],
                          const double* const Uhat[5], double* const Uout[5],
                          double* const sig[5]) {
-    return redistribute_impl(g, geo, w, Uhat, Uout, sig);
+    return redistribute_impl(g, geo, w, Uhat, Uout, sig, NULL);
+}
+
+int orc_redistribute_diag(const orc_grid* g, double* const geo[4], double* const w[4],
+                          const double* const Uhat[5], double* const Uout[5], double* const sig[5],
+                          double* const qhat[5]) {
+    return redistribute_impl(g, geo, w, Uhat, Uout, sig, qhat);
 }
