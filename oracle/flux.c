@@ -12,8 +12,9 @@
  * The source term is zero (Section 3.1).
  *
  * Readings where the paper is silent (each also listed in the design notes):
- *  - the mass flux that advects a momentum on a staggered face is the plain
- *    average of the two stored face momenta next to it;
+ *  - the mass flux that advects a momentum on a staggered face is the mean
+ *    of the two stored face momenta next to it over those whose control
+ *    volume holds fluid (one such: its value);
  *  - face velocities are the face momentum divided by the mean density of the
  *    fluid cells on either side; theta = (rho theta) / rho;
  *  - the "upstream cell" is the far end of the upwind three-point stencil; it
@@ -133,14 +134,20 @@ static double mass_flux(const Diag* D, int inst, int d, int i, int j, int k) {
     const double* mom = D->U[2 + d];
     const int minst = d + 1; /* instance on which the d-momentum lives */
     if (inst == 0) return sval(c, mom, minst, i, j, k);
-    /* staggered instances: average of the two face momenta adjacent to the
-     * face, offset by one cell in the instance's own direction */
+    /* staggered instances: the face is made of two halves, one in each of the
+     * two face momenta adjacent to it (offset by one cell in the instance's
+     * own direction); the mass flux is the mean of those momenta over the
+     * ones whose CV holds fluid (the half of a covered one is closed, and the
+     * area fraction already accounts for it) */
     const int s = inst - 1;
     int i0 = i, j0 = j, k0 = k;
     if (s == 0) i0 = i - 1;
     if (s == 1) j0 = j - 1;
     if (s == 2) k0 = k - 1;
-    return 0.5 * (sval(c, mom, minst, i0, j0, k0) + sval(c, mom, minst, i, j, k));
+    const int fa = alpha(c, minst, i0, j0, k0) > 0.0, fb = alpha(c, minst, i, j, k) > 0.0;
+    const double sum = sval(c, mom, minst, i0, j0, k0) + sval(c, mom, minst, i, j, k);
+    if (fa && fb) return 0.5 * sum;
+    return sum; /* one fluid CV: its momentum; none: 0 */
 }
 
 /* provisional flux on the lower d-face of CV p=(i,j,k) of the field's instance */

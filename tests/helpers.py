@@ -100,3 +100,94 @@ def sample_vface(h_nodes, grid, d, f, s0, s1, z0, z1, M=4096):
     else:
         h, _, _ = interp_h(h_nodes, grid, s, np.full(M, f))
     return float((z1 - np.clip(h, z0, z1)).mean() / (z1 - z0))
+
+
+def clip_polygon(poly, a, b, c):
+    """Part of a convex polygon [(u, v), ...] where a u + b v + c >= 0
+    (one Sutherland-Hodgman pass)."""
+    out = []
+    n = len(poly)
+    for q in range(n):
+        P, Q = poly[q], poly[(q + 1) % n]
+        fp = a * P[0] + b * P[1] + c
+        fq = a * Q[0] + b * Q[1] + c
+        if fp >= 0:
+            out.append(P)
+        if (fp >= 0) != (fq >= 0):
+            t = fp / (fp - fq)
+            out.append((P[0] + t * (Q[0] - P[0]), P[1] + t * (Q[1] - P[1])))
+    return out
+
+
+def polygon_area_centroid(poly):
+    """Area and centroid of a simple polygon by the shoelace formula
+    (0, (0, 0) for fewer than three vertices or zero area)."""
+    if len(poly) < 3:
+        return 0.0, (0.0, 0.0)
+    A = cx = cy = 0.0
+    n = len(poly)
+    for q in range(n):
+        x0, y0 = poly[q]
+        x1, y1 = poly[(q + 1) % n]
+        cr = x0 * y1 - x1 * y0
+        A += cr
+        cx += (x0 + x1) * cr
+        cy += (y0 + y1) * cr
+    A *= 0.5
+    if A == 0.0:
+        return 0.0, (0.0, 0.0)
+    return abs(A), (cx / (6 * A), cy / (6 * A))
+
+
+def rect(u0, u1, v0, v1):
+    return [(u0, v0), (u1, v0), (u1, v1), (u0, v1)]
+
+
+def sample_vface_moments(h_nodes, grid, d, f, s0, s1, z0, z1, M=8192):
+    """Fluid fraction and centroid (s, z) of the vertical face {x = f}
+    (d = 0) or {y = f} (d = 1), s in [s0, s1], z in [z0, z1]: 1-D midpoint
+    rule in s with the z extent of the fluid (z > h) integrated exactly."""
+    s = s0 + (np.arange(M) + 0.5) * (s1 - s0) / M
+    if d == 0:
+        h, _, _ = interp_h(h_nodes, grid, np.full(M, f), s)
+    else:
+        h, _, _ = interp_h(h_nodes, grid, s, np.full(M, f))
+    zc = np.clip(h, z0, z1)
+    L = z1 - zc
+    tot = L.sum()
+    frac = float(tot / M / (z1 - z0))
+    if tot <= 0:
+        return frac, (0.0, 0.0)
+    return frac, (float((s * L).sum() / tot), float((0.5 * (z1 * z1 - zc * zc)).sum() / tot))
+
+
+def sample_zface_moments(h_nodes, grid, zf, x0, x1, y0, y1, M=512):
+    """Fluid fraction and centroid (x, y) of the horizontal face {z = zf}
+    over [x0, x1] x [y0, y1] (fluid where h < zf), 2-D midpoint rule."""
+    xs = x0 + (np.arange(M) + 0.5) * (x1 - x0) / M
+    ys = y0 + (np.arange(M) + 0.5) * (y1 - y0) / M
+    X, Y = np.meshgrid(xs, ys)
+    h, _, _ = interp_h(h_nodes, grid, X, Y)
+    fl = h < zf
+    n = fl.sum()
+    if n == 0:
+        return 0.0, (0.0, 0.0)
+    return float(n / (M * M)), (float(X[fl].mean()), float(Y[fl].mean()))
+
+
+def sample_facet(h_nodes, grid, box, M=400):
+    """EB facet inside a box by a 2-D midpoint rule over the box's xy
+    rectangle: true area and area-weighted centroid (x, y, h) of the part of
+    the terrain surface with z0 <= h < z1."""
+    x0, x1, y0, y1, z0, z1 = box
+    xs = x0 + (np.arange(M) + 0.5) * (x1 - x0) / M
+    ys = y0 + (np.arange(M) + 0.5) * (y1 - y0) / M
+    X, Y = np.meshgrid(xs, ys)
+    h, gx, gy = interp_h(h_nodes, grid, X, Y)
+    inside = (h >= z0) & (h < z1)
+    w = np.sqrt(1.0 + gx * gx + gy * gy) * inside
+    dA = (x1 - x0) * (y1 - y0) / (M * M)
+    A = w.sum() * dA
+    if A <= 0:
+        return 0.0, np.zeros(3)
+    return float(A), np.array([(X * w).sum(), (Y * w).sum(), (h * w).sum()]) * dA / A

@@ -5,7 +5,8 @@ import pytest
 
 import oracle
 import synth
-from tests.helpers import halfspace_box_volume, sample_cv, sample_vface
+from tests.helpers import (halfspace_box_volume, sample_cv, sample_facet, sample_vface,
+                           sample_vface_moments, sample_zface_moments)
 
 OQ = oracle.OQ
 
@@ -242,3 +243,62 @@ def test_mirror_symmetry():
     assert np.allclose(Gu[OQ["ALPHA"]], T(Gv[OQ["ALPHA"]]), rtol=0, atol=1e-14)
     assert np.allclose(Gu[OQ["BZ"]], T(Gv[OQ["BZ"]]), rtol=0, atol=1e-14)
     assert np.array_equal(o.ctype[1], T(o.ctype[2]))
+
+
+def test_brute_force_face_centroids_and_facets_all_instances():
+    """Face centroid offsets (FX1 .. FZ2), EB facet area and EB centroid of
+    every CV of all four instances on the bump terrain (facets of two
+    different slopes per xy-cell) against brute-force sampling of the
+    definitions; offsets compared as moments (fraction x offset).  Catches
+    swapped or mis-signed offsets, offsets from the wrong face centre and a
+    staggered face or facet assembled from the wrong halves."""
+    g = synth.Grid((6, 6, 4), (1.0, 1.0, 0.5))
+    x, y = synth.node_coords(g)
+    X, Y = np.meshgrid(x, y)
+    h = 0.2 + 1.1 * np.exp(-((X - 3.1) ** 2 + (Y - 2.7) ** 2) / 2.0) + 0.05 * np.sin(X + 2 * Y)
+    h = synth._periodic_fix(h)
+    o = oracle.Oracle(g, h)
+    nx, ny, nz = g.n
+    dx = np.array(g.dx)
+    worst = np.zeros(3)
+    cut_faces = 0
+    for inst in range(4):
+        G = o.geo[inst]
+        for k in range(nz + 1):
+            if inst == 3 and not (1 <= k <= nz - 1):
+                continue
+            if inst != 3 and k == nz:
+                continue
+            for j in range(ny):
+                for i in range(nx):
+                    if (inst == 1 and i == 0) or (inst == 2 and j == 0):
+                        continue
+                    box = cv_box(g, inst, i, j, k)
+                    ctr = np.array([(box[0] + box[1]) / 2, (box[2] + box[3]) / 2, (box[4] + box[5]) / 2])
+                    # vertical lower faces
+                    for d, (e1, e2) in ((0, (1, 2)), (1, (0, 2))):
+                        lo_s, hi_s = (box[2], box[3]) if d == 0 else (box[0], box[1])
+                        b, (cs, cz) = sample_vface_moments(h, g, d, box[2 * d], lo_s, hi_s, box[4], box[5])
+                        q = OQ["FX1"] + 2 * d
+                        e_s = abs(b * (cs - ctr[e1]) / dx[e1] - G[OQ["BX"] + d, k, j, i] * G[q, k, j, i])
+                        e_z = abs(b * (cz - ctr[2]) / dx[2] - G[OQ["BX"] + d, k, j, i] * G[q + 1, k, j, i])
+                        worst[0] = max(worst[0], e_s, e_z)
+                        assert e_s < 1e-7 and e_z < 1e-7, (inst, d, i, j, k, e_s, e_z)
+                        cut_faces += 0.01 < b < 0.99
+                    # horizontal lower face
+                    b, (cx, cy) = sample_zface_moments(h, g, box[4], box[0], box[1], box[2], box[3])
+                    e_x = abs(b * (cx - ctr[0]) / dx[0] - G[OQ["BZ"], k, j, i] * G[OQ["FZ1"], k, j, i])
+                    e_y = abs(b * (cy - ctr[1]) / dx[1] - G[OQ["BZ"], k, j, i] * G[OQ["FZ2"], k, j, i])
+                    worst[1] = max(worst[1], e_x, e_y)
+                    assert e_x < 2e-4 and e_y < 2e-4, (inst, i, j, k, e_x, e_y)
+                    # EB facet: area and centroid
+                    A, c = sample_facet(h, g, box)
+                    a_or = G[OQ["AREA"], k, j, i] * dx[0] * dx[1]
+                    assert abs(A - a_or) < 2e-3 * dx[0] * dx[1], (inst, i, j, k, A, a_or)
+                    if A > 0.05 * dx[0] * dx[1]:
+                        ebc = np.array([G[OQ["EBX"] + q, k, j, i] for q in range(3)])
+                        err = np.abs(a_or * ebc - A * (c - ctr) / dx).max()
+                        worst[2] = max(worst[2], err)
+                        assert err < 1e-3, (inst, i, j, k, err)
+    assert cut_faces > 100
+    print("worst face-centroid moment errors (vertical, horizontal, facet)", worst)
