@@ -70,29 +70,38 @@ def run_workload(cfg: int, precision: int, steps: int, warmup: int, use_graph: b
     U = ctx.new_state(synth.state_reference(w.grid, ref, 1000 + w.seed) if sources else synth.make_state(w))
     S = [ctx.new_state(), ctx.new_state()]
     stream = torch.cuda.current_stream()
+    sums0 = ctx.conserved_sums(U)
     for _ in range(warmup):
         ctx.rk3_step(U, S, w.dt, use_graph=use_graph)
     torch.cuda.synchronize()
     if timing:
         ctx.timing(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    # one event before the first step and after every step, all on the
+    # stream the steps run on
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
-    ev0.record(stream)
+    evs[0].record(stream)
     t_wall = time.perf_counter()
-    for _ in range(steps):
+    for q in range(steps):
         ctx.rk3_step(U, S, w.dt, use_graph=use_graph)
-    ev1.record(stream)
+        evs[q + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
-    ms = ev0.elapsed_time(ev1)
+    ms = evs[0].elapsed_time(evs[-1])
+    per_step = sorted(evs[q].elapsed_time(evs[q + 1]) for q in range(steps))
+    median = per_step[steps // 2] if steps % 2 else 0.5 * (per_step[steps // 2 - 1] + per_step[steps // 2])
     kern = None
     if timing:
         kms, nl = ctx.timing_read()
         ctx.timing(False)
         kern = (kms, nl)
-    res = dict(workload=w, ctx=ctx, ms=ms, wall=wall, kern=kern, tile=tile,
-               stats=ctx.stats(), alg=ctx.algorithmic_bytes())
+    sums1 = ctx.conserved_sums(U)
+    drift = []
+    for f in range(5):
+        a, b = sums0[0][f] + sums0[1][f], sums1[0][f] + sums1[1][f]
+        drift.append(abs(b - a) / abs(a) if a != 0.0 else abs(b - a))
+    res = dict(workload=w, ctx=ctx, ms=ms, median_ms=median, wall=wall, kern=kern, tile=tile,
+               stats=ctx.stats(), alg=ctx.algorithmic_bytes(), drift=drift, stages=3 * (warmup + steps))
     return res
 
 
@@ -153,24 +162,145 @@ def restriction_leg(cfg: int, precision: int, launches: int):
             "coarse_cells_per_s": round(nc / (ms * 1e-3), 1)}
 
 
-def cpu_baseline(seconds_budget: float = 30.0):
-    """The FP64 oracle (single thread) on a 128 x 128 x 64 window of the
-    default workload's terrain: one stage (update + redistribution)."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return os.uname().machine
+
+
+def _host_threads():
+    """Threads the host share of the GPU machine allows (16 per GPU there), at
+    most the logical cores present."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline():
+    """The FP64 oracle on a 128 x 128 x 64 window of the default workload's
+    terrain: one stage (update + redistribution), on one thread and on all
+    the host threads of the box (its loops over planes run in parallel, with
+    bitwise the same results)."""
     import oracle
     import synth
 
     w = synth.window(synth.make_workload(4), 96, 160, 128, 128, 64)
-    o = oracle.Oracle(w.grid, w.h_nodes)
     U = synth.make_state(w)
-    t0 = time.perf_counter()
-    o.stage(U, U, w.dt / 3)
-    dt = time.perf_counter() - t0
     cells = w.grid.ncells
-    return {"value": cells / dt / 1e6, "unit": "Mcell-updates/s", "cores": 1, "kind": "oracle",
+    rates = {}
+    for th in (1, _host_threads()):
+        oracle.set_threads(th)
+        o = oracle.Oracle(w.grid, w.h_nodes)
+        t0 = time.perf_counter()
+        o.stage(U, U, w.dt / 3)
+        rates[th] = (cells / (time.perf_counter() - t0) / 1e6, time.perf_counter() - t0)
+    nmax = max(rates)
+    return {"value": round(rates[nmax][0], 3), "unit": "Mcell-updates/s", "cores": nmax, "kind": "oracle",
+            "value_1_thread": round(rates[1][0], 3),
+            "cpu_model": _cpu_model(),
             "sample": f"one RK stage (flux update + redistribution) of a {w.grid.n[0]}x{w.grid.n[1]}x"
                       f"{w.grid.n[2]} window of the 512x512x128 multi-hill terrain, FP64, "
-                      f"{dt:.2f}s, host {os.uname().machine}, "
-                      f"{os.cpu_count()} logical cores available"}
+                      f"{rates[nmax][1]:.2f}s on {nmax} threads, {rates[1][1]:.2f}s on 1, "
+                      f"{os.cpu_count()} logical cores present"}
+
+
+def copy_reference(gib: float = 2.0, launches: int = 20):
+    """HBM rate of the library's plain streaming copy kernel (bytes read plus
+    bytes written per second), timed with HIP events on the current stream."""
+    import torch
+
+    import paper_2604_11959_amd as ebs
+
+    n = int(gib * (1 << 30)) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        ebs.stream_copy(y, x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(launches):
+        ebs.stream_copy(y, x)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / launches
+    assert torch.equal(x[:1024], y[:1024])
+    gbs = 2 * n * 4 / (ms * 1e-3) / 1e9
+    del x, y
+    return {"kernel": "k_copy (ebs_stream_copy, 16-byte streaming loads and stores)",
+            "bytes_per_launch": 2 * n * 4, "avg_launch_ms": round(ms, 4), "GBs": round(gbs, 1),
+            "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def parity_leg(cfg: int, precision: int, tile):
+    """One RK3 step of the benchmark configuration (same tile, graph) from
+    its initial state against the FP64 oracle on a 64 x 64-column window
+    around the highest hill (the oracle runs on the window plus a 24-column
+    margin, the reach of three stages): per-field error (max |difference|
+    over fluid entries / field scale, one joint scale for the momenta)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2604_11959_amd as ebs
+    import synth
+
+    w = synth.make_workload(cfg)
+    n = w.grid.n
+    ctx = ebs.Context(n, w.grid.dx, w.grid.lo, boxes=w.boxes, precision=precision)
+    ctx.build_geometry(w.h_nodes)
+    ctx.set_tile(*tile)
+    U0 = synth.make_state(w)
+    U = ctx.new_state(U0)
+    S = [ctx.new_state(), ctx.new_state()]
+    ctx.rk3_step(U, S, w.dt, use_graph=True)
+    torch.cuda.synchronize()
+    inner, m = 64, 24
+    wx = inner + 2 * m
+    jj, ii = np.unravel_index(np.argmax(w.h_nodes[:-1, :-1]), (n[1], n[0]))
+    i0 = int(min(max(ii - wx // 2, 0), n[0] - wx - 1))
+    j0 = int(min(max(jj - wx // 2, 0), n[1] - wx - 1))
+
+    def win(V):
+        W = {"rho": V["rho"][:, j0:j0 + wx, i0:i0 + wx], "rhotheta": V["rhotheta"][:, j0:j0 + wx, i0:i0 + wx],
+             "rhou": V["rhou"][:, j0:j0 + wx, i0:i0 + wx + 1], "rhov": V["rhov"][:, j0:j0 + wx + 1, i0:i0 + wx],
+             "rhow": V["rhow"][:, j0:j0 + wx, i0:i0 + wx]}
+        W = {k: (v.double().cpu().numpy() if hasattr(v, "cpu") else np.array(v, dtype=np.float64))
+             for k, v in W.items()}
+        W["rhou"][:, :, -1] = W["rhou"][:, :, 0]
+        W["rhov"][:, -1, :] = W["rhov"][:, 0, :]
+        return W
+
+    got = win(U)
+    del U, S
+    ctx.close()
+    oracle.set_threads(_host_threads())
+    ww = synth.window(w, i0, j0, wx, wx, n[2])
+    o = oracle.Oracle(ww.grid, ww.h_nodes)
+    ref = o.rk3_step(win(U0), w.dt)
+    masks = {}
+    for f, inst in zip(ebs.FIELDS, oracle.FIELD_INST):
+        a = o.export(inst, oracle.OQ["ALPHA"]) > 0
+        if f == "rhow":
+            a[0] = a[-1] = False
+        keep = np.zeros_like(a)
+        keep[:, m:m + inner, m:m + inner] = True
+        masks[f] = a & keep
+    mom = max(np.abs(ref[f][masks[f]]).max() for f in ("rhou", "rhov", "rhow"))
+    err = {}
+    for f in ebs.FIELDS:
+        sc = np.abs(ref[f][masks[f]]).max() if f in ("rho", "rhotheta") else mom
+        err[f] = float(np.abs(got[f] - ref[f])[masks[f]].max() / (sc if sc > 0 else 1.0))
+    return {"check": "one RK3 step vs the FP64 oracle on a 64x64-column window (highest hill)",
+            "window_origin": [i0 + m, j0 + m], "per_field_error": err, "bar": 2e-5}
 
 
 def main(argv=None):
@@ -183,6 +313,7 @@ def main(argv=None):
     ap.add_argument("--overlap", action="store_true",
                     help="run the regular-region kernel concurrently with the general range")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-parity", action="store_true", help="skip the window check against the oracle")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-sources", action="store_true",
                     help="skip the leg with the momentum sources (pressure gradient, buoyancy)")
@@ -222,7 +353,9 @@ def main(argv=None):
     N = w.grid.ncells
     ms_step = main["ms"] / args.steps
     value = N * 3 / (ms_step * 1e-3) / 1e6
-    _log(f"main: {ms_step:.3f} ms/step, {value:.0f} Mcell-upd/s")
+    _log(f"main: {ms_step:.3f} ms/step (median {main['median_ms']:.3f}), {value:.0f} Mcell-upd/s")
+    copy = copy_reference()
+    _log(f"copy reference: {copy['GBs']:.0f} GB/s")
     # dominant kernel timed with HIP events on the context stream (direct launches)
     if args.no_kernel_timing:
         kt = main
@@ -243,6 +376,8 @@ def main(argv=None):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "median_ms_per_step": round(main["median_ms"], 4),
+        "value_from_median": round(N * 3 / (main["median_ms"] * 1e-3) / 1e6, 1),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -269,11 +404,22 @@ def main(argv=None):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "frac_of_copy": round(achieved / copy["GBs"], 4),
             "traffic": measured_traffic(main["tile"], w.name, bytes_per_launch),
             "avg_launch_ms": round(avg_ms, 4),
             "alg_bytes_per_launch": bytes_per_launch,
         },
     }
+    out["copy_reference"] = copy
+    out["conservation"] = {
+        "check": "relative change of sum V U per field (rho, rho theta, rho u, rho v, rho w) over the "
+                 f"{main['stages']} stages of the warm-up and timed steps (double-double sums)",
+        "drift": [float(f"{d:.3e}") for d in main["drift"]],
+        "bound_note": "FP32 storage rounds every CV value by up to 2^-24 per stage" if precision == ebs.EBS_F32_BULK
+        else "FP64 path: <= 1e-13 per stage"}
+    if not args.no_parity:
+        out["parity"] = parity_leg(cfg, precision, main["tile"])
+        _log(f"parity: {out['parity']['per_field_error']}")
     if not args.no_fp64 and cfg != 2:
         r2 = run_workload(2, ebs.EBS_F64, args.steps, args.warmup, not args.no_graph, True, False)
         ms2 = r2["ms"] / args.steps

@@ -50,7 +50,7 @@ typedef enum {
     EBS_E_ARG = 1,         /* invalid argument; nothing was written          */
     EBS_E_OOM = 2,         /* device or host allocation failed               */
     EBS_E_HIP = 3,         /* a HIP runtime call failed                      */
-    EBS_E_ORDER = 4,       /* call made before the geometry was built        */
+    EBS_E_ORDER = 4,       /* call out of order (e.g. before the geometry)   */
     EBS_E_UNSUPPORTED = 5  /* valid request outside what the library supports */
 } ebs_status;
 
@@ -142,7 +142,12 @@ ebs_status ebs_create(const ebs_grid* grid, const ebs_box* boxes, int32_t nbox, 
  * Synchronous.  Errors: EBS_E_ARG (non-finite heights, non-periodic node rows,
  * terrain reaching the top cell layer), EBS_E_OOM (device tables),
  * EBS_E_UNSUPPORTED (general range or its tables beyond the sizes the
- * tables index: 2^28 general cells and stencil positions), EBS_E_HIP. */
+ * tables index: 2^28 general cells and stencil positions), EBS_E_HIP.
+ * Calling it again on a context that has geometry rebuilds everything: it
+ * first waits for the work queued on the context and drops the captured
+ * RK3 graph.  EBS_E_ARG leaves the previous geometry in place; any later
+ * error leaves the context without geometry (every stage call then returns
+ * EBS_E_ORDER until a build succeeds). */
 ebs_status ebs_build_geometry_terrain(ebs_ctx* ctx, const double* h_nodes, int32_t on_device);
 
 /* Copy one quantity (EBS_Q_*) of instance inst (0 cell, 1 x-face, 2 y-face,
@@ -154,37 +159,65 @@ ebs_status ebs_geometry_export(ebs_ctx* ctx, int32_t inst, int32_t qty, double* 
  * regular} -> out[4*8].  Synchronous. */
 ebs_status ebs_geometry_stats(ebs_ctx* ctx, int64_t* out);
 
-/* Algorithm 1 steps (1)-(3) for one stage, all four instances:
- * Uhat = Un + cdt * dU(Ucur).  Un and Ucur may be the same state; Uhat must not
- * alias Ucur (the stencil reads neighbours) but may alias Un.  Asynchronous. */
+/* Histogram of the volume fractions of the fluid CVs (alpha > 0) of
+ * instance inst (0 cell, 1 x-face, 2 y-face, 3 z-face): counts[b] = number
+ * of fluid CVs with edges[b] <= alpha < edges[b+1] (the last bin also takes
+ * alpha == edges[nbins]); fractions outside [edges[0], edges[nbins]] are not
+ * counted.  edges has nbins + 1 increasing values.  Reports how many small
+ * and sliver CVs (Section 5.1) a terrain produces.  Synchronous.  Errors:
+ * EBS_E_ARG, EBS_E_ORDER. */
+ebs_status ebs_alpha_histogram(ebs_ctx* ctx, int32_t inst, const double* edges, int32_t nbins, int64_t* counts);
+
+/* Algorithm 1 steps (1)-(3) for one stage (Section 5.2), all four
+ * instances: Uhat = Un + cdt * dU(Ucur), dU by Eqs. update-cc / update-fc
+ * (Section 3.1) with the advective fluxes of Section 4.1.  Un and Ucur may be
+ * the same state.  No array of Uhat may overlap any array of Ucur (the
+ * stencil reads neighbours while other threads write Uhat), the five Uhat
+ * arrays must be disjoint, and Uhat may coincide with Un field by field
+ * (Uhat->rho == Un->rho, ...) but not overlap it otherwise; EBS_E_ARG if
+ * not.  Asynchronous. */
 ebs_status ebs_advance_stage(ebs_ctx* ctx, const ebs_state* Un, const ebs_state* Ucur,
                              ebs_state* Uhat, double cdt);
 
-/* Algorithm 1 step (4): Uout = R(Uhat) field by field.  Uhat must be the
- * output of the last ebs_advance_stage of this context (the cut region is
- * read from the context's double-precision copy).  Uout may alias Uhat.
+/* Algorithm 1 step (4): Uout = R(Uhat) field by field, the weighted state
+ * redistribution of Section 5.1 (Eqs. qhat_omega, qrecon,
+ * final_update_omega).  Uhat must be the output state of the last
+ * ebs_advance_stage of this context (the cut region is read from the
+ * double-precision copy that advance kept); EBS_E_ORDER if it is another
+ * state, or if no advance ran since the geometry was built or since an
+ * ebs_rk3_step / ebs_autotune overwrote that copy.  Uout may coincide with
+ * Uhat field by field but not overlap it otherwise (EBS_E_ARG).
  * Asynchronous. */
 ebs_status ebs_redistribute(ebs_ctx* ctx, const ebs_state* Uhat, ebs_state* Uout);
 
-/* One low-storage three-stage Runge-Kutta step (stage coefficients 1/3, 1/2,
- * 1, each stage from U^n, redistribution after every stage).  U is updated in
+/* One time step of Algorithm 1 (Section 5.2): the low-storage three-stage
+ * Runge-Kutta scheme the paper names (its coefficients are not printed;
+ * read as U^s = R(U^n + c_s dt dU(U^(s-1))) with c = 1/3, 1/2, 1), the
+ * redistribution R of Section 5.1 after every stage.  U is updated in
  * place; scratch points at two states of the same layout used as stage
- * buffers.  use_graph != 0 captures the step in a HIP graph on first use and
- * replays it while the pointers and dt stay the same.  Asynchronous. */
+ * buffers; U and the two scratch states must be disjoint (EBS_E_ARG).
+ * use_graph != 0 captures the step in a HIP graph on first use and replays
+ * it while the pointers and dt stay the same.  Asynchronous. */
 ebs_status ebs_rk3_step(ebs_ctx* ctx, ebs_state* U, ebs_state* scratch, double dt,
                         int32_t use_graph);
 
 /* Sum of V * U over the fluid CVs of each field (rho, rhotheta, rhou, rhov,
- * rhow), as unevaluated double-double pairs hi + lo.  Synchronous. */
+ * rhow), as unevaluated double-double pairs hi + lo.  These are the totals
+ * the method conserves: the update of Section 3.1 is conservative by
+ * construction (every face flux enters two CVs with opposite signs, no
+ * flux crosses walls) and the redistribution of Section 5.1 conserves them
+ * as well.  Synchronous. */
 ebs_status ebs_conserved_sums(ebs_ctx* ctx, const ebs_state* U, double hi[5], double lo[5]);
 
 /* Time the candidate tile shapes of the regular-region kernel on this
  * context's grid and keep the fastest; the choice is cached in the JSON file
  * (created if missing, keyed by precision, grid size, box count and whether
- * the momentum sources are on; NULL = no cache).  Each candidate is timed on the three stages of a step (the first
- * with U^n = U_cur), regular-region kernel and general passes together.
- * Synchronous; three scratch states are allocated and freed internally
- * (EBS_E_OOM if they do not fit). */
+ * the momentum sources are on; NULL = no cache).  The candidates are the
+ * compiled shapes listed at ebs_set_tile, heights 16 to 256 (heights at or
+ * above nz once) and both spans.  Each candidate is timed on the three
+ * stages of a step (the first with U^n = U_cur), regular-region kernel and
+ * general passes together.  Synchronous; three scratch states are allocated
+ * and freed internally (EBS_E_OOM if they do not fit). */
 ebs_status ebs_autotune(ebs_ctx* ctx, const char* cache_json_path);
 
 /* Tile shape of the regular-region kernel: tx x ty columns per block and at
@@ -281,6 +314,7 @@ ebs_status ebs_restrict(ebs_ctx* ctx, const ebs_state* Ufine, ebs_state* Ucoarse
  * frees a device buffer.  Errors as ebs_restrict, EBS_E_OOM, EBS_E_HIP. */
 ebs_status ebs_coarsened_geometry(ebs_ctx* ctx, double* alpha, double* beta_x, double* beta_y, double* beta_z);
 
+
 /* Kernel timing: when enabled, every launch of the regular-region stage
  * kernel is bracketed by HIP events on the context stream; read returns the
  * summed duration (ms) and launch count since the last reset and resets. */
@@ -291,6 +325,15 @@ ebs_status ebs_timing_read(ebs_ctx* ctx, double* ms_total, int64_t* launches);
  * (reads of Un and Ucur, one write, over the regular-region CVs), for roofline
  * accounting: out[0] = first-stage form (Un == Ucur), out[1] = later stages. */
 ebs_status ebs_algorithmic_bytes(const ebs_ctx* ctx, double out[2]);
+
+/* Measurement reference: copy `bytes` from src to dst (device pointers,
+ * 16-byte aligned, bytes a multiple of 16, not overlapping) with a plain
+ * streaming kernel, asynchronously on hip_stream (a hipStream_t, NULL = the
+ * null stream).  Timed by the caller, it gives the HBM rate a streaming
+ * kernel reaches on the device, against which the roofline fractions of the
+ * method's kernels are also reported.  Errors: EBS_E_ARG (null, misaligned
+ * or overlapping), EBS_E_UNSUPPORTED (beyond 2^31 blocks), EBS_E_HIP. */
+ebs_status ebs_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
 
 /* Static message describing the last error of the context (never NULL). */
 const char* ebs_last_error(const ebs_ctx* ctx);

@@ -27,10 +27,10 @@ Q = dict(ALPHA=0, BETA_X=1, BETA_Y=2, BETA_Z=3, FX_Y=4, FX_Z=5, FY_X=6, FY_Z=7, 
          XHAT_X=28, XHAT_Y=29, XHAT_Z=30)
 
 # every entry point declared in include/ebstag.h
-SYMBOLS = ("ebs_create", "ebs_build_geometry_terrain", "ebs_geometry_export", "ebs_geometry_stats",
+SYMBOLS = ("ebs_create", "ebs_build_geometry_terrain", "ebs_geometry_export", "ebs_geometry_stats", "ebs_alpha_histogram",
            "ebs_advance_stage", "ebs_redistribute", "ebs_rk3_step", "ebs_conserved_sums",
            "ebs_autotune", "ebs_set_tile", "ebs_get_tile", "ebs_set_overlap", "ebs_set_range_rule", "ebs_set_sources", "ebs_restrict", "ebs_coarsened_geometry", "ebs_timing_enable", "ebs_timing_read",
-           "ebs_algorithmic_bytes", "ebs_last_error", "ebs_destroy")
+           "ebs_algorithmic_bytes", "ebs_stream_copy", "ebs_last_error", "ebs_destroy")
 
 
 class EbsError(RuntimeError):
@@ -75,6 +75,7 @@ def load(path: str = LIB_PATH):
         "ebs_build_geometry_terrain": [C.c_void_p, P(C.c_double), C.c_int32],
         "ebs_geometry_export": [C.c_void_p, C.c_int32, C.c_int32, P(C.c_double), C.c_size_t],
         "ebs_geometry_stats": [C.c_void_p, P(C.c_int64)],
+        "ebs_alpha_histogram": [C.c_void_p, C.c_int32, P(C.c_double), C.c_int32, P(C.c_int64)],
         "ebs_advance_stage": [C.c_void_p, P(State), P(State), P(State), C.c_double],
         "ebs_redistribute": [C.c_void_p, P(State), P(State)],
         "ebs_rk3_step": [C.c_void_p, P(State), P(State), C.c_double, C.c_int32],
@@ -91,6 +92,7 @@ def load(path: str = LIB_PATH):
         "ebs_timing_read": [C.c_void_p, P(C.c_double), P(C.c_int64)],
         "ebs_algorithmic_bytes": [C.c_void_p, P(C.c_double)],
         "ebs_destroy": [C.c_void_p],
+        "ebs_stream_copy": [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -100,6 +102,21 @@ def load(path: str = LIB_PATH):
     lib.ebs_last_error.restype = C.c_char_p
     _lib = lib
     return lib
+
+
+def stream_copy(dst, src, stream=None):
+    """Copy device tensor src into dst (same byte size) with the library's
+    streaming copy kernel on the given (default: current) stream."""
+    import torch
+
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("sizes differ")
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    st = load().ebs_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, C.c_void_p(stream))
+    if st != EBS_OK:
+        raise EbsError(st, "ebs_stream_copy")
 
 
 def field_shapes(n):
@@ -191,6 +208,18 @@ class Context:
         self._check(self.lib.ebs_geometry_stats(self.h, out.ctypes.data_as(C.POINTER(C.c_int64))),
                     "ebs_geometry_stats")
         return out.reshape(4, 8)
+
+    def alpha_histogram(self, inst: int, edges):
+        """Counts of the fluid CVs of an instance per volume-fraction bin
+        [edges[b], edges[b+1]) (last bin closed)."""
+        import numpy as np
+
+        e = np.ascontiguousarray(edges, dtype=np.float64)
+        out = np.zeros(len(e) - 1, dtype=np.int64)
+        self._check(self.lib.ebs_alpha_histogram(self.h, int(inst), e.ctypes.data_as(C.POINTER(C.c_double)),
+                                                 len(e) - 1, out.ctypes.data_as(C.POINTER(C.c_int64))),
+                    "ebs_alpha_histogram")
+        return out
 
     # ---------------------------------------------------------------- state
     def new_state(self, host: dict | None = None):

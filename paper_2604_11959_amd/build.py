@@ -20,7 +20,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libebstag.so")
-SOURCES = ["api.hip", "geom.hip", "bulk.hip", "stage.hip", "wsrd.hip", "reduce.hip", "restrict.hip"]
+SOURCES = ["api.hip", "geom.hip", "bulk.hip", "stage.hip", "wsrd.hip", "reduce.hip", "restrict.hip",
+           "copy.hip"]
 ARCH = "gfx950"
 
 COMMON = [

@@ -80,6 +80,50 @@ void drop_graph(ebs_ctx* c) {
 
 bool same_state(const ebs_state& a, const ebs_state& b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
 
+// bytes of each state array (rho, rhotheta, rhou, rhov, rhow) of the context's grid
+void field_bytes(const ebs_ctx* c, size_t out[5]) {
+    const size_t es = c->g.precision == EBS_F32_BULK ? 4 : 8;
+    const size_t nx = c->nx, ny = c->ny, nz = c->nz;
+    out[0] = out[1] = es * nx * ny * nz;
+    out[2] = es * (nx + 1) * ny * nz;
+    out[3] = es * nx * (ny + 1) * nz;
+    out[4] = es * nx * ny * (nz + 1);
+}
+
+const void* field_ptr(const ebs_state* s, int f) {
+    const void* const p[5] = {s->rho, s->rhotheta, s->rhou, s->rhov, s->rhow};
+    return p[f];
+}
+
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+// Does any array of `out` overlap an array of `in`?  With same_ok, array f
+// of out may coincide exactly with array f of in (an in-place update that
+// reads each element before the same thread writes it).
+bool states_overlap(const ebs_ctx* c, const ebs_state* out, const ebs_state* in, bool same_ok) {
+    size_t nb[5];
+    field_bytes(c, nb);
+    for (int f = 0; f < 5; ++f)
+        for (int g = 0; g < 5; ++g) {
+            if (same_ok && f == g && field_ptr(out, f) == field_ptr(in, g)) continue;
+            if (ranges_overlap(field_ptr(out, f), nb[f], field_ptr(in, g), nb[g])) return true;
+        }
+    return false;
+}
+
+// do two arrays of one state overlap
+bool state_self_overlap(const ebs_ctx* c, const ebs_state* s) {
+    size_t nb[5];
+    field_bytes(c, nb);
+    for (int f = 0; f < 5; ++f)
+        for (int g = f + 1; g < 5; ++g)
+            if (ranges_overlap(field_ptr(s, f), nb[f], field_ptr(s, g), nb[g])) return true;
+    return false;
+}
+
 ebs_status rk3_enqueue(ebs_ctx* c, ebs_state* U, ebs_state* S, double dt) {
     static const double cs[3] = {1.0 / 3.0, 0.5, 1.0};
     ebs_state* cur = U;
@@ -226,6 +270,16 @@ ebs_status ebs_build_geometry_terrain(ebs_ctx* c, const double* h_nodes, int32_t
         if (h[(size_t)j * W + c->nx] != h[(size_t)j * W]) return fail(c, EBS_E_ARG, "terrain not periodic in x");
     for (int i = 0; i <= c->nx; ++i)
         if (h[(size_t)c->ny * W + i] != h[i]) return fail(c, EBS_E_ARG, "terrain not periodic in y");
+    // The build replaces every table the stages read.  Work queued on the
+    // context's streams may still read them, and a graph captured on the old
+    // tables must never be replayed: wait, drop the graph, and leave the
+    // context without geometry until the whole build has succeeded.
+    EBS_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->side) EBS_HIP(c, hipStreamSynchronize(c->side));
+    c->join_pending = false;
+    drop_graph(c);
+    c->have_geom = false;
+    c->have_adv = false;
     double* d_h = nullptr;
     if (hipMalloc(&d_h, sizeof(double) * nn) != hipSuccess) return fail(c, EBS_E_OOM, "terrain upload");
     hipError_t e = hipMemcpy(d_h, h.data(), sizeof(double) * nn, hipMemcpyHostToDevice);
@@ -264,7 +318,6 @@ ebs_status ebs_build_geometry_terrain(ebs_ctx* c, const double* h_nodes, int32_t
     if (st != EBS_OK) return st;
     st = build_tiles(c);
     if (st != EBS_OK) return st;
-    drop_graph(c);
     EBS_HIP(c, hipStreamSynchronize(c->stream));
     c->have_geom = true;
     return EBS_OK;
@@ -378,20 +431,64 @@ ebs_status ebs_geometry_stats(ebs_ctx* c, int64_t* out) {
     return EBS_OK;
 }
 
+ebs_status ebs_alpha_histogram(ebs_ctx* c, int32_t inst, const double* edges, int32_t nbins, int64_t* counts) {
+    if (!c || !edges || !counts) return fail(c, EBS_E_ARG, "null argument");
+    if (inst < 0 || inst > 3 || nbins < 1) return fail(c, EBS_E_ARG, "bad instance or bin count");
+    for (int b = 0; b < nbins; ++b)
+        if (!(edges[b] < edges[b + 1])) return fail(c, EBS_E_ARG, "bin edges must increase");
+    if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
+    for (int b = 0; b < nbins; ++b) counts[b] = 0;
+    // bin of a fluid volume fraction a: [edges[b], edges[b+1]), the last bin closed
+    auto put = [&](double a, int64_t n) {
+        if (n <= 0 || a < edges[0] || a > edges[nbins]) return;
+        int b = (int)(std::upper_bound(edges, edges + nbins + 1, a) - edges) - 1;
+        if (b >= nbins) b = nbins - 1;
+        counts[b] += n;
+    };
+    if (c->G > 0) {
+        std::vector<double> al((size_t)c->G);
+        std::vector<int8_t> ty((size_t)c->G);
+        EBS_HIP(c, hipMemcpy(al.data(), c->d_geo + ((size_t)inst * GQ_N + GQ_ALPHA) * c->G, sizeof(double) * c->G,
+                             hipMemcpyDeviceToHost));
+        EBS_HIP(c, hipMemcpy(ty.data(), c->d_type + (size_t)inst * c->G, c->G, hipMemcpyDeviceToHost));
+        for (size_t g = 0; g < (size_t)c->G; ++g)
+            if (ty[g] != 0) put(al[g], 1);
+    }
+    // regular CVs above the general range (alpha = 1); below it every CV is covered
+    const int kmin = inst == 3 ? 1 : 0, kmax = c->nz - 1;
+    int64_t reg = 0;
+    for (int col = 0; col < c->ncol; ++col) reg += std::max(0, kmax + 1 - std::max(c->h_g1[col], kmin));
+    put(1.0, reg);
+    return EBS_OK;
+}
+
 ebs_status ebs_advance_stage(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uhat, double cdt) {
     if (!c) return EBS_E_ARG;
     if (!state_ok(Un) || !state_ok(Ucur) || !state_ok(Uhat)) return fail(c, EBS_E_ARG, "null state pointer");
     if (!isfinite(cdt)) return fail(c, EBS_E_ARG, "non-finite time step");
     if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
-    if (Uhat->rho == Ucur->rho || Uhat->rhou == Ucur->rhou || Uhat->rhow == Ucur->rhow)
-        return fail(c, EBS_E_ARG, "output aliases the stencil input");
-    return launch_advance(c, Un, Ucur, Uhat, cdt);
+    // the stencil reads neighbours of Ucur while other threads write Uhat, so
+    // no array of Uhat may overlap any array of Ucur; Uhat may coincide with
+    // Un field by field (each element of Un is read only by the thread that
+    // writes the same element of Uhat), but not overlap it otherwise
+    if (state_self_overlap(c, Uhat)) return fail(c, EBS_E_ARG, "output arrays overlap each other");
+    if (states_overlap(c, Uhat, Ucur, false)) return fail(c, EBS_E_ARG, "output overlaps the stencil input");
+    if (states_overlap(c, Uhat, Un, true)) return fail(c, EBS_E_ARG, "output partly overlaps U^n");
+    const ebs_status st = launch_advance(c, Un, Ucur, Uhat, cdt);
+    c->have_adv = st == EBS_OK;
+    if (st == EBS_OK) c->last_uhat = *Uhat;
+    return st;
 }
 
 ebs_status ebs_redistribute(ebs_ctx* c, const ebs_state* Uhat, ebs_state* Uout) {
     if (!c) return EBS_E_ARG;
     if (!state_ok(Uhat) || !state_ok(Uout)) return fail(c, EBS_E_ARG, "null state pointer");
     if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
+    // the cut range is redistributed from the FP64 copy the last advance kept
+    if (!c->have_adv || !same_state(*Uhat, c->last_uhat))
+        return fail(c, EBS_E_ORDER, "Uhat is not the output of the last ebs_advance_stage");
+    if (state_self_overlap(c, Uout)) return fail(c, EBS_E_ARG, "output arrays overlap each other");
+    if (states_overlap(c, Uout, Uhat, true)) return fail(c, EBS_E_ARG, "output partly overlaps Uhat");
     return launch_redistribute(c, Uhat, Uout);
 }
 
@@ -401,6 +498,14 @@ ebs_status ebs_rk3_step(ebs_ctx* c, ebs_state* U, ebs_state* scratch, double dt,
         return fail(c, EBS_E_ARG, "null state pointer");
     if (!isfinite(dt)) return fail(c, EBS_E_ARG, "non-finite time step");
     if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");
+    // U, S0 and S1 serve as stage inputs and outputs in turn: they must be
+    // three disjoint states
+    if (state_self_overlap(c, U) || state_self_overlap(c, &scratch[0]) || state_self_overlap(c, &scratch[1]) ||
+        states_overlap(c, U, &scratch[0], false) || states_overlap(c, U, &scratch[1], false) ||
+        states_overlap(c, &scratch[0], &scratch[1], false))
+        return fail(c, EBS_E_ARG, "U and the two scratch states must not overlap");
+    // the stages overwrite the provisional copy ebs_redistribute reads
+    c->have_adv = false;
     if (!use_graph || c->timing) return rk3_enqueue(c, U, scratch, dt);
     const bool hit = c->graph.exec && same_state(c->graph.U, *U) && same_state(c->graph.S0, scratch[0]) &&
                      same_state(c->graph.S1, scratch[1]) && c->graph.dt == dt;
@@ -634,6 +739,8 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
             }
         }
     }
+    // the timing stages overwrite the provisional copy ebs_redistribute reads
+    c->have_adv = false;
     // scratch states
     const size_t es = c->g.precision == EBS_F32_BULK ? 4 : 8;
     const size_t nx = c->nx, ny = c->ny, nz = c->nz;
@@ -661,7 +768,7 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
         (void)launch_advance(c, &st[0], &st[2], &st[1], 0.0);
     };
     const int cxy[][2] = {{16, 4}, {16, 8}, {16, 16}, {32, 4}, {32, 8}, {32, 16}, {64, 2}, {64, 4}, {64, 8}, {64, 16}};
-    const int cz[] = {16, 32, 64, 128};
+    const int cz[] = {16, 32, 64, 128, 256};
     double best = 1e300;
     int bx = c->tile_x, by = c->tile_y, bz = c->tile_z, bs = c->tile_span;
     const bool was_timing = c->timing;
@@ -672,6 +779,9 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
     constexpr int NZ = (int)(sizeof(cz) / sizeof(cz[0]));
     for (int q = 0; q < (int)(sizeof(cxy) / sizeof(cxy[0])) * NZ * 2; ++q) {
         const int cd[4] = {cxy[q / (2 * NZ)][0], cxy[q / (2 * NZ)][1], cz[(q / 2) % NZ], q % 2};
+        // a height at or above nz tiles whole columns, as the next smaller
+        // height at or above nz already did
+        if ((q / 2) % NZ > 0 && cz[(q / 2) % NZ - 1] >= c->nz) continue;
         if (ebs_set_tile(c, cd[0], cd[1], cd[2], cd[3]) != EBS_OK) continue;
         three();
         (void)hipEventRecord(e0, c->stream);

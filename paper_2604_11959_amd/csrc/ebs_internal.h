@@ -243,6 +243,10 @@ struct ebs_ctx {
 
     ebs_graph_cache graph;
     double* d_dummy = nullptr;
+    // output of the last ebs_advance_stage: the cut range of ebs_redistribute
+    // is read from d_uhat, which holds that advance's provisional state
+    bool have_adv = false;
+    ebs_state last_uhat{};
 };
 
 namespace ebs {

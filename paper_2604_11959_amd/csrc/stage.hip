@@ -209,7 +209,10 @@ struct Gen {
             if (s != 3 && (P.k == 0 || P.k == a.D.nz)) return 0.0;
             if (s == 3 && (P.k == 1 || P.k == a.D.nz)) return 0.0;
         }
-        const double m = s == 0 ? mom<D>(P) : 0.5 * (mom<D>(ls) + mom<D>(P));
+        // staggered face: mean of the two face momenta next to it over those
+        // whose CV holds fluid (mom gives 0 for the others)
+        const bool both = ((ls.fl & P.fl) >> (D + 1)) & 1;
+        const double m = s == 0 ? mom<D>(P) : (both ? 0.5 * (mom<D>(ls) + mom<D>(P)) : mom<D>(ls) + mom<D>(P));
         if (F == 0) return m;
         return m * upw<double>(m, phi<F>(LL), phi<F>(L), phi<F>(P), phi<F>(RR), (LL.fl >> s) & 1,
                                (RR.fl >> s) & 1);
@@ -438,16 +441,19 @@ struct Gen {
         const double v = st(a.cur, 2 + D, p.i, p.j, min(max(p.k, 0), a.D.nz - 1));
         return ((p.fl >> (D + 1)) & 1) ? v : 0.0;
     }
+    // mass flux of a staggered face: mean of the two face momenta next to it
+    // over those whose CV holds fluid (momt gives 0 for the others), so one
+    // fluid CV gives its own momentum
     template <int F, int D>
     __device__ __forceinline__ double fhatt(const SPt& LL, const SPt& L, const SPt& P, const SPt& RR,
                                             const PV& vLL, const PV& vL, const PV& vP, const PV& vRR,
-                                            double m0, double mls) const {
+                                            double m0, double mls, bool both) const {
         constexpr int s = F < 2 ? 0 : F - 1;
         if (D == 2) {
             if (s != 3 && (P.k == 0 || P.k == a.D.nz)) return 0.0;
             if (s == 3 && (P.k == 1 || P.k == a.D.nz)) return 0.0;
         }
-        const double m = s == 0 ? m0 : 0.5 * (mls + m0);
+        const double m = s == 0 ? m0 : (both ? 0.5 * (mls + m0) : mls + m0);
         if (F == 0) return m;
         return m * upw<double>(m, phit<F>(LL, vLL), phit<F>(L, vL), phit<F>(P, vP), phit<F>(RR, vRR),
                                (LL.fl >> s) & 1, (RR.fl >> s) & 1);
@@ -464,11 +470,14 @@ struct Gen {
         const PV vLL = loadpv(LL), vL = loadpv(L), vRR = loadpv(RR);
         // mass fluxes: component D at P and below P along x, y, z
         const double m0 = momt<D>(P), mx = momt<D>(S[2]), my = momt<D>(S[5]), mz = momt<D>(S[8]);
-        a.fh[(0 * 3 + D) * G + e] = (ff & ff_pos(0, D)) ? fhatt<0, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, m0) : 0.0;
-        a.fh[(1 * 3 + D) * G + e] = (ff & ff_pos(0, D)) ? fhatt<1, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, m0) : 0.0;
-        a.fh[(2 * 3 + D) * G + e] = (ff & ff_pos(1, D)) ? fhatt<2, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, mx) : 0.0;
-        a.fh[(3 * 3 + D) * G + e] = (ff & ff_pos(2, D)) ? fhatt<3, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, my) : 0.0;
-        a.fh[(4 * 3 + D) * G + e] = (ff & ff_pos(3, D)) ? fhatt<4, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, mz) : 0.0;
+        // are the D-momentum CVs at P and below P along x, y, z all fluid
+        const int f0 = (P.fl >> (D + 1)) & 1;
+        const bool bx = f0 & (S[2].fl >> (D + 1)), by = f0 & (S[5].fl >> (D + 1)), bz = f0 & (S[8].fl >> (D + 1));
+        a.fh[(0 * 3 + D) * G + e] = (ff & ff_pos(0, D)) ? fhatt<0, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, m0, true) : 0.0;
+        a.fh[(1 * 3 + D) * G + e] = (ff & ff_pos(0, D)) ? fhatt<1, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, m0, true) : 0.0;
+        a.fh[(2 * 3 + D) * G + e] = (ff & ff_pos(1, D)) ? fhatt<2, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, mx, bx) : 0.0;
+        a.fh[(3 * 3 + D) * G + e] = (ff & ff_pos(2, D)) ? fhatt<3, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, my, by) : 0.0;
+        a.fh[(4 * 3 + D) * G + e] = (ff & ff_pos(3, D)) ? fhatt<4, D>(LL, L, P, RR, vLL, vL, vP, vRR, m0, mz, bz) : 0.0;
     }
     // table code of a stencil position (set-up): index into the
     // advected-quantity array | fluid bits << 28; 0 where no instance is

@@ -614,8 +614,9 @@ def test_stage_parity_rough_vertical_momentum_c2():
     the bracket -- summed in different orders by the two implementations -- is
     amplified by 1/alpha, and the redistributed value of the sliver keeps part
     of it.  Per CV the bound is 1e-12 of the field scale plus
-    64 eps * 6 F_max * c dt / (alpha * min(dx)), with F_max the largest
-    advective flux of the field (mass flux times advected quantity)."""
+    eps * 6 F_max * c dt / (alpha * min(dx)), with F_max the largest
+    advective flux of the field (mass flux times advected quantity); the
+    largest difference measured is about a tenth of it."""
     w, o = _oracle(2)
     ref_state = synth.reference_isentropic(w.grid)
     U0 = synth.state_reference(w.grid, ref_state, 42)
@@ -638,7 +639,7 @@ def test_stage_parity_rough_vertical_momentum_c2():
     for f, inst in zip(FIELDS, oracle.FIELD_INST):
         a = o.export(inst, oracle.OQ["ALPHA"])
         scale = np.abs(ref[f][masks[f]]).max() if f in ("rho", "rhotheta") else mom
-        bound = 1e-12 * scale + 64 * eps * 6 * mmax * phi[f] * cdt / (np.where(a > 0, a, 1.0) * min(w.grid.dx))
+        bound = 1e-12 * scale + eps * 6 * mmax * phi[f] * cdt / (np.where(a > 0, a, 1.0) * min(w.grid.dx))
         d = np.abs(got[f] - ref[f])
         ratio = (d / bound)[masks[f]]
         worst = max(worst, ratio.max())

@@ -83,19 +83,51 @@ def _storage_bound(w, ref, cdts, mom):
 @pytest.mark.parametrize("cfg", [1, 2])
 def test_sources_stage_parity_fp64(cfg):
     """One stage (advance with sources + redistribution) from a perturbed
-    reference state, FP64."""
+    reference state, FP64.  The provisional state is compared in extensive
+    form (alpha U-hat) at the 1e-12 bar.  After the redistribution the bar
+    holds on every CV with alpha > 1e-3; a sliver's provisional value is its
+    flux bracket divided by alpha, so the rounding of the bracket (summed in
+    different orders by the two implementations) is amplified by 1/alpha and
+    part of it stays in the sliver's redistributed value: there the bound is
+    1e-12 of the scale plus eps 6 F_max c dt / (alpha min dx), F_max the
+    largest advective flux of the field."""
     w, o, ref = _oracle(cfg)
     U0 = synth.state_reference(w.grid, ref, 40 + cfg)
     cdt = w.dt / 3
-    want = o.stage(U0, U0, cdt, ref)
+    uh = o.advance(U0, U0, cdt, ref)
+    want = o.redistribute(uh)
     c = _ctx(w, ref)
     Ud, Uh = c.new_state(U0), c.new_state()
     c.advance(Ud, Ud, Uh, cdt)
+    torch.cuda.synchronize()
+    h = _host(Uh)
+    for f, inst in zip(FIELDS, oracle.FIELD_INST):
+        a = o.export(inst, oracle.OQ["ALPHA"])
+        e = np.abs(a * (h[f] - uh[f])).max() / np.abs(a * uh[f]).max()
+        assert e <= 1e-12, (f, e)
     c.redistribute(Uh, Uh)
     torch.cuda.synchronize()
-    err, _ = rel_err(_host(Uh), want, _masks(o))
+    got = _host(Uh)
+    masks = _masks(o)
+    err, mom = rel_err(got, want, masks)
     print(err)
-    assert max(err.values()) <= 1e-12, err
+    eps = np.finfo(np.float64).eps
+    mmax = max(np.abs(U0[f]).max() for f in ("rhou", "rhov", "rhow"))
+    vmax = mmax / U0["rho"].min()
+    phi = {"rho": 1.0, "rhotheta": np.abs(U0["rhotheta"] / U0["rho"]).max(), "rhou": vmax, "rhov": vmax,
+           "rhow": vmax}
+    worst = 0.0
+    for f, inst in zip(FIELDS, oracle.FIELD_INST):
+        a = o.export(inst, oracle.OQ["ALPHA"])
+        scale = np.abs(want[f][masks[f]]).max() if f in ("rho", "rhotheta") else mom
+        d = np.abs(got[f] - want[f])
+        big = masks[f] & (a > 1e-3)
+        assert d[big].max() <= 1e-12 * scale, (f, d[big].max() / scale)
+        bound = 1e-12 * scale + eps * 6 * mmax * phi[f] * cdt / (np.where(a > 0, a, 1.0) * min(w.grid.dx))
+        ratio = (d / bound)[masks[f]].max()
+        worst = max(worst, ratio)
+        assert ratio <= 1.0, (f, ratio)
+    print("worst fraction of the sliver bound", worst)
     # the sources moved the momenta well beyond the tolerance
     plain = o.stage(U0, U0, cdt)
     d, _ = rel_err(plain, want, _masks(o))
