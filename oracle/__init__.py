@@ -23,7 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = ["geom.c", "flux.c", "wsrd.c", "source.c", "restrict.c"]
+_SRC = ["geom.c", "flux.c", "wsrd.c", "source.c", "restrict.c", "diffusion.c"]
 
 # geometry quantity indices (mirror oracle.h)
 OQ = dict(ALPHA=0, BX=1, BY=2, BZ=3, FX1=4, FX2=5, FY1=6, FY2=7, FZ1=8, FZ2=9,
@@ -57,6 +57,10 @@ class _Src(C.Structure):
     _fields_ = [("P00", C.c_double), ("R", C.c_double), ("gamma", C.c_double), ("g", C.c_double)]
 
 
+class _Diff(C.Structure):
+    _fields_ = [("alpha_theta", C.c_double), ("eb_mode", C.c_int32), ("theta_wall", C.c_double)]
+
+
 class _Grid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("dx", C.c_double * 3), ("lo", C.c_double * 3),
                 ("small_vfrac", C.c_double), ("limiter", C.c_int32), ("eb_flux", C.c_int32)]
@@ -86,6 +90,7 @@ def _load():
         lib.orc_restrict.argtypes = [P(_Grid), dpp, dpp, dpp]
         lib.orc_box_moments.argtypes = [P(_Grid), dp, C.c_int, C.c_int, dp, C.c_double,
                                         C.c_double, C.c_int, dp]
+        lib.orc_diffusion.argtypes = [P(_Grid), dpp, dpp, P(_Diff), dp, dpp, dp]
         lib.orc_set_threads.argtypes = [C.c_int]
         lib.orc_set_threads.restype = C.c_int
         _lib = lib
@@ -217,9 +222,25 @@ class Oracle:
         out = from_dense(zero + S, self.n)
         return {k: out[k] for k in ("rhou", "rhov", "rhow")}
 
-    def advance_dense(self, Un: list, Ucur: list, cdt: float, ref=None) -> list:
+    def diffusion_dense(self, Ucur: list, diff, fluxes: bool = False):
+        """Intensive diffusive update of rho theta (dense, instance 0) for
+        ``diff`` (attributes alpha_theta, eb_mode, theta_wall); with fluxes,
+        also the lower-face flux densities [3] and the EB terms."""
+        p = _Diff(float(diff.alpha_theta), int(diff.eb_mode), float(diff.theta_wall))
+        D = np.zeros_like(Ucur[0])
+        F = [np.zeros_like(Ucur[0]) for _ in range(3)]
+        E = np.zeros_like(Ucur[0])
+        _load().orc_diffusion(C.byref(self.g), _dpp(self.geo), _dpp(Ucur), C.byref(p), _dptr(D), _dpp(F),
+                              _dptr(E))
+        return (D, F, E) if fluxes else D
+
+    def diffusion(self, U: dict, diff, fluxes: bool = False):
+        return self.diffusion_dense(to_dense(U, self.n), diff, fluxes)
+
+    def advance_dense(self, Un: list, Ucur: list, cdt: float, ref=None, diff=None) -> list:
         """Uhat = Un + cdt dU(Ucur); with a reference state, plus cdt times the
-        momentum sources of Ucur on every fluid CV."""
+        momentum sources of Ucur on every fluid CV; with a diffusion setting,
+        plus cdt times the diffusive update of rho theta."""
         out = [np.zeros_like(Un[0]) for _ in range(5)]
         _load().orc_advance(C.byref(self.g), _dpp(self.geo), _dpp(Un), _dpp(Ucur), _dpp(out),
                             float(cdt))
@@ -227,6 +248,8 @@ class Oracle:
             S = self.sources_dense(Ucur, ref)
             for d in range(3):
                 out[2 + d] = out[2 + d] + float(cdt) * S[d]
+        if diff is not None:
+            out[1] = out[1] + float(cdt) * self.diffusion_dense(Ucur, diff)
         return out
 
     def redistribute_dense(self, Uhat: list) -> list:
@@ -257,25 +280,25 @@ class Oracle:
                                       _dpp(out), _dpp(sig), _dpp(qh))
         return from_dense(out, self.n), sig, qh
 
-    def advance(self, Un: dict, Ucur: dict, cdt: float, ref=None) -> dict:
-        return from_dense(self.advance_dense(to_dense(Un, self.n), to_dense(Ucur, self.n), cdt, ref),
+    def advance(self, Un: dict, Ucur: dict, cdt: float, ref=None, diff=None) -> dict:
+        return from_dense(self.advance_dense(to_dense(Un, self.n), to_dense(Ucur, self.n), cdt, ref, diff),
                           self.n)
 
     def redistribute(self, Uhat: dict) -> dict:
         return from_dense(self.redistribute_dense(to_dense(Uhat, self.n)), self.n)
 
-    def stage(self, Un: dict, Ucur: dict, cdt: float, ref=None) -> dict:
+    def stage(self, Un: dict, Ucur: dict, cdt: float, ref=None, diff=None) -> dict:
         """Algorithm 1 steps (1)-(4) for one stage: U^s = R(U^n + c dt dU(U^{s-1}))."""
         d_n = to_dense(Un, self.n)
         d_c = d_n if Ucur is Un else to_dense(Ucur, self.n)
-        return from_dense(self.redistribute_dense(self.advance_dense(d_n, d_c, cdt, ref)), self.n)
+        return from_dense(self.redistribute_dense(self.advance_dense(d_n, d_c, cdt, ref, diff)), self.n)
 
-    def rk3_step(self, U: dict, dt: float, ref=None) -> dict:
+    def rk3_step(self, U: dict, dt: float, ref=None, diff=None) -> dict:
         """Low-storage three-stage Runge-Kutta (Wicker-Skamarock form)."""
         d_n = to_dense(U, self.n)
         cur = d_n
         for c in RK3_C:
-            cur = self.redistribute_dense(self.advance_dense(d_n, cur, c * dt, ref))
+            cur = self.redistribute_dense(self.advance_dense(d_n, cur, c * dt, ref, diff))
         return from_dense(cur, self.n)
 
     # ------------------------------------------------------------ two levels

@@ -124,6 +124,25 @@ int orc_restrict(const orc_grid* g, double* const geo[4], const double* const Uf
 int orc_box_moments(const orc_grid* g, const double* h_nodes, int ci, int cj,
                     const double rect[4], double za, double zb, int bottom, double* out);
 
+/* Thermal diffusion of rho theta (Section 4.2): thermal diffusivity
+ * alpha_theta (>= 0); the EB is adiabatic (eb_mode 0) or held at theta_wall
+ * (eb_mode 1). */
+typedef struct {
+    double alpha_theta;
+    int32_t eb_mode;
+    double theta_wall;
+} orc_diff;
+
+/* Intensive diffusive update of rho theta on the cell-centred CVs, D (dense
+ * instance storage; 0 where not fluid): (1/V) times the sum of
+ * rho alpha_theta grad(theta) . n_out over the open face areas and the EB
+ * facet.  Optional outputs (NULL to skip): Fd[d] the flux density
+ * rho alpha_theta d(theta)/dx_d on the lower d-face of every cell (0 on
+ * closed faces and walls), Feb the EB term (rho alpha_theta grad(theta) .
+ * n_out times the facet area) of every cell. */
+int orc_diffusion(const orc_grid* g, double* const geo[4], const double* const U[5], const orc_diff* p,
+                  double* D, double* const Fd[3], double* Feb);
+
 /* Threads used by the plane loops of the geometry, stage and redistribution
  * (n > 0 sets the count; returns the count in use).  Each loop iteration
  * writes only its own plane's entries, so results are bitwise independent
