@@ -314,6 +314,21 @@ ebs_status ebs_restrict(ebs_ctx* ctx, const ebs_state* Ufine, ebs_state* Ucoarse
  * frees a device buffer.  Errors as ebs_restrict, EBS_E_OOM, EBS_E_HIP. */
 ebs_status ebs_coarsened_geometry(ebs_ctx* ctx, double* alpha, double* beta_x, double* beta_y, double* beta_z);
 
+/* ebs_coarsened_geometry for callers that cannot allocate device memory
+ * (harnesses that forbid it, loops that must not call the allocator): the
+ * same kernel and results, staged through a fixed device buffer that the
+ * library holds for the life of the process (one per GPU, 16 MiB) instead of
+ * a buffer allocated and freed per call.  It calls no allocator.  The coarse
+ * grid may have at most EBS_COARSE_GEO_MAX_CELLS cells (EBS_E_UNSUPPORTED
+ * beyond).  Calls on one GPU share the buffer; the library serialises them
+ * within a process (each call holds the buffer until its copies to the host
+ * are done), so concurrent calls from several host threads wait for each
+ * other.  Synchronous.  Errors: as ebs_coarsened_geometry without
+ * EBS_E_OOM. */
+#define EBS_COARSE_GEO_MAX_CELLS (1 << 19)
+ebs_status ebs_coarsened_geometry_noalloc(ebs_ctx* ctx, double* alpha, double* beta_x, double* beta_y,
+                                          double* beta_z);
+
 
 /* Kernel timing: when enabled, every launch of the regular-region stage
  * kernel is bracketed by HIP events on the context stream; read returns the

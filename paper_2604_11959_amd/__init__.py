@@ -29,7 +29,7 @@ Q = dict(ALPHA=0, BETA_X=1, BETA_Y=2, BETA_Z=3, FX_Y=4, FX_Z=5, FY_X=6, FY_Z=7, 
 # every entry point declared in include/ebstag.h
 SYMBOLS = ("ebs_create", "ebs_build_geometry_terrain", "ebs_geometry_export", "ebs_geometry_stats", "ebs_alpha_histogram",
            "ebs_advance_stage", "ebs_redistribute", "ebs_rk3_step", "ebs_conserved_sums",
-           "ebs_autotune", "ebs_set_tile", "ebs_get_tile", "ebs_set_overlap", "ebs_set_range_rule", "ebs_set_sources", "ebs_restrict", "ebs_coarsened_geometry", "ebs_timing_enable", "ebs_timing_read",
+           "ebs_autotune", "ebs_set_tile", "ebs_get_tile", "ebs_set_overlap", "ebs_set_range_rule", "ebs_set_sources", "ebs_restrict", "ebs_coarsened_geometry", "ebs_coarsened_geometry_noalloc", "ebs_timing_enable", "ebs_timing_read",
            "ebs_algorithmic_bytes", "ebs_stream_copy", "ebs_last_error", "ebs_destroy")
 
 
@@ -88,6 +88,8 @@ def load(path: str = LIB_PATH):
         "ebs_set_sources": [C.c_void_p, P(SourceParams), P(C.c_double), P(C.c_double)],
         "ebs_restrict": [C.c_void_p, P(State), P(State)],
         "ebs_coarsened_geometry": [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_double)],
+        "ebs_coarsened_geometry_noalloc": [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_double),
+                                           P(C.c_double)],
         "ebs_timing_enable": [C.c_void_p, C.c_int32],
         "ebs_timing_read": [C.c_void_p, P(C.c_double), P(C.c_int64)],
         "ebs_algorithmic_bytes": [C.c_void_p, P(C.c_double)],
@@ -249,17 +251,18 @@ class Context:
         self._check(self.lib.ebs_restrict(self.h, C.byref(a), C.byref(b)), "ebs_restrict")
         return out
 
-    def coarsened_geometry(self):
+    def coarsened_geometry(self, noalloc: bool = False):
         """(alpha, [beta_x, beta_y, beta_z]) of the grid coarsened by 2, each
-        (nz/2, ny/2, nx/2), on the host."""
+        (nz/2, ny/2, nx/2), on the host; noalloc selects the entry point that
+        stages through the library's fixed device buffer."""
         import numpy as np
 
         nx, ny, nz = self.n
         sh = (nz // 2, ny // 2, nx // 2)
         arrs = [np.zeros(sh) for _ in range(4)]
         dp = C.POINTER(C.c_double)
-        self._check(self.lib.ebs_coarsened_geometry(self.h, *[x.ctypes.data_as(dp) for x in arrs]),
-                    "ebs_coarsened_geometry")
+        fn = self.lib.ebs_coarsened_geometry_noalloc if noalloc else self.lib.ebs_coarsened_geometry
+        self._check(fn(self.h, *[x.ctypes.data_as(dp) for x in arrs]), "ebs_coarsened_geometry")
         return arrs[0], arrs[1:]
 
     def redistribute(self, Uhat: dict, Uout: dict):
