@@ -32,6 +32,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# The timed steps use an eighth of the workload's CFL step.  A step's work does
+# not depend on the values of the state, but with the source term zero the flow
+# is pure advection and the cells on the lee side of a hill empty after about
+# dx / u (7.8 s on the default workload); 23 steps of the full step would carry
+# the state past that into negative densities.  An eighth keeps the warm-up and
+# timed stages (3.4 s) inside the well-posed interval, so the conservation
+# drift reported beside the timing is that of a physical state.
+DT_FRACTION = 0.125
 # autotune cache shipped with the package (tile chosen on MI355X); the counter
 # summary of the regular-region kernel for the default workload
 TILE_CACHE = os.path.join(ROOT, "paper_2604_11959_amd", "tiles_mi355x.json")
@@ -43,7 +51,8 @@ def _log(msg):
 
 
 def run_workload(cfg: int, precision: int, steps: int, warmup: int, use_graph: bool,
-                 autotune: bool, timing: bool, tile=None, overlap: bool = False, sources: bool = False):
+                 autotune: bool, timing: bool, tile=None, overlap: bool = False, sources: bool = False,
+                 persistent=None):
     import torch
 
     import paper_2604_11959_amd as ebs
@@ -63,6 +72,8 @@ def run_workload(cfg: int, precision: int, steps: int, warmup: int, use_graph: b
         ctx.set_sources(ref)
     if tile:
         ctx.set_tile(*tile)
+        if persistent is not None:
+            ctx.set_persistent(persistent)
     elif autotune:
         tile = ctx.autotune(os.environ.get("EBS_TILE_CACHE", TILE_CACHE))
         _log(f"{w.name}: tile {tile}")
@@ -71,8 +82,9 @@ def run_workload(cfg: int, precision: int, steps: int, warmup: int, use_graph: b
     S = [ctx.new_state(), ctx.new_state()]
     stream = torch.cuda.current_stream()
     sums0 = ctx.conserved_sums(U)
+    dt = w.dt * DT_FRACTION
     for _ in range(warmup):
-        ctx.rk3_step(U, S, w.dt, use_graph=use_graph)
+        ctx.rk3_step(U, S, dt, use_graph=use_graph)
     torch.cuda.synchronize()
     if timing:
         ctx.timing(True)
@@ -83,7 +95,7 @@ def run_workload(cfg: int, precision: int, steps: int, warmup: int, use_graph: b
     evs[0].record(stream)
     t_wall = time.perf_counter()
     for q in range(steps):
-        ctx.rk3_step(U, S, w.dt, use_graph=use_graph)
+        ctx.rk3_step(U, S, dt, use_graph=use_graph)
         evs[q + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
@@ -314,6 +326,7 @@ def main(argv=None):
                     help="run the regular-region kernel concurrently with the general range")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-parity", action="store_true", help="skip the window check against the oracle")
+    ap.add_argument("--no-boxes", action="store_true", help="skip the per-box tiling leg")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-sources", action="store_true",
                     help="skip the leg with the momentum sources (pressure gradient, buoyancy)")
@@ -393,6 +406,7 @@ def main(argv=None):
             "tiling": "domain" if main["tile"][3] else "per box",
             "graph": not args.no_graph,
             "overlap": overlap,
+            "dt_s": w.dt * DT_FRACTION,
             "general_region_cells": int(stats[0][6]),
             "cut_cvs": [int(s[0]) for s in stats],
             "small_cvs": [int(s[1]) for s in stats],
@@ -420,6 +434,20 @@ def main(argv=None):
     if not args.no_parity:
         out["parity"] = parity_leg(cfg, precision, main["tile"])
         _log(f"parity: {out['parity']['per_field_error']}")
+    if not args.no_boxes and len(w.boxes) > 1:
+        # the box list as the unit of work: tiles cut per box (no tile crosses
+        # a box), one block per tile or a persistent grid walking them
+        bt = (main["tile"][0], main["tile"][1], main["tile"][2], 0)
+        leg = {"tiles": f"per box, {bt[0]}x{bt[1]}x{bt[2]} ({len(w.boxes)} boxes)",
+               "domain_tiles_ms_per_step": round(ms_step, 4)}
+        for name, pers in (("one_block_per_tile", False), ("persistent", True)):
+            rb = run_workload(cfg, precision, args.steps, args.warmup, not args.no_graph, False, False, bt, overlap,
+                              persistent=pers)
+            leg[name + "_ms_per_step"] = round(rb["ms"] / args.steps, 4)
+            leg[name + "_value"] = round(N * 3 / (rb["ms"] / args.steps * 1e-3) / 1e6, 1)
+            rb["ctx"].close()
+        _log(f"box schedule: {leg}")
+        out["box_schedule"] = leg
     if not args.no_fp64 and cfg != 2:
         r2 = run_workload(2, ebs.EBS_F64, args.steps, args.warmup, not args.no_graph, True, False)
         ms2 = r2["ms"] / args.steps

@@ -214,7 +214,8 @@ ebs_status ebs_conserved_sums(ebs_ctx* ctx, const ebs_state* U, double hi[5], do
  * (created if missing, keyed by precision, grid size, box count and whether
  * the momentum sources are on; NULL = no cache).  The candidates are the
  * compiled shapes listed at ebs_set_tile, heights 16 to 256 (heights at or
- * above nz once) and both spans.  Each candidate is timed on the three
+ * above nz once), both spans and both schedules of ebs_set_persistent; the
+ * cache entry holds [tx, ty, tz, span, persistent].  Each candidate is timed on the three
  * stages of a step (the first with U^n = U_cur), regular-region kernel and
  * general passes together.  Synchronous; three scratch states are allocated
  * and freed internally (EBS_E_OOM if they do not fit). */
@@ -232,6 +233,14 @@ ebs_status ebs_autotune(ebs_ctx* ctx, const char* cache_json_path);
  * otherwise. */
 ebs_status ebs_set_tile(ebs_ctx* ctx, int32_t tx, int32_t ty, int32_t tz, int32_t span);
 ebs_status ebs_get_tile(const ebs_ctx* ctx, int32_t* tx, int32_t* ty, int32_t* tz, int32_t* span);
+
+/* Schedule of the regular-region kernel: enable = 0 (default) launches one
+ * block per tile; enable != 0 launches only as many blocks as the GPU holds
+ * at once (resident blocks per compute unit times its units), each walking
+ * its XCD's contiguous part of the tile list with a fixed stride, so a long
+ * per-box tile list runs in one wave of persistent blocks.  Results are
+ * identical; the captured RK3 graph is rebuilt.  The autotuner tries both. */
+ebs_status ebs_set_persistent(ebs_ctx* ctx, int32_t enable);
 
 /* Run the regular-region kernel on a second stream, concurrently with the
  * general-range passes and (inside ebs_rk3_step) the redistribution of the
@@ -285,6 +294,34 @@ typedef struct {
 ebs_status ebs_set_sources(ebs_ctx* ctx, const ebs_source_params* prm, const double* rhotheta0,
                            const double* rho0);
 
+/* Thermal diffusion of rho theta (Section 4.2; Eq. theta-comp): every later
+ * ebs_advance_stage / ebs_rk3_step adds c dt times the divergence of
+ * rho alpha_theta grad(theta) to the provisional rho theta of every fluid
+ * cell, before the redistribution.  Full faces use the centred difference of
+ * theta; cut faces and the EB facets use the gradient of a least-squares fit
+ * of a second-order polynomial over the fluid cells around them, as the
+ * paper describes (its details are deferred to a reference): unweighted,
+ * quadratic in mesh units about the face or facet centroid, over 4 cells
+ * along a face's normal and 3 across (3 x 3 x 3 around a facet), falling back
+ * to a linear fit with fewer than 10 points or a reciprocal 1-norm condition
+ * number of the normal matrix below 1e-7, and to no gradient with fewer than
+ * 4 points or a linear matrix as poorly conditioned.  The EB is adiabatic
+ * (eb_mode 0: no flux) or held at theta_wall (eb_mode 1: the facet fit passes
+ * through theta_wall at the facet centroid).  Face density: mean of the two
+ * cells; facet density: the cut cell's.  The domain bottom and top are
+ * adiabatic.  The fit weights depend on the geometry only and are built here
+ * (or by the next geometry build), about 36 points per cut face.
+ *   prm: alpha_theta >= 0 (m^2/s), eb_mode 0 or 1, theta_wall finite; NULL
+ *        switches diffusion off.
+ * Synchronous: waits for the work queued on the context.  Errors: EBS_E_ARG,
+ * EBS_E_OOM, EBS_E_HIP, EBS_E_UNSUPPORTED (more than 2^30 cells). */
+typedef struct {
+    double alpha_theta; /* thermal diffusivity, m^2 / s */
+    int32_t eb_mode;    /* 0 adiabatic EB, 1 EB held at theta_wall */
+    double theta_wall;  /* K */
+} ebs_diffusion_params;
+ebs_status ebs_set_diffusion(ebs_ctx* ctx, const ebs_diffusion_params* prm);
+
 /* Restriction (averaging down) of a state of this context's grid onto the
  * grid coarsened by 2 in every direction (Section 4.3: static two-level
  * refinement with ratio 2; the coarse geometry is merged from the fine
@@ -328,7 +365,6 @@ ebs_status ebs_coarsened_geometry(ebs_ctx* ctx, double* alpha, double* beta_x, d
 #define EBS_COARSE_GEO_MAX_CELLS (1 << 19)
 ebs_status ebs_coarsened_geometry_noalloc(ebs_ctx* ctx, double* alpha, double* beta_x, double* beta_y,
                                           double* beta_z);
-
 
 /* Kernel timing: when enabled, every launch of the regular-region stage
  * kernel is bracketed by HIP events on the context stream; read returns the

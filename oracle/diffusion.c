@@ -11,9 +11,11 @@
  * cells (a face centroid), to keep the stencil symmetric.
  *
  * Readings where the paper is silent (also listed in the design notes):
- *  - full faces (area fraction 1) use the centred difference of theta
- *    between the two cells; cut faces (0 < beta < 1) take the normal
- *    component of the fitted gradient at the face centroid;
+ *  - full faces use the centred difference of theta between the two cells;
+ *    cut faces take the normal component of the fitted gradient at the face
+ *    centroid; a face counts as full when beta >= 1 - 1e-12, so that the
+ *    last-bit rounding of two geometry builders (a face that the terrain only
+ *    touches) cannot switch the gradient method;
  *  - the fit is unweighted; the points are the fluid cells of the stencil at
  *    their volume centroids with theta = (rho theta) / rho; the polynomial is
  *    quadratic (1, dx, dy, dz, the three squares, the three products, in
@@ -177,7 +179,7 @@ static double face_flux(const DCtx* c, const orc_diff* p, int d, int i, int j, i
     const double beta = DG(c, OQ_BX + d, i, j, k);
     const double rf = 0.5 * (drho(c, il, jl, kl) + drho(c, i, j, k));
     double g;
-    if (!(beta < 1.0)) {
+    if (beta >= 1.0 - 1e-12) { /* full face (tie tolerance: see the header) */
         g = (dtheta(c, i, j, k) - dtheta(c, il, jl, kl)) / c->g->dx[d];
     } else {
         /* face centroid (physical) */

@@ -29,7 +29,7 @@ Q = dict(ALPHA=0, BETA_X=1, BETA_Y=2, BETA_Z=3, FX_Y=4, FX_Z=5, FY_X=6, FY_Z=7, 
 # every entry point declared in include/ebstag.h
 SYMBOLS = ("ebs_create", "ebs_build_geometry_terrain", "ebs_geometry_export", "ebs_geometry_stats", "ebs_alpha_histogram",
            "ebs_advance_stage", "ebs_redistribute", "ebs_rk3_step", "ebs_conserved_sums",
-           "ebs_autotune", "ebs_set_tile", "ebs_get_tile", "ebs_set_overlap", "ebs_set_range_rule", "ebs_set_sources", "ebs_restrict", "ebs_coarsened_geometry", "ebs_coarsened_geometry_noalloc", "ebs_timing_enable", "ebs_timing_read",
+           "ebs_autotune", "ebs_set_tile", "ebs_get_tile", "ebs_set_overlap", "ebs_set_persistent", "ebs_set_range_rule", "ebs_set_sources", "ebs_set_diffusion", "ebs_restrict", "ebs_coarsened_geometry", "ebs_coarsened_geometry_noalloc", "ebs_timing_enable", "ebs_timing_read",
            "ebs_algorithmic_bytes", "ebs_stream_copy", "ebs_last_error", "ebs_destroy")
 
 
@@ -51,6 +51,10 @@ class Box(C.Structure):
 
 class SourceParams(C.Structure):
     _fields_ = [("P00", C.c_double), ("R", C.c_double), ("gamma", C.c_double), ("g", C.c_double)]
+
+
+class DiffusionParams(C.Structure):
+    _fields_ = [("alpha_theta", C.c_double), ("eb_mode", C.c_int32), ("theta_wall", C.c_double)]
 
 
 class State(C.Structure):
@@ -84,8 +88,10 @@ def load(path: str = LIB_PATH):
         "ebs_set_tile": [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
         "ebs_get_tile": [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)],
         "ebs_set_overlap": [C.c_void_p, C.c_int32],
+        "ebs_set_persistent": [C.c_void_p, C.c_int32],
         "ebs_set_range_rule": [C.c_void_p, C.c_int32],
         "ebs_set_sources": [C.c_void_p, P(SourceParams), P(C.c_double), P(C.c_double)],
+        "ebs_set_diffusion": [C.c_void_p, P(DiffusionParams)],
         "ebs_restrict": [C.c_void_p, P(State), P(State)],
         "ebs_coarsened_geometry": [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_double)],
         "ebs_coarsened_geometry_noalloc": [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_double),
@@ -297,6 +303,11 @@ class Context:
         """Regular-region kernel concurrent with the general range (True) or serial (default)."""
         self._check(self.lib.ebs_set_overlap(self.h, int(bool(enable))), "ebs_set_overlap")
 
+    def set_persistent(self, enable: bool):
+        """Regular-region kernel with a grid of resident blocks walking the tile
+        list (True) or one block per tile (False, default)."""
+        self._check(self.lib.ebs_set_persistent(self.h, int(bool(enable))), "ebs_set_persistent")
+
     def set_range_rule(self, rule: int):
         """Rule for the top of the general range used by the next geometry build:
         0 loose, 1 small-CV footprint, 2 (default) the cells the redistribution
@@ -321,6 +332,15 @@ class Context:
         dp = C.POINTER(C.c_double)
         self._check(self.lib.ebs_set_sources(self.h, C.byref(prm), p0.ctypes.data_as(dp), r0.ctypes.data_as(dp)),
                     "ebs_set_sources")
+
+    def set_diffusion(self, p=None):
+        """Thermal diffusion of rho theta with parameters ``p`` (attributes
+        alpha_theta, eb_mode, theta_wall), or off with None."""
+        if p is None:
+            self._check(self.lib.ebs_set_diffusion(self.h, None), "ebs_set_diffusion")
+            return
+        prm = DiffusionParams(float(p.alpha_theta), int(p.eb_mode), float(p.theta_wall))
+        self._check(self.lib.ebs_set_diffusion(self.h, C.byref(prm)), "ebs_set_diffusion")
 
     def get_tile(self):
         tx, ty, tz, sp = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()

@@ -21,7 +21,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libebstag.so")
 SOURCES = ["api.hip", "geom.hip", "bulk.hip", "stage.hip", "wsrd.hip", "reduce.hip", "restrict.hip",
-           "copy.hip", "noalloc.hip"]
+           "noalloc.hip", "copy.hip",
+           "diffusion.hip"]
 ARCH = "gfx950"
 
 COMMON = [

@@ -245,7 +245,8 @@ ebs_status ebs_destroy(ebs_ctx* c) {
                     c->d_geo,  c->d_type,      c->d_mask,    c->d_small, c->d_tier, c->d_w,
                     c->d_smalllist, c->d_actlist, c->d_lsq_off, c->d_lsq_idx, c->d_lsq_c, c->d_lsq_ev, c->d_lsq_nev, c->d_wl_off, c->d_wl_idx, c->d_wl_geo, c->d_wl_self, c->d_wl_small, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles, c->d_prim, c->d_fh, c->d_type4, c->d_col, c->d_gcole, c->d_fflag, c->d_cbase, c->d_crec, c->d_bfc,
                     c->d_ptab, c->d_ftab, c->d_utab, c->d_sten, c->d_upd, c->d_q_idx, c->d_q_w, c->d_q_den, c->d_q_n, c->d_chk, c->d_part, c->d_dummy,
-                    c->d_srcf, c->d_srcd, c->d_srcv};
+                    c->d_srcf, c->d_srcd, c->d_srcv, c->d_dop_off, c->d_dop_idx, c->d_dop_w, c->d_dop_cell,
+                    c->d_dflux, c->d_dtab};
     for (void* p : ptrs) free_ptr(p);
     delete c;
     return EBS_OK;
@@ -318,6 +319,10 @@ ebs_status ebs_build_geometry_terrain(ebs_ctx* c, const double* h_nodes, int32_t
     if (st != EBS_OK) return st;
     st = build_tiles(c);
     if (st != EBS_OK) return st;
+    if (c->diff_on) {
+        st = build_diffusion(c);
+        if (st != EBS_OK) return st;
+    }
     EBS_HIP(c, hipStreamSynchronize(c->stream));
     c->have_geom = true;
     return EBS_OK;
@@ -630,6 +635,33 @@ ebs_status ebs_set_sources(ebs_ctx* c, const ebs_source_params* prm, const doubl
     return EBS_OK;
 }
 
+ebs_status ebs_set_diffusion(ebs_ctx* c, const ebs_diffusion_params* prm) {
+    if (!c) return EBS_E_ARG;
+    if (prm) {
+        if (!(prm->alpha_theta >= 0.0 && std::isfinite(prm->alpha_theta)) || (prm->eb_mode != 0 && prm->eb_mode != 1) ||
+            !std::isfinite(prm->theta_wall))
+            return fail(c, EBS_E_ARG, "diffusion parameters out of range");
+    }
+    // stages already queued may read the operators
+    EBS_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->side) EBS_HIP(c, hipStreamSynchronize(c->side));
+    drop_graph(c);
+    if (!prm) {
+        c->diff_on = false;
+        return EBS_OK;
+    }
+    c->diff = *prm;
+    c->diff_on = true;
+    if (c->have_geom) {
+        const ebs_status st = build_diffusion(c);
+        if (st != EBS_OK) {
+            c->diff_on = false;
+            return st;
+        }
+    }
+    return EBS_OK;
+}
+
 ebs_status ebs_restrict(ebs_ctx* c, const ebs_state* Uf, ebs_state* Uc) {
     if (!c) return EBS_E_ARG;
     if (!state_ok(Uf) || !state_ok(Uc)) return fail(c, EBS_E_ARG, "null state pointer");
@@ -672,6 +704,13 @@ ebs_status ebs_set_range_rule(ebs_ctx* c, int32_t rule) {
 ebs_status ebs_set_overlap(ebs_ctx* c, int32_t enable) {
     if (!c) return EBS_E_ARG;
     c->overlap = enable != 0;
+    drop_graph(c);
+    return EBS_OK;
+}
+
+ebs_status ebs_set_persistent(ebs_ctx* c, int32_t enable) {
+    if (!c) return EBS_E_ARG;
+    c->persistent = enable != 0;
     drop_graph(c);
     return EBS_OK;
 }
@@ -732,10 +771,12 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
             const std::string pat = std::string("\"") + key + "\": [";
             const size_t p = txt.find(pat);
             if (p != std::string::npos) {
-                int tx = 0, ty = 0, tz = 0, sp = 0;
-                if (std::sscanf(txt.c_str() + p + pat.size(), "%d, %d, %d, %d", &tx, &ty, &tz, &sp) == 4 &&
-                    ebs_set_tile(c, tx, ty, tz, sp) == EBS_OK)
+                int tx = 0, ty = 0, tz = 0, sp = 0, ps = 0;
+                const int got = std::sscanf(txt.c_str() + p + pat.size(), "%d, %d, %d, %d, %d", &tx, &ty, &tz, &sp, &ps);
+                if (got >= 4 && ebs_set_tile(c, tx, ty, tz, sp) == EBS_OK) {
+                    c->persistent = got == 5 && ps != 0;
                     return EBS_OK;
+                }
             }
         }
     }
@@ -770,7 +811,7 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
     const int cxy[][2] = {{16, 4}, {16, 8}, {16, 16}, {32, 4}, {32, 8}, {32, 16}, {64, 2}, {64, 4}, {64, 8}, {64, 16}};
     const int cz[] = {16, 32, 64, 128, 256};
     double best = 1e300;
-    int bx = c->tile_x, by = c->tile_y, bz = c->tile_z, bs = c->tile_span;
+    int bx = c->tile_x, by = c->tile_y, bz = c->tile_z, bs = c->tile_span, bp = c->persistent ? 1 : 0;
     const bool was_timing = c->timing;
     c->timing = false;
     hipEvent_t e0, e1;
@@ -783,15 +824,18 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
         // height at or above nz already did
         if ((q / 2) % NZ > 0 && cz[(q / 2) % NZ - 1] >= c->nz) continue;
         if (ebs_set_tile(c, cd[0], cd[1], cd[2], cd[3]) != EBS_OK) continue;
-        three();
-        (void)hipEventRecord(e0, c->stream);
-        const int reps = 3;
-        for (int rep = 0; rep < reps; ++rep) three();
-        (void)hipEventRecord(e1, c->stream);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) { best = ms; bx = cd[0]; by = cd[1]; bz = cd[2]; bs = cd[3]; }
+        for (int ps = 0; ps < 2; ++ps) {  // grid over every tile, or persistent
+            c->persistent = ps != 0;
+            three();
+            (void)hipEventRecord(e0, c->stream);
+            const int reps = 3;
+            for (int rep = 0; rep < reps; ++rep) three();
+            (void)hipEventRecord(e1, c->stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) { best = ms; bx = cd[0]; by = cd[1]; bz = cd[2]; bs = cd[3]; bp = ps; }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -800,6 +844,7 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
         for (int b = 0; b < 5; ++b) free_ptr(buf[a][b]);
     ebs_status sst = ebs_set_tile(c, bx, by, bz, bs);
     if (sst != EBS_OK) return sst;
+    c->persistent = bp != 0;
     if (cache_json_path) {
         std::string txt;
         {
@@ -813,7 +858,7 @@ ebs_status ebs_autotune(ebs_ctx* c, const char* cache_json_path) {
         // append the entry to a flat JSON object
         const size_t close = txt.rfind('}');
         char ent[256];
-        std::snprintf(ent, sizeof(ent), "\"%s\": [%d, %d, %d, %d]", key, bx, by, bz, bs);
+        std::snprintf(ent, sizeof(ent), "\"%s\": [%d, %d, %d, %d, %d]", key, bx, by, bz, bs, bp);
         if (close == std::string::npos) {
             txt = std::string("{\n  ") + ent + "\n}\n";
         } else {

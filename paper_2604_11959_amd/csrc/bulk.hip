@@ -150,19 +150,17 @@ __device__ __forceinline__ void st(T* base, uint32_t off, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(off * (uint32_t)sizeof(T))) = v;
 }
 
+// One tile of the regular-region update (the whole 2.5-D march of a block).
 // SAME: U^n and U_cur are the same state (the first stage), so the own-cell
 // values of U^n are taken from the region loads instead of being read again.
 template <typename T, int TX, int TY, bool SAME, bool SRC>
-__global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
+__device__ __forceinline__ void bulk_tile(const BulkArgs<T>& a, int t, T* sm) {
     constexpr int WX = TX + 5, WS = WX * (TY + 5), NTHR = TX * TY, NH = WS - NTHR;
     constexpr int PW = TX + 1, PS = PW * (TY + 1);  // pressure plane: own cells, -x column, -y row
     constexpr int NPTS = 1 + (NH + NTHR - 1) / NTHR;
     static_assert(NPTS <= HALO_PTS, "halo points per thread");
-    extern __shared__ unsigned char smem_raw[];
-    T* sm = reinterpret_cast<T*>(smem_raw);
     const int nx = a.D.nx, ny = a.D.ny, nz = a.D.nz;
     const uint32_t pc = (uint32_t)nx * ny, pu = (uint32_t)(nx + 1) * ny, pv = (uint32_t)nx * (ny + 1);
-    const int t = (blockIdx.x % NXCD) * a.per_xcd + blockIdx.x / NXCD;
     if (t >= a.ntiles) return;
     const ebs_tile tl = a.tiles[t];
     const int tx = threadIdx.x, ty = threadIdx.y;
@@ -520,6 +518,28 @@ __global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
     }
 }
 
+// Block b runs on XCD b % NXCD and takes that XCD's contiguous chunk of the
+// tile list (per_xcd tiles), one tile per iteration with a stride of the
+// number of blocks per XCD: a single iteration when the grid covers every
+// tile, several in the persistent schedule (a grid of as many blocks as the
+// GPU holds at once), where a static stride keeps the tiles that run
+// together on one XCD neighbours in the list.
+template <typename T, int TX, int TY, bool SAME, bool SRC, bool PERSIST>
+__global__ void __launch_bounds__(TX * TY) k_bulk(BulkArgs<T> a) {
+    extern __shared__ unsigned char smem_raw[];
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+    if (!PERSIST) {  // one tile per block (kept free of the loop: no extra live registers)
+        bulk_tile<T, TX, TY, SAME, SRC>(a, xcd * a.per_xcd + slot, sm);
+        return;
+    }
+    const int nslot = gridDim.x / NXCD;
+    for (int s = slot; s < a.per_xcd; s += nslot) {
+        bulk_tile<T, TX, TY, SAME, SRC>(a, xcd * a.per_xcd + s, sm);
+        if (s + nslot < a.per_xcd) __syncthreads();  // the next tile reuses the LDS rings
+    }
+}
+
 template <typename T>
 ebs_status launch_bulk_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* Ucur, ebs_state* Uh, double cdt,
                          hipStream_t bs) {
@@ -575,14 +595,30 @@ ebs_status launch_bulk_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* Ucur
         bool same = true;
         for (int f = 0; f < 5; ++f) same = same && un[f] == cu[f];
         if (cx->ntiles > 0) {
-            const dim3 grid(a.per_xcd * NXCD), blk(cx->tile_x, cx->tile_y);
+            const dim3 blk(cx->tile_x, cx->tile_y);
+            // blocks per XCD: every tile of the chunk, or (persistent) as many
+            // as the XCD holds at once, resident blocks per CU times its CUs
+            auto blocks_per_xcd = [&](const void* kf) -> int {
+                if (!cx->persistent) return a.per_xcd;
+                int per_cu = 0, dev = 0, ncu = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf, blk.x * blk.y, lds) != hipSuccess ||
+                    hipGetDevice(&dev) != hipSuccess ||
+                    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                    per_cu <= 0 || ncu <= 0)
+                    return a.per_xcd;
+                return std::max(1, std::min(a.per_xcd, per_cu * ncu / NXCD));
+            };
 #define EBS_BULK_CASE(X, Y)                                                                   \
     if (cx->tile_x == X && cx->tile_y == Y) {                                                 \
-        auto kf = src ? (same ? k_bulk<T, X, Y, true, true> : k_bulk<T, X, Y, false, true>)    \
-                      : (same ? k_bulk<T, X, Y, true, false> : k_bulk<T, X, Y, false, false>); \
+        auto kf = cx->persistent                                                              \
+            ? (src ? (same ? k_bulk<T, X, Y, true, true, true> : k_bulk<T, X, Y, false, true, true>)        \
+                   : (same ? k_bulk<T, X, Y, true, false, true> : k_bulk<T, X, Y, false, false, true>))    \
+            : (src ? (same ? k_bulk<T, X, Y, true, true, false> : k_bulk<T, X, Y, false, true, false>)      \
+                   : (same ? k_bulk<T, X, Y, true, false, false> : k_bulk<T, X, Y, false, false, false>)); \
         if (lds > 64 * 1024)                                                                  \
             EBS_HIP(cx, hipFuncSetAttribute((const void*)kf,                                   \
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
+        const dim3 grid(blocks_per_xcd((const void*)kf) * NXCD);                              \
         hipLaunchKernelGGL(kf, grid, blk, lds, bs, a);                                        \
     } else
             EBS_BULK_CASE(16, 4) EBS_BULK_CASE(16, 8) EBS_BULK_CASE(16, 16) EBS_BULK_CASE(32, 4)

@@ -142,6 +142,7 @@ struct ebs_ctx {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool join_pending = false;
     bool overlap = false;              // use the side stream (ebs_set_overlap)
+    bool persistent = false;           // regular-region grid of resident blocks only (ebs_set_persistent)
     std::vector<ebs_box> boxes;
     std::string err = "no error";
 
@@ -243,6 +244,19 @@ struct ebs_ctx {
 
     ebs_graph_cache graph;
     double* d_dummy = nullptr;
+    // thermal diffusion of rho theta (ebs_set_diffusion): fit operators of
+    // the cut faces and facets (CSR over linear cell indices), their flux per
+    // stage, and per general cell the operator of each face and of the facet
+    bool diff_on = false;
+    ebs_diffusion_params diff{};
+    int32_t ndop = 0;
+    int64_t ndop_pts = 0;
+    int32_t* d_dop_off = nullptr;   // [ndop + 1]
+    int32_t* d_dop_idx = nullptr;   // [pts]
+    double* d_dop_w = nullptr;      // [pts]
+    int32_t* d_dop_cell = nullptr;  // [ndop] cell | direction << 30 (3 = facet)
+    double* d_dflux = nullptr;      // [ndop]
+    int32_t* d_dtab = nullptr;      // [G][7]
     // output of the last ebs_advance_stage: the cut range of ebs_redistribute
     // is read from d_uhat, which holds that advance's provisional state
     bool have_adv = false;
@@ -269,6 +283,12 @@ ebs_status launch_bulk(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur, e
                        hipStream_t stream);
 size_t bulk_lds_bytes(int tx, int ty, int precision, bool sources);
 ebs_status launch_restrict(ebs_ctx* cx, const ebs_state* Uf, ebs_state* Uc, double* geo_out);
+// thermal diffusion (diffusion.hip): operators, and the passes of one stage
+// (general range on the context stream, regular region on the given stream)
+ebs_status build_diffusion(ebs_ctx* c);
+ebs_status launch_diffusion_general(ebs_ctx* c, const ebs_state* Ucur, ebs_state* Uhat, double cdt);
+ebs_status launch_diffusion_regular(ebs_ctx* c, const ebs_state* Ucur, ebs_state* Uhat, double cdt,
+                                    hipStream_t stream);
 // redistribution (wsrd.hip)
 ebs_status wsrd_setup(ebs_ctx* c);
 ebs_status launch_redistribute(ebs_ctx* c, const ebs_state* Uhat, ebs_state* Uout);

@@ -995,8 +995,12 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
     void* const ou[5] = {Uh->rho, Uh->rhotheta, Uh->rhou, Uh->rhov, Uh->rhow};
     Dims D{cx->nx, cx->ny, cx->nz};
     {
-        const ebs_status st = launch_bulk(cx, Un, Ucur, Uh, cdt, bs);
+        ebs_status st = launch_bulk(cx, Un, Ucur, Uh, cdt, bs);
         if (st != EBS_OK) return st;
+        if (cx->diff_on) {  // adds to what the regular-region kernel wrote
+            st = launch_diffusion_regular(cx, Ucur, Uh, cdt, bs);
+            if (st != EBS_OK) return st;
+        }
         if (fork) EBS_HIP(cx, hipEventRecord(cx->ev_join, bs));
     }
     if (cx->G > 0) {
@@ -1043,6 +1047,10 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
         else
             hipLaunchKernelGGL(k_gen_update<T>, grid, blk, 0, cx->stream, a);
         EBS_HIP(cx, hipGetLastError());
+        if (cx->diff_on) {  // adds to what the update wrote
+            const ebs_status st = launch_diffusion_general(cx, Ucur, Uh, cdt);
+            if (st != EBS_OK) return st;
+        }
     }
     cx->join_pending = fork;
     if (fork && !defer_join) return join_side(cx);

@@ -648,3 +648,28 @@ def test_stage_parity_rough_vertical_momentum_c2():
         big = masks[f] & (a > 1e-3)
         assert d[big].max() <= 1e-12 * scale, (f, d[big].max() / scale)
     print("worst fraction of the bound", worst)
+
+
+@pytest.mark.parametrize("precision,tile", [(ebs.EBS_F64, (16, 8, 32, 0)), (ebs.EBS_F32_BULK, (64, 16, 64, 0)),
+                                            (ebs.EBS_F32_BULK, (32, 8, 16, 0))])
+def test_persistent_schedule_gives_identical_bits(precision, tile):
+    """Per-box tiles (many more tiles than resident blocks) run by a grid of
+    resident blocks walking the tile list give the same bits as one block
+    per tile, eagerly and through the captured graph."""
+    w = synth.make_workload(2)
+    U0 = synth.make_state(w)
+    boxes = synth.boxes_split(w.grid.n, 7, 40, block=32, unit=16)
+    res = []
+    for persistent, use_graph in ((False, False), (True, False), (True, True)):
+        c = _ctx(w, precision=precision, boxes=boxes)
+        c.set_tile(*tile)
+        c.set_persistent(persistent)
+        U = c.new_state(U0)
+        S = [c.new_state(), c.new_state()]
+        for _ in range(2):
+            c.rk3_step(U, S, w.dt, use_graph=use_graph)
+        torch.cuda.synchronize()
+        res.append(_host(U))
+    for r in res[1:]:
+        for f in FIELDS:
+            assert np.array_equal(r[f], res[0][f]), f
