@@ -23,7 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = ["geom.c", "flux.c", "wsrd.c", "source.c", "restrict.c", "diffusion.c"]
+_SRC = ["geom.c", "levelset.c", "flux.c", "wsrd.c", "source.c", "restrict.c", "diffusion.c"]
 
 # geometry quantity indices (mirror oracle.h)
 OQ = dict(ALPHA=0, BX=1, BY=2, BZ=3, FX1=4, FX2=5, FY1=6, FY2=7, FZ1=8, FZ2=9,
@@ -43,7 +43,8 @@ def build(force: bool = False) -> str:
     srcs = [os.path.join(_HERE, s) for s in _SRC]
     if not force and os.path.exists(_SO):
         so_t = os.path.getmtime(_SO)
-        if all(os.path.getmtime(s) <= so_t for s in srcs + [os.path.join(_HERE, "oracle.h")]):
+        hdrs = [os.path.join(_HERE, h) for h in ("oracle.h", "geom_piece.h")]
+        if all(os.path.getmtime(s) <= so_t for s in srcs + hdrs):
             return _SO
     tmp = _SO + ".tmp"
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp", "-Wall",
@@ -79,6 +80,8 @@ def _load():
         dpp = P(dp)
         i8pp = P(P(C.c_int8))
         lib.orc_geometry.argtypes = [P(_Grid), dp, dpp, i8pp]
+        lib.orc_geometry_levelset.argtypes = [P(_Grid), dp, dpp, i8pp]
+        lib.orc_levelset_piece.argtypes = [P(_Grid), dp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
         lib.orc_wsrd_setup.argtypes = [P(_Grid), dpp, dpp]
         lib.orc_advance.argtypes = [P(_Grid), dpp, dpp, dpp, dpp, C.c_double]
         lib.orc_redistribute.argtypes = [P(_Grid), dpp, dpp, dpp, dpp]
@@ -166,8 +169,13 @@ class Oracle:
     eb_flux: 0 no-flux wall (default), 1 free-stream closure test mode.
     """
 
-    def __init__(self, grid, h_nodes: np.ndarray, limiter: int = 0, eb_flux: int = 0):
+    def __init__(self, grid, h_nodes: np.ndarray = None, limiter: int = 0, eb_flux: int = 0,
+                 phi_nodes: np.ndarray = None):
+        """Exactly one of h_nodes (terrain heights, (ny+1, nx+1)) and
+        phi_nodes (level set, (nz+1, ny+1, nx+1), nondecreasing in z)."""
         lib = _load()
+        if (h_nodes is None) == (phi_nodes is None):
+            raise ValueError("give exactly one of h_nodes and phi_nodes")
         self.n = tuple(int(v) for v in grid.n)
         nx, ny, nz = self.n
         if min(nx, ny) < 6 or nz < 2:
@@ -175,14 +183,21 @@ class Oracle:
         self.g = _Grid((C.c_int32 * 3)(*self.n), (C.c_double * 3)(*grid.dx),
                        (C.c_double * 3)(*grid.lo), float(grid.small_vfrac), limiter, eb_flux)
         self.dx = tuple(float(v) for v in grid.dx)
-        self.h = np.ascontiguousarray(h_nodes, dtype=np.float64)
-        assert self.h.shape == (ny + 1, nx + 1)
         self.NI = (nz + 1) * ny * nx
         shape = (OQ_N, nz + 1, ny, nx)
         self.geo = [np.zeros(shape) for _ in range(4)]
         self.ctype = [np.zeros((nz + 1, ny, nx), dtype=np.int8) for _ in range(4)]
         i8 = (C.POINTER(C.c_int8) * 4)(*[c.ctypes.data_as(C.POINTER(C.c_int8)) for c in self.ctype])
-        lib.orc_geometry(C.byref(self.g), _dptr(self.h), _dpp(self.geo), i8)
+        if h_nodes is not None:
+            self.h = np.ascontiguousarray(h_nodes, dtype=np.float64)
+            assert self.h.shape == (ny + 1, nx + 1)
+            lib.orc_geometry(C.byref(self.g), _dptr(self.h), _dpp(self.geo), i8)
+        else:
+            self.h = None
+            self.phi = np.ascontiguousarray(phi_nodes, dtype=np.float64)
+            assert self.phi.shape == (nz + 1, ny + 1, nx + 1)
+            if lib.orc_geometry_levelset(C.byref(self.g), _dptr(self.phi), _dpp(self.geo), i8) != 0:
+                raise ValueError("level set not nondecreasing along z")
         self.w = [np.zeros((OW_N, nz + 1, ny, nx)) for _ in range(4)]
         lib.orc_wsrd_setup(C.byref(self.g), _dpp(self.geo), _dpp(self.w))
 
@@ -382,4 +397,17 @@ def box_moments(grid, h_nodes, ci, cj, rect, za, zb, bottom=False) -> np.ndarray
     out = np.zeros(14)
     lib.orc_box_moments(C.byref(g), _dptr(h), int(ci), int(cj), _dptr(r), float(za), float(zb),
                         int(bottom), _dptr(out))
+    return out
+
+
+def levelset_piece(grid, phi_nodes, i, j, k, part) -> np.ndarray:
+    """[vol, mx, my, mz, EB area vector (3), EB area, 6 face areas, type] of
+    box piece `part` of cell (i, j, k) for a level set (moments relative to
+    the cell's lower node)."""
+    lib = _load()
+    g = _Grid((C.c_int32 * 3)(*[int(v) for v in grid.n]), (C.c_double * 3)(*grid.dx),
+              (C.c_double * 3)(*grid.lo), float(grid.small_vfrac), 0, 0)
+    phi = np.ascontiguousarray(phi_nodes, dtype=np.float64)
+    out = np.zeros(15)
+    lib.orc_levelset_piece(C.byref(g), _dptr(phi), int(i), int(j), int(k), int(part), _dptr(out))
     return out

@@ -23,7 +23,7 @@
  * exact for the (at most quadratic) integrands that occur.  Faces are clipped
  * as polygons in their own plane.
  */
-#include "oracle.h"
+#include "geom_piece.h"
 
 #include <math.h>
 #include <stdlib.h>
@@ -99,14 +99,6 @@ static void poly_moments(const Poly* P, Mom* m) {
         }
     }
 }
-
-/* Result for one axis-aligned box; all moments relative to the cell's lower
- * corner node (X_i, Y_j, Z_k). Faces: 0 x-lo, 1 x-hi, 2 y-lo, 3 y-hi, 4 z-lo, 5 z-hi. */
-typedef struct {
-    double vol, mv[3];
-    double fa[6], fm[6][3];
-    double av[3], area, em[3];
-} BoxOut;
 
 typedef struct {
     double DX, DY;
@@ -469,16 +461,30 @@ static void store_zface(const orc_grid* g, const BoxOut* o, double cx, double cy
     geo[OQ_FZ2 * NI + idx] = a > 0 ? (o->fm[4][1] / a - cy) / dy : 0.0;
 }
 
+static void terrain_piece(const PieceSrc* s, int i, int j, int k, int part, BoxOut* o) {
+    piece((const GeoCtx*)s->data, i, j, k, part, o);
+}
+
+static int terrain_type(const PieceSrc* s, int i, int j, int k, int part) {
+    return piece_type((const GeoCtx*)s->data, i, j, k, part);
+}
+
 int orc_geometry(const orc_grid* g, const double* h, double* const geo[4], int8_t* const ctype[4]) {
+    GeoCtx G = {g, h};
+    PieceSrc S = {g, &G, terrain_piece, terrain_type};
+    (void)node_h;
+    return orc_assemble(&S, geo, ctype);
+}
+
+int orc_assemble(const PieceSrc* S, double* const geo[4], int8_t* const ctype[4]) {
+    const orc_grid* g = S->g;
     const int nx = g->n[0], ny = g->n[1], nz = g->n[2];
     const size_t NI = (size_t)(nz + 1) * ny * nx;
     const double dx = g->dx[0], dy = g->dx[1], dz = g->dx[2];
-    GeoCtx G = {g, h};
     for (int q = 0; q < 4; ++q) {
         memset(geo[q], 0, sizeof(double) * OQ_N * NI);
         memset(ctype[q], 0, NI);
     }
-    (void)node_h;
     /* every iteration writes only its own entries: planes run in parallel */
 #pragma omp parallel for schedule(dynamic, 1)
     for (int k = 0; k <= nz; ++k) {
@@ -488,69 +494,69 @@ int orc_geometry(const orc_grid* g, const double* h, double* const geo[4], int8_
                 if (k == nz) {
                     /* domain top: lower z-face of the pseudo planes */
                     BoxOut top, A, B, C;
-                    piece(&G, i, j, nz - 1, 0, &top);
+                    S->piece(S, i, j, nz - 1, 0, &top);
                     /* the top face of cell nz-1 is face 5; move it into slot 4 */
                     top.fa[4] = top.fa[5];
                     for (int e = 0; e < 3; ++e) top.fm[4][e] = top.fm[5][e];
                     store_zface(g, &top, 0.5 * dx, 0.5 * dy, geo[0], NI, idx);
-                    piece(&G, i - 1, j, nz - 1, 2, &A);
-                    piece(&G, i, j, nz - 1, 1, &B);
+                    S->piece(S, i - 1, j, nz - 1, 2, &A);
+                    S->piece(S, i, j, nz - 1, 1, &B);
                     shift(&A, -dx, 0, 0);
                     combine(&A, &B, 0, &C);
                     C.fa[4] = C.fa[5];
                     for (int e = 0; e < 3; ++e) C.fm[4][e] = C.fm[5][e];
                     store_zface(g, &C, 0.0, 0.5 * dy, geo[1], NI, idx);
-                    piece(&G, i, j - 1, nz - 1, 4, &A);
-                    piece(&G, i, j, nz - 1, 3, &B);
+                    S->piece(S, i, j - 1, nz - 1, 4, &A);
+                    S->piece(S, i, j, nz - 1, 3, &B);
                     shift(&A, 0, -dy, 0);
                     combine(&A, &B, 1, &C);
                     C.fa[4] = C.fa[5];
                     for (int e = 0; e < 3; ++e) C.fm[4][e] = C.fm[5][e];
                     store_zface(g, &C, 0.5 * dx, 0.0, geo[2], NI, idx);
                     /* z instance: lower face of pseudo CV nz = mid plane of cell nz-1 */
-                    piece(&G, i, j, nz - 1, 6, &A);
+                    S->piece(S, i, j, nz - 1, 6, &A);
                     store_zface(g, &A, 0.5 * dx, 0.5 * dy, geo[3], NI, idx);
                     continue;
                 }
                 /* cell-centred instance */
                 {
                     BoxOut o;
-                    piece(&G, i, j, k, 0, &o);
+                    S->piece(S, i, j, k, 0, &o);
                     store_cv(g, &o, 0.5 * dx, 0.5 * dy, 0.5 * dz, geo[0], NI, idx);
-                    ctype[0][idx] = (int8_t)piece_type(&G, i, j, k, 0);
+                    ctype[0][idx] = (int8_t)S->type(S, i, j, k, 0);
                 }
                 /* x-face instance: hi-x half of cell i-1 + lo-x half of cell i */
                 {
                     BoxOut A, B, C;
-                    piece(&G, i - 1, j, k, 2, &A);
-                    piece(&G, i, j, k, 1, &B);
+                    S->piece(S, i - 1, j, k, 2, &A);
+                    S->piece(S, i, j, k, 1, &B);
                     shift(&A, -dx, 0, 0);
                     combine(&A, &B, 0, &C);
                     store_cv(g, &C, 0.0, 0.5 * dy, 0.5 * dz, geo[1], NI, idx);
-                    ctype[1][idx] = (int8_t)combine_type(piece_type(&G, i - 1, j, k, 2),
-                                                         piece_type(&G, i, j, k, 1));
+                    ctype[1][idx] = (int8_t)combine_type(S->type(S, i - 1, j, k, 2),
+                                                         S->type(S, i, j, k, 1));
                 }
                 /* y-face instance */
                 {
                     BoxOut A, B, C;
-                    piece(&G, i, j - 1, k, 4, &A);
-                    piece(&G, i, j, k, 3, &B);
+                    S->piece(S, i, j - 1, k, 4, &A);
+                    S->piece(S, i, j, k, 3, &B);
                     shift(&A, 0, -dy, 0);
                     combine(&A, &B, 1, &C);
                     store_cv(g, &C, 0.5 * dx, 0.0, 0.5 * dz, geo[2], NI, idx);
-                    ctype[2][idx] = (int8_t)combine_type(piece_type(&G, i, j - 1, k, 4),
-                                                         piece_type(&G, i, j, k, 3));
+                    ctype[2][idx] = (int8_t)combine_type(S->type(S, i, j - 1, k, 4),
+                                                         S->type(S, i, j, k, 3));
                 }
                 /* z-face instance: hi-z half of cell k-1 + lo-z half of cell k (k >= 1) */
                 if (k >= 1) {
                     BoxOut A, B, C;
-                    piece(&G, i, j, k - 1, 6, &A);
-                    piece(&G, i, j, k, 5, &B);
+                    S->piece(S, i, j, k - 1, 6, &A);
+                    S->piece(S, i, j, k, 5, &B);
                     shift(&A, 0, 0, -dz);
                     combine(&A, &B, 2, &C);
                     store_cv(g, &C, 0.5 * dx, 0.5 * dy, 0.0, geo[3], NI, idx);
-                    ctype[3][idx] = (int8_t)combine_type(piece_type(&G, i, j, k - 1, 6),
-                                                         piece_type(&G, i, j, k, 5));
+                    ctype[3][idx] = (int8_t)combine_type(S->type(S, i, j, k - 1, 6),
+                                                         S->type(S, i, j, k, 5));
                 }
             }
         }

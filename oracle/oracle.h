@@ -63,6 +63,21 @@ typedef struct {
 int orc_geometry(const orc_grid* g, const double* h_nodes, double* const geo[4],
                  int8_t* const ctype[4]);
 
+/* Geometry of a general level set phi (Section 3.2), layout as orc_geometry.
+ * phi_nodes: (nz+1) x (ny+1) x (nx+1) nodal values, x fastest; fluid is
+ * {phi > 0} for the piecewise linear interpolant over the six Kuhn
+ * tetrahedra of every cell.  phi must be nondecreasing along z at every node
+ * column; returns 1 (and writes nothing) otherwise. */
+int orc_geometry_levelset(const orc_grid* g, const double* phi_nodes, double* const geo[4],
+                          int8_t* const ctype[4]);
+
+/* Moments of box piece `part` (0 whole cell, 1/2 lower/upper half in x, 3/4
+ * in y, 5/6 in z) of cell (i,j,k) for a level set, relative to the cell's
+ * lower node: out = [vol, mx, my, mz, EB area vector x,y,z, EB area, 6 face
+ * areas, type (0 covered, 1 regular, 2 cut)].  Exposed for tests. */
+int orc_levelset_piece(const orc_grid* g, const double* phi_nodes, int i, int j, int k, int part,
+                       double* out);
+
 /* redistribution tables: w[inst] points at OW_N * (nz+1)*ny*nx doubles */
 int orc_wsrd_setup(const orc_grid* g, double* const geo[4], double* const w[4]);
 

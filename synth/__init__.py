@@ -56,6 +56,7 @@ class Workload:
     boxes: list = field(default_factory=list)   # [(lo3, hi3)], half-open cell ranges
     state_kind: str = "c1"
     terrain_note: str = ""
+    phi_nodes: np.ndarray = None  # level-set workloads: (nz+1, ny+1, nx+1) nodal values
 
 
 def field_shapes(n):
@@ -354,6 +355,80 @@ def boxes_split(n, seed: int, target: int, block: int = 64, unit: int = 16):
 
 
 # -------------------------------------------------------------------- workloads
+
+# ------------------------------------------------------------------ level sets
+
+def node_coords3(grid: Grid):
+    x, y = node_coords(grid)
+    z = grid.lo[2] + np.arange(grid.n[2] + 1, dtype=np.float64) * grid.dx[2]
+    return x, y, z
+
+
+def _periodic_fix3(phi: np.ndarray) -> np.ndarray:
+    phi[:, :, -1] = phi[:, :, 0]
+    phi[:, -1, :] = phi[:, 0, :]
+    return phi
+
+
+def levelset_terrain(grid: Grid, h_nodes: np.ndarray) -> np.ndarray:
+    """phi = z - h(x, y) at the nodes: the terrain as a level set."""
+    _, _, z = node_coords3(grid)
+    return np.ascontiguousarray(z[:, None, None] - h_nodes[None, :, :])
+
+
+def levelset_hemisphere(grid: Grid, radius: float, centre=None) -> np.ndarray:
+    """Signed distance to a hemisphere of the given radius standing on the
+    domain bottom (Section 6.2), centred in x and y unless given; periodic
+    minimum image in x and y."""
+    x, y, z = node_coords3(grid)
+    Lx, Ly, _ = grid.length
+    cx, cy = centre if centre is not None else (grid.lo[0] + Lx / 2, grid.lo[1] + Ly / 2)
+    dx = _min_image(x - cx, Lx)
+    dy = _min_image(y - cy, Ly)
+    dz = z - grid.lo[2]
+    r = np.sqrt(dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2)
+    return _periodic_fix3(np.ascontiguousarray(r - radius))
+
+
+def levelset_box_cylinder(grid: Grid, width: float, height: float, angle: float,
+                          centre=None) -> np.ndarray:
+    """Signed distance to a wall-mounted square cylinder (Section 6.3) of the
+    given width and height standing on the domain bottom, its sides turned by
+    `angle` against the grid lines; periodic minimum image in x and y."""
+    x, y, z = node_coords3(grid)
+    Lx, Ly, _ = grid.length
+    cx, cy = centre if centre is not None else (grid.lo[0] + Lx / 2, grid.lo[1] + Ly / 2)
+    dx = _min_image(x - cx, Lx)[None, None, :]
+    dy = _min_image(y - cy, Ly)[None, :, None]
+    dz = (z - grid.lo[2])[:, None, None]
+    c, s = np.cos(angle), np.sin(angle)
+    qx = np.abs(c * dx + s * dy) - 0.5 * width
+    qy = np.abs(-s * dx + c * dy) - 0.5 * width
+    qz = np.abs(dz) - height
+    qx, qy, qz = np.broadcast_arrays(qx, qy, qz)
+    out = np.sqrt(np.maximum(qx, 0) ** 2 + np.maximum(qy, 0) ** 2 + np.maximum(qz, 0) ** 2)
+    inside = np.minimum(np.maximum(np.maximum(qx, qy), qz), 0.0)
+    return _periodic_fix3(np.ascontiguousarray(out + inside))
+
+
+def make_levelset_workload(name: str) -> Workload:
+    """Level-set geometries of the paper's validation cases, on windows sized
+    for the oracle: "hemisphere" (radius 0.5 on the paper's mesh spacing
+    10/256, a 64 x 64 x 32 window around it) and "cylinder" (square cylinder
+    of width 1 and height 3 at 12 cells per width, turned by 0.3 rad, in a
+    48^3 window of edge 4)."""
+    if name == "hemisphere":
+        d = 10.0 / 256
+        g = Grid((64, 64, 32), (d, d, d))
+        return Workload("hemisphere_64x64x32", g, None, cfl_dt(g), 21, [((0, 0, 0), g.n)], "unit",
+                        phi_nodes=levelset_hemisphere(g, 0.5))
+    if name == "cylinder":
+        d = 1.0 / 12
+        g = Grid((48, 48, 48), (d, d, d))
+        return Workload("cylinder_48x48x48", g, None, cfl_dt(g), 22, [((0, 0, 0), g.n)], "unit",
+                        phi_nodes=levelset_box_cylinder(g, 1.0, 3.0, 0.3))
+    raise ValueError(f"unknown level-set workload {name}")
+
 
 def make_workload(cfg: int) -> Workload:
     """Configurations 1-5 (see the design notes for the full recipe)."""

@@ -191,3 +191,65 @@ def sample_facet(h_nodes, grid, box, M=400):
     if A <= 0:
         return 0.0, np.zeros(3)
     return float(A), np.array([(X * w).sum(), (Y * w).sum(), (h * w).sum()]) * dA / A
+
+
+# ------------------------------------------------------------------ level sets
+
+def kuhn_phi(phi_nodes, grid, x, y, z):
+    """Piecewise-linear interpolant of nodal phi ((nz+1, ny+1, nx+1)) over
+    the six Kuhn tetrahedra of each cell, evaluated at points: with the unit
+    coordinates sorted u(1) >= u(2) >= u(3) (axes s0, s1, s2) the value is
+    (1 - u(1)) phi(0) + (u(1) - u(2)) phi(e_s0) + (u(2) - u(3)) phi(e_s0 + e_s1)
+    + u(3) phi(1, 1, 1)."""
+    nx, ny, nz = grid.n
+    x, y, z = np.broadcast_arrays(np.asarray(x, float), np.asarray(y, float), np.asarray(z, float))
+    f = [(x - grid.lo[0]) / grid.dx[0], (y - grid.lo[1]) / grid.dx[1], (z - grid.lo[2]) / grid.dx[2]]
+    lim = (nx - 1, ny - 1, nz - 1)
+    idx = [np.clip(np.floor(f[d]).astype(int), 0, lim[d]) for d in range(3)]
+    u = np.stack([f[d] - idx[d] for d in range(3)], axis=-1)
+    order = np.argsort(-u, axis=-1, kind="stable")
+    us = np.take_along_axis(u, order, axis=-1)
+
+    def node(bits):
+        return phi_nodes[idx[2] + bits[..., 2], idx[1] + bits[..., 1], idx[0] + bits[..., 0]]
+
+    b = np.zeros(u.shape, dtype=int)
+    val = (1.0 - us[..., 0]) * node(b)
+    for m in range(3):
+        np.put_along_axis(b, order[..., m:m + 1], 1, axis=-1)
+        w = us[..., m] - (us[..., m + 1] if m < 2 else 0.0)
+        val = val + w * node(b)
+    return val
+
+
+def levelset_fluid_length(phi_nodes, grid, x, y, z0, z1):
+    """Length of {z in [z0, z1] : phi > 0} on vertical lines at points (x, y)
+    (arrays): the interpolant is linear in z between the breakpoints z_k + u dz
+    and z_k + v dz (u, v the point's unit x, y coordinates) and the node
+    planes, so the positive part of every segment is exact."""
+    x = np.asarray(x, float)
+    y = np.asarray(y, float)
+    dz = grid.dx[2]
+    u = (x - grid.lo[0]) / grid.dx[0]
+    v = (y - grid.lo[1]) / grid.dx[1]
+    u = u - np.floor(u)
+    v = v - np.floor(v)
+    k0 = int(np.floor((z0 - grid.lo[2]) / dz))
+    k1 = int(np.ceil((z1 - grid.lo[2]) / dz))
+    bps = [np.full(x.shape, z0), np.full(x.shape, z1)]
+    for k in range(k0, k1 + 1):
+        zk = grid.lo[2] + k * dz
+        for t in (np.zeros(x.shape), u, v):
+            bps.append(np.clip(zk + t * dz, z0, z1))
+    B = np.sort(np.stack(bps, axis=-1), axis=-1)
+    L = np.zeros(x.shape)
+    for q in range(B.shape[-1] - 1):
+        za, zb = B[..., q], B[..., q + 1]
+        fa = kuhn_phi(phi_nodes, grid, x, y, za)
+        fb = kuhn_phi(phi_nodes, grid, x, y, zb)
+        seg = zb - za
+        pos = np.where((fa > 0) & (fb > 0), seg,
+                       np.where((fa > 0) | (fb > 0),
+                                seg * np.maximum(fa, fb) / np.maximum(np.abs(fa - fb), 1e-300), 0.0))
+        L += np.where(seg > 0, pos, 0.0)
+    return L
