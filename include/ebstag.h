@@ -150,6 +150,26 @@ ebs_status ebs_create(const ebs_grid* grid, const ebs_box* boxes, int32_t nbox, 
  * EBS_E_ORDER until a build succeeds). */
 ebs_status ebs_build_geometry_terrain(ebs_ctx* ctx, const double* h_nodes, int32_t on_device);
 
+/* The same build from a general level set (Section 3.2: the EB is the zero
+ * set of an implicit function such as a signed distance, sampled at the
+ * nodes; Sections 6.2-6.3 use a hemisphere and a wall-mounted square
+ * cylinder).  phi_nodes has (nx+1)*(ny+1)*(nz+1) doubles, x fastest, then y,
+ * then z, on the host (on_device = 0) or device; node index n of a periodic
+ * axis repeats node 0.  Inside every cell the level set is interpolated
+ * linearly over the six Kuhn tetrahedra {1 >= u[s0] >= u[s1] >= u[s2] >= 0}
+ * (u the unit cell coordinates, s a permutation of the axes) and the fluid
+ * is where it is positive; a face carries fluid where phi > 0 (phi >= 0 on
+ * the domain bottom), a piece of the zero set belongs to the fluid it
+ * bounds, and on the domain bottom the wall takes precedence.  phi = z - h
+ * gives the terrain geometry of ebs_build_geometry_terrain.  Synchronous.
+ * Errors: EBS_E_ARG (non-finite values, non-periodic node rows, phi <= 0 at
+ * a node of the plane below the top cell layer), EBS_E_UNSUPPORTED (phi
+ * decreasing along z at some node column: every column must be covered,
+ * cut, then regular from the bottom up; and the sizes of
+ * ebs_build_geometry_terrain), EBS_E_OOM, EBS_E_HIP; rebuild and failure
+ * behaviour as for ebs_build_geometry_terrain. */
+ebs_status ebs_build_geometry_levelset(ebs_ctx* ctx, const double* phi_nodes, int32_t on_device);
+
 /* Copy one quantity (EBS_Q_*) of instance inst (0 cell, 1 x-face, 2 y-face,
  * 3 z-face) to host memory in the instance's state layout (n = element count
  * of that layout).  Synchronous. */

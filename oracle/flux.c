@@ -182,7 +182,10 @@ static double fhat(const Diag* D, int field, int d, int i, int j, int k) {
     return m * pf;
 }
 
-static int sgn0(double x) { return x > 0.0 ? 1 : (x < 0.0 ? -1 : 0); }
+/* side of a face-centroid offset (mesh units); offsets within 1e-12 of zero
+ * count as none: a face cut by a vertical wall has its centroid at
+ * mid-height, which rounding puts a few 1e-17 to either side */
+static int sgn0(double x) { return x > 1e-12 ? 1 : (x < -1e-12 ? -1 : 0); }
 
 /* flux used in the divergence on the lower d-face of CV (i,j,k) */
 static double face_flux(const Diag* D, int field, int d, int i, int j, int k) {
@@ -216,7 +219,7 @@ static double face_flux(const Diag* D, int field, int d, int i, int j, int k) {
         if (nb[q][2] != k && !is_cv(c, inst, nb[q][2])) return F0;
         if (!(G(c, inst, qb, nb[q][0], nb[q][1], nb[q][2]) > 0.0)) return F0;
     }
-    const double w1 = fabs(g1), w2 = fabs(g2);
+    const double w1 = s1 ? fabs(g1) : 0.0, w2 = s2 ? fabs(g2) : 0.0;
     double F = (1.0 - w1) * (1.0 - w2) * F0;
     if (use[0]) F += w1 * (1.0 - w2) * fhat(D, field, d, nb[0][0], nb[0][1], nb[0][2]);
     if (use[1]) F += (1.0 - w1) * w2 * fhat(D, field, d, nb[1][0], nb[1][1], nb[1][2]);

@@ -252,6 +252,58 @@ ebs_status ebs_destroy(ebs_ctx* c) {
     return EBS_OK;
 }
 
+// Everything after the upload of a validated terrain (d_h) or level set
+// (d_phi), both device arrays.
+static ebs_status build_from(ebs_ctx* c, const double* d_h, const double* d_phi) {
+    // The build replaces every table the stages read.  Work queued on the
+    // context's streams may still read them, and a graph captured on the old
+    // tables must never be replayed: wait, drop the graph, and leave the
+    // context without geometry until the whole build has succeeded.
+    EBS_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->side) EBS_HIP(c, hipStreamSynchronize(c->side));
+    c->join_pending = false;
+    drop_graph(c);
+    c->have_geom = false;
+    c->have_adv = false;
+    // The general range is built three times at most: with the footprint of
+    // the small CVs (mode 1), then with the cells the resulting redistribution
+    // tables actually touch (mode 2).  The set-up steps check that every
+    // stencil, interpolation and redistribution read stays inside the range;
+    // a check that fails falls back to the previous mode (mode 0 takes every
+    // CV below kr as possibly small).  ebs_set_range_rule caps the strictest
+    // mode tried.
+    auto build_all = [&](int mode) -> ebs_status {
+        c->range_mode = mode;
+        ebs_status r = build_geometry(c, d_h, d_phi);
+        (void)hipStreamSynchronize(c->stream);
+        if (r == EBS_OK) r = build_cut_faces(c);
+        if (r == EBS_OK) r = build_stencils(c);
+        if (r == EBS_OK) r = wsrd_setup(c);
+        return r;
+    };
+    ebs_status st = build_all(std::min(c->range_rule, 1));
+    if (st == EBS_OK && c->range_rule == 2) {
+        std::vector<int32_t> ftop;
+        st = redistribution_tops(c, ftop);
+        if (st == EBS_OK) {
+            c->h_ftop.swap(ftop);
+            st = build_all(2);
+            if (st == EBS_E_UNSUPPORTED) st = build_all(1);
+        }
+    }
+    if (st == EBS_E_UNSUPPORTED && c->range_mode != 0) st = build_all(0);
+    if (st != EBS_OK) return st;
+    st = build_tiles(c);
+    if (st != EBS_OK) return st;
+    if (c->diff_on) {
+        st = build_diffusion(c);
+        if (st != EBS_OK) return st;
+    }
+    EBS_HIP(c, hipStreamSynchronize(c->stream));
+    c->have_geom = true;
+    return EBS_OK;
+}
+
 ebs_status ebs_build_geometry_terrain(ebs_ctx* c, const double* h_nodes, int32_t on_device) {
     if (!c || !h_nodes) return fail(c, EBS_E_ARG, "null argument");
     const size_t nn = (size_t)(c->nx + 1) * (c->ny + 1);
@@ -271,16 +323,6 @@ ebs_status ebs_build_geometry_terrain(ebs_ctx* c, const double* h_nodes, int32_t
         if (h[(size_t)j * W + c->nx] != h[(size_t)j * W]) return fail(c, EBS_E_ARG, "terrain not periodic in x");
     for (int i = 0; i <= c->nx; ++i)
         if (h[(size_t)c->ny * W + i] != h[i]) return fail(c, EBS_E_ARG, "terrain not periodic in y");
-    // The build replaces every table the stages read.  Work queued on the
-    // context's streams may still read them, and a graph captured on the old
-    // tables must never be replayed: wait, drop the graph, and leave the
-    // context without geometry until the whole build has succeeded.
-    EBS_HIP(c, hipStreamSynchronize(c->stream));
-    if (c->side) EBS_HIP(c, hipStreamSynchronize(c->side));
-    c->join_pending = false;
-    drop_graph(c);
-    c->have_geom = false;
-    c->have_adv = false;
     double* d_h = nullptr;
     if (hipMalloc(&d_h, sizeof(double) * nn) != hipSuccess) return fail(c, EBS_E_OOM, "terrain upload");
     hipError_t e = hipMemcpy(d_h, h.data(), sizeof(double) * nn, hipMemcpyHostToDevice);
@@ -288,44 +330,47 @@ ebs_status ebs_build_geometry_terrain(ebs_ctx* c, const double* h_nodes, int32_t
         (void)hipFree(d_h);
         return hip_fail(c, e, "terrain upload");
     }
-    // The general range is built three times at most: with the footprint of
-    // the small CVs (mode 1), then with the cells the resulting redistribution
-    // tables actually touch (mode 2).  The set-up steps check that every
-    // stencil, interpolation and redistribution read stays inside the range;
-    // a check that fails falls back to the previous mode (mode 0 takes every
-    // CV below kr as possibly small).  ebs_set_range_rule caps the strictest
-    // mode tried.
-    auto build_all = [&](int mode) -> ebs_status {
-        c->range_mode = mode;
-        ebs_status r = build_geometry(c, d_h);
-        (void)hipStreamSynchronize(c->stream);
-        if (r == EBS_OK) r = build_cut_faces(c);
-        if (r == EBS_OK) r = build_stencils(c);
-        if (r == EBS_OK) r = wsrd_setup(c);
-        return r;
-    };
-    ebs_status st = build_all(std::min(c->range_rule, 1));
-    if (st == EBS_OK && c->range_rule == 2) {
-        std::vector<int32_t> ftop;
-        st = redistribution_tops(c, ftop);
-        if (st == EBS_OK) {
-            c->h_ftop.swap(ftop);
-            st = build_all(2);
-            if (st == EBS_E_UNSUPPORTED) st = build_all(1);
-        }
-    }
-    if (st == EBS_E_UNSUPPORTED && c->range_mode != 0) st = build_all(0);
+    const ebs_status st = build_from(c, d_h, nullptr);
     (void)hipFree(d_h);
-    if (st != EBS_OK) return st;
-    st = build_tiles(c);
-    if (st != EBS_OK) return st;
-    if (c->diff_on) {
-        st = build_diffusion(c);
-        if (st != EBS_OK) return st;
+    return st;
+}
+
+ebs_status ebs_build_geometry_levelset(ebs_ctx* c, const double* phi_nodes, int32_t on_device) {
+    if (!c || !phi_nodes) return fail(c, EBS_E_ARG, "null argument");
+    const int nx = c->nx, ny = c->ny, nz = c->nz;
+    const size_t plane = (size_t)(nx + 1) * (ny + 1), nn = plane * (nz + 1);
+    std::vector<double> f(nn);
+    if (on_device) {
+        EBS_HIP(c, hipMemcpy(f.data(), phi_nodes, sizeof(double) * nn, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(f.data(), phi_nodes, sizeof(double) * nn);
     }
-    EBS_HIP(c, hipStreamSynchronize(c->stream));
-    c->have_geom = true;
-    return EBS_OK;
+    for (size_t q = 0; q < nn; ++q)
+        if (!isfinite(f[q])) return fail(c, EBS_E_ARG, "non-finite level set");
+    const int W = nx + 1;
+    for (int k = 0; k <= nz; ++k) {
+        const double* P = f.data() + (size_t)k * plane;
+        for (int j = 0; j <= ny; ++j)
+            if (P[(size_t)j * W + nx] != P[(size_t)j * W]) return fail(c, EBS_E_ARG, "level set not periodic in x");
+        for (int i = 0; i <= nx; ++i)
+            if (P[(size_t)ny * W + i] != P[i]) return fail(c, EBS_E_ARG, "level set not periodic in y");
+    }
+    for (size_t q = 0; q < plane; ++q)
+        if (!(f[(size_t)(nz - 1) * plane + q] > 0.0)) return fail(c, EBS_E_ARG, "level set reaches the top cell layer");
+    for (int k = 0; k < nz; ++k)
+        for (size_t q = 0; q < plane; ++q)
+            if (!(f[(size_t)(k + 1) * plane + q] >= f[(size_t)k * plane + q]))
+                return fail(c, EBS_E_UNSUPPORTED, "level set decreases along z (the column structure needs it nondecreasing)");
+    double* d_phi = nullptr;
+    if (hipMalloc(&d_phi, sizeof(double) * nn) != hipSuccess) return fail(c, EBS_E_OOM, "level-set upload");
+    hipError_t e = hipMemcpy(d_phi, f.data(), sizeof(double) * nn, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d_phi);
+        return hip_fail(c, e, "level-set upload");
+    }
+    const ebs_status st = build_from(c, nullptr, d_phi);
+    (void)hipFree(d_phi);
+    return st;
 }
 
 ebs_status ebs_geometry_export(ebs_ctx* c, int32_t inst, int32_t qty, double* host, size_t n) {

@@ -265,7 +265,8 @@ struct ebs_ctx {
 
 namespace ebs {
 // geometry (geom.hip)
-ebs_status build_geometry(ebs_ctx* c, const double* d_h);
+// exactly one of d_h (terrain heights) and d_phi (level set) is non-null
+ebs_status build_geometry(ebs_ctx* c, const double* d_h, const double* d_phi);
 // stage kernels (stage.hip)
 // defer_join: leave the regular-region kernel running on the side stream;
 // join_side() makes the context stream wait for it

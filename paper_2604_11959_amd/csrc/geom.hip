@@ -311,10 +311,235 @@ __device__ inline void combine_box(const BoxM& A, const BoxM& B, int d, BoxM& o)
     }
 }
 
+// ------------------------------------------------------ general level sets
+//
+// Fluid is {phi > 0} for the piecewise linear interpolant of nodal phi over
+// the six Kuhn tetrahedra of the cell, T_s = {1 >= u[s0] >= u[s1] >= u[s2]
+// >= 0} in unit cell coordinates, with vertices 0, e[s0], e[s0] + e[s1] and
+// (1,1,1).  The fluid part of a tetrahedron inside a box piece is cut into
+// tetrahedra in two steps, by the piece's mid-plane and then by phi = 0; a
+// tetrahedron cut by a plane leaves one corner tetrahedron or a prism of
+// three.  Every vertex carries the set of planes it lies on: the faces of
+// its Kuhn tetrahedron (bit m: the face opposite vertex m), the mid-plane and
+// the zero set.  A face of a final tetrahedron lies on a plane exactly when
+// all three of its vertices do, which books it to a box face, to the EB or
+// to the interior with no geometric tolerance.  Ties follow the terrain
+// rules: a face carries fluid where phi > 0 (phi >= 0 on the domain bottom),
+// a piece of the zero set belongs to the fluid it bounds, and on the domain
+// bottom the wall takes precedence.
+
+struct TV {
+    double x[3];  // offset from the cell's lower node
+    double f;     // the tetrahedron's linear level set
+    unsigned m;   // planes the point lies on
+};
+
+constexpr unsigned LS_F0 = 1u, LS_F3 = 8u, LS_MID = 16u, LS_ZERO = 32u;
+
+__constant__ int kKuhn[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+// point where the plane g = 0 crosses edge (a inside, g < 0; b outside, g >= 0)
+__device__ inline TV ls_cross(const TV& a, const TV& b, double ga, double gb, unsigned bit, bool zero_set) {
+    TV r;
+    if (gb == 0.0) {  // b lies on the plane
+        r = b;
+        r.m |= bit;
+        return r;
+    }
+    const double t = ga / (ga - gb);
+    for (int d = 0; d < 3; ++d) r.x[d] = (1.0 - t) * a.x[d] + t * b.x[d];
+    if (zero_set) {
+        r.f = 0.0;
+        r.m = (a.m & b.m) | bit;
+    } else {
+        r.f = (1.0 - t) * a.f + t * b.f;
+        r.m = (a.m & b.m) | bit | (r.f == 0.0 ? LS_ZERO : 0u);
+    }
+    return r;
+}
+
+// the part {g < 0} of tetrahedron v as at most three tetrahedra
+template <class Emit>
+__device__ inline void ls_cut(const TV* v, const double* g, unsigned bit, bool zero_set, Emit&& emit) {
+    int in[4], out[4], ni = 0, no = 0;
+    for (int q = 0; q < 4; ++q) {
+        if (g[q] < 0.0) in[ni++] = q;
+        else out[no++] = q;
+    }
+    if (ni == 0) return;
+    if (ni == 4) {
+        emit(v[0], v[1], v[2], v[3]);
+        return;
+    }
+    auto X = [&](int a, int b) { return ls_cross(v[a], v[b], g[a], g[b], bit, zero_set); };
+    if (ni == 1) {
+        const int a = in[0];
+        emit(v[a], X(a, out[0]), X(a, out[1]), X(a, out[2]));
+        return;
+    }
+    // a prism p0 p1 p2 - q0 q1 q2 with lateral edges p_i q_i, as three
+    // tetrahedra
+    TV p0, p1, p2, q0, q1, q2;
+    if (ni == 3) {
+        const int d = out[0];
+        p0 = v[in[0]]; p1 = v[in[1]]; p2 = v[in[2]];
+        q0 = X(in[0], d); q1 = X(in[1], d); q2 = X(in[2], d);
+    } else {
+        const int a = in[0], b = in[1];
+        p0 = v[a]; p1 = X(a, out[0]); p2 = X(a, out[1]);
+        q0 = v[b]; q1 = X(b, out[0]); q2 = X(b, out[1]);
+    }
+    emit(p0, p1, p2, q2);
+    emit(p0, p1, q1, q2);
+    emit(p0, q0, q1, q2);
+}
+
+__device__ inline bool same_point(const TV& a, const TV& b) {
+    return a.x[0] == b.x[0] && a.x[1] == b.x[1] && a.x[2] == b.x[2];
+}
+
+__device__ inline void ls_add_face(BoxM& o, int f, double A, const double c[3]) {
+    const int tg[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+    const int d = f / 2;
+    o.fa[f] += A;
+    o.ft[f][0] += A * c[tg[d][0]];
+    o.ft[f][1] += A * c[tg[d][1]];
+}
+
+// one fluid tetrahedron of Kuhn tetrahedron s: volume moments and its faces
+__device__ void ls_accumulate(const TV* p, const int* s, int mid_face, bool bottom, BoxM& o) {
+    for (int a = 0; a < 4; ++a)
+        for (int b = a + 1; b < 4; ++b)
+            if (same_point(p[a], p[b])) return;
+    double e[3][3];
+    for (int q = 0; q < 3; ++q)
+        for (int d = 0; d < 3; ++d) e[q][d] = p[q + 1].x[d] - p[0].x[d];
+    const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                       e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                       e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+    const double vol = fabs(det) / 6.0;
+    if (vol == 0.0) return;
+    o.vol += vol;
+    for (int d = 0; d < 3; ++d) o.m[d] += vol * 0.25 * (p[0].x[d] + p[1].x[d] + p[2].x[d] + p[3].x[d]);
+    for (int j = 0; j < 4; ++j) {
+        const TV& A = p[(j + 1) & 3];
+        const TV& B = p[(j + 2) & 3];
+        const TV& C = p[(j + 3) & 3];
+        const unsigned mk = A.m & B.m & C.m;
+        if (!(mk & (LS_F0 | LS_F3 | LS_MID | LS_ZERO))) continue;
+        const double u[3] = {B.x[0] - A.x[0], B.x[1] - A.x[1], B.x[2] - A.x[2]};
+        const double w[3] = {C.x[0] - A.x[0], C.x[1] - A.x[1], C.x[2] - A.x[2]};
+        double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+        const double area = 0.5 * sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        const double c[3] = {(A.x[0] + B.x[0] + C.x[0]) / 3.0, (A.x[1] + B.x[1] + C.x[1]) / 3.0,
+                             (A.x[2] + B.x[2] + C.x[2]) / 3.0};
+        if (mk & LS_ZERO) {
+            if (bottom && (mk & LS_F3) && s[2] == 2) {
+                ls_add_face(o, 4, area, c);
+            } else {
+                // a piece of the zero set bounding this fluid: its area
+                // vector points into the tetrahedron
+                const double* P = p[j].x;
+                const double side = cr[0] * (P[0] - A.x[0]) + cr[1] * (P[1] - A.x[1]) + cr[2] * (P[2] - A.x[2]);
+                const double sg = side > 0.0 ? 0.5 : -0.5;
+                for (int d = 0; d < 3; ++d) o.av[d] += sg * cr[d];
+                o.area += area;
+                for (int d = 0; d < 3; ++d) o.em[d] += area * c[d];
+            }
+        } else if (mk & LS_MID) {
+            ls_add_face(o, mid_face, area, c);
+        } else if (mk & LS_F0) {
+            ls_add_face(o, 2 * s[0] + 1, area, c);
+        } else {
+            ls_add_face(o, 2 * s[2], area, c);
+        }
+    }
+}
+
+// Moments of box piece `part` (0 the cell; 1 / 2 lower / upper half in x,
+// 3 / 4 in y, 5 / 6 in z) of a cell with nodal values ph (bit 0 = x, bit 1 =
+// y, bit 2 = z), relative to the cell's lower node; bottom marks a cell on
+// the domain bottom.
+__device__ void box_eval_ls(const double ph[8], double DX, double DY, double DZ, int part, bool bottom, BoxM& o) {
+    for (int q = 0; q < 6; ++q) { o.fa[q] = 0; o.ft[q][0] = o.ft[q][1] = 0; o.fz[q] = 0; }
+    o.vol = o.m[0] = o.m[1] = o.m[2] = 0;
+    o.av[0] = o.av[1] = o.av[2] = o.area = o.em[0] = o.em[1] = o.em[2] = 0;
+    const double del[3] = {DX, DY, DZ};
+    const int md = part ? (part - 1) / 2 : 0;
+    const bool upper = part && ((part - 1) % 2);
+    const int mid_face = part ? 2 * md + (upper ? 0 : 1) : -1;
+    const bool touches_bottom = bottom && part != 6;
+    for (int t = 0; t < 6; ++t) {
+        const int s[3] = {kKuhn[t][0], kKuhn[t][1], kKuhn[t][2]};
+        const int node[4] = {0, 1 << s[0], (1 << s[0]) | (1 << s[1]), 7};
+        TV v[4];
+        bool any = false;
+        for (int q = 0; q < 4; ++q) {
+            for (int d = 0; d < 3; ++d) v[q].x[d] = ((node[q] >> d) & 1) ? del[d] : 0.0;
+            v[q].f = ph[node[q]];
+            v[q].m = (0xFu & ~(1u << q)) | (v[q].f == 0.0 ? LS_ZERO : 0u);
+            any = any || v[q].f > 0.0;
+        }
+        if (!any) continue;
+        auto fluid = [&](const TV& a, const TV& b, const TV& c, const TV& d) {
+            const TV w[4] = {a, b, c, d};
+            const double g[4] = {-a.f, -b.f, -c.f, -d.f};
+            ls_cut(w, g, LS_ZERO, true, [&](const TV& p0, const TV& p1, const TV& p2, const TV& p3) {
+                const TV p[4] = {p0, p1, p2, p3};
+                ls_accumulate(p, s, mid_face, touches_bottom, o);
+            });
+        };
+        if (!part) {
+            fluid(v[0], v[1], v[2], v[3]);
+        } else {
+            double g[4];
+            for (int q = 0; q < 4; ++q) g[q] = (upper ? -1.0 : 1.0) * (v[q].x[md] - 0.5 * del[md]);
+            ls_cut(v, g, LS_MID, false, fluid);
+        }
+    }
+}
+
+// nodal values of cell (i, j, k) (i and j wrap periodically)
+__device__ inline void cell_phi(const double* phi, int nx, int ny, int i, int j, int k, double ph[8]) {
+    i = wrapi(i, nx);
+    j = wrapi(j, ny);
+    for (int c = 0; c < 8; ++c)
+        ph[c] = phi[((size_t)(k + ((c >> 2) & 1)) * (ny + 1) + j + ((c >> 1) & 1)) * (nx + 1) + i + (c & 1)];
+}
+
+// 0 covered, 1 regular, 2 cut for box piece `part`: the extremes of the
+// interpolant over the piece lie among its nodes and, for a half cell, the
+// midpoints of the tetrahedron edges crossing its mid-plane (node pairs
+// a <= b componentwise that differ in the split coordinate); samples on the
+// domain bottom count as fluid when >= 0.
+__device__ inline int ls_piece_type(const double ph[8], int part, bool bottom) {
+    bool covered = true, regular = true;
+    auto sample = [&](double v, bool onb) {
+        if (v > 0.0) covered = false;
+        if (onb ? !(v >= 0.0) : !(v > 0.0)) regular = false;
+    };
+    if (!part) {
+        for (int c = 0; c < 8; ++c) sample(ph[c], bottom && !(c & 4));
+    } else {
+        const int d = (part - 1) / 2, up = (part - 1) % 2;
+        for (int c = 0; c < 8; ++c)
+            if (((c >> d) & 1) == up) sample(ph[c], bottom && !(c & 4));
+        for (int a = 0; a < 8; ++a) {
+            if ((a >> d) & 1) continue;
+            for (int b = 0; b < 8; ++b) {
+                if (!((b >> d) & 1) || (a & b) != a) continue;
+                sample(0.5 * ph[a] + 0.5 * ph[b], bottom && !(a & 4) && !(b & 4));
+            }
+        }
+    }
+    return covered ? 0 : (regular ? 1 : 2);
+}
+
 struct GeomArgs {
     int nx, ny, nz;
     double dx, dy, dz, lo_z;
-    const double* h;   // nodes (ny+1) x (nx+1)
+    const double* h;   // terrain: nodes (ny+1) x (nx+1); null for a level set
+    const double* phi; // level set: nodes (nz+1) x (ny+1) x (nx+1); null for a terrain
     int32_t* kf;       // [4][ncol]
     int32_t* kr;
     int32_t* g0;
@@ -385,6 +610,52 @@ __global__ void k_classify(GeomArgs a) {
             }
             if (kf < 0 && !covered) kf = k;
             if (kr < 0 && regular) { kr = k; break; }
+        }
+        if (kf < 0) kf = k1 + 1;
+        if (kr < 0) kr = k1 + 1;
+        if (kf > kr) kf = kr;
+        a.kf[inst * ncol + c] = kf;
+        a.kr[inst * ncol + c] = kr;
+        gmin = min(gmin, kf);
+    }
+    a.g0[c] = gmin;
+}
+
+// Type of CV (inst, i, j, k) of a level set: the staggered CV is regular
+// (covered) when both halves are.
+__device__ inline int ls_cv_type(const GeomArgs& a, int inst, int i, int j, int k) {
+    double ph[8];
+    cell_phi(a.phi, a.nx, a.ny, i, j, k, ph);
+    if (inst == 0) return ls_piece_type(ph, 0, k == 0);
+    const int d = inst - 1;
+    double pn[8];
+    cell_phi(a.phi, a.nx, a.ny, i - (d == 0), j - (d == 1), k - (d == 2), pn);
+    const int ta = ls_piece_type(pn, 2 + 2 * d, k - (d == 2) == 0);
+    const int tb = ls_piece_type(ph, 1 + 2 * d, k == 0);
+    if (ta == 0 && tb == 0) return 0;
+    if (ta == 1 && tb == 1) return 1;
+    return 2;
+}
+
+// first fluid and first regular level of every instance in column (i, j),
+// for a level set nondecreasing along z (every column covered, cut, then
+// regular from the bottom up)
+__global__ void k_classify_ls(GeomArgs a) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncol = a.nx * a.ny;
+    if (c >= ncol) return;
+    const int i = c % a.nx, j = c / a.nx;
+    int gmin = a.nz;
+    for (int inst = 0; inst < 4; ++inst) {
+        int kf = -1, kr = -1;
+        const int k0 = inst == 3 ? 1 : 0, k1 = a.nz - 1;
+        for (int k = k0; k <= k1; ++k) {
+            const int ty = ls_cv_type(a, inst, i, j, k);
+            if (kf < 0 && ty != 0) kf = k;
+            if (ty == 1) {
+                kr = k;
+                break;
+            }
         }
         if (kf < 0) kf = k1 + 1;
         if (kr < 0) kr = k1 + 1;
@@ -491,15 +762,11 @@ __global__ void k_pack_types(RecArgs r, uint32_t* type4, uint32_t* fflag, const 
     fflag[g] = f;
 }
 
-__global__ void k_records(RecArgs r) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    const int inst = blockIdx.y;
-    if (g >= r.G) return;
+// Type of CV (inst, c, k) from the column's kf / kr; writes it and, for
+// non-cut CVs, their constant records.  Returns true for a cut CV.
+__device__ inline bool record_type(const RecArgs& r, int inst, int g, int c, int k) {
     const GeomArgs& a = r.a;
     const int ncol = a.nx * a.ny;
-    const int c = r.gcol[g];
-    const int i = c % a.nx, j = c / a.nx;
-    const int k = a.g0[c] + (g - r.goff[c]);
     const bool is_cv = inst == 3 ? (k >= 1 && k <= a.nz - 1) : (k <= a.nz - 1);
     int ty;
     if (!is_cv || k < a.kf[inst * ncol + c]) ty = 0;
@@ -514,8 +781,45 @@ __global__ void k_records(RecArgs r) {
             put(r, inst, GQ_BY, g, 1.0);
             put(r, inst, GQ_BZ, g, 1.0);
         }
-        return;
+        return false;
     }
+    return true;
+}
+
+// The record of a cut CV from its moments o (relative to the lower node of
+// the cell the CV is centred in, the CV centre at (cx, cy, cz) from there).
+__device__ inline void record_store(const RecArgs& r, int inst, int g, const BoxM& o, double cx, double cy,
+                                    double cz) {
+    const double DX = r.a.dx, DY = r.a.dy, DZ = r.a.dz;
+    const double dv = DX * DY * DZ;
+    const double del[3] = {DX, DY, DZ};
+    const double ctr[3] = {cx, cy, cz};
+    const double farea[3] = {DY * DZ, DX * DZ, DX * DY};
+    const int tg[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+    put(r, inst, GQ_ALPHA, g, o.vol / dv);
+    for (int d = 0; d < 3; ++d) {
+        const double fa = o.fa[2 * d];
+        put(r, inst, GQ_BX + d, g, fa / farea[d]);
+        for (int t = 0; t < 2; ++t) {
+            const int e = tg[d][t];
+            put(r, inst, GQ_FX1 + 2 * d + t, g, fa > 0.0 ? (o.ft[2 * d][t] / fa - ctr[e]) / del[e] : 0.0);
+        }
+        put(r, inst, GQ_VCX + d, g, o.vol > 0.0 ? (o.m[d] / o.vol - ctr[d]) / del[d] : 0.0);
+        put(r, inst, GQ_AX + d, g, o.av[d] / farea[d]);
+        put(r, inst, GQ_EBX + d, g, o.area > 0.0 ? (o.em[d] / o.area - ctr[d]) / del[d] : 0.0);
+    }
+    put(r, inst, GQ_AREA, g, o.area / (DX * DY));
+}
+
+__global__ void k_records(RecArgs r) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int inst = blockIdx.y;
+    if (g >= r.G) return;
+    const GeomArgs& a = r.a;
+    const int c = r.gcol[g];
+    const int i = c % a.nx, j = c / a.nx;
+    const int k = a.g0[c] + (g - r.goff[c]);
+    if (!record_type(r, inst, g, c, k)) return;
     const double DX = a.dx, DY = a.dy, DZ = a.dz;
     const Heights H = cell_heights(a.h, a.nx, a.ny, i, j);
     const double zk = zplane(a.lo_z, DZ, k);
@@ -548,24 +852,40 @@ __global__ void k_records(RecArgs r) {
         combine_box(A, B, 2, o);
         cz = 0.0;
     }
-    const double dv = DX * DY * DZ;
-    const double del[3] = {DX, DY, DZ};
-    const double ctr[3] = {cx, cy, cz};
-    const double farea[3] = {DY * DZ, DX * DZ, DX * DY};
-    const int tg[3][2] = {{1, 2}, {0, 2}, {0, 1}};
-    put(r, inst, GQ_ALPHA, g, o.vol / dv);
-    for (int d = 0; d < 3; ++d) {
-        const double fa = o.fa[2 * d];
-        put(r, inst, GQ_BX + d, g, fa / farea[d]);
-        for (int t = 0; t < 2; ++t) {
-            const int e = tg[d][t];
-            put(r, inst, GQ_FX1 + 2 * d + t, g, fa > 0.0 ? (o.ft[2 * d][t] / fa - ctr[e]) / del[e] : 0.0);
-        }
-        put(r, inst, GQ_VCX + d, g, o.vol > 0.0 ? (o.m[d] / o.vol - ctr[d]) / del[d] : 0.0);
-        put(r, inst, GQ_AX + d, g, o.av[d] / farea[d]);
-        put(r, inst, GQ_EBX + d, g, o.area > 0.0 ? (o.em[d] / o.area - ctr[d]) / del[d] : 0.0);
+    record_store(r, inst, g, o, cx, cy, cz);
+}
+
+// The same records for a level set: the staggered CVs join the halves of
+// the two cells they straddle.
+__global__ void k_records_ls(RecArgs r) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int inst = blockIdx.y;
+    if (g >= r.G) return;
+    const GeomArgs& a = r.a;
+    const int c = r.gcol[g];
+    const int i = c % a.nx, j = c / a.nx;
+    const int k = a.g0[c] + (g - r.goff[c]);
+    if (!record_type(r, inst, g, c, k)) return;
+    const double DX = a.dx, DY = a.dy, DZ = a.dz;
+    double ph[8], pn[8];
+    cell_phi(a.phi, a.nx, a.ny, i, j, k, ph);
+    BoxM o;
+    double cx = 0.5 * DX, cy = 0.5 * DY, cz = 0.5 * DZ;
+    if (inst == 0) {
+        box_eval_ls(ph, DX, DY, DZ, 0, k == 0, o);
+    } else {
+        BoxM A, B;
+        const int d = inst - 1;
+        cell_phi(a.phi, a.nx, a.ny, i - (d == 0), j - (d == 1), k - (d == 2), pn);
+        box_eval_ls(pn, DX, DY, DZ, 2 + 2 * d, d != 2 && k == 0, A);
+        box_eval_ls(ph, DX, DY, DZ, 1 + 2 * d, k == 0, B);
+        shift_box(A, d == 0 ? -DX : 0.0, d == 1 ? -DY : 0.0, d == 2 ? -DZ : 0.0);
+        combine_box(A, B, d, o);
+        if (d == 0) cx = 0.0;
+        if (d == 1) cy = 0.0;
+        if (d == 2) cz = 0.0;
     }
-    put(r, inst, GQ_AREA, g, o.area / (DX * DY));
+    record_store(r, inst, g, o, cx, cy, cz);
 }
 
 // highest level of a small CV (0 < volume fraction < vfrac, any instance) per
@@ -588,18 +908,22 @@ __global__ void k_small_top(RecArgs r, double vfrac, int32_t* stop) {
 
 static ebs_status build_range(ebs_ctx* cx, const GeomArgs& a);
 
-ebs_status build_geometry(ebs_ctx* cx, const double* d_h) {
+ebs_status build_geometry(ebs_ctx* cx, const double* d_h, const double* d_phi) {
     const int ncol = cx->ncol;
     GeomArgs a;
     a.nx = cx->nx; a.ny = cx->ny; a.nz = cx->nz;
     a.dx = cx->g.dx[0]; a.dy = cx->g.dx[1]; a.dz = cx->g.dx[2];
     a.lo_z = cx->g.lo[2];
     a.h = d_h;
+    a.phi = d_phi;
     a.kf = cx->d_kf; a.kr = cx->d_kr; a.g0 = cx->d_g0; a.g1 = cx->d_g1;
     a.stop = nullptr;
     a.ftop = nullptr;
     const int tb = 256;
-    hipLaunchKernelGGL(k_classify, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
+    if (d_phi)
+        hipLaunchKernelGGL(k_classify_ls, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
+    else
+        hipLaunchKernelGGL(k_classify, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
     EBS_HIP(cx, hipGetLastError());
     if (cx->range_mode == 2) {
         // one pass with the redistribution footprint of an earlier build
@@ -778,7 +1102,10 @@ static ebs_status build_range(ebs_ctx* cx, const GeomArgs& a) {
         r.G = cx->G;
         r.geo = cx->d_geo;
         r.type = cx->d_type;
-        hipLaunchKernelGGL(k_records, dim3((G + 127) / 128, NINST), dim3(128), 0, cx->stream, r);
+        if (a.phi)
+            hipLaunchKernelGGL(k_records_ls, dim3((G + 127) / 128, NINST), dim3(128), 0, cx->stream, r);
+        else
+            hipLaunchKernelGGL(k_records, dim3((G + 127) / 128, NINST), dim3(128), 0, cx->stream, r);
         hipLaunchKernelGGL(k_pack_types, dim3((G + 255) / 256), dim3(256), 0, cx->stream, r, cx->d_type4,
                            cx->d_fflag, cx->d_col);
         EBS_HIP(cx, hipGetLastError());

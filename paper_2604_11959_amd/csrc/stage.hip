@@ -315,8 +315,10 @@ struct Gen {
         r.c[1] = r.c[2] = r.c[3] = 0.0;
         if (!(b < 1.0)) return true;
         const double g1 = geo(s, GQ_FX1 + 2 * D, P.g), g2 = geo(s, GQ_FX1 + 2 * D + 1, P.g);
-        const int s1 = g1 > 0.0 ? 1 : (g1 < 0.0 ? -1 : 0);
-        const int s2 = g2 > 0.0 ? 1 : (g2 < 0.0 ? -1 : 0);
+        // offsets within 1e-12 of zero count as none (a face cut by a
+        // vertical wall has its centroid at mid-height up to rounding)
+        const int s1 = g1 > 1e-12 ? 1 : (g1 < -1e-12 ? -1 : 0);
+        const int s2 = g2 > 1e-12 ? 1 : (g2 < -1e-12 ? -1 : 0);
         if (s1 == 0 && s2 == 0) return true;
         const int ax = D == 0 ? 0 : s1, ay = D == 0 ? s1 : 0;
         const int by = D == 2 ? s2 : 0, bz = D == 2 ? 0 : s2;
@@ -335,7 +337,7 @@ struct Gen {
             N12 = at(wx(P.i + ax), wy(P.j + ay + by), P.k + bz);
             if (!(beta_rt<D>(s, N12) > 0.0)) return true;
         }
-        const double w1 = fabs(g1), w2 = fabs(g2);
+        const double w1 = u1 ? fabs(g1) : 0.0, w2 = u2 ? fabs(g2) : 0.0;
         r.c[0] = (1.0 - w1) * (1.0 - w2);
         bool ok = true;
         if (u1) { r.n[0] = N1.ge; r.c[1] = w1 * (1.0 - w2); ok &= N1.ge >= 0; }
