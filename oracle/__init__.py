@@ -23,7 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = ["geom.c", "levelset.c", "flux.c", "wsrd.c", "source.c", "restrict.c", "diffusion.c"]
+_SRC = ["geom.c", "levelset.c", "coarse.c", "flux.c", "wsrd.c", "source.c", "restrict.c", "diffusion.c"]
 
 # geometry quantity indices (mirror oracle.h)
 OQ = dict(ALPHA=0, BX=1, BY=2, BZ=3, FX1=4, FX2=5, FY1=6, FY2=7, FZ1=8, FZ2=9,
@@ -81,6 +81,7 @@ def _load():
         i8pp = P(P(C.c_int8))
         lib.orc_geometry.argtypes = [P(_Grid), dp, dpp, i8pp]
         lib.orc_geometry_levelset.argtypes = [P(_Grid), dp, dpp, i8pp]
+        lib.orc_geometry_merged.argtypes = [P(_Grid), dp, C.c_int, dpp, i8pp]
         lib.orc_levelset_piece.argtypes = [P(_Grid), dp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
         lib.orc_wsrd_setup.argtypes = [P(_Grid), dpp, dpp]
         lib.orc_advance.argtypes = [P(_Grid), dpp, dpp, dpp, dpp, C.c_double]
@@ -170,9 +171,11 @@ class Oracle:
     """
 
     def __init__(self, grid, h_nodes: np.ndarray = None, limiter: int = 0, eb_flux: int = 0,
-                 phi_nodes: np.ndarray = None):
+                 phi_nodes: np.ndarray = None, merged: bool = False):
         """Exactly one of h_nodes (terrain heights, (ny+1, nx+1)) and
-        phi_nodes (level set, (nz+1, ny+1, nx+1), nondecreasing in z)."""
+        phi_nodes (level set, (nz+1, ny+1, nx+1), nondecreasing in z).  With
+        merged=True they are the nodes of the grid refined by 2, and the
+        geometry of `grid` is merged from the fine cells (Section 4.3)."""
         lib = _load()
         if (h_nodes is None) == (phi_nodes is None):
             raise ValueError("give exactly one of h_nodes and phi_nodes")
@@ -188,7 +191,15 @@ class Oracle:
         self.geo = [np.zeros(shape) for _ in range(4)]
         self.ctype = [np.zeros((nz + 1, ny, nx), dtype=np.int8) for _ in range(4)]
         i8 = (C.POINTER(C.c_int8) * 4)(*[c.ctypes.data_as(C.POINTER(C.c_int8)) for c in self.ctype])
-        if h_nodes is not None:
+        if merged:
+            self.h = None
+            kind = 0 if h_nodes is not None else 1
+            self.fine_nodes = np.ascontiguousarray(h_nodes if kind == 0 else phi_nodes, dtype=np.float64)
+            want = (2 * ny + 1, 2 * nx + 1) if kind == 0 else (2 * nz + 1, 2 * ny + 1, 2 * nx + 1)
+            assert self.fine_nodes.shape == want
+            if lib.orc_geometry_merged(C.byref(self.g), _dptr(self.fine_nodes), kind, _dpp(self.geo), i8) != 0:
+                raise ValueError("level set not nondecreasing along z")
+        elif h_nodes is not None:
             self.h = np.ascontiguousarray(h_nodes, dtype=np.float64)
             assert self.h.shape == (ny + 1, nx + 1)
             lib.orc_geometry(C.byref(self.g), _dptr(self.h), _dpp(self.geo), i8)

@@ -462,16 +462,28 @@ static void store_zface(const orc_grid* g, const BoxOut* o, double cx, double cy
 }
 
 static void terrain_piece(const PieceSrc* s, int i, int j, int k, int part, BoxOut* o) {
-    piece((const GeoCtx*)s->data, i, j, k, part, o);
+    const NodeData* d = (const NodeData*)s->data;
+    const GeoCtx G = {d->g, d->v};
+    piece(&G, i, j, k, part, o);
 }
 
 static int terrain_type(const PieceSrc* s, int i, int j, int k, int part) {
-    return piece_type((const GeoCtx*)s->data, i, j, k, part);
+    const NodeData* d = (const NodeData*)s->data;
+    const GeoCtx G = {d->g, d->v};
+    return piece_type(&G, i, j, k, part);
+}
+
+void orc_terrain_src(const NodeData* d, PieceSrc* s) {
+    s->g = d->g;
+    s->data = d;
+    s->piece = terrain_piece;
+    s->type = terrain_type;
 }
 
 int orc_geometry(const orc_grid* g, const double* h, double* const geo[4], int8_t* const ctype[4]) {
-    GeoCtx G = {g, h};
-    PieceSrc S = {g, &G, terrain_piece, terrain_type};
+    const NodeData d = {g, h};
+    PieceSrc S;
+    orc_terrain_src(&d, &S);
     (void)node_h;
     return orc_assemble(&S, geo, ctype);
 }

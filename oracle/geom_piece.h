@@ -34,6 +34,17 @@ typedef struct PieceSrc {
     int (*type)(const struct PieceSrc* s, int i, int j, int k, int part);
 } PieceSrc;
 
+/* Nodal data of a source: terrain heights ((ny+1) x (nx+1)) or a level set
+ * ((nz+1) x (ny+1) x (nx+1)), x fastest; it must outlive the source. */
+typedef struct {
+    const orc_grid* g;
+    const double* v;
+} NodeData;
+
+/* The terrain builder's and the level-set builder's sources. */
+void orc_terrain_src(const NodeData* d, PieceSrc* s);
+void orc_levelset_src(const NodeData* d, PieceSrc* s);
+
 /* Fill geo / ctype (layout of orc_geometry) from a geometry source. */
 int orc_assemble(const PieceSrc* src, double* const geo[4], int8_t* const ctype[4]);
 

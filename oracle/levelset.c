@@ -342,7 +342,9 @@ static void tet_piece(const orc_grid* g, const double ph[8], int s, int part, in
 }
 
 static void ls_piece(const PieceSrc* S, int i, int j, int k, int part, BoxOut* o) {
-    const LsCtx* L = (const LsCtx*)S->data;
+    const NodeData* d = (const NodeData*)S->data;
+    const LsCtx Lc = {d->g, d->v};
+    const LsCtx* L = &Lc;
     double ph[8];
     cell_phi(L, i, j, k, ph);
     memset(o, 0, sizeof(*o));
@@ -356,7 +358,9 @@ static void ls_piece(const PieceSrc* S, int i, int j, int k, int part, BoxOut* o
  * componentwise that differ in the split coordinate).  Samples on the domain
  * bottom count as fluid when >= 0. */
 static int ls_type(const PieceSrc* S, int i, int j, int k, int part) {
-    const LsCtx* L = (const LsCtx*)S->data;
+    const NodeData* d = (const NodeData*)S->data;
+    const LsCtx Lc = {d->g, d->v};
+    const LsCtx* L = &Lc;
     double ph[8];
     cell_phi(L, i, j, k, ph);
     double smp[20];
@@ -404,15 +408,24 @@ int orc_geometry_levelset(const orc_grid* g, const double* phi, double* const ge
                 const size_t b = a + (size_t)(ny + 1) * (nx + 1);
                 if (!(phi[b] >= phi[a])) return 1;
             }
-    LsCtx L = {g, phi};
-    PieceSrc S = {g, &L, ls_piece, ls_type};
+    const NodeData d = {g, phi};
+    PieceSrc S;
+    orc_levelset_src(&d, &S);
     return orc_assemble(&S, geo, ctype);
+}
+
+void orc_levelset_src(const NodeData* d, PieceSrc* s) {
+    s->g = d->g;
+    s->data = d;
+    s->piece = ls_piece;
+    s->type = ls_type;
 }
 
 int orc_levelset_piece(const orc_grid* g, const double* phi, int i, int j, int k, int part,
                        double* out) {
-    LsCtx L = {g, phi};
-    PieceSrc S = {g, &L, ls_piece, ls_type};
+    const NodeData d = {g, phi};
+    PieceSrc S;
+    orc_levelset_src(&d, &S);
     BoxOut o;
     ls_piece(&S, i, j, k, part, &o);
     out[0] = o.vol;

@@ -78,6 +78,15 @@ int orc_geometry_levelset(const orc_grid* g, const double* phi_nodes, double* co
 int orc_levelset_piece(const orc_grid* g, const double* phi_nodes, int i, int j, int k, int part,
                        double* out);
 
+/* Geometry of the coarse grid g of a two-level hierarchy with refinement
+ * ratio 2, merged from the fine cells (Section 4.3): fine_nodes are the
+ * nodal terrain heights (kind 0, (2ny+1) x (2nx+1)) or level set (kind 1,
+ * (2nz+1) x (2ny+1) x (2nx+1)) of the fine grid (2n cells of dx/2, same
+ * origin).  Layout as orc_geometry; returns 1 for a level set that
+ * decreases along z. */
+int orc_geometry_merged(const orc_grid* g, const double* fine_nodes, int kind, double* const geo[4],
+                        int8_t* const ctype[4]);
+
 /* redistribution tables: w[inst] points at OW_N * (nz+1)*ny*nx doubles */
 int orc_wsrd_setup(const orc_grid* g, double* const geo[4], double* const w[4]);
 
