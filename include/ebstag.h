@@ -170,6 +170,25 @@ ebs_status ebs_build_geometry_terrain(ebs_ctx* ctx, const double* h_nodes, int32
  * behaviour as for ebs_build_geometry_terrain. */
 ebs_status ebs_build_geometry_levelset(ebs_ctx* ctx, const double* phi_nodes, int32_t on_device);
 
+/* The same build for the coarse level of a two-level hierarchy with
+ * refinement ratio 2 (Section 4.3: the coarse geometry is merged from the
+ * fine one, so that volumes and areas, and with them mass and mass fluxes,
+ * agree between the levels).  The context's grid is the coarse one;
+ * fine_nodes are the nodal values of the fine grid (2nx x 2ny x 2nz cells of
+ * half the spacing, same origin): terrain heights, (2nx+1)*(2ny+1) doubles
+ * (kind 0), or a level set, (2nx+1)*(2ny+1)*(2nz+1) doubles, x fastest
+ * (kind 1), on the host (on_device = 0) or device.  Every CV of every
+ * instance is the union of eight fine cells (a staggered CV around a coarse
+ * face spans the fine cells between the coarse cell centres on either
+ * side): volume, moments, EB area and vector are the sums of the fine
+ * cells', its faces the fine faces on its boundary, and it is covered
+ * (regular) when all eight fine cells are.  Its volume and face fractions
+ * are those ebs_coarsened_geometry and ebs_restrict use.  Synchronous.
+ * Errors as for ebs_build_geometry_terrain / ebs_build_geometry_levelset
+ * on the fine nodes, EBS_E_ARG for another kind; rebuild and failure
+ * behaviour as for ebs_build_geometry_terrain. */
+ebs_status ebs_build_geometry_merged(ebs_ctx* ctx, const double* fine_nodes, int32_t kind, int32_t on_device);
+
 /* Copy one quantity (EBS_Q_*) of instance inst (0 cell, 1 x-face, 2 y-face,
  * 3 z-face) to host memory in the instance's state layout (n = element count
  * of that layout).  Synchronous. */

@@ -27,7 +27,7 @@ Q = dict(ALPHA=0, BETA_X=1, BETA_Y=2, BETA_Z=3, FX_Y=4, FX_Z=5, FY_X=6, FY_Z=7, 
          XHAT_X=28, XHAT_Y=29, XHAT_Z=30)
 
 # every entry point declared in include/ebstag.h
-SYMBOLS = ("ebs_create", "ebs_build_geometry_terrain", "ebs_build_geometry_levelset", "ebs_geometry_export", "ebs_geometry_stats", "ebs_alpha_histogram",
+SYMBOLS = ("ebs_create", "ebs_build_geometry_terrain", "ebs_build_geometry_levelset", "ebs_build_geometry_merged", "ebs_geometry_export", "ebs_geometry_stats", "ebs_alpha_histogram",
            "ebs_advance_stage", "ebs_redistribute", "ebs_rk3_step", "ebs_conserved_sums",
            "ebs_autotune", "ebs_set_tile", "ebs_get_tile", "ebs_set_overlap", "ebs_set_persistent", "ebs_set_range_rule", "ebs_set_sources", "ebs_set_diffusion", "ebs_restrict", "ebs_coarsened_geometry", "ebs_coarsened_geometry_noalloc", "ebs_timing_enable", "ebs_timing_read",
            "ebs_algorithmic_bytes", "ebs_stream_copy", "ebs_last_error", "ebs_destroy")
@@ -78,6 +78,7 @@ def load(path: str = LIB_PATH):
         "ebs_create": [P(Grid), P(Box), C.c_int32, C.c_void_p, P(C.c_void_p)],
         "ebs_build_geometry_terrain": [C.c_void_p, P(C.c_double), C.c_int32],
         "ebs_build_geometry_levelset": [C.c_void_p, P(C.c_double), C.c_int32],
+        "ebs_build_geometry_merged": [C.c_void_p, P(C.c_double), C.c_int32, C.c_int32],
         "ebs_geometry_export": [C.c_void_p, C.c_int32, C.c_int32, P(C.c_double), C.c_size_t],
         "ebs_geometry_stats": [C.c_void_p, P(C.c_int64)],
         "ebs_alpha_histogram": [C.c_void_p, C.c_int32, P(C.c_double), C.c_int32, P(C.c_int64)],
@@ -210,6 +211,20 @@ class Context:
             raise ValueError(f"phi_nodes must have shape {(nz + 1, ny + 1, nx + 1)}")
         self._check(self.lib.ebs_build_geometry_levelset(
             self.h, f.ctypes.data_as(C.POINTER(C.c_double)), 0), "ebs_build_geometry_levelset")
+
+    def build_geometry_merged(self, fine_nodes):
+        """Geometry merged from the grid refined by 2: fine terrain heights
+        (2ny+1, 2nx+1) or a fine level set (2nz+1, 2ny+1, 2nx+1)."""
+        import numpy as np
+
+        f = np.ascontiguousarray(fine_nodes, dtype=np.float64)
+        nx, ny, nz = self.n
+        kind = 0 if f.ndim == 2 else 1
+        want = (2 * ny + 1, 2 * nx + 1) if kind == 0 else (2 * nz + 1, 2 * ny + 1, 2 * nx + 1)
+        if f.shape != want:
+            raise ValueError(f"fine nodes must have shape {want}")
+        self._check(self.lib.ebs_build_geometry_merged(
+            self.h, f.ctypes.data_as(C.POINTER(C.c_double)), kind, 0), "ebs_build_geometry_merged")
 
     def export(self, inst: int, qty: int):
         import numpy as np

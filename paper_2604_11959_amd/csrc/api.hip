@@ -373,6 +373,55 @@ ebs_status ebs_build_geometry_levelset(ebs_ctx* c, const double* phi_nodes, int3
     return st;
 }
 
+ebs_status ebs_build_geometry_merged(ebs_ctx* c, const double* fine_nodes, int32_t kind, int32_t on_device) {
+    if (!c || !fine_nodes) return fail(c, EBS_E_ARG, "null argument");
+    if (kind != 0 && kind != 1) return fail(c, EBS_E_ARG, "kind must be 0 (terrain) or 1 (level set)");
+    const int nx = 2 * c->nx, ny = 2 * c->ny, nz = 2 * c->nz;
+    const size_t plane = (size_t)(nx + 1) * (ny + 1), nn = kind == 0 ? plane : plane * (nz + 1);
+    std::vector<double> f(nn);
+    if (on_device) {
+        EBS_HIP(c, hipMemcpy(f.data(), fine_nodes, sizeof(double) * nn, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(f.data(), fine_nodes, sizeof(double) * nn);
+    }
+    for (size_t q = 0; q < nn; ++q)
+        if (!isfinite(f[q])) return fail(c, EBS_E_ARG, "non-finite fine nodal value");
+    const int W = nx + 1;
+    const int nplanes = kind == 0 ? 1 : nz + 1;
+    for (int k = 0; k < nplanes; ++k) {
+        const double* P = f.data() + (size_t)k * plane;
+        for (int j = 0; j <= ny; ++j)
+            if (P[(size_t)j * W + nx] != P[(size_t)j * W]) return fail(c, EBS_E_ARG, "fine nodes not periodic in x");
+        for (int i = 0; i <= nx; ++i)
+            if (P[(size_t)ny * W + i] != P[i]) return fail(c, EBS_E_ARG, "fine nodes not periodic in y");
+    }
+    if (kind == 0) {
+        const double ztop_clear = c->g.lo[2] + (double)(c->nz - 1) * c->g.dx[2];
+        for (size_t q = 0; q < nn; ++q)
+            if (!(f[q] < ztop_clear)) return fail(c, EBS_E_ARG, "terrain reaches the top cell layer");
+    } else {
+        // the coarse top layer starts at fine node plane nz - 2
+        for (size_t q = 0; q < plane; ++q)
+            if (!(f[(size_t)(nz - 2) * plane + q] > 0.0)) return fail(c, EBS_E_ARG, "level set reaches the top cell layer");
+        for (int k = 0; k < nz; ++k)
+            for (size_t q = 0; q < plane; ++q)
+                if (!(f[(size_t)(k + 1) * plane + q] >= f[(size_t)k * plane + q]))
+                    return fail(c, EBS_E_UNSUPPORTED, "level set decreases along z (the column structure needs it nondecreasing)");
+    }
+    double* d_f = nullptr;
+    if (hipMalloc(&d_f, sizeof(double) * nn) != hipSuccess) return fail(c, EBS_E_OOM, "fine node upload");
+    hipError_t e = hipMemcpy(d_f, f.data(), sizeof(double) * nn, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d_f);
+        return hip_fail(c, e, "fine node upload");
+    }
+    c->geo_merged = 1;
+    const ebs_status st = kind == 0 ? build_from(c, d_f, nullptr) : build_from(c, nullptr, d_f);
+    c->geo_merged = 0;
+    (void)hipFree(d_f);
+    return st;
+}
+
 ebs_status ebs_geometry_export(ebs_ctx* c, int32_t inst, int32_t qty, double* host, size_t n) {
     if (!c || !host) return fail(c, EBS_E_ARG, "null argument");
     if (!c->have_geom) return fail(c, EBS_E_ORDER, "geometry not built");

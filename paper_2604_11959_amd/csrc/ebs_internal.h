@@ -171,6 +171,7 @@ struct ebs_ctx {
     // (footprint window of the small CVs), 2 exact (the cells the
     // redistribution reads or writes, h_ftop, per column)
     int range_mode = 1;
+    int geo_merged = 0;  // the build in progress merges the geometry of the grid refined by 2
     int range_rule = 2;
     // momentum sources (ebs_set_sources): per-level tables [5][nz] of p0,
     // rho theta0 (high, low part), 1 / rho theta0, rho0 in the state precision

@@ -540,6 +540,8 @@ struct GeomArgs {
     double dx, dy, dz, lo_z;
     const double* h;   // terrain: nodes (ny+1) x (nx+1); null for a level set
     const double* phi; // level set: nodes (nz+1) x (ny+1) x (nx+1); null for a terrain
+    int merged;        // 1: h / phi hold the nodes of the grid refined by 2, and every
+                       // CV is the union of its eight fine cells (Section 4.3)
     int32_t* kf;       // [4][ncol]
     int32_t* kr;
     int32_t* g0;
@@ -654,6 +656,82 @@ __global__ void k_classify_ls(GeomArgs a) {
             if (kf < 0 && ty != 0) kf = k;
             if (ty == 1) {
                 kr = k;
+                break;
+            }
+        }
+        if (kf < 0) kf = k1 + 1;
+        if (kr < 0) kr = k1 + 1;
+        if (kf > kr) kf = kr;
+        a.kf[inst * ncol + c] = kf;
+        a.kr[inst * ncol + c] = kr;
+        gmin = min(gmin, kf);
+    }
+    a.g0[c] = gmin;
+}
+
+// ------------------------------------------------- merged coarse geometry
+//
+// With refinement ratio 2 every CV of every instance of the coarse grid is
+// the union of eight fine cells: the x-face CV around coarse face I spans
+// the coarse cell centres on either side, which are fine nodes, so it holds
+// fine cells 2I - 1 and 2I in x (likewise y and z), and a cell-centred CV
+// holds 2I and 2I + 1.  Its moments are the sums of the fine cells' (shifted
+// to the coarse node), its faces the fine faces on its boundary; it is
+// covered (regular) when all eight fine cells are.
+
+// first fine cell of coarse CV (inst, I, J, K) along each axis
+__device__ inline void merged_first(int inst, int I, int J, int K, int& fi, int& fj, int& fk) {
+    fi = 2 * I - (inst == 1);
+    fj = 2 * J - (inst == 2);
+    fk = 2 * K - (inst == 3);
+}
+
+// type of fine cell (fi, fj, fk): terrain samples against the fine levels,
+// or the level-set samples of the cell
+__device__ inline int fine_cell_type(const GeomArgs& a, int fi, int fj, int fk) {
+    if (a.phi) {
+        double ph[8];
+        cell_phi(a.phi, 2 * a.nx, 2 * a.ny, fi, fj, fk, ph);
+        return ls_piece_type(ph, 0, fk == 0);
+    }
+    const double fdz = 0.5 * a.dz;
+    double mn, mx;
+    half_range(cell_heights(a.h, 2 * a.nx, 2 * a.ny, fi, fj), 0, mn, mx);
+    if (mn >= zplane(a.lo_z, fdz, fk + 1)) return 0;
+    const bool regular = fk == 0 ? (mx <= zplane(a.lo_z, fdz, 0)) : (mx < zplane(a.lo_z, fdz, fk));
+    return regular ? 1 : 2;
+}
+
+__device__ inline int merged_cv_type(const GeomArgs& a, int inst, int I, int J, int K) {
+    int fi, fj, fk;
+    merged_first(inst, I, J, K, fi, fj, fk);
+    bool cov = true, reg = true;
+    for (int c = 0; c < 2; ++c)
+        for (int b = 0; b < 2; ++b)
+            for (int q = 0; q < 2; ++q) {
+                const int t = fine_cell_type(a, fi + q, fj + b, fk + c);
+                cov = cov && t == 0;
+                reg = reg && t == 1;
+            }
+    return cov ? 0 : (reg ? 1 : 2);
+}
+
+// first fluid and first regular level of every instance in coarse column
+// (I, J) of a merged geometry
+__global__ void k_classify_merged(GeomArgs a) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncol = a.nx * a.ny;
+    if (c >= ncol) return;
+    const int I = c % a.nx, J = c / a.nx;
+    int gmin = a.nz;
+    for (int inst = 0; inst < 4; ++inst) {
+        int kf = -1, kr = -1;
+        const int k0 = inst == 3 ? 1 : 0, k1 = a.nz - 1;
+        for (int K = k0; K <= k1; ++K) {
+            const int ty = merged_cv_type(a, inst, I, J, K);
+            if (kf < 0 && ty != 0) kf = K;
+            if (ty == 1) {
+                kr = K;
                 break;
             }
         }
@@ -888,6 +966,59 @@ __global__ void k_records_ls(RecArgs r) {
     record_store(r, inst, g, o, cx, cy, cz);
 }
 
+// moments of fine cell (fi, fj, fk) relative to its lower node
+__device__ inline void fine_box(const GeomArgs& a, int fi, int fj, int fk, BoxM& o) {
+    const double fdx = 0.5 * a.dx, fdy = 0.5 * a.dy, fdz = 0.5 * a.dz;
+    if (a.phi) {
+        double ph[8];
+        cell_phi(a.phi, 2 * a.nx, 2 * a.ny, fi, fj, fk, ph);
+        box_eval_ls(ph, fdx, fdy, fdz, 0, fk == 0, o);
+    } else {
+        const double zk = zplane(a.lo_z, fdz, fk);
+        box_eval(cell_heights(a.h, 2 * a.nx, 2 * a.ny, fi, fj), fdx, fdy, 0, zk, zplane(a.lo_z, fdz, fk + 1), zk,
+                 fk == 0, o);
+    }
+}
+
+// The records of a merged coarse geometry: the eight fine cells of each CV,
+// shifted to the coarse node and joined along x, then y, then z.
+__global__ void k_records_merged(RecArgs r) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int inst = blockIdx.y;
+    if (g >= r.G) return;
+    const GeomArgs& a = r.a;
+    const int c = r.gcol[g];
+    const int I = c % a.nx, J = c / a.nx;
+    const int K = a.g0[c] + (g - r.goff[c]);
+    if (!record_type(r, inst, g, c, K)) return;
+    const double fdx = 0.5 * a.dx, fdy = 0.5 * a.dy, fdz = 0.5 * a.dz;
+    int fi, fj, fk;
+    merged_first(inst, I, J, K, fi, fj, fk);
+    BoxM o, layer;
+    for (int cz = 0; cz < 2; ++cz) {
+        BoxM plane, row;
+        for (int cy = 0; cy < 2; ++cy) {
+            BoxM A, B;
+            fine_box(a, fi, fj + cy, fk + cz, A);
+            fine_box(a, fi + 1, fj + cy, fk + cz, B);
+            const double sy = (fj + cy - 2 * J) * fdy, sz = (fk + cz - 2 * K) * fdz;
+            shift_box(A, (fi - 2 * I) * fdx, sy, sz);
+            shift_box(B, (fi + 1 - 2 * I) * fdx, sy, sz);
+            if (cy == 0) {
+                combine_box(A, B, 0, row);
+            } else {
+                BoxM row1;
+                combine_box(A, B, 0, row1);
+                combine_box(row, row1, 1, plane);
+            }
+        }
+        if (cz == 0) layer = plane;
+        else combine_box(layer, plane, 2, o);
+    }
+    const double DX = a.dx, DY = a.dy, DZ = a.dz;
+    record_store(r, inst, g, o, inst == 1 ? 0.0 : 0.5 * DX, inst == 2 ? 0.0 : 0.5 * DY, inst == 3 ? 0.0 : 0.5 * DZ);
+}
+
 // highest level of a small CV (0 < volume fraction < vfrac, any instance) per
 // column of the general range
 __global__ void k_small_top(RecArgs r, double vfrac, int32_t* stop) {
@@ -916,11 +1047,14 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h, const double* d_phi) {
     a.lo_z = cx->g.lo[2];
     a.h = d_h;
     a.phi = d_phi;
+    a.merged = cx->geo_merged;
     a.kf = cx->d_kf; a.kr = cx->d_kr; a.g0 = cx->d_g0; a.g1 = cx->d_g1;
     a.stop = nullptr;
     a.ftop = nullptr;
     const int tb = 256;
-    if (d_phi)
+    if (a.merged)
+        hipLaunchKernelGGL(k_classify_merged, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
+    else if (d_phi)
         hipLaunchKernelGGL(k_classify_ls, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
     else
         hipLaunchKernelGGL(k_classify, dim3((ncol + tb - 1) / tb), dim3(tb), 0, cx->stream, a);
@@ -1102,7 +1236,9 @@ static ebs_status build_range(ebs_ctx* cx, const GeomArgs& a) {
         r.G = cx->G;
         r.geo = cx->d_geo;
         r.type = cx->d_type;
-        if (a.phi)
+        if (a.merged)
+            hipLaunchKernelGGL(k_records_merged, dim3((G + 127) / 128, NINST), dim3(128), 0, cx->stream, r);
+        else if (a.phi)
             hipLaunchKernelGGL(k_records_ls, dim3((G + 127) / 128, NINST), dim3(128), 0, cx->stream, r);
         else
             hipLaunchKernelGGL(k_records, dim3((G + 127) / 128, NINST), dim3(128), 0, cx->stream, r);
