@@ -1035,6 +1035,80 @@ __global__ void k_small_top(RecArgs r, double vfrac, int32_t* stop) {
     atomicMax(&stop[c], k);
 }
 
+// ------------------------------------------ general-range index on the GPU
+//
+// Per column: the general range [g0, g1) and the extended face range
+// [g0, g1e), which also holds the lower faces that bound a general CV from
+// above (+x, +y neighbours and the cell above the range) and the faces a
+// cut-face interpolation reads (one column away and up to one level above a
+// cut CV: up to level kr of every cut column in the 3 x 3 neighbourhood).
+// Their offsets are exclusive prefix sums of the column lengths; the cell
+// lists hold the column of every entry.
+
+// length of the general range and the interpolation reach of a column
+__global__ void k_range_len(const int32_t* g0, const int32_t* g1, const int32_t* kr, int ncol, int32_t* len,
+                            int32_t* krcut) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncol) return;
+    len[c] = g1[c] - g0[c];
+    int r = 0;
+    for (int s = 0; s < NINST; ++s) {
+        const int k = kr[(size_t)s * ncol + c];
+        if (k > (s == 3 ? 1 : 0)) r = max(r, k + 1);
+    }
+    krcut[c] = r;
+}
+
+__global__ void k_range_ext(const int32_t* g0, const int32_t* g1, const int32_t* krcut, int nx, int ny, int nz,
+                            int32_t* g1e, int32_t* lene) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nx * ny) return;
+    const int i = c % nx, j = c / nx;
+    const int own = g1[c] > g0[c] ? g1[c] + 1 : g0[c];
+    int interp = 0;
+    for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) interp = max(interp, krcut[wrapi(j + dj, ny) * nx + wrapi(i + di, nx)]);
+    const int e = min(nz, max(max(own, interp), max(g1[j * nx + wrapi(i - 1, nx)], g1[wrapi(j - 1, ny) * nx + i])));
+    g1e[c] = e;
+    lene[c] = e - g0[c];
+}
+
+// exclusive prefix sum of n values by one block, 1024 at a time with a
+// running carry; out[n] receives the total (64-bit, checked by the caller)
+__global__ void __launch_bounds__(1024) k_scan_excl(const int32_t* in, int n, int32_t* out, int64_t* total) {
+    __shared__ int64_t part[1024];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += 1024) {
+        const int q = base + (int)threadIdx.x;
+        const int64_t v = q < n ? in[q] : 0;
+        part[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int64_t t = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
+            __syncthreads();
+            part[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (q < n) out[q] = (int32_t)(carry + part[threadIdx.x] - v);
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += part[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+// column of every entry of both lists, and the packed column records
+__global__ void k_range_fill(const int32_t* g0, const int32_t* g1, const int32_t* g1e, const int32_t* goff,
+                             const int32_t* goffe, int ncol, int32_t* gcol, int32_t* gcole, int4* col) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncol) return;
+    for (int k = g0[c]; k < g1[c]; ++k) gcol[goff[c] + (k - g0[c])] = c;
+    for (int k = g0[c]; k < g1e[c]; ++k) gcole[goffe[c] + (k - g0[c])] = c;
+    col[c] = col_pack(g0[c], g1[c], g1e[c], goff[c], goffe[c]);
+}
+
 }  // namespace
 
 static ebs_status build_range(ebs_ctx* cx, const GeomArgs& a);
@@ -1127,74 +1201,72 @@ ebs_status build_geometry(ebs_ctx* cx, const double* d_h, const double* d_phi) {
 // cell allocations, geometry records, packed types and face flags
 static ebs_status build_range(ebs_ctx* cx, const GeomArgs& a) {
     const int ncol = cx->ncol;
+    const int tb = 256, nb = (ncol + tb - 1) / tb;
+    // the index is computed on the device; the host keeps copies of the
+    // per-column ranges for the set-up steps that run there
+    int32_t *d_len = nullptr, *d_krcut = nullptr, *d_g1e = nullptr, *d_lene = nullptr, *d_goffe = nullptr;
+    int64_t* d_tot = nullptr;
+    auto release = [&]() {
+        for (void* p : {(void*)d_len, (void*)d_krcut, (void*)d_g1e, (void*)d_lene, (void*)d_goffe, (void*)d_tot})
+            if (p) (void)hipFree(p);
+    };
+    bool ok = hipMalloc(&d_len, sizeof(int32_t) * ncol) == hipSuccess;
+    ok = ok && hipMalloc(&d_krcut, sizeof(int32_t) * ncol) == hipSuccess;
+    ok = ok && hipMalloc(&d_g1e, sizeof(int32_t) * ncol) == hipSuccess;
+    ok = ok && hipMalloc(&d_lene, sizeof(int32_t) * ncol) == hipSuccess;
+    ok = ok && hipMalloc(&d_goffe, sizeof(int32_t) * ncol) == hipSuccess;
+    ok = ok && hipMalloc(&d_tot, sizeof(int64_t) * 2) == hipSuccess;
+    if (cx->d_goff) (void)hipFree(cx->d_goff);
+    cx->d_goff = nullptr;
+    ok = ok && hipMalloc(&cx->d_goff, sizeof(int32_t) * ncol) == hipSuccess;
+    if (!ok) {
+        release();
+        cx->err = "device allocation of geometry tables failed";
+        return EBS_E_OOM;
+    }
+    int64_t tot[2] = {0, 0};
+    hipLaunchKernelGGL(k_range_len, dim3(nb), dim3(tb), 0, cx->stream, cx->d_g0, cx->d_g1, cx->d_kr, ncol, d_len,
+                       d_krcut);
+    hipLaunchKernelGGL(k_range_ext, dim3(nb), dim3(tb), 0, cx->stream, cx->d_g0, cx->d_g1, d_krcut, cx->nx, cx->ny,
+                       cx->nz, d_g1e, d_lene);
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, cx->stream, d_len, ncol, cx->d_goff, d_tot);
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, cx->stream, d_lene, ncol, d_goffe, d_tot + 1);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(tot, d_tot, sizeof(tot), hipMemcpyDeviceToHost, cx->stream);
     cx->h_g0.assign(ncol, 0);
     cx->h_g1.assign(ncol, 0);
-    EBS_HIP(cx, hipMemcpyAsync(cx->h_g0.data(), cx->d_g0, sizeof(int32_t) * ncol,
-                               hipMemcpyDeviceToHost, cx->stream));
-    EBS_HIP(cx, hipMemcpyAsync(cx->h_g1.data(), cx->d_g1, sizeof(int32_t) * ncol,
-                               hipMemcpyDeviceToHost, cx->stream));
-    EBS_HIP(cx, hipStreamSynchronize(cx->stream));
     cx->h_goff.assign(ncol, 0);
-    int64_t G = 0;
-    for (int c = 0; c < ncol; ++c) {
-        cx->h_goff[c] = (int32_t)G;
-        G += cx->h_g1[c] - cx->h_g0[c];
+    cx->h_g1e.assign(ncol, 0);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cx->h_g0.data(), cx->d_g0, sizeof(int32_t) * ncol, hipMemcpyDeviceToHost, cx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cx->h_g1.data(), cx->d_g1, sizeof(int32_t) * ncol, hipMemcpyDeviceToHost, cx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cx->h_goff.data(), cx->d_goff, sizeof(int32_t) * ncol, hipMemcpyDeviceToHost, cx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cx->h_g1e.data(), d_g1e, sizeof(int32_t) * ncol, hipMemcpyDeviceToHost, cx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(cx->stream);
+    if (e != hipSuccess) {
+        release();
+        cx->err = std::string("general range: ") + hipGetErrorString(e);
+        return EBS_E_HIP;
     }
-    if (G > INT32_MAX / 8) {
+    const int64_t G = tot[0], Ge = tot[1];
+    if (G > INT32_MAX / 8 || Ge > INT32_MAX / 16) {
+        release();
         cx->err = "general region too large";
         return EBS_E_UNSUPPORTED;
     }
-    std::vector<int32_t> gcol((size_t)std::max<int64_t>(G, 1));
-    for (int c = 0; c < ncol; ++c)
-        for (int k = cx->h_g0[c]; k < cx->h_g1[c]; ++k) gcol[cx->h_goff[c] + (k - cx->h_g0[c])] = c;
     cx->G = (int32_t)G;
-    const size_t Gs = (size_t)std::max<int64_t>(G, 1);
-    // extended face range: the lower faces of every CV whose face bounds a
-    // general CV from above (+x, +y neighbours and the cell above the range).
-    // It also holds the faces a cut-face interpolation reads: one column away
-    // and up to one level above a cut CV, i.e. up to level kr of every cut
-    // column in the 3 x 3 neighbourhood.
-    std::vector<int32_t> h_kr((size_t)NINST * ncol), krcut(ncol, 0);
-    EBS_HIP(cx, hipMemcpy(h_kr.data(), cx->d_kr, sizeof(int32_t) * NINST * ncol, hipMemcpyDeviceToHost));
-    for (int c = 0; c < ncol; ++c)
-        for (int s = 0; s < NINST; ++s) {
-            const int kr = h_kr[(size_t)s * ncol + c];
-            if (kr > (s == 3 ? 1 : 0)) krcut[c] = std::max(krcut[c], kr + 1);
-        }
-    std::vector<int32_t> g1e(ncol), goffe(ncol);
-    int64_t Ge = 0;
-    for (int c = 0; c < ncol; ++c) {
-        const int i = c % cx->nx, j = c / cx->nx;
-        const int cxm = j * cx->nx + (i == 0 ? cx->nx - 1 : i - 1);
-        const int cym = (j == 0 ? cx->ny - 1 : j - 1) * cx->nx + i;
-        const int own = cx->h_g1[c] > cx->h_g0[c] ? cx->h_g1[c] + 1 : cx->h_g0[c];
-        int interp = 0;
-        for (int dj = -1; dj <= 1; ++dj)
-            for (int di = -1; di <= 1; ++di) {
-                const int ii = (i + di + cx->nx) % cx->nx, jj = (j + dj + cx->ny) % cx->ny;
-                interp = std::max(interp, krcut[jj * cx->nx + ii]);
-            }
-        g1e[c] = std::min(cx->nz, std::max(std::max(own, interp), std::max(cx->h_g1[cxm], cx->h_g1[cym])));
-        goffe[c] = (int32_t)Ge;
-        Ge += g1e[c] - cx->h_g0[c];
-    }
-    if (Ge > INT32_MAX / 16) {
-        cx->err = "general region too large";
-        return EBS_E_UNSUPPORTED;
-    }
-    std::vector<int32_t> gcole((size_t)std::max<int64_t>(Ge, 1));
-    for (int c = 0; c < ncol; ++c)
-        for (int k = cx->h_g0[c]; k < g1e[c]; ++k) gcole[goffe[c] + (k - cx->h_g0[c])] = c;
     cx->Ge = (int32_t)Ge;
-    cx->h_g1e = g1e;
+    const size_t Gs = (size_t)std::max<int64_t>(G, 1);
     const size_t Ges = (size_t)std::max<int64_t>(Ge, 1);
     auto alloc = [&](void** p, size_t bytes) -> bool {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
         return hipMalloc(p, bytes) == hipSuccess;
     };
-    bool ok = true;
-    ok &= alloc((void**)&cx->d_goff, sizeof(int32_t) * ncol);
+    ok = true;
     ok &= alloc((void**)&cx->d_col, sizeof(int4) * ncol);
     ok &= alloc((void**)&cx->d_gcol, sizeof(int32_t) * Gs);
     ok &= alloc((void**)&cx->d_geo, sizeof(double) * NINST * GQ_N * Gs);
@@ -1214,19 +1286,19 @@ static ebs_status build_range(ebs_ctx* cx, const GeomArgs& a) {
     ok &= alloc((void**)&cx->d_fflag, sizeof(uint32_t) * Gs);
     ok &= alloc((void**)&cx->d_type4, sizeof(uint32_t) * Gs);
     if (!ok) {
+        release();
         cx->err = "device allocation of geometry tables failed";
         return EBS_E_OOM;
     }
-    EBS_HIP(cx, hipMemcpyAsync(cx->d_goff, cx->h_goff.data(), sizeof(int32_t) * ncol,
-                               hipMemcpyHostToDevice, cx->stream));
-    EBS_HIP(cx, hipMemcpyAsync(cx->d_gcol, gcol.data(), sizeof(int32_t) * Gs, hipMemcpyHostToDevice,
-                               cx->stream));
-    std::vector<int4> colinfo(ncol);
-    for (int c = 0; c < ncol; ++c) colinfo[c] = col_pack(cx->h_g0[c], cx->h_g1[c], g1e[c], cx->h_goff[c], goffe[c]);
-    EBS_HIP(cx, hipMemcpyAsync(cx->d_gcole, gcole.data(), sizeof(int32_t) * Ges, hipMemcpyHostToDevice,
-                               cx->stream));
-    EBS_HIP(cx, hipMemcpyAsync(cx->d_col, colinfo.data(), sizeof(int4) * ncol, hipMemcpyHostToDevice,
-                               cx->stream));
+    hipLaunchKernelGGL(k_range_fill, dim3(nb), dim3(tb), 0, cx->stream, cx->d_g0, cx->d_g1, d_g1e, cx->d_goff,
+                       d_goffe, ncol, cx->d_gcol, cx->d_gcole, cx->d_col);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(cx->stream);
+    release();
+    if (e != hipSuccess) {
+        cx->err = std::string("general range: ") + hipGetErrorString(e);
+        return EBS_E_HIP;
+    }
     EBS_HIP(cx, hipMemsetAsync(cx->d_uhat, 0, sizeof(double) * 5 * Gs, cx->stream));
     if (G > 0) {
         RecArgs r;
