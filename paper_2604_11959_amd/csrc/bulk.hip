@@ -68,9 +68,14 @@ __device__ __forceinline__ double expm1_t(double x) { return expm1(x); }
 //
 // FP32: (1 + x)^gamma - 1 from the binomial series sum_{n=1..8} C(gamma, n) x^n
 // for |x| < 1/8 (truncation below 1e-9 relative; coefficients in bc[]), and
-// from the hardware base-2 exponential and logarithm beyond, where the result
-// is at least 0.15 and no cancellation occurs.  FP64: log1p and expm1.
+// from expm1(gamma log1p(x)) beyond (the hardware base-2 exponential and
+// logarithm lose the low bits of the result to the subtraction of 1 and put
+// an error of about 1.5e-7 p0 on p', several times its own rounding).  FP64:
+// log1p and expm1.
 constexpr int PP_DEG = 8;
+// kept out of line: the branch is rare and its library calls would otherwise
+// raise the register pressure of the whole regular-region kernel
+__device__ __attribute__((noinline)) float pow_departure(float gam, float x) { return expm1f(gam * log1pf(x)); }
 template <typename T>
 __device__ __forceinline__ T pprime(const T* __restrict__ sref, int nz, T gam, const T* bc, T rt, int k) {
     if constexpr (sizeof(T) == 8) {
@@ -85,7 +90,7 @@ __device__ __forceinline__ T pprime(const T* __restrict__ sref, int nz, T gam, c
             for (int n = PP_DEG - 2; n >= 0; --n) e = e * x + bc[n];
             e *= x;
         } else {
-            e = __builtin_amdgcn_exp2f(gam * __builtin_amdgcn_logf(1.0f + x)) - 1.0f;
+            e = pow_departure(gam, x);
         }
         return sref[k] * e;
     }

@@ -175,6 +175,30 @@ def test_sources_f32_bulk_one_stage():
     assert max(err.values()) <= 2e-5, err
 
 
+def test_sources_f32_large_departures():
+    """FP32 bulk, one stage with a 60 K potential-temperature anomaly: the
+    relative departure x = rho theta / rho theta0 - 1 exceeds 1/8 on part of
+    the fluid, where p' = p0 ((1 + x)^gamma - 1) is evaluated with the
+    hardware base-2 exponential and logarithm instead of the binomial series
+    used for small x; against the oracle within 2e-5."""
+    w, o, ref = _oracle(2)
+    U0 = _f32(synth.state_reference(w.grid, ref, 66, theta_amp=60.0))
+    rt0 = ref.rhotheta0[:, None, None]
+    x = U0["rhotheta"] / rt0 - 1.0
+    fl = o.export(0, oracle.OQ["ALPHA"]) > 0
+    assert (np.abs(x[fl]) > 0.125).mean() > 0.02
+    cdt = w.dt / 3
+    want = o.stage(U0, U0, cdt, ref)
+    c = _ctx(w, ref, precision=ebs.EBS_F32_BULK)
+    Ud, Uh = c.new_state(U0), c.new_state()
+    c.advance(Ud, Ud, Uh, cdt)
+    c.redistribute(Uh, Uh)
+    torch.cuda.synchronize()
+    err, _ = rel_err(_host(Uh), want, _masks(o))
+    print(err)
+    assert max(err.values()) <= 2e-5, err
+
+
 def test_sources_f32_bulk_rk3_step_graph():
     """FP32 bulk, one RK3 step captured in a HIP graph (replayed after an
     eager step from the same input: identical bits), against the oracle within
