@@ -23,7 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = ["geom.c", "levelset.c", "coarse.c", "flux.c", "wsrd.c", "source.c", "restrict.c", "diffusion.c"]
+_SRC = ["geom.c", "levelset.c", "coarse.c", "flux.c", "wsrd.c", "source.c", "restrict.c", "diffusion.c", "viscous.c"]
 
 # geometry quantity indices (mirror oracle.h)
 OQ = dict(ALPHA=0, BX=1, BY=2, BZ=3, FX1=4, FX2=5, FY1=6, FY2=7, FZ1=8, FZ2=9,
@@ -43,7 +43,7 @@ def build(force: bool = False) -> str:
     srcs = [os.path.join(_HERE, s) for s in _SRC]
     if not force and os.path.exists(_SO):
         so_t = os.path.getmtime(_SO)
-        hdrs = [os.path.join(_HERE, h) for h in ("oracle.h", "geom_piece.h")]
+        hdrs = [os.path.join(_HERE, h) for h in ("oracle.h", "geom_piece.h", "lsq.h")]
         if all(os.path.getmtime(s) <= so_t for s in srcs + hdrs):
             return _SO
     tmp = _SO + ".tmp"
@@ -60,6 +60,10 @@ class _Src(C.Structure):
 
 class _Diff(C.Structure):
     _fields_ = [("alpha_theta", C.c_double), ("eb_mode", C.c_int32), ("theta_wall", C.c_double)]
+
+
+class _Visc(C.Structure):
+    _fields_ = [("mu", C.c_double), ("eb_mode", C.c_int32)]
 
 
 class _Grid(C.Structure):
@@ -95,6 +99,7 @@ def _load():
         lib.orc_box_moments.argtypes = [P(_Grid), dp, C.c_int, C.c_int, dp, C.c_double,
                                         C.c_double, C.c_int, dp]
         lib.orc_diffusion.argtypes = [P(_Grid), dpp, dpp, P(_Diff), dp, dpp, dp]
+        lib.orc_viscous.argtypes = [P(_Grid), dpp, dpp, P(_Visc), dpp, dpp, dpp]
         lib.orc_set_threads.argtypes = [C.c_int]
         lib.orc_set_threads.restype = C.c_int
         _lib = lib
@@ -263,10 +268,25 @@ class Oracle:
     def diffusion(self, U: dict, diff, fluxes: bool = False):
         return self.diffusion_dense(to_dense(U, self.n), diff, fluxes)
 
-    def advance_dense(self, Un: list, Ucur: list, cdt: float, ref=None, diff=None) -> list:
+    def viscous_dense(self, Ucur: list, visc, fluxes: bool = False):
+        """Intensive viscous update of the three momenta (dense, instances
+        1-3) for ``visc`` (attributes mu, eb_mode); with fluxes, also the
+        stresses on the lower faces [3 c + d] and the EB terms [c]."""
+        p = _Visc(float(visc.mu), int(visc.eb_mode))
+        D = [np.zeros_like(Ucur[0]) for _ in range(3)]
+        F = [np.zeros_like(Ucur[0]) for _ in range(9)]
+        E = [np.zeros_like(Ucur[0]) for _ in range(3)]
+        _load().orc_viscous(C.byref(self.g), _dpp(self.geo), _dpp(Ucur), C.byref(p), _dpp(D), _dpp(F), _dpp(E))
+        return (D, F, E) if fluxes else D
+
+    def viscous(self, U: dict, visc, fluxes: bool = False):
+        return self.viscous_dense(to_dense(U, self.n), visc, fluxes)
+
+    def advance_dense(self, Un: list, Ucur: list, cdt: float, ref=None, diff=None, visc=None) -> list:
         """Uhat = Un + cdt dU(Ucur); with a reference state, plus cdt times the
         momentum sources of Ucur on every fluid CV; with a diffusion setting,
-        plus cdt times the diffusive update of rho theta."""
+        plus cdt times the diffusive update of rho theta; with a viscosity
+        setting, plus cdt times the viscous update of the momenta."""
         out = [np.zeros_like(Un[0]) for _ in range(5)]
         _load().orc_advance(C.byref(self.g), _dpp(self.geo), _dpp(Un), _dpp(Ucur), _dpp(out),
                             float(cdt))
@@ -276,6 +296,10 @@ class Oracle:
                 out[2 + d] = out[2 + d] + float(cdt) * S[d]
         if diff is not None:
             out[1] = out[1] + float(cdt) * self.diffusion_dense(Ucur, diff)
+        if visc is not None:
+            V = self.viscous_dense(Ucur, visc)
+            for cc in range(3):
+                out[2 + cc] = out[2 + cc] + float(cdt) * V[cc]
         return out
 
     def redistribute_dense(self, Uhat: list) -> list:
@@ -306,25 +330,25 @@ class Oracle:
                                       _dpp(out), _dpp(sig), _dpp(qh))
         return from_dense(out, self.n), sig, qh
 
-    def advance(self, Un: dict, Ucur: dict, cdt: float, ref=None, diff=None) -> dict:
-        return from_dense(self.advance_dense(to_dense(Un, self.n), to_dense(Ucur, self.n), cdt, ref, diff),
+    def advance(self, Un: dict, Ucur: dict, cdt: float, ref=None, diff=None, visc=None) -> dict:
+        return from_dense(self.advance_dense(to_dense(Un, self.n), to_dense(Ucur, self.n), cdt, ref, diff, visc),
                           self.n)
 
     def redistribute(self, Uhat: dict) -> dict:
         return from_dense(self.redistribute_dense(to_dense(Uhat, self.n)), self.n)
 
-    def stage(self, Un: dict, Ucur: dict, cdt: float, ref=None, diff=None) -> dict:
+    def stage(self, Un: dict, Ucur: dict, cdt: float, ref=None, diff=None, visc=None) -> dict:
         """Algorithm 1 steps (1)-(4) for one stage: U^s = R(U^n + c dt dU(U^{s-1}))."""
         d_n = to_dense(Un, self.n)
         d_c = d_n if Ucur is Un else to_dense(Ucur, self.n)
-        return from_dense(self.redistribute_dense(self.advance_dense(d_n, d_c, cdt, ref, diff)), self.n)
+        return from_dense(self.redistribute_dense(self.advance_dense(d_n, d_c, cdt, ref, diff, visc)), self.n)
 
-    def rk3_step(self, U: dict, dt: float, ref=None, diff=None) -> dict:
+    def rk3_step(self, U: dict, dt: float, ref=None, diff=None, visc=None) -> dict:
         """Low-storage three-stage Runge-Kutta (Wicker-Skamarock form)."""
         d_n = to_dense(U, self.n)
         cur = d_n
         for c in RK3_C:
-            cur = self.redistribute_dense(self.advance_dense(d_n, cur, c * dt, ref, diff))
+            cur = self.redistribute_dense(self.advance_dense(d_n, cur, c * dt, ref, diff, visc))
         return from_dense(cur, self.n)
 
     # ------------------------------------------------------------ two levels

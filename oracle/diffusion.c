@@ -36,6 +36,7 @@
  *    and facet of rho alpha grad(theta) . n_out times the open area.
  */
 #include "oracle.h"
+#include "lsq.h"
 
 #include <math.h>
 #include <stdlib.h>
@@ -71,97 +72,6 @@ static double dtheta(const DCtx* c, int i, int j, int k) {
 }
 
 static double drho(const DCtx* c, int i, int j, int k) { return c->U[0][DID(c, i, j, k)]; }
-
-/* Solve the n x n system M x = r (n <= 10) by Gaussian elimination with
- * partial pivoting; also the 1-norm reciprocal condition number from the
- * explicit inverse.  Returns 0 if singular. */
-static int solve_n(int n, const double Min[10][10], const double rin[10], double x[10], double* rcond) {
-    double A[10][10], I[10][10], r[10];
-    for (int a = 0; a < n; ++a) {
-        r[a] = rin[a];
-        for (int b = 0; b < n; ++b) {
-            A[a][b] = Min[a][b];
-            I[a][b] = a == b ? 1.0 : 0.0;
-        }
-    }
-    for (int col = 0; col < n; ++col) {
-        int piv = col;
-        for (int a = col + 1; a < n; ++a)
-            if (fabs(A[a][col]) > fabs(A[piv][col])) piv = a;
-        if (!(fabs(A[piv][col]) > 0.0)) return 0;
-        if (piv != col) {
-            for (int b = 0; b < n; ++b) {
-                double t = A[col][b]; A[col][b] = A[piv][b]; A[piv][b] = t;
-                t = I[col][b]; I[col][b] = I[piv][b]; I[piv][b] = t;
-            }
-            double t = r[col]; r[col] = r[piv]; r[piv] = t;
-        }
-        const double p = A[col][col];
-        for (int b = 0; b < n; ++b) { A[col][b] /= p; I[col][b] /= p; }
-        r[col] /= p;
-        for (int a = 0; a < n; ++a) {
-            if (a == col) continue;
-            const double f = A[a][col];
-            for (int b = 0; b < n; ++b) { A[a][b] -= f * A[col][b]; I[a][b] -= f * I[col][b]; }
-            r[a] -= f * r[col];
-        }
-    }
-    double n1 = 0.0, ni = 0.0;
-    for (int b = 0; b < n; ++b) {
-        double ca = 0.0, cb = 0.0;
-        for (int a = 0; a < n; ++a) { ca += fabs(Min[a][b]); cb += fabs(I[a][b]); }
-        n1 = fmax(n1, ca);
-        ni = fmax(ni, cb);
-    }
-    *rcond = 1.0 / (n1 * ni);
-    for (int a = 0; a < n; ++a) x[a] = r[a];
-    return 1;
-}
-
-/* basis row of a point at mesh-unit offset e from the evaluation point:
- * with_const: 1, e, e^2 terms (10); without: e, e^2 terms (9) */
-static int basis(const double e[3], int quad, int with_const, double row[10]) {
-    int n = 0;
-    if (with_const) row[n++] = 1.0;
-    row[n++] = e[0];
-    row[n++] = e[1];
-    row[n++] = e[2];
-    if (quad) {
-        row[n++] = 0.5 * e[0] * e[0];
-        row[n++] = 0.5 * e[1] * e[1];
-        row[n++] = 0.5 * e[2] * e[2];
-        row[n++] = e[0] * e[1];
-        row[n++] = e[0] * e[2];
-        row[n++] = e[1] * e[2];
-    }
-    return n;
-}
-
-/* Least-squares gradient (physical units) at point x (physical) from the
- * points P (offsets in mesh units) with values q; with_const = 0 fits
- * q - q_wall with no constant term.  Quadratic, then linear fallback. */
-static void lsq_gradient(const DCtx* c, int np, double (*e)[3], const double* q, int with_const, double grad[3]) {
-    grad[0] = grad[1] = grad[2] = 0.0;
-    for (int quad = 1; quad >= 0; --quad) {
-        double row[10];
-        const int nb = basis(e[0], quad, with_const, row);
-        if (np < nb) continue;
-        double M[10][10] = {{0}}, r[10] = {0};
-        for (int s = 0; s < np; ++s) {
-            basis(e[s], quad, with_const, row);
-            for (int a = 0; a < nb; ++a) {
-                r[a] += row[a] * q[s];
-                for (int b = 0; b < nb; ++b) M[a][b] += row[a] * row[b];
-            }
-        }
-        double x[10], rc;
-        if (!solve_n(nb, M, r, x, &rc)) continue;
-        if (!(rc >= 1e-7)) continue;
-        const int o = with_const ? 1 : 0;
-        for (int d = 0; d < 3; ++d) grad[d] = x[o + d] / c->g->dx[d];
-        return;
-    }
-}
 
 /* physical centroid of cell (i,j,k) (unwrapped indices: positions follow
  * the stencil across the periodic seams) */
@@ -207,7 +117,7 @@ static double face_flux(const DCtx* c, const orc_diff* p, int d, int i, int j, i
                     ++np;
                 }
         double gr[3];
-        lsq_gradient(c, np, e, q, 1, gr);
+        lsq_gradient(c->g->dx, np, e, q, 1, gr);
         g = gr[d];
     }
     return rf * p->alpha_theta * g;
@@ -252,7 +162,7 @@ int orc_diffusion(const orc_grid* g, double* const geo[4], const double* const U
                                 ++np;
                             }
                     double gr[3];
-                    lsq_gradient(&c, np, e, q, 0, gr);
+                    lsq_gradient(g->dx, np, e, q, 0, gr);
                     /* area vector into the fluid (physical); the outward normal of
                      * the fluid CV is its opposite */
                     const double av[3] = {DG(&c, OQ_AX, i, j, k) * g->dx[1] * g->dx[2],

@@ -167,6 +167,22 @@ typedef struct {
 int orc_diffusion(const orc_grid* g, double* const geo[4], const double* const U[5], const orc_diff* p,
                   double* D, double* const Fd[3], double* Feb);
 
+/* Momentum diffusion (Sections 2.1 and 4.2): dynamic viscosity mu (>= 0);
+ * the EB is stress-free (eb_mode 0) or no-slip (eb_mode 1). */
+typedef struct {
+    double mu;
+    int32_t eb_mode;
+} orc_visc;
+
+/* Intensive viscous update of the three momenta, D[c] (dense storage of
+ * instance c + 1; 0 where not fluid): (1/V) times the sum of tau_c . n_out
+ * over the open face areas and the EB facet.  Optional outputs (NULL to
+ * skip): F[3 c + d] the stress tau_{c d} on the lower d-face of every CV of
+ * instance c + 1 (0 where the face is closed or a wall), E[c] the facet term
+ * of every CV. */
+int orc_viscous(const orc_grid* g, double* const geo[4], const double* const U[5], const orc_visc* p,
+                double* const D[3], double* const F[9], double* const E[3]);
+
 /* Threads used by the plane loops of the geometry, stage and redistribution
  * (n > 0 sets the count; returns the count in use).  Each loop iteration
  * writes only its own plane's entries, so results are bitwise independent
