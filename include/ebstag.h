@@ -361,6 +361,35 @@ typedef struct {
 } ebs_diffusion_params;
 ebs_status ebs_set_diffusion(ebs_ctx* ctx, const ebs_diffusion_params* prm);
 
+/* Momentum diffusion (Sections 2.1 and 4.2; Eq. mom-comp): every later
+ * ebs_advance_stage / ebs_rk3_step adds c dt times the divergence of the
+ * viscous stress tau = lambda (div u) I + mu (grad u + grad u^T), lambda =
+ * -2/3 mu, to the provisional momenta of every fluid u, v and w CV, before
+ * the redistribution.  The velocity of a staggered CV is its momentum over
+ * the mean density of the fluid cells beside its face.  tau_xx, tau_yy and
+ * tau_zz act on the CV faces at cell centres, the shear components on those
+ * at cell edges.  Full faces (area fraction >= 1 - 1e-12) use the centred
+ * differences of the staggered grid.  Cut faces and EB facets use gradients
+ * of least-squares fits of each velocity component over the fluid CVs of its
+ * own grid, 3 CVs wide along an axis on which the face or facet CV centre
+ * lines up with that grid and 4 wide otherwise (the stencil sizes the paper
+ * gives for fits across grid types); the fit is that of ebs_set_diffusion.
+ * The EB is stress-free (eb_mode 0) or no-slip (eb_mode 1: the fits at the
+ * facet centroid take the velocity there as zero).  The domain bottom and
+ * top are stress-free for u and v; the w CVs next to them end at the first
+ * and last cell centres and feel tau_zz there, with w = 0 on the walls.  The
+ * fit weights depend on the geometry only and are built here (or by the
+ * next geometry build).
+ *   prm: mu >= 0 finite (dynamic viscosity, kg / (m s)), eb_mode 0 or 1;
+ *        NULL switches momentum diffusion off.
+ * Synchronous: waits for the work queued on the context.  Errors: EBS_E_ARG,
+ * EBS_E_OOM, EBS_E_HIP, EBS_E_UNSUPPORTED (more than 2^30 cells). */
+typedef struct {
+    double mu;       /* dynamic viscosity */
+    int32_t eb_mode; /* 0 stress-free EB, 1 no-slip EB */
+} ebs_viscosity_params;
+ebs_status ebs_set_viscosity(ebs_ctx* ctx, const ebs_viscosity_params* prm);
+
 /* Restriction (averaging down) of a state of this context's grid onto the
  * grid coarsened by 2 in every direction (Section 4.3: static two-level
  * refinement with ratio 2; the coarse geometry is merged from the fine

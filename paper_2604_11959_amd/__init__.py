@@ -29,7 +29,7 @@ Q = dict(ALPHA=0, BETA_X=1, BETA_Y=2, BETA_Z=3, FX_Y=4, FX_Z=5, FY_X=6, FY_Z=7, 
 # every entry point declared in include/ebstag.h
 SYMBOLS = ("ebs_create", "ebs_build_geometry_terrain", "ebs_build_geometry_levelset", "ebs_build_geometry_merged", "ebs_geometry_export", "ebs_geometry_stats", "ebs_alpha_histogram",
            "ebs_advance_stage", "ebs_redistribute", "ebs_rk3_step", "ebs_conserved_sums",
-           "ebs_autotune", "ebs_set_tile", "ebs_get_tile", "ebs_set_overlap", "ebs_set_persistent", "ebs_set_range_rule", "ebs_set_sources", "ebs_set_diffusion", "ebs_restrict", "ebs_coarsened_geometry", "ebs_coarsened_geometry_noalloc", "ebs_timing_enable", "ebs_timing_read",
+           "ebs_autotune", "ebs_set_tile", "ebs_get_tile", "ebs_set_overlap", "ebs_set_persistent", "ebs_set_range_rule", "ebs_set_sources", "ebs_set_diffusion", "ebs_set_viscosity", "ebs_restrict", "ebs_coarsened_geometry", "ebs_coarsened_geometry_noalloc", "ebs_timing_enable", "ebs_timing_read",
            "ebs_algorithmic_bytes", "ebs_stream_copy", "ebs_last_error", "ebs_destroy")
 
 
@@ -55,6 +55,10 @@ class SourceParams(C.Structure):
 
 class DiffusionParams(C.Structure):
     _fields_ = [("alpha_theta", C.c_double), ("eb_mode", C.c_int32), ("theta_wall", C.c_double)]
+
+
+class ViscosityParams(C.Structure):
+    _fields_ = [("mu", C.c_double), ("eb_mode", C.c_int32)]
 
 
 class State(C.Structure):
@@ -94,6 +98,7 @@ def load(path: str = LIB_PATH):
         "ebs_set_range_rule": [C.c_void_p, C.c_int32],
         "ebs_set_sources": [C.c_void_p, P(SourceParams), P(C.c_double), P(C.c_double)],
         "ebs_set_diffusion": [C.c_void_p, P(DiffusionParams)],
+        "ebs_set_viscosity": [C.c_void_p, P(ViscosityParams)],
         "ebs_restrict": [C.c_void_p, P(State), P(State)],
         "ebs_coarsened_geometry": [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_double)],
         "ebs_coarsened_geometry_noalloc": [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_double),
@@ -368,6 +373,15 @@ class Context:
             return
         prm = DiffusionParams(float(p.alpha_theta), int(p.eb_mode), float(p.theta_wall))
         self._check(self.lib.ebs_set_diffusion(self.h, C.byref(prm)), "ebs_set_diffusion")
+
+    def set_viscosity(self, p=None):
+        """Momentum diffusion with parameters ``p`` (attributes mu, eb_mode),
+        or off with None."""
+        if p is None:
+            self._check(self.lib.ebs_set_viscosity(self.h, None), "ebs_set_viscosity")
+            return
+        prm = ViscosityParams(float(p.mu), int(p.eb_mode))
+        self._check(self.lib.ebs_set_viscosity(self.h, C.byref(prm)), "ebs_set_viscosity")
 
     def get_tile(self):
         tx, ty, tz, sp = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()

@@ -246,7 +246,8 @@ ebs_status ebs_destroy(ebs_ctx* c) {
                     c->d_smalllist, c->d_actlist, c->d_lsq_off, c->d_lsq_idx, c->d_lsq_c, c->d_lsq_ev, c->d_lsq_nev, c->d_wl_off, c->d_wl_idx, c->d_wl_geo, c->d_wl_self, c->d_wl_small, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles, c->d_prim, c->d_fh, c->d_type4, c->d_col, c->d_gcole, c->d_fflag, c->d_cbase, c->d_crec, c->d_bfc,
                     c->d_ptab, c->d_ftab, c->d_utab, c->d_sten, c->d_upd, c->d_q_idx, c->d_q_w, c->d_q_den, c->d_q_n, c->d_chk, c->d_part, c->d_dummy,
                     c->d_srcf, c->d_srcd, c->d_srcv, c->d_dop_off, c->d_dop_idx, c->d_dop_w, c->d_dop_cell,
-                    c->d_dflux, c->d_dtab};
+                    c->d_dflux, c->d_dtab, c->d_vop_off, c->d_vop_pt, c->d_vop_fl, c->d_vop_w, c->d_vflux,
+                    c->d_vtab};
     for (void* p : ptrs) free_ptr(p);
     delete c;
     return EBS_OK;
@@ -297,6 +298,10 @@ static ebs_status build_from(ebs_ctx* c, const double* d_h, const double* d_phi)
     if (st != EBS_OK) return st;
     if (c->diff_on) {
         st = build_diffusion(c);
+        if (st != EBS_OK) return st;
+    }
+    if (c->visc_on) {
+        st = build_viscous(c);
         if (st != EBS_OK) return st;
     }
     EBS_HIP(c, hipStreamSynchronize(c->stream));
@@ -750,6 +755,30 @@ ebs_status ebs_set_diffusion(ebs_ctx* c, const ebs_diffusion_params* prm) {
         const ebs_status st = build_diffusion(c);
         if (st != EBS_OK) {
             c->diff_on = false;
+            return st;
+        }
+    }
+    return EBS_OK;
+}
+
+ebs_status ebs_set_viscosity(ebs_ctx* c, const ebs_viscosity_params* prm) {
+    if (!c) return EBS_E_ARG;
+    if (prm && (!(prm->mu >= 0.0 && std::isfinite(prm->mu)) || (prm->eb_mode != 0 && prm->eb_mode != 1)))
+        return fail(c, EBS_E_ARG, "viscosity parameters out of range");
+    // stages already queued may read the operators
+    EBS_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->side) EBS_HIP(c, hipStreamSynchronize(c->side));
+    drop_graph(c);
+    if (!prm) {
+        c->visc_on = false;
+        return EBS_OK;
+    }
+    c->visc = *prm;
+    c->visc_on = true;
+    if (c->have_geom) {
+        const ebs_status st = build_viscous(c);
+        if (st != EBS_OK) {
+            c->visc_on = false;
             return st;
         }
     }

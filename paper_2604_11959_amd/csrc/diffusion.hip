@@ -240,9 +240,12 @@ int basis_row(const double e[3], bool quad, bool with_const, double (&row)[10]) 
     return n;
 }
 
+}  // namespace
+
 // Weights of the fitted gradient (physical units, per direction) at the
 // evaluation point from np points at mesh-unit offsets e: grad_d =
-// sum_s W[s][d] q_s.  All zero when no fit qualifies.
+// sum_s W[s][d] q_s.  All zero when no fit qualifies.  Also used by the
+// momentum diffusion.
 void lsq_weights(int np, const double (*e)[3], bool with_const, const double* del, double (*W)[3]) {
     for (int s = 0; s < np; ++s) W[s][0] = W[s][1] = W[s][2] = 0.0;
     for (int quad = 1; quad >= 0; --quad) {
@@ -269,8 +272,6 @@ void lsq_weights(int np, const double (*e)[3], bool with_const, const double* de
         return;
     }
 }
-
-}  // namespace
 
 // Builds the fit operators of every cut face of the cell-centred instance
 // inside the general range and, with an isothermal EB, of every cut cell's

@@ -258,6 +258,19 @@ struct ebs_ctx {
     int32_t* d_dop_cell = nullptr;  // [ndop] cell | direction << 30 (3 = facet)
     double* d_dflux = nullptr;      // [ndop]
     int32_t* d_dtab = nullptr;      // [G][7]
+    // momentum diffusion (ebs_set_viscosity): fit operators of the cut faces
+    // and facets of the u, v and w CVs (CSR over velocity points), their
+    // stress per stage, and per general cell and momentum the operator of
+    // each face and of the facet
+    bool visc_on = false;
+    ebs_viscosity_params visc{};
+    int32_t nvop = 0;
+    int32_t* d_vop_off = nullptr;  // [nvop + 1]
+    int32_t* d_vop_pt = nullptr;   // [pts] component << 30 | cell
+    uint8_t* d_vop_fl = nullptr;   // [pts] fluid cells beside the velocity's face
+    double* d_vop_w = nullptr;     // [pts]
+    double* d_vflux = nullptr;     // [nvop]
+    int32_t* d_vtab = nullptr;     // [G][3][7]
     // output of the last ebs_advance_stage: the cut range of ebs_redistribute
     // is read from d_uhat, which holds that advance's provisional state
     bool have_adv = false;
@@ -291,6 +304,11 @@ ebs_status build_diffusion(ebs_ctx* c);
 ebs_status launch_diffusion_general(ebs_ctx* c, const ebs_state* Ucur, ebs_state* Uhat, double cdt);
 ebs_status launch_diffusion_regular(ebs_ctx* c, const ebs_state* Ucur, ebs_state* Uhat, double cdt,
                                     hipStream_t stream);
+// momentum diffusion (viscous.hip), same split
+ebs_status build_viscous(ebs_ctx* c);
+ebs_status launch_viscous_general(ebs_ctx* c, const ebs_state* Ucur, ebs_state* Uhat, double cdt);
+ebs_status launch_viscous_regular(ebs_ctx* c, const ebs_state* Ucur, ebs_state* Uhat, double cdt,
+                                  hipStream_t stream);
 // redistribution (wsrd.hip)
 ebs_status wsrd_setup(ebs_ctx* c);
 ebs_status launch_redistribute(ebs_ctx* c, const ebs_state* Uhat, ebs_state* Uout);

@@ -1003,6 +1003,10 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
             st = launch_diffusion_regular(cx, Ucur, Uh, cdt, bs);
             if (st != EBS_OK) return st;
         }
+        if (cx->visc_on) {
+            st = launch_viscous_regular(cx, Ucur, Uh, cdt, bs);
+            if (st != EBS_OK) return st;
+        }
         if (fork) EBS_HIP(cx, hipEventRecord(cx->ev_join, bs));
     }
     if (cx->G > 0) {
@@ -1051,6 +1055,10 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
         EBS_HIP(cx, hipGetLastError());
         if (cx->diff_on) {  // adds to what the update wrote
             const ebs_status st = launch_diffusion_general(cx, Ucur, Uh, cdt);
+            if (st != EBS_OK) return st;
+        }
+        if (cx->visc_on) {
+            const ebs_status st = launch_viscous_general(cx, Ucur, Uh, cdt);
             if (st != EBS_OK) return st;
         }
     }
