@@ -13,7 +13,8 @@ region, redistribution and sums in FP64), tile shape chosen by the autotuner,
 RK3 step captured in a HIP graph.  Besides the main line it reports the plain
 FP64 single-box case (128 x 128 x 64 Witch of Agnesi hill), the same workload
 with the momentum sources (perturbation pressure gradient and buoyancy over an
-isentropic reference atmosphere), the restriction of the state onto the grid
+isentropic reference atmosphere), with the thermal and momentum diffusion
+(isothermal, no-slip EB), the restriction of the state onto the grid
 coarsened by 2, the regular-region kernel against the HBM roofline, and the
 FP64 oracle timed on the host.
 
@@ -52,7 +53,7 @@ def _log(msg):
 
 def run_workload(cfg: int, precision: int, steps: int, warmup: int, use_graph: bool,
                  autotune: bool, timing: bool, tile=None, overlap: bool = False, sources: bool = False,
-                 persistent=None):
+                 persistent=None, diffusion=None):
     import torch
 
     import paper_2604_11959_amd as ebs
@@ -70,6 +71,9 @@ def run_workload(cfg: int, precision: int, steps: int, warmup: int, use_graph: b
     if sources:
         ref = synth.reference_isentropic(w.grid)
         ctx.set_sources(ref)
+    if diffusion is not None:
+        ctx.set_diffusion(diffusion[0])
+        ctx.set_viscosity(diffusion[1])
     if tile:
         ctx.set_tile(*tile)
         if persistent is not None:
@@ -135,6 +139,18 @@ def measured_traffic(tile, workload_name, alg_bytes):
     if s.get("alg_bytes_per_launch") != alg_bytes:
         return None
     return float(s["traffic_bytes_per_launch"])
+
+
+def diffusion_params(w):
+    """Thermal diffusivity and dynamic viscosity for the diffusion leg:
+    diffusion numbers 0.1 (rho theta) and 0.05 (momenta, at density 1.2) per
+    step on the smallest spacing; isothermal EB at 299 K, no-slip EB."""
+    from types import SimpleNamespace
+
+    h2 = min(w.grid.dx) ** 2
+    dt = w.dt * DT_FRACTION
+    return (SimpleNamespace(alpha_theta=0.1 * h2 / dt, eb_mode=1, theta_wall=299.0),
+            SimpleNamespace(mu=0.05 * 1.2 * h2 / dt, eb_mode=1))
 
 
 def restriction_leg(cfg: int, precision: int, launches: int):
@@ -330,6 +346,8 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-sources", action="store_true",
                     help="skip the leg with the momentum sources (pressure gradient, buoyancy)")
+    ap.add_argument("--no-diffusion", action="store_true",
+                    help="skip the leg with the thermal and momentum diffusion")
     ap.add_argument("--no-restrict", action="store_true",
                     help="skip the leg that restricts the state onto the grid coarsened by 2")
     ap.add_argument("--tile", default=None,
@@ -475,6 +493,18 @@ def main(argv=None):
             leg["k_bulk_frac_of_hbm_peak"] = round(b3 / (a3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         _log(f"sources: {ms3:.3f} ms/step")
         out["with_sources"] = leg
+    if not args.no_diffusion:
+        # the same workload with the thermal diffusion of rho theta (EB held
+        # at 299 K) and the momentum diffusion (no-slip EB), diffusion numbers
+        # 0.1 and 0.05 per step on the smallest spacing
+        rd = run_workload(cfg, precision, args.steps, args.warmup, not args.no_graph, True, False, None, overlap,
+                          diffusion=diffusion_params(w))
+        ms4 = rd["ms"] / args.steps
+        out["with_diffusion"] = {"workload": rd["workload"].name + " + thermal and momentum diffusion",
+                                 "value": round(N * 3 / (ms4 * 1e-3) / 1e6, 1), "ms_per_step": round(ms4, 4),
+                                 "tile": list(rd["tile"][:3])}
+        rd["ctx"].close()
+        _log(f"diffusion: {ms4:.3f} ms/step")
     if not args.no_restrict:
         out["restriction"] = restriction_leg(cfg, precision, args.steps)
     if not args.no_cpu:

@@ -349,11 +349,15 @@ ebs_status ebs_set_sources(ebs_ctx* ctx, const ebs_source_params* prm, const dou
  * through theta_wall at the facet centroid).  Face density: mean of the two
  * cells; facet density: the cut cell's.  The domain bottom and top are
  * adiabatic.  The fit weights depend on the geometry only and are built here
- * (or by the next geometry build), about 36 points per cut face.
+ * (or by the next geometry build), about 36 points per cut face; switching
+ * diffusion on after a geometry build also rebuilds the stencil tables, whose
+ * range of positions above the general range the fits read.
  *   prm: alpha_theta >= 0 (m^2/s), eb_mode 0 or 1, theta_wall finite; NULL
  *        switches diffusion off.
  * Synchronous: waits for the work queued on the context.  Errors: EBS_E_ARG,
- * EBS_E_OOM, EBS_E_HIP, EBS_E_UNSUPPORTED (more than 2^30 cells). */
+ * EBS_E_OOM, EBS_E_HIP, EBS_E_UNSUPPORTED (more than 2^30 cells, or a table
+ * beyond its index range; after an error other than EBS_E_ARG the geometry
+ * must be built again). */
 typedef struct {
     double alpha_theta; /* thermal diffusivity, m^2 / s */
     int32_t eb_mode;    /* 0 adiabatic EB, 1 EB held at theta_wall */
@@ -379,11 +383,14 @@ ebs_status ebs_set_diffusion(ebs_ctx* ctx, const ebs_diffusion_params* prm);
  * top are stress-free for u and v; the w CVs next to them end at the first
  * and last cell centres and feel tau_zz there, with w = 0 on the walls.  The
  * fit weights depend on the geometry only and are built here (or by the
- * next geometry build).
+ * next geometry build); switching it on after a geometry build also
+ * rebuilds the stencil tables, whose range of positions above the general
+ * range the fits read.
  *   prm: mu >= 0 finite (dynamic viscosity, kg / (m s)), eb_mode 0 or 1;
  *        NULL switches momentum diffusion off.
  * Synchronous: waits for the work queued on the context.  Errors: EBS_E_ARG,
- * EBS_E_OOM, EBS_E_HIP, EBS_E_UNSUPPORTED (more than 2^30 cells). */
+ * EBS_E_OOM, EBS_E_HIP, EBS_E_UNSUPPORTED (a table beyond its index range;
+ * after an error other than EBS_E_ARG the geometry must be built again). */
 typedef struct {
     double mu;       /* dynamic viscosity */
     int32_t eb_mode; /* 0 stress-free EB, 1 no-slip EB */

@@ -22,7 +22,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libebstag.so")
 SOURCES = ["api.hip", "geom.hip", "bulk.hip", "stage.hip", "wsrd.hip", "reduce.hip", "restrict.hip",
            "noalloc.hip", "copy.hip",
-           "diffusion.hip", "viscous.hip"]
+           "diffusion.hip", "viscous.hip", "regdiff.hip"]
 ARCH = "gfx950"
 
 COMMON = [

@@ -246,8 +246,8 @@ ebs_status ebs_destroy(ebs_ctx* c) {
                     c->d_smalllist, c->d_actlist, c->d_lsq_off, c->d_lsq_idx, c->d_lsq_c, c->d_lsq_ev, c->d_lsq_nev, c->d_wl_off, c->d_wl_idx, c->d_wl_geo, c->d_wl_self, c->d_wl_small, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles, c->d_prim, c->d_fh, c->d_type4, c->d_col, c->d_gcole, c->d_fflag, c->d_cbase, c->d_crec, c->d_bfc,
                     c->d_ptab, c->d_ftab, c->d_utab, c->d_sten, c->d_upd, c->d_q_idx, c->d_q_w, c->d_q_den, c->d_q_n, c->d_chk, c->d_part, c->d_dummy,
                     c->d_srcf, c->d_srcd, c->d_srcv, c->d_dop_off, c->d_dop_idx, c->d_dop_w, c->d_dop_cell,
-                    c->d_dflux, c->d_dtab, c->d_vop_off, c->d_vop_pt, c->d_vop_fl, c->d_vop_w, c->d_vflux,
-                    c->d_vtab};
+                    c->d_dflux, c->d_dtab, c->d_vop_off, c->d_vop_pt, c->d_vop_w, c->d_vflux,
+                    c->d_vtab, c->d_acol};
     for (void* p : ptrs) free_ptr(p);
     delete c;
     return EBS_OK;
@@ -749,12 +749,17 @@ ebs_status ebs_set_diffusion(ebs_ctx* c, const ebs_diffusion_params* prm) {
         c->diff_on = false;
         return EBS_OK;
     }
+    const bool was_on = c->diff_on;
     c->diff = *prm;
     c->diff_on = true;
     if (c->have_geom) {
-        const ebs_status st = build_diffusion(c);
+        // the fits read theta at positions above the general range, which
+        // the aux range of the stencil tables then holds
+        ebs_status st = (was_on || c->visc_on) ? EBS_OK : build_stencils(c);
+        if (st == EBS_OK) st = build_diffusion(c);
         if (st != EBS_OK) {
             c->diff_on = false;
+            c->have_geom = false;  // tables half rebuilt: a new geometry build is needed
             return st;
         }
     }
@@ -770,15 +775,20 @@ ebs_status ebs_set_viscosity(ebs_ctx* c, const ebs_viscosity_params* prm) {
     if (c->side) EBS_HIP(c, hipStreamSynchronize(c->side));
     drop_graph(c);
     if (!prm) {
-        c->visc_on = false;
+        c->visc_on = false;  // (the wider aux range stays until the next build)
         return EBS_OK;
     }
+    const bool was_on = c->visc_on;
     c->visc = *prm;
     c->visc_on = true;
     if (c->have_geom) {
-        const ebs_status st = build_viscous(c);
+        // the fits read velocities at positions above the general range,
+        // which the aux range of the stencil tables then holds
+        ebs_status st = (was_on || c->diff_on) ? EBS_OK : build_stencils(c);
+        if (st == EBS_OK) st = build_viscous(c);
         if (st != EBS_OK) {
             c->visc_on = false;
+            c->have_geom = false;  // tables half rebuilt: a new geometry build is needed
             return st;
         }
     }

@@ -19,13 +19,13 @@
 // Every fit depends on the geometry only, so its weights are built once: the
 // gradient component a stage needs is a fixed linear combination of the theta
 // values of the stencil cells.  Per stage:
-//   k_diff_ops  one thread per operator (cut face or EB facet): its flux;
+//   k_diff_ops  a group of lanes per operator (cut face or EB facet): its
+//               flux;
 //   k_diff_gen  one thread per general cell: divergence over its six faces
 //               (full faces by centred differences) and the facet, added to
-//               the provisional rho theta (FP64 copy and the output state);
-//   k_diff_reg  one thread per cell above the general range, where every
-//               face is full: centred differences in the state precision,
-//               added to the output rho theta.
+//               the provisional rho theta (FP64 copy and the output state).
+// The cells above the general range, where every face is full, are updated
+// with the momentum diffusion in one pass (regdiff.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,8 +46,9 @@ struct DiffArgs {
     const T* cur_rt;
     T* out_rt;
     double* uhat_rt;          // [G] FP64 provisional rho theta of the general cells
+    const double* prim;       // [G + naux][4] advected quantities of the stage (theta first)
     const int32_t* op_off;    // [nop + 1]
-    const int32_t* op_idx;    // [pts] linear cell index of each stencil point
+    const int32_t* op_idx;    // [pts] position of each stencil point in prim
     const double* op_w;       // [pts] weight of its theta
     const int32_t* op_cell;   // [nop] linear index of the operator's cell | direction << 30 (3 = facet)
     double* flux;             // [nop] flux density (face) or facet term
@@ -66,21 +67,32 @@ __device__ __forceinline__ uint32_t lin(const Dims& D, int i, int j, int k) {
     return ((uint32_t)k * D.ny + j) * D.nx + i;
 }
 
+// One operator per group of DO_LANES lanes: the lanes split its stencil
+// points (theta from the advected-quantity pass of the stage) and add their
+// partial sums by a butterfly over the group.
+constexpr int DO_LANES = 8;
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_diff_ops(DiffArgs<T> a) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= a.nop) return;
-    const int32_t m = a.op_cell[q];
-    const uint32_t c = (uint32_t)m & 0x3FFFFFFFu;
+    const int q = (blockIdx.x * blockDim.x + threadIdx.x) / DO_LANES;
+    const int lane = threadIdx.x % DO_LANES;
+    const bool valid = q < a.nop;
+    const int32_t m = valid ? a.op_cell[q] : 0;
     const int d = (int)((uint32_t)m >> 30);
-    const int b = a.op_off[q], e = a.op_off[q + 1];
+    // facet: the weights act on theta - theta_wall
+    const double sh = d == 3 ? a.theta_wall : 0.0;
     double s = 0.0;
-    if (d == 3) {  // facet: weights act on theta - theta_wall
-        for (int p = b; p < e; ++p) s += a.op_w[p] * (theta_at(a, (uint32_t)a.op_idx[p]) - a.theta_wall);
+    const int e = valid ? a.op_off[q + 1] : 0;
+    for (int p = (valid ? a.op_off[q] : 0) + lane; p < e; p += DO_LANES)
+        s += a.op_w[p] * (a.prim[4 * (size_t)a.op_idx[p]] - sh);
+#pragma unroll
+    for (int mm = DO_LANES / 2; mm >= 1; mm >>= 1) s += __shfl_xor(s, mm, DO_LANES);
+    if (!valid || lane != 0) return;
+    const uint32_t c = (uint32_t)m & 0x3FFFFFFFu;
+    if (d == 3) {
         a.flux[q] = -(double)a.cur_rho[c] * a.alpha * s;
         return;
     }
-    for (int p = b; p < e; ++p) s += a.op_w[p] * theta_at(a, (uint32_t)a.op_idx[p]);
     // the cell below the face along d
     const int nx = a.D.nx, ny = a.D.ny;
     const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((uint32_t)nx * ny));
@@ -147,31 +159,6 @@ __global__ void __launch_bounds__(256) k_diff_gen(DiffArgs<T> a) {
     const double val = a.uhat_rt[g] + a.cdt * br / gq(a.v, 0, GQ_ALPHA, g);
     a.uhat_rt[g] = val;
     a.out_rt[me] = (T)val;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_diff_reg(DiffArgs<T> a) {
-    const int nx = a.D.nx, ny = a.D.ny, nz = a.D.nz;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y, k = blockIdx.z;
-    if (i >= nx) return;
-    if (k < a.v.g1[j * nx + i]) return;  // general range or below
-    const uint32_t me = lin(a.D, i, j, k);
-    const T r0 = a.cur_rho[me];
-    const T t0 = a.cur_rt[me] / r0;
-    const T al = (T)a.alpha;
-    T br = T(0);
-    auto face = [&](uint32_t n) -> T {  // rho_f alpha (theta_n - theta_me), n the other cell
-        const T rn = a.cur_rho[n];
-        return T(0.5) * (rn + r0) * al * (a.cur_rt[n] / rn - t0);
-    };
-    br += (face(lin(a.D, wrapi(i + 1, nx), j, k)) + face(lin(a.D, wrapi(i - 1, nx), j, k))) * (T)(a.rdel[0] * a.rdel[0]);
-    br += (face(lin(a.D, i, wrapi(j + 1, ny), k)) + face(lin(a.D, i, wrapi(j - 1, ny), k))) * (T)(a.rdel[1] * a.rdel[1]);
-    T bz = T(0);
-    if (k + 1 < nz) bz += face(lin(a.D, i, j, k + 1));
-    if (k > 0) bz += face(lin(a.D, i, j, k - 1));
-    br += bz * (T)(a.rdel[2] * a.rdel[2]);
-    a.out_rt[me] = a.out_rt[me] + (T)a.cdt * br;
 }
 
 // ---------------------------------------------------------------- set-up
@@ -310,6 +297,16 @@ ebs_status build_diffusion(ebs_ctx* cx) {
         for (int d = 0; d < 3; ++d) vc[d] = Q(GQ_VCX + d, g);
         return true;
     };
+    // position of a fluid cell in the advected-quantity array: general index,
+    // or an aux position above the range; -1 if the aux range ends below
+    bool reach_ok = true;
+    auto pos = [&](int i, int j, int k) -> int32_t {
+        const int c = wrapi(j, ny) * nx + wrapi(i, nx);
+        if (k < cx->h_g1[c]) return cx->h_goff[c] + (k - cx->h_g0[c]);
+        if (k < cx->h_gp[c]) return (int32_t)(G + cx->h_aoff[c] + (k - cx->h_g1[c]));
+        reach_ok = false;
+        return 0;
+    };
     const double* del = cx->g.dx;
     std::vector<int32_t> off(1, 0), idx, ocell, dtab((size_t)7 * G, -1);
     std::vector<double> wts;
@@ -345,7 +342,7 @@ ebs_status build_diffusion(ebs_ctx* cx) {
                             if (!cell(i + ox, j + oy, k + oz, vc)) continue;
                             const int o3[3] = {ox, oy, oz};
                             for (int a = 0; a < 3; ++a) e[np][a] = (o3[a] + 0.5 + vc[a]) - xf[a];
-                            pidx[np] = (int32_t)(((int64_t)(k + oz) * ny + wrapi(j + oy, ny)) * nx + wrapi(i + ox, nx));
+                            pidx[np] = pos(i + ox, j + oy, k + oz);
                             ++np;
                         }
                 lsq_weights(np, e, true, del, W);
@@ -372,7 +369,7 @@ ebs_status build_diffusion(ebs_ctx* cx) {
                             if (!cell(i + ox, j + oy, k + oz, vc)) continue;
                             const int o3[3] = {ox, oy, oz};
                             for (int a = 0; a < 3; ++a) e[np][a] = (o3[a] + 0.5 + vc[a]) - xe[a];
-                            pidx[np] = (int32_t)(((int64_t)(k + oz) * ny + wrapi(j + oy, ny)) * nx + wrapi(i + ox, nx));
+                            pidx[np] = pos(i + ox, j + oy, k + oz);
                             ++np;
                         }
                 lsq_weights(np, e, false, del, W);
@@ -391,6 +388,10 @@ ebs_status build_diffusion(ebs_ctx* cx) {
         }
     }
     const int nop = (int)ocell.size();
+    if (!reach_ok) {
+        cx->err = "a diffusion fit reads a cell above the stored aux range";
+        return EBS_E_UNSUPPORTED;
+    }
     if ((int64_t)nx * ny * nz > (int64_t)1 << 30) {
         cx->err = "diffusion operators index cells with 30 bits";
         return EBS_E_UNSUPPORTED;
@@ -427,6 +428,7 @@ static DiffArgs<T> diff_args(ebs_ctx* cx, const ebs_state* Ucur, ebs_state* Uh, 
     a.cur_rt = (const T*)Ucur->rhotheta;
     a.out_rt = (T*)Uh->rhotheta;
     a.uhat_rt = cx->d_uhat ? cx->d_uhat + (size_t)cx->G : nullptr;
+    a.prim = cx->d_prim;
     a.op_off = cx->d_dop_off;
     a.op_idx = cx->d_dop_idx;
     a.op_w = cx->d_dop_w;
@@ -446,16 +448,10 @@ template <typename T>
 static ebs_status diff_general_t(ebs_ctx* cx, const ebs_state* Ucur, ebs_state* Uh, double cdt) {
     if (cx->G == 0) return EBS_OK;
     const DiffArgs<T> a = diff_args<T>(cx, Ucur, Uh, cdt);
-    if (a.nop > 0) hipLaunchKernelGGL(k_diff_ops<T>, dim3((a.nop + 255) / 256), dim3(256), 0, cx->stream, a);
+    if (a.nop > 0)
+        hipLaunchKernelGGL(k_diff_ops<T>, dim3((unsigned)(((int64_t)a.nop * DO_LANES + 255) / 256)), dim3(256), 0,
+                           cx->stream, a);
     hipLaunchKernelGGL(k_diff_gen<T>, dim3((cx->G + 255) / 256), dim3(256), 0, cx->stream, a);
-    EBS_HIP(cx, hipGetLastError());
-    return EBS_OK;
-}
-
-template <typename T>
-static ebs_status diff_regular_t(ebs_ctx* cx, const ebs_state* Ucur, ebs_state* Uh, double cdt, hipStream_t s) {
-    const DiffArgs<T> a = diff_args<T>(cx, Ucur, Uh, cdt);
-    hipLaunchKernelGGL(k_diff_reg<T>, dim3((cx->nx + 255) / 256, cx->ny, cx->nz), dim3(256), 0, s, a);
     EBS_HIP(cx, hipGetLastError());
     return EBS_OK;
 }
@@ -465,9 +461,5 @@ ebs_status launch_diffusion_general(ebs_ctx* cx, const ebs_state* Ucur, ebs_stat
     return diff_general_t<double>(cx, Ucur, Uh, cdt);
 }
 
-ebs_status launch_diffusion_regular(ebs_ctx* cx, const ebs_state* Ucur, ebs_state* Uh, double cdt, hipStream_t s) {
-    if (cx->g.precision == EBS_F32_BULK) return diff_regular_t<float>(cx, Ucur, Uh, cdt, s);
-    return diff_regular_t<double>(cx, Ucur, Uh, cdt, s);
-}
 
 }  // namespace ebs

@@ -218,6 +218,9 @@ struct ebs_ctx {
     double* d_sig = nullptr;   // [5][3][G]
     double* d_prim = nullptr;  // [G + naux][4] advected quantities: general range, then aux positions
     int32_t naux = 0;          // positions above the general range read by the face-range stencils
+                               // (and, with momentum diffusion, by its fits and centred differences)
+    std::vector<int32_t> h_gp, h_aoff;  // [ncol] top of the aux range, first aux position
+    int2* d_acol = nullptr;             // [ncol] {first aux position, top of the aux range}
     int4* d_ptab = nullptr;    // [G + naux] cell table of the prims pass
     int4* d_ftab = nullptr;    // [Ge] cell table of the flux pass
     int4* d_utab = nullptr;    // [G] cell table of the update pass
@@ -266,8 +269,7 @@ struct ebs_ctx {
     ebs_viscosity_params visc{};
     int32_t nvop = 0;
     int32_t* d_vop_off = nullptr;  // [nvop + 1]
-    int32_t* d_vop_pt = nullptr;   // [pts] component << 30 | cell
-    uint8_t* d_vop_fl = nullptr;   // [pts] fluid cells beside the velocity's face
+    uint32_t* d_vop_pt = nullptr;  // [pts] component << 28 | position in the advected-quantity array
     double* d_vop_w = nullptr;     // [pts]
     double* d_vflux = nullptr;     // [nvop]
     int32_t* d_vtab = nullptr;     // [G][3][7]
@@ -299,16 +301,16 @@ ebs_status launch_bulk(ebs_ctx* c, const ebs_state* Un, const ebs_state* Ucur, e
 size_t bulk_lds_bytes(int tx, int ty, int precision, bool sources);
 ebs_status launch_restrict(ebs_ctx* cx, const ebs_state* Uf, ebs_state* Uc, double* geo_out);
 // thermal diffusion (diffusion.hip): operators, and the passes of one stage
-// (general range on the context stream, regular region on the given stream)
+// over the general range (context stream)
 ebs_status build_diffusion(ebs_ctx* c);
 ebs_status launch_diffusion_general(ebs_ctx* c, const ebs_state* Ucur, ebs_state* Uhat, double cdt);
-ebs_status launch_diffusion_regular(ebs_ctx* c, const ebs_state* Ucur, ebs_state* Uhat, double cdt,
-                                    hipStream_t stream);
-// momentum diffusion (viscous.hip), same split
+// momentum diffusion (viscous.hip), the same
 ebs_status build_viscous(ebs_ctx* c);
 ebs_status launch_viscous_general(ebs_ctx* c, const ebs_state* Ucur, ebs_state* Uhat, double cdt);
-ebs_status launch_viscous_regular(ebs_ctx* c, const ebs_state* Ucur, ebs_state* Uhat, double cdt,
-                                  hipStream_t stream);
+// thermal and momentum diffusion above the general range (regdiff.hip), one
+// pass on the given stream for whichever of the two is on
+ebs_status launch_regular_diffusion(ebs_ctx* c, const ebs_state* Ucur, ebs_state* Uhat, double cdt,
+                                    hipStream_t stream);
 // redistribution (wsrd.hip)
 ebs_status wsrd_setup(ebs_ctx* c);
 ebs_status launch_redistribute(ebs_ctx* c, const ebs_state* Uhat, ebs_state* Uout);

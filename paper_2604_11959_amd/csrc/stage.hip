@@ -878,7 +878,7 @@ ebs_status build_cut_faces(ebs_ctx* cx) {
 // cut-face record of their CV.
 ebs_status build_stencils(ebs_ctx* cx) {
     for (void** q : {(void**)&cx->d_sten, (void**)&cx->d_upd, (void**)&cx->d_ptab, (void**)&cx->d_ftab,
-                     (void**)&cx->d_utab}) {
+                     (void**)&cx->d_utab, (void**)&cx->d_acol}) {
         if (*q) (void)hipFree(*q);
         *q = nullptr;
     }
@@ -901,6 +901,20 @@ ebs_status build_stencils(ebs_ctx* cx) {
             b = std::max(b, g1e[c]);
         }
     }
+    // With diffusion the fits of the general cells' faces and facets, and
+    // the centred differences, read theta and velocities up to two cells
+    // away in every direction (diagonals included): up to level g1 + 1 of
+    // every column within two columns of a general one.
+    if (cx->visc_on || cx->diff_on)
+        for (int c = 0; c < ncol; ++c) {
+            if (g1[c] <= g0[c]) continue;
+            const int i = c % nx, j = c / nx, top = std::min(nz, g1[c] + 2);
+            for (int dj = -2; dj <= 2; ++dj)
+                for (int di = -2; di <= 2; ++di) {
+                    int& a = gp[cid(i + di, j + dj)];
+                    a = std::max(a, top);
+                }
+        }
     std::vector<int32_t> aoff(ncol);
     int64_t A = 0;
     for (int c = 0; c < ncol; ++c) {
@@ -915,6 +929,8 @@ ebs_status build_stencils(ebs_ctx* cx) {
     for (int c = 0; c < ncol; ++c)
         for (int k = g1[c]; k < gp[c]; ++k) aux[aoff[c] + (k - g1[c])] = make_int2(c, k);
     cx->naux = (int32_t)A;
+    cx->h_gp = gp;
+    cx->h_aoff = aoff;
     const size_t P = (size_t)std::max<int64_t>(G + A, 1);
     const size_t Gs = (size_t)std::max(G, 1), Ges = (size_t)std::max(Ge, 1);
     if (cx->d_prim) (void)hipFree(cx->d_prim);
@@ -934,6 +950,9 @@ ebs_status build_stencils(ebs_ctx* cx) {
     ok = ok && hipMalloc(&d_gp, sizeof(int32_t) * ncol) == hipSuccess;
     ok = ok && hipMalloc(&d_aoff, sizeof(int32_t) * ncol) == hipSuccess;
     ok = ok && hipMalloc(&d_bad, sizeof(int32_t)) == hipSuccess;
+    ok = ok && hipMalloc(&cx->d_acol, sizeof(int2) * ncol) == hipSuccess;
+    std::vector<int2> acol(ncol);
+    for (int c = 0; c < ncol; ++c) acol[c] = make_int2(aoff[c], gp[c]);
     int32_t bad = 0;
     hipError_t e = ok ? hipSuccess : hipErrorOutOfMemory;
     auto chk = [&](hipError_t r) {
@@ -943,6 +962,7 @@ ebs_status build_stencils(ebs_ctx* cx) {
         chk(hipMemcpyAsync(d_aux, aux.data(), sizeof(int2) * aux.size(), hipMemcpyHostToDevice, cx->stream));
         chk(hipMemcpyAsync(d_gp, gp.data(), sizeof(int32_t) * ncol, hipMemcpyHostToDevice, cx->stream));
         chk(hipMemcpyAsync(d_aoff, aoff.data(), sizeof(int32_t) * ncol, hipMemcpyHostToDevice, cx->stream));
+        chk(hipMemcpyAsync(cx->d_acol, acol.data(), sizeof(int2) * ncol, hipMemcpyHostToDevice, cx->stream));
         chk(hipMemsetAsync(d_bad, 0, sizeof(int32_t), cx->stream));
         GenArgs<double> a{};
         a.D = Dims{nx, ny, nz};
@@ -999,12 +1019,8 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
     {
         ebs_status st = launch_bulk(cx, Un, Ucur, Uh, cdt, bs);
         if (st != EBS_OK) return st;
-        if (cx->diff_on) {  // adds to what the regular-region kernel wrote
-            st = launch_diffusion_regular(cx, Ucur, Uh, cdt, bs);
-            if (st != EBS_OK) return st;
-        }
-        if (cx->visc_on) {
-            st = launch_viscous_regular(cx, Ucur, Uh, cdt, bs);
+        if (cx->diff_on || cx->visc_on) {  // adds to what the regular-region kernel wrote
+            st = launch_regular_diffusion(cx, Ucur, Uh, cdt, bs);
             if (st != EBS_OK) return st;
         }
         if (fork) EBS_HIP(cx, hipEventRecord(cx->ev_join, bs));

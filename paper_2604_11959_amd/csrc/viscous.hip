@@ -17,14 +17,16 @@
 // fallback, reciprocal condition number >= 1e-7).
 //
 // The fitted stresses are fixed linear combinations of velocities at fixed
-// CVs, so their weights are built once.  Per stage:
-//   k_visc_ops  one thread per operator (cut face or facet of a CV): its
-//               stress or facet term;
+// CVs, so their weights are built once; the velocities are those the
+// advected-quantity pass of the stage computed for the general range and
+// the positions above it.  Per stage:
+//   k_visc_ops  a group of lanes per operator (cut face or facet of a CV):
+//               its stress or facet term;
 //   k_visc_gen  one thread per general cell and momentum: divergence over the
 //               six faces (full faces by centred differences) and the facet,
-//               added to the provisional momentum (FP64 copy and state);
-//   k_visc_reg  one thread per cell above the general range: the three
-//               momentum CVs there have only full faces.
+//               added to the provisional momentum (FP64 copy and state).
+// The cells above the general range, whose momentum CVs have only full
+// faces, are updated with the thermal diffusion in one pass (regdiff.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,9 +51,10 @@ struct ViscArgs {
     const T* mom[3];
     T* out[3];
     double* uhat;             // [5][G] FP64 provisional state of the general cells
+    const double* prim;       // [G + naux][4] advected quantities of the stage (theta, u, v, w)
+    const int2* acol;         // [ncol] {first aux position, top of the aux range}
     const int32_t* op_off;    // [nop + 1]
-    const int32_t* op_pt;     // [pts] component << 30 | linear cell index of the velocity's CV
-    const uint8_t* op_fl;     // [pts] bit 0: own cell fluid, bit 1: cell below along the component fluid
+    const uint32_t* op_pt;    // [pts] component << 28 | position of the velocity in prim
     const double* op_w;       // [pts]
     double* flux;             // [nop] stress of a face or facet term of a CV
     const int32_t* vtab;      // [G][3][7] operator of the lower x, y, z, upper x, y, z faces, facet
@@ -66,17 +69,6 @@ __device__ __forceinline__ size_t mom_index(const Dims& D, int e, int i, int j, 
     return ((size_t)k * D.ny + j) * D.nx + i;
 }
 
-// volume fraction of the CV (i, j, k) (i, j in range) of an instance: the
-// records in the general range, 1 above it, 0 below it and on the walls
-__device__ __forceinline__ double alpha_at(const GeoView& v, int inst, int i, int j, int k) {
-    if (k < 0 || k > v.nz - 1) return 0.0;
-    if (inst == 3 && k == 0) return 0.0;
-    const int g = gidx(v, i, j, k);
-    if (g == -2) return 0.0;
-    if (g == -1) return 1.0;
-    return gq(v, inst, GQ_ALPHA, g);
-}
-
 // area fraction of the lower d-face of the CV (i, j, k) of an instance
 __device__ __forceinline__ double beta_at(const GeoView& v, int inst, int d, int i, int j, int k) {
     const int g = gidx(v, i, j, k);
@@ -85,25 +77,28 @@ __device__ __forceinline__ double beta_at(const GeoView& v, int inst, int d, int
     return gq(v, inst, GQ_BX + d, g);
 }
 
+// Velocity component e of the CV (i, j, k): the value the advected-quantity
+// pass of the stage computed (momentum over the mean density of the fluid
+// cells beside the face, zero where the CV is not fluid) for positions in
+// the general or aux range; zero below the range and beyond the walls; the
+// plain two-sided formula above the aux range (every CV there is regular).
 template <typename T>
 __device__ double vel_at(const ViscArgs<T>& a, int e, int i, int j, int k) {
     const int nx = a.D.nx, ny = a.D.ny, nz = a.D.nz;
+    if (k < 0 || k >= nz) return 0.0;
     i = wrapi(i, nx);
     j = wrapi(j, ny);
-    if (!(alpha_at(a.v, e + 1, i, j, k) > 0.0)) return 0.0;
-    double s = 0.0;
-    int n = 0;
-    if (k < nz && alpha_at(a.v, 0, i, j, k) > 0.0) {
-        s += (double)a.rho[((size_t)k * ny + j) * nx + i];
-        ++n;
-    }
+    const int c = j * nx + i;
+    const int4 ci = a.v.col[c];
+    const int g0 = col_g0(ci), g1 = col_g1(ci);
+    if (k < g0) return 0.0;
+    if (k < g1) return a.prim[4 * (size_t)(ci.z + (k - g0)) + 1 + e];
+    const int2 ac = a.acol[c];
+    if (k < ac.y) return a.prim[4 * ((size_t)a.v.G + ac.x + (k - g1)) + 1 + e];
+    if (e == 2 && k == 0) return 0.0;
     const int il = e == 0 ? wrapi(i - 1, nx) : i, jl = e == 1 ? wrapi(j - 1, ny) : j, kl = e == 2 ? k - 1 : k;
-    if (kl >= 0 && alpha_at(a.v, 0, il, jl, kl) > 0.0) {
-        s += (double)a.rho[((size_t)kl * ny + jl) * nx + il];
-        ++n;
-    }
-    if (!n) return 0.0;
-    return (double)a.mom[e][mom_index(a.D, e, i, j, k)] / (s / n);
+    const double s = (double)a.rho[((size_t)kl * ny + jl) * nx + il] + (double)a.rho[(size_t)k * ny * nx + c];
+    return (double)a.mom[e][mom_index(a.D, e, i, j, k)] / (0.5 * s);
 }
 
 // stress tau_cd on the lower d-face of the c-momentum CV (i, j, k) from the
@@ -125,32 +120,24 @@ __device__ double mac_stress(const ViscArgs<T>& a, int c, int d, int i, int j, i
     return a.mu * (a1 + a2);
 }
 
+// One operator per group of VO_LANES lanes: the lanes split its points and
+// add their partial sums by a butterfly over the group.
+constexpr int VO_LANES = 8;
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_visc_ops(ViscArgs<T> a) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= a.nop) return;
-    const int nx = a.D.nx, ny = a.D.ny;
+    const int q = (blockIdx.x * blockDim.x + threadIdx.x) / VO_LANES;
+    const int lane = threadIdx.x % VO_LANES;
+    const bool valid = q < a.nop;
     double s = 0.0;
-    for (int p = a.op_off[q]; p < a.op_off[q + 1]; ++p) {
-        const uint32_t code = (uint32_t)a.op_pt[p];
-        const int e = (int)(code >> 30);
-        const uint32_t cidx = code & 0x3FFFFFFFu;
-        const int i = (int)(cidx % nx), j = (int)((cidx / nx) % ny), k = (int)(cidx / ((uint32_t)nx * ny));
-        const uint8_t fl = a.op_fl[p];
-        double r = 0.0;
-        int n = 0;
-        if (fl & 1) {
-            r += (double)a.rho[cidx];
-            ++n;
-        }
-        if (fl & 2) {
-            const int il = e == 0 ? wrapi(i - 1, nx) : i, jl = e == 1 ? wrapi(j - 1, ny) : j, kl = e == 2 ? k - 1 : k;
-            r += (double)a.rho[((size_t)kl * ny + jl) * nx + il];
-            ++n;
-        }
-        if (n) s += a.op_w[p] * (double)a.mom[e][mom_index(a.D, e, i, j, k)] / (r / n);
+    const int p1 = valid ? a.op_off[q + 1] : 0;
+    for (int p = (valid ? a.op_off[q] : 0) + lane; p < p1; p += VO_LANES) {
+        const uint32_t code = a.op_pt[p];
+        s += a.op_w[p] * a.prim[4 * (size_t)(code & 0x0FFFFFFFu) + 1 + (code >> 28)];
     }
-    a.flux[q] = s;
+#pragma unroll
+    for (int m = VO_LANES / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, VO_LANES);
+    if (valid && lane == 0) a.flux[q] = s;
 }
 
 template <typename T>
@@ -214,23 +201,6 @@ __global__ void __launch_bounds__(256) k_visc_gen(ViscArgs<T> a) {
     store_mom(a, c, i, j, k, val);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_visc_reg(ViscArgs<T> a) {
-    const int nx = a.D.nx;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y, k = blockIdx.z;
-    if (i >= nx) return;
-    if (k < a.v.g1[j * nx + i]) return;  // general range or below
-#pragma unroll 1
-    for (int c = 0; c < 3; ++c) {
-        if (c == 2 && k == 0) continue;  // the bottom wall of the w CVs
-        const double blo[3] = {1.0, 1.0, (c != 2 && k == 0) ? 0.0 : 1.0};
-        const double br = visc_div(a, c, i, j, k, blo, [](int) { return -1; });
-        const size_t o = mom_index(a.D, c, i, j, k);
-        store_mom(a, c, i, j, k, (double)a.out[c][o] + a.cdt * br);
-    }
-}
-
 // the CVs of component e whose velocities a fit around the nominal point xn
 // (global cell units) uses: 3 along an axis where xn lines up with the
 // component's CV centres, 4 (two on each side) otherwise
@@ -254,17 +224,13 @@ void stencil_range(int e, const double xn[3], int lo[3], int hi[3]) {
 
 ebs_status build_viscous(ebs_ctx* cx) {
     const int G = cx->G, nx = cx->nx, ny = cx->ny, nz = cx->nz;
-    for (void** p : {(void**)&cx->d_vop_off, (void**)&cx->d_vop_pt, (void**)&cx->d_vop_fl, (void**)&cx->d_vop_w,
+    for (void** p : {(void**)&cx->d_vop_off, (void**)&cx->d_vop_pt, (void**)&cx->d_vop_w,
                      (void**)&cx->d_vflux, (void**)&cx->d_vtab}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
     cx->nvop = 0;
     if (G == 0) return EBS_OK;
-    if ((int64_t)nx * ny * nz > (int64_t)1 << 30) {
-        cx->err = "viscous operators index cells with 30 bits";
-        return EBS_E_UNSUPPORTED;
-    }
     const int NQ = GQ_N;
     std::vector<double> geo((size_t)NINST * NQ * G);
     EBS_HIP(cx, hipMemcpy(geo.data(), cx->d_geo, sizeof(double) * geo.size(), hipMemcpyDeviceToHost));
@@ -284,18 +250,26 @@ ebs_status build_viscous(ebs_ctx* cx) {
         if (g == -1) return 1.0;
         return Q(inst, GQ_ALPHA, g);
     };
+    // position of a fluid velocity CV in the advected-quantity array: general
+    // index, or an aux position above the range; -1 if the aux range ends below
+    auto pos_h = [&](int i, int j, int k) -> int64_t {
+        const int c = mod(j, ny) * nx + mod(i, nx);
+        if (k < cx->h_g1[c]) return cx->h_goff[c] + (k - cx->h_g0[c]);
+        if (k < cx->h_gp[c]) return (int64_t)G + cx->h_aoff[c] + (k - cx->h_g1[c]);
+        return -1;
+    };
+    bool reach_ok = true;
     auto vc_h = [&](int inst, int i, int j, int k, double vc[3]) {
         const int g = gid(i, j, k);
         for (int d = 0; d < 3; ++d) vc[d] = g >= 0 ? Q(inst, GQ_VCX + d, g) : 0.0;
     };
     const double* del = cx->g.dx;
     const double mu = cx->visc.mu, lam = -2.0 / 3.0 * cx->visc.mu;
-    std::vector<int32_t> off(1, 0), pts, vtab((size_t)G * 3 * 7, -1);
-    std::vector<uint8_t> fls;
+    std::vector<int32_t> off(1, 0), vtab((size_t)G * 3 * 7, -1);
+    std::vector<uint32_t> pts;
     std::vector<double> wts;
     double ev[64][3], W[64][3];
-    int32_t code[64];
-    uint8_t flag[64];
+    uint32_t code[64];
     // the fluid CVs of component e in the stencil around xn, offsets from x
     auto gather = [&](int e, const double xn[3], const double x[3]) -> int {
         int lo[3], hi[3];
@@ -309,13 +283,9 @@ ebs_status build_viscous(ebs_ctx* cx) {
                     vc_h(e + 1, i, j, k, vc);
                     const int idx[3] = {i, j, k};
                     for (int a = 0; a < 3; ++a) ev[np][a] = (idx[a] + 0.5 - (a == e ? 0.5 : 0.0) + vc[a]) - x[a];
-                    const int wi = mod(i, nx), wj = mod(j, ny);
-                    code[np] = (int32_t)(((uint32_t)e << 30) | (uint32_t)(((int64_t)k * ny + wj) * nx + wi));
-                    uint8_t f = 0;
-                    if (k < nz && alpha_h(0, wi, wj, k) > 0.0) f |= 1;
-                    const int il = e == 0 ? wi - 1 : wi, jl = e == 1 ? wj - 1 : wj, kl = e == 2 ? k - 1 : k;
-                    if (kl >= 0 && alpha_h(0, il, jl, kl) > 0.0) f |= 2;
-                    flag[np] = f;
+                    const int64_t ps = pos_h(i, j, k);
+                    if (ps < 0) reach_ok = false;
+                    code[np] = ((uint32_t)e << 28) | (uint32_t)std::max<int64_t>(ps, 0);
                     ++np;
                 }
         return np;
@@ -353,7 +323,6 @@ ebs_status build_viscous(ebs_ctx* cx) {
                         lsq_weights(np, ev, true, del, W);
                         for (int p = 0; p < np; ++p) {
                             pts.push_back(code[p]);
-                            fls.push_back(flag[p]);
                             wts.push_back(coef(e, c, d, W[p]));
                         }
                     }
@@ -378,7 +347,6 @@ ebs_status build_viscous(ebs_ctx* cx) {
                             double t = 0.0;  // tau_c . n_out A, n_out A = -(area vector into the fluid)
                             for (int d = 0; d < 3; ++d) t -= av[d] * coef(e, c, d, W[p]);
                             pts.push_back(code[p]);
-                            fls.push_back(flag[p]);
                             wts.push_back(t);
                         }
                     }
@@ -389,11 +357,14 @@ ebs_status build_viscous(ebs_ctx* cx) {
             }
         }
     }
+    if (!reach_ok) {
+        cx->err = "a viscous fit reads a velocity above the stored aux range";
+        return EBS_E_UNSUPPORTED;
+    }
     const int nop = (int)off.size() - 1;
     const size_t np = std::max<size_t>(pts.size(), 1);
     bool ok = hipMalloc(&cx->d_vop_off, sizeof(int32_t) * (nop + 1)) == hipSuccess;
     ok = ok && hipMalloc(&cx->d_vop_pt, sizeof(int32_t) * np) == hipSuccess;
-    ok = ok && hipMalloc(&cx->d_vop_fl, np) == hipSuccess;
     ok = ok && hipMalloc(&cx->d_vop_w, sizeof(double) * np) == hipSuccess;
     ok = ok && hipMalloc(&cx->d_vflux, sizeof(double) * std::max(nop, 1)) == hipSuccess;
     ok = ok && hipMalloc(&cx->d_vtab, sizeof(int32_t) * vtab.size()) == hipSuccess;
@@ -403,8 +374,7 @@ ebs_status build_viscous(ebs_ctx* cx) {
     }
     EBS_HIP(cx, hipMemcpy(cx->d_vop_off, off.data(), sizeof(int32_t) * (nop + 1), hipMemcpyHostToDevice));
     if (!pts.empty()) {
-        EBS_HIP(cx, hipMemcpy(cx->d_vop_pt, pts.data(), sizeof(int32_t) * pts.size(), hipMemcpyHostToDevice));
-        EBS_HIP(cx, hipMemcpy(cx->d_vop_fl, fls.data(), fls.size(), hipMemcpyHostToDevice));
+        EBS_HIP(cx, hipMemcpy(cx->d_vop_pt, pts.data(), sizeof(uint32_t) * pts.size(), hipMemcpyHostToDevice));
         EBS_HIP(cx, hipMemcpy(cx->d_vop_w, wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
     }
     EBS_HIP(cx, hipMemcpy(cx->d_vtab, vtab.data(), sizeof(int32_t) * vtab.size(), hipMemcpyHostToDevice));
@@ -427,7 +397,8 @@ static ViscArgs<T> visc_args(ebs_ctx* cx, const ebs_state* Ucur, ebs_state* Uh, 
     a.uhat = cx->d_uhat;
     a.op_off = cx->d_vop_off;
     a.op_pt = cx->d_vop_pt;
-    a.op_fl = cx->d_vop_fl;
+    a.prim = cx->d_prim;
+    a.acol = cx->d_acol;
     a.op_w = cx->d_vop_w;
     a.flux = cx->d_vflux;
     a.vtab = cx->d_vtab;
@@ -444,16 +415,10 @@ template <typename T>
 static ebs_status visc_general_t(ebs_ctx* cx, const ebs_state* Ucur, ebs_state* Uh, double cdt) {
     if (cx->G == 0) return EBS_OK;
     const ViscArgs<T> a = visc_args<T>(cx, Ucur, Uh, cdt);
-    if (a.nop > 0) hipLaunchKernelGGL(k_visc_ops<T>, dim3((a.nop + 255) / 256), dim3(256), 0, cx->stream, a);
+    if (a.nop > 0)
+        hipLaunchKernelGGL(k_visc_ops<T>, dim3((unsigned)(((int64_t)a.nop * VO_LANES + 255) / 256)), dim3(256), 0,
+                           cx->stream, a);
     hipLaunchKernelGGL(k_visc_gen<T>, dim3((cx->G + 255) / 256, 3), dim3(256), 0, cx->stream, a);
-    EBS_HIP(cx, hipGetLastError());
-    return EBS_OK;
-}
-
-template <typename T>
-static ebs_status visc_regular_t(ebs_ctx* cx, const ebs_state* Ucur, ebs_state* Uh, double cdt, hipStream_t s) {
-    const ViscArgs<T> a = visc_args<T>(cx, Ucur, Uh, cdt);
-    hipLaunchKernelGGL(k_visc_reg<T>, dim3((cx->nx + 255) / 256, cx->ny, cx->nz), dim3(256), 0, s, a);
     EBS_HIP(cx, hipGetLastError());
     return EBS_OK;
 }
@@ -463,9 +428,5 @@ ebs_status launch_viscous_general(ebs_ctx* cx, const ebs_state* Ucur, ebs_state*
     return visc_general_t<double>(cx, Ucur, Uh, cdt);
 }
 
-ebs_status launch_viscous_regular(ebs_ctx* cx, const ebs_state* Ucur, ebs_state* Uh, double cdt, hipStream_t s) {
-    if (cx->g.precision == EBS_F32_BULK) return visc_regular_t<float>(cx, Ucur, Uh, cdt, s);
-    return visc_regular_t<double>(cx, Ucur, Uh, cdt, s);
-}
 
 }  // namespace ebs
