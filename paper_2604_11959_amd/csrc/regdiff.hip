@@ -120,6 +120,19 @@ __global__ void __launch_bounds__(TX * TY) k_diff_regular(RegDiffArgs<T> a) {
     const int dme = (ty + 2) * DX + (tx + 2);  // own point in the density region
     const T mu = a.mu, mu2 = a.mu2, lam = a.lam, rdx = a.rd[0], rdy = a.rd[1], rdz = a.rd[2];
     T thm1 = T(0), rhm1 = T(0);  // own theta and rho of the plane below the updated one
+    // the output values of the own cell that the next update adds to (rho
+    // theta, rho u, rho v, rho w of plane p - 1), loaded one iteration ahead
+    T oo[4] = {T(0), T(0), T(0), T(0)};
+    auto fetch_out = [&](int kk) {
+        if (!(act && kk >= kmin && kk >= kg && kk < nz)) return;
+        if (TH) oo[0] = a.out_rt[((size_t)kk * ny + j) * nx + i];
+        if (VI) {
+            oo[1] = a.out[0][((size_t)kk * ny + j) * (nx + 1) + i];
+            oo[2] = a.out[1][((size_t)kk * (ny + 1) + j) * nx + i];
+            if (kk >= 1) oo[3] = a.out[2][((size_t)kk * ny + j) * nx + i];
+        }
+    };
+    fetch_out(kmin - 1);
     for (int p = kmin - 2; p <= nz; ++p) {
         // density plane p enters the ring (its slot held plane p - 3, which
         // no thread reads any more; planes p - 2 and p - 1, which the update
@@ -155,6 +168,8 @@ __global__ void __launch_bounds__(TX * TY) k_diff_regular(RegDiffArgs<T> a) {
             }
         }
         fetch(p + 1);
+        T on[4] = {oo[0], oo[1], oo[2], oo[3]};  // this update's output values
+        fetch_out(p);
         __syncthreads();
         const int k = p - 1;  // the plane updated now
         if (k >= kmin && act && k >= kg) {
@@ -172,7 +187,7 @@ __global__ void __launch_bounds__(TX * TY) k_diff_regular(RegDiffArgs<T> a) {
                 if (k > 0) bz += face(rhm1, thm1);
                 br += bz * (rdz * rdz);
                 const size_t o = ((size_t)k * ny + j) * nx + i;
-                a.out_rt[o] = a.out_rt[o] + a.cdt * br;
+                a.out_rt[o] = on[0] + a.cdt * br;
             }
             if (VI) {
                 // velocity slots of planes k - 1, k, k + 1
@@ -213,7 +228,7 @@ __global__ void __launch_bounds__(TX * TY) k_diff_regular(RegDiffArgs<T> a) {
                     const T zhi = k == nz - 1 ? T(0) : exz(V0, Vp, 0);
                     const T br = (t1 - t0) * rdx + (exy(0, 1) - xy00) * rdy + (zhi - zlo) * rdz;
                     const size_t o = ((size_t)k * ny + j) * (nx + 1) + i;
-                    const T val = a.out[0][o] + a.cdt * br;
+                    const T val = on[1] + a.cdt * br;
                     a.out[0][o] = val;
                     if (i == 0) a.out[0][o + nx] = val;
                 }
@@ -225,7 +240,7 @@ __global__ void __launch_bounds__(TX * TY) k_diff_regular(RegDiffArgs<T> a) {
                     const T zhi = k == nz - 1 ? T(0) : eyz(V0, Vp, 0);
                     const T br = (exy(1, 0) - xy00) * rdx + (t1 - t0) * rdy + (zhi - zlo) * rdz;
                     const size_t o = ((size_t)k * (ny + 1) + j) * nx + i;
-                    const T val = a.out[1][o] + a.cdt * br;
+                    const T val = on[2] + a.cdt * br;
                     a.out[1][o] = val;
                     if (j == 0) a.out[1][o + (size_t)ny * nx] = val;
                 }
@@ -236,7 +251,7 @@ __global__ void __launch_bounds__(TX * TY) k_diff_regular(RegDiffArgs<T> a) {
                     const T br =
                         (exz(Vm, V0, 1) - xz_lo) * rdx + (eyz(Vm, V0, 1) - yz_lo) * rdy + (t1 - t0) * rdz;
                     const size_t o = ((size_t)k * ny + j) * nx + i;
-                    a.out[2][o] = a.out[2][o] + a.cdt * br;
+                    a.out[2][o] = on[3] + a.cdt * br;
                 }
             }
         }

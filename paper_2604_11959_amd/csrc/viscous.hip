@@ -131,9 +131,23 @@ __global__ void __launch_bounds__(256) k_visc_ops(ViscArgs<T> a) {
     const bool valid = q < a.nop;
     double s = 0.0;
     const int p1 = valid ? a.op_off[q + 1] : 0;
-    for (int p = (valid ? a.op_off[q] : 0) + lane; p < p1; p += VO_LANES) {
-        const uint32_t code = a.op_pt[p];
-        s += a.op_w[p] * a.prim[4 * (size_t)(code & 0x0FFFFFFFu) + 1 + (code >> 28)];
+    // four points per lane and pass: their codes and weights, then their
+    // velocities, are loaded together
+    constexpr int U = 4;
+    for (int p = (valid ? a.op_off[q] : 0) + lane; p < p1; p += U * VO_LANES) {
+        uint32_t code[U];
+        double w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int pp = p + u * VO_LANES;
+            code[u] = pp < p1 ? a.op_pt[pp] : 0u;
+            w[u] = pp < p1 ? a.op_w[pp] : 0.0;
+        }
+        double vv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) vv[u] = a.prim[4 * (size_t)(code[u] & 0x0FFFFFFFu) + 1 + (code[u] >> 28)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += w[u] * vv[u];
     }
 #pragma unroll
     for (int m = VO_LANES / 2; m >= 1; m >>= 1) s += __shfl_xor(s, m, VO_LANES);
