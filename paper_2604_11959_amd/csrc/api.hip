@@ -720,14 +720,27 @@ ebs_status ebs_set_sources(ebs_ctx* c, const ebs_source_params* prm, const doubl
         c->d_srcd = nullptr;
         return fail(c, EBS_E_OOM, "source tables");
     }
-    if (!c->d_srcf && hipMalloc(&c->d_srcf, sizeof(float) * 5 * nz) != hipSuccess) {
+    // FP32 power table after the level values (see pprime in bulk.hip): for
+    // m = -32..32, R' = 2^(-m/8) in FP32, R' - 1, c = R'^(-gamma), c - 1
+    const int ntab = 4 * 65;
+    tf.resize((size_t)5 * nz + ntab);
+    for (int m = -32; m <= 32; ++m) {
+        const float r = (float)std::exp2(-m / 8.0);
+        const double cm = std::pow((double)r, -q.gamma);
+        float* e = &tf[(size_t)5 * nz + 4 * (m + 32)];
+        e[0] = r;
+        e[1] = (float)((double)r - 1.0);
+        e[2] = (float)cm;
+        e[3] = (float)(cm - 1.0);
+    }
+    if (!c->d_srcf && hipMalloc(&c->d_srcf, sizeof(float) * (5 * nz + ntab)) != hipSuccess) {
         c->d_srcf = nullptr;
         return fail(c, EBS_E_OOM, "source tables");
     }
     // stages already queued on the context stream may still read the tables
     EBS_HIP(c, hipStreamSynchronize(c->stream));
     EBS_HIP(c, hipMemcpy(c->d_srcd, td.data(), sizeof(double) * 5 * nz, hipMemcpyHostToDevice));
-    EBS_HIP(c, hipMemcpy(c->d_srcf, tf.data(), sizeof(float) * 5 * nz, hipMemcpyHostToDevice));
+    EBS_HIP(c, hipMemcpy(c->d_srcf, tf.data(), sizeof(float) * tf.size(), hipMemcpyHostToDevice));
     c->src = q;
     c->src_on = true;
     drop_graph(c);

@@ -67,15 +67,27 @@ __device__ __forceinline__ double expm1_t(double x) { return expm1(x); }
 // as a float pair, so the departure is exact up to one rounding)
 //
 // FP32: (1 + x)^gamma - 1 from the binomial series sum_{n=1..8} C(gamma, n) x^n
-// for |x| < 1/8 (truncation below 1e-9 relative; coefficients in bc[]), and
-// from expm1(gamma log1p(x)) beyond (the hardware base-2 exponential and
-// logarithm lose the low bits of the result to the subtraction of 1 and put
-// an error of about 1.5e-7 p0 on p', several times its own rounding).  FP64:
-// log1p and expm1.
+// for |x| < 1/8 (truncation below 1e-9 relative; coefficients in bc[]).
+// Beyond, 1 + x is first divided by a tabulated R = 2^(m/8) close to it (m
+// from the hardware base-2 logarithm, which only has to pick the entry):
+// y = x R' + (R' - 1) with R' = 1/R is exact up to one rounding and below
+// 2^(1/16) - 1 in magnitude, so the same series gives (1 + y)^gamma - 1, and
+// (1 + x)^gamma - 1 = c (1 + y)^gamma - 1 = c s + (c - 1) with c = R^gamma
+// (table entries {R', R' - 1, c, c - 1} for m = -32..32, formed in FP64 from
+// the FP32 value of R').  No library call and no extra registers on the
+// common path (expm1f / log1pf made the kernel spill or, out of line, cost a
+// call frame), and no subtraction of two values near 1 (the hardware base-2
+// exponential and logarithm of the whole power would put an error of about
+// 1.5e-7 p0 on p', several times its own rounding).  FP64: log1p and expm1.
 constexpr int PP_DEG = 8;
-// kept out of line: the branch is rare and its library calls would otherwise
-// raise the register pressure of the whole regular-region kernel
-__device__ __attribute__((noinline)) float pow_departure(float gam, float x) { return expm1f(gam * log1pf(x)); }
+constexpr int PP_TAB = 32;  // table entries m = -PP_TAB .. PP_TAB, after the 5 nz level values
+template <typename T>
+__device__ __forceinline__ T pow_series(const T* bc, T x) {
+    T e = bc[PP_DEG - 1];
+#pragma unroll
+    for (int n = PP_DEG - 2; n >= 0; --n) e = e * x + bc[n];
+    return e * x;
+}
 template <typename T>
 __device__ __forceinline__ T pprime(const T* __restrict__ sref, int nz, T gam, const T* bc, T rt, int k) {
     if constexpr (sizeof(T) == 8) {
@@ -85,12 +97,12 @@ __device__ __forceinline__ T pprime(const T* __restrict__ sref, int nz, T gam, c
         const float x = ((rt - sref[nz + k]) - sref[2 * nz + k]) * sref[3 * nz + k];
         float e;
         if (fabsf(x) < 0.125f) {
-            e = bc[PP_DEG - 1];
-#pragma unroll
-            for (int n = PP_DEG - 2; n >= 0; --n) e = e * x + bc[n];
-            e *= x;
+            e = pow_series<float>(bc, x);
         } else {
-            e = pow_departure(gam, x);
+            const int m = (int)rintf(8.0f * __builtin_amdgcn_logf(1.0f + x));
+            const float* t = sref + 5 * nz + 4 * (min(max(m, -PP_TAB), PP_TAB) + PP_TAB);
+            const float y = fmaf(x, t[0], t[1]);
+            e = fmaf(t[2], pow_series<float>(bc, y), t[3]);
         }
         return sref[k] * e;
     }
