@@ -39,6 +39,13 @@ class Visc:
     eb_mode: int = 0
 
 
+@dataclass
+class Diff:
+    alpha_theta: float
+    eb_mode: int = 1
+    theta_wall: float = 299.0
+
+
 def _case(name):
     if name not in _cache:
         if name == "cylinder":
@@ -209,3 +216,32 @@ def test_viscous_conserves_with_stress_free_eb(name):
     for bad in (Visc(mu=-1.0), Visc(mu=float("nan")), Visc(mu=1.0, eb_mode=2)):
         with pytest.raises(ebs.EbsError):
             c.set_viscosity(bad)
+
+
+def test_diffusion_switched_on_before_or_after_the_geometry():
+    """Switching the thermal and momentum diffusion on before the geometry
+    build (the build sizes the stencil tables for them) or after it (the
+    switch rebuilds them) gives the same stage bit for bit, FP64 and FP32."""
+    w, o = _case("c2")
+    p = _visc(w, 1)
+    d = Diff(alpha_theta=0.1 * min(w.grid.dx) ** 2 / w.dt)
+    U0 = _state(w)
+    for prec in (ebs.EBS_F64, ebs.EBS_F32_BULK):
+        outs = []
+        for before in (True, False):
+            c = ebs.Context(w.grid.n, w.grid.dx, w.grid.lo, precision=prec)
+            if before:
+                c.set_diffusion(d)
+                c.set_viscosity(p)
+                c.build_geometry(w.h_nodes)
+            else:
+                c.build_geometry(w.h_nodes)
+                c.set_viscosity(p)
+                c.set_diffusion(d)
+            Ud, Uh = c.new_state(U0), c.new_state()
+            c.advance(Ud, Ud, Uh, w.dt / 3)
+            c.redistribute(Uh, Uh)
+            torch.cuda.synchronize()
+            outs.append(Uh)
+        for f in FIELDS:
+            assert torch.equal(outs[0][f], outs[1][f]), (prec, f)
