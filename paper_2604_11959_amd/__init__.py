@@ -75,6 +75,11 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise OSError(f"{path} not found: build it with `python -m paper_2604_11959_amd.build`")
+    # PyTorch ships its own HIP runtime; loading it first makes the library
+    # bind to that one, so streams and device pointers from torch are valid
+    # in the library (a second runtime would reject them)
+    import torch  # noqa: F401
+
     lib = C.CDLL(path)
     P = C.POINTER
     st = C.c_int
