@@ -141,6 +141,54 @@ def measured_traffic(tile, workload_name, alg_bytes):
     return float(s["traffic_bytes_per_launch"])
 
 
+# bytes per cut CV-instance of an FP64 geometry record (volume and area
+# fractions, centroids, normal): the middle of the 160-200 B such a record takes
+GEOM_RECORD_BYTES = 180.0
+
+
+def general_range_leg(stats, precision, workload_name):
+    """The general range and the redistribution against the extras the cut
+    cells add to the regular-region bytes: the general cells' own state
+    passes (8/3 x 5 x s per cell, as for a regular cell), one FP64 geometry
+    record per cut CV-instance, and the FP64 side buffer U-hat written and
+    read once (2 x 5 x 8 B per general cell).  Counter bytes per stage come
+    from the committed counter summary when it was taken on the same
+    general-range sources and workload, else null."""
+    import paper_2604_11959_amd as ebs
+    from paper_2604_11959_amd import profile_traffic
+
+    s = 4.0 if precision == ebs.EBS_F32_BULK else 8.0
+    G = int(stats[0][6])
+    cut = int(sum(int(r[0]) for r in stats))
+    small = int(sum(int(r[1]) for r in stats))
+    extras = {"state": G * 8.0 / 3.0 * 5 * s, "geometry_records": cut * GEOM_RECORD_BYTES, "uhat": G * 2 * 5 * 8.0}
+    extras["total"] = sum(extras.values())
+    leg = {"general_cells": G, "cut_cv_instances": cut, "small_cvs": small,
+           "extras_formula": f"G*8/3*5*{int(s)} + cut*{int(GEOM_RECORD_BYTES)} + G*2*5*8 B per stage",
+           "extras_bytes_per_stage": {k: round(v) for k, v in extras.items()},
+           "counter_bytes_per_stage": None}
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            summ = json.load(f)
+    except (OSError, ValueError):
+        return leg
+    per = summ.get("general_range_bytes_per_stage")
+    if (not per or summ.get("workload") != workload_name
+            or summ.get("general_source_sha256") != profile_traffic.source_sha256(profile_traffic.GENERAL_SOURCES)):
+        return leg
+    upd = sum(per.get(k, 0.0) for k in ("k_gen_prims", "k_gen_fhat", "k_gen_cut", "k_gen_update"))
+    red = sum(per.get(k, 0.0) for k in ("k_qhat", "k_grad", "k_final"))
+    leg["counter_bytes_per_stage"] = {"per_kernel": {k: round(v) for k, v in per.items()},
+                                      "update_passes": round(upd), "redistribution": round(red),
+                                      "total": round(upd + red)}
+    leg["update_passes_over_extras"] = round(upd / extras["total"], 2)
+    leg["total_over_extras"] = round((upd + red) / extras["total"], 2)
+    # the extras name no byte figure for the redistribution tables: their
+    # counter bytes per small CV instead
+    leg["redistribution_bytes_per_small_cv"] = round(red / max(small, 1), 1)
+    return leg
+
+
 def diffusion_params(w):
     """Thermal diffusivity and dynamic viscosity for the diffusion leg:
     diffusion numbers 0.1 (rho theta) and 0.05 (momenta, at density 1.2) per
@@ -444,6 +492,7 @@ def main(argv=None):
             "alg_bytes_per_launch": bytes_per_launch,
         },
     }
+    out["general_range"] = general_range_leg(stats, precision, w.name)
     out["copy_reference"] = copy
     out["conservation"] = {
         "check": "relative change of sum V U per field (rho, rho theta, rho u, rho v, rho w) over the "

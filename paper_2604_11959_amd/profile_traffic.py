@@ -23,7 +23,10 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = [os.path.join(HERE, "csrc", n) for n in ("bulk.hip", "stage_common.h")]
+GENERAL_SOURCES = [os.path.join(HERE, "csrc", n) for n in ("stage.hip", "wsrd.hip", "stage_common.h")]
 COPY_BYTES = 1 << 30
+# the kernels of a stage besides the regular-region one
+GENERAL_PASSES = ("k_gen_prims", "k_gen_fhat", "k_gen_cut", "k_gen_update", "k_qhat", "k_grad", "k_final")
 
 
 def source_sha256(paths=None) -> str:
@@ -66,6 +69,22 @@ def summarize(pmc_dir: str, kernel_prefix: str = "k_bulk"):
     if not fk or len(fk) != len(wk):
         raise SystemExit("fetch / write runs do not hold the same regular-region dispatches")
     per_launch = [fv * 1024.0 * fscale + wv * 1024.0 * wscale for fv, wv in zip(fk, wk)]
+    # the passes over the general range and the redistribution: calibrated
+    # bytes per stage of each of their kernels, averaged over the stages of
+    # the run (dispatches from the first regular-region launch on)
+    ids = sorted(fetch)
+    first = next(d for d in ids if kernel_prefix in fetch[d][0])
+    other = {}
+    for d in ids:
+        if d <= first or d not in write:
+            continue
+        name = fetch[d][0].replace("void ", "").replace("ebs::(anonymous namespace)::", "").strip()
+        name = name.split("<")[0].split("(")[0]
+        if name not in GENERAL_PASSES:
+            continue
+        b = fetch[d][1] * 1024.0 * fscale + write[d][1] * 1024.0 * wscale
+        other.setdefault(name, []).append(b)
+    stage_bytes = {n: sum(v) / len(per_launch) for n, v in other.items()}
     return {
         "kernel": kernel_prefix,
         "launches": len(per_launch),
@@ -74,7 +93,9 @@ def summarize(pmc_dir: str, kernel_prefix: str = "k_bulk"):
         "fetch_scale": fscale,
         "write_scale": wscale,
         "traffic_bytes_per_launch": sum(per_launch) / len(per_launch),
+        "general_range_bytes_per_stage": stage_bytes,
         "kernel_source_sha256": source_sha256(),
+        "general_source_sha256": source_sha256(GENERAL_SOURCES),
     }
 
 
