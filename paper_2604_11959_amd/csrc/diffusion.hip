@@ -34,6 +34,7 @@
 
 #include "ebs_internal.h"
 #include "stage_common.h"
+#include "xcd.h"
 
 namespace ebs {
 namespace {
@@ -74,7 +75,7 @@ constexpr int DO_LANES = 8;
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_diff_ops(DiffArgs<T> a) {
-    const int q = (blockIdx.x * blockDim.x + threadIdx.x) / DO_LANES;
+    const int q = (xcd_block() * blockDim.x + threadIdx.x) / DO_LANES;
     const int lane = threadIdx.x % DO_LANES;
     const bool valid = q < a.nop;
     const int32_t m = valid ? a.op_cell[q] : 0;
@@ -112,7 +113,7 @@ __device__ __forceinline__ double beta0(const GeoView& v, int d, int i, int j, i
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_diff_gen(DiffArgs<T> a) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = xcd_block() * blockDim.x + threadIdx.x;
     if (g >= a.v.G) return;
     if (a.v.type[g] == 0) return;  // cell-centred CV without fluid
     const int c = a.v.gcol[g];
@@ -449,9 +450,9 @@ static ebs_status diff_general_t(ebs_ctx* cx, const ebs_state* Ucur, ebs_state* 
     if (cx->G == 0) return EBS_OK;
     const DiffArgs<T> a = diff_args<T>(cx, Ucur, Uh, cdt);
     if (a.nop > 0)
-        hipLaunchKernelGGL(k_diff_ops<T>, dim3((unsigned)(((int64_t)a.nop * DO_LANES + 255) / 256)), dim3(256), 0,
+        hipLaunchKernelGGL(k_diff_ops<T>, dim3(xcd_grid(((int64_t)a.nop * DO_LANES + 255) / 256)), dim3(256), 0,
                            cx->stream, a);
-    hipLaunchKernelGGL(k_diff_gen<T>, dim3((cx->G + 255) / 256), dim3(256), 0, cx->stream, a);
+    hipLaunchKernelGGL(k_diff_gen<T>, dim3(xcd_grid((cx->G + 255) / 256)), dim3(256), 0, cx->stream, a);
     EBS_HIP(cx, hipGetLastError());
     return EBS_OK;
 }

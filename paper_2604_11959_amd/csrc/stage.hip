@@ -22,6 +22,7 @@
 
 #include "ebs_internal.h"
 #include "stage_common.h"
+#include "xcd.h"
 
 namespace ebs {
 namespace {
@@ -534,7 +535,7 @@ struct PrimIn {
 template <typename T>
 __global__ void __launch_bounds__(256) k_gen_prims(GenArgs<T> a) {
     const int n = a.v.G + a.naux;
-    const int base = blockIdx.x * (GEN_CO * 256) + threadIdx.x;
+    const int base = xcd_block() * (GEN_CO * 256) + threadIdx.x;
     const Gen<T> G(a);
     int4 t[GEN_CO];
     PrimIn in[GEN_CO];
@@ -595,7 +596,7 @@ __global__ void __launch_bounds__(256) k_gen_prims(GenArgs<T> a) {
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_gen_fhat(GenArgs<T> a) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;  // extended face range
+    const int e = xcd_block() * blockDim.x + threadIdx.x;  // extended face range
     if (e >= a.v.Ge) return;
     const Gen<T> G(a);
     const int4 t = a.ftab[e];
@@ -646,7 +647,7 @@ __global__ void __launch_bounds__(256) k_gen_update_eb(GenArgs<T> a) {
 // the update (EB flux zero), from the update table
 template <typename T>
 __global__ void __launch_bounds__(256) k_gen_update(GenArgs<T> a) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = xcd_block() * blockDim.x + threadIdx.x;
     if (g >= a.v.G) return;
     const Gen<T> G(a);
     const int Gn = a.v.G;
@@ -688,7 +689,7 @@ __global__ void __launch_bounds__(256) k_gen_update(GenArgs<T> a) {
 // field(s) of the face's instance (slot 1: rho theta of the cell-centred CVs).
 template <typename T>
 __global__ void __launch_bounds__(256) k_gen_cut(GenArgs<T> a) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = xcd_block() * blockDim.x + threadIdx.x;
     if (r >= a.ncut) return;
     const CutRec c = a.crec[r];
     const int s = c.sd / 3, d = c.sd - 3 * s;
@@ -1056,18 +1057,20 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
         a.sR = cx->src.R;
         a.sgam = cx->src.gamma;
         a.sg = cx->src.g;
-        const dim3 grid((cx->G + 255) / 256), gride((cx->Ge + 255) / 256), blk(256);
+        // work-list passes spread over the XCDs in contiguous chunks (xcd.h);
+        // the test-mode update keeps the plain mapping
+        const dim3 grid((cx->G + 255) / 256), blk(256);
         // the first two passes only read the input state; the update writes
         // the output (which may alias U^n, never U_cur)
-        hipLaunchKernelGGL(k_gen_prims<T>, dim3((cx->G + cx->naux + GEN_CO * 256 - 1) / (GEN_CO * 256)), blk, 0,
-                           cx->stream, a);
-        hipLaunchKernelGGL(k_gen_fhat<T>, gride, blk, 0, cx->stream, a);
+        hipLaunchKernelGGL(k_gen_prims<T>, dim3(xcd_grid((cx->G + cx->naux + GEN_CO * 256 - 1) / (GEN_CO * 256))),
+                           blk, 0, cx->stream, a);
+        hipLaunchKernelGGL(k_gen_fhat<T>, dim3(xcd_grid((cx->Ge + 255) / 256)), blk, 0, cx->stream, a);
         if (cx->ncut > 0)
-            hipLaunchKernelGGL(k_gen_cut<T>, dim3((cx->ncut + 255) / 256), blk, 0, cx->stream, a);
+            hipLaunchKernelGGL(k_gen_cut<T>, dim3(xcd_grid((cx->ncut + 255) / 256)), blk, 0, cx->stream, a);
         if (a.eb_mode == 1)
             hipLaunchKernelGGL(k_gen_update_eb<T>, grid, blk, 0, cx->stream, a);
         else
-            hipLaunchKernelGGL(k_gen_update<T>, grid, blk, 0, cx->stream, a);
+            hipLaunchKernelGGL(k_gen_update<T>, dim3(xcd_grid((cx->G + 255) / 256)), blk, 0, cx->stream, a);
         EBS_HIP(cx, hipGetLastError());
         if (cx->diff_on) {  // adds to what the update wrote
             const ebs_status st = launch_diffusion_general(cx, Ucur, Uh, cdt);

@@ -35,6 +35,7 @@
 
 #include "ebs_internal.h"
 #include "stage_common.h"
+#include "xcd.h"
 
 namespace ebs {
 
@@ -126,7 +127,7 @@ constexpr int VO_LANES = 8;
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_visc_ops(ViscArgs<T> a) {
-    const int q = (blockIdx.x * blockDim.x + threadIdx.x) / VO_LANES;
+    const int q = (xcd_block() * blockDim.x + threadIdx.x) / VO_LANES;
     const int lane = threadIdx.x % VO_LANES;
     const bool valid = q < a.nop;
     double s = 0.0;
@@ -191,7 +192,7 @@ __device__ double visc_div(const ViscArgs<T>& a, int c, int i, int j, int k, con
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_visc_gen(ViscArgs<T> a) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = xcd_block() * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (g >= a.v.G) return;
     const double alpha = gq(a.v, c + 1, GQ_ALPHA, g);
@@ -430,9 +431,9 @@ static ebs_status visc_general_t(ebs_ctx* cx, const ebs_state* Ucur, ebs_state* 
     if (cx->G == 0) return EBS_OK;
     const ViscArgs<T> a = visc_args<T>(cx, Ucur, Uh, cdt);
     if (a.nop > 0)
-        hipLaunchKernelGGL(k_visc_ops<T>, dim3((unsigned)(((int64_t)a.nop * VO_LANES + 255) / 256)), dim3(256), 0,
+        hipLaunchKernelGGL(k_visc_ops<T>, dim3(xcd_grid(((int64_t)a.nop * VO_LANES + 255) / 256)), dim3(256), 0,
                            cx->stream, a);
-    hipLaunchKernelGGL(k_visc_gen<T>, dim3((cx->G + 255) / 256, 3), dim3(256), 0, cx->stream, a);
+    hipLaunchKernelGGL(k_visc_gen<T>, dim3(xcd_grid((cx->G + 255) / 256), 3), dim3(256), 0, cx->stream, a);
     EBS_HIP(cx, hipGetLastError());
     return EBS_OK;
 }

@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "ebs_internal.h"
+#include "xcd.h"
 
 namespace ebs {
 namespace {
@@ -334,7 +335,7 @@ __global__ void __launch_bounds__(128) k_qtab(AArgs a, int32_t* qidx, double* qw
 // instances in one launch (blockIdx.y = instance)
 __global__ void __launch_bounds__(128) k_qhat(AArgs a) {
     const int inst = blockIdx.y;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
     if (t >= a.ns[inst]) return;
     const size_t e = (size_t)a.sbase[inst] + t;
     int32_t id[LSQ_MAXEV];
@@ -455,7 +456,7 @@ __device__ __forceinline__ void grad_group(const AArgs& a, int inst, int f0, int
 __global__ void __launch_bounds__(256) k_grad(AArgs a) {
     const int inst = blockIdx.y;
     const int lane = threadIdx.x % GRAD_LANES;
-    const int t = blockIdx.x * (256 / GRAD_LANES) + threadIdx.x / GRAD_LANES;
+    const int t = xcd_block() * (256 / GRAD_LANES) + threadIdx.x / GRAD_LANES;
     if (inst == 0)
         grad_group<2>(a, 0, 0, lane, t);
     else
@@ -543,7 +544,7 @@ template <typename T>
 __global__ void __launch_bounds__(128) k_final(FArgs<T> F) {
     const int inst = blockIdx.y;
     const int lane = threadIdx.x % FINAL_LANES;
-    const int t = (blockIdx.x * blockDim.x + threadIdx.x) / FINAL_LANES;
+    const int t = (xcd_block() * blockDim.x + threadIdx.x) / FINAL_LANES;
     if (inst == 0)
         final_group<T, 2>(F, 0, 0, lane, t);
     else
@@ -1096,9 +1097,11 @@ static ebs_status redistribute_t(ebs_ctx* cx, ebs_state* Uout) {
     a.limiter = cx->g.limiter;
     a.dv = cx->g.dx[0] * cx->g.dx[1] * cx->g.dx[2];
     if (nsmax > 0) {
-        hipLaunchKernelGGL(k_qhat, dim3((nsmax + 127) / 128, NINST), dim3(128), 0, cx->stream, a);
+        // x extents from xcd_grid: each XCD takes a contiguous chunk of every
+        // instance's list (xcd.h)
+        hipLaunchKernelGGL(k_qhat, dim3(xcd_grid((nsmax + 127) / 128), NINST), dim3(128), 0, cx->stream, a);
         const int per = 256 / GRAD_LANES;
-        hipLaunchKernelGGL(k_grad, dim3((nsmax + per - 1) / per, NINST), dim3(256), 0, cx->stream, a);
+        hipLaunchKernelGGL(k_grad, dim3(xcd_grid((nsmax + per - 1) / per), NINST), dim3(256), 0, cx->stream, a);
     }
     if (namax > 0) {
         FArgs<T> F;
@@ -1107,7 +1110,8 @@ static ebs_status redistribute_t(ebs_ctx* cx, ebs_state* Uout) {
         F.ny = cx->ny;
         F.nz = cx->nz;
         for (int f = 0; f < 5; ++f) F.out[f] = (T*)ou[f];
-        hipLaunchKernelGGL(k_final<T>, dim3((namax * FINAL_LANES + 127) / 128, NINST), dim3(128), 0, cx->stream, F);
+        hipLaunchKernelGGL(k_final<T>, dim3(xcd_grid(((long long)namax * FINAL_LANES + 127) / 128), NINST), dim3(128),
+                           0, cx->stream, F);
     }
     EBS_HIP(cx, hipGetLastError());
     return EBS_OK;

@@ -23,7 +23,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = [os.path.join(HERE, "csrc", n) for n in ("bulk.hip", "stage_common.h")]
-GENERAL_SOURCES = [os.path.join(HERE, "csrc", n) for n in ("stage.hip", "wsrd.hip", "stage_common.h")]
+GENERAL_SOURCES = [os.path.join(HERE, "csrc", n) for n in ("stage.hip", "wsrd.hip", "stage_common.h", "xcd.h")]
 COPY_BYTES = 1 << 30
 # the kernels of a stage besides the regular-region one
 GENERAL_PASSES = ("k_gen_prims", "k_gen_fhat", "k_gen_cut", "k_gen_update", "k_qhat", "k_grad", "k_final")
