@@ -243,7 +243,7 @@ ebs_status ebs_destroy(ebs_ctx* c) {
     if (c->side) (void)hipStreamDestroy(c->side);
     void* ptrs[] = {c->d_kf,   c->d_kr,        c->d_g0,      c->d_g1,   c->d_goff, c->d_gcol,
                     c->d_geo,  c->d_type,      c->d_mask,    c->d_small, c->d_tier, c->d_w,
-                    c->d_smalllist, c->d_actlist, c->d_lsq_off, c->d_lsq_idx, c->d_lsq_c, c->d_lsq_ev, c->d_lsq_nev, c->d_wl_off, c->d_wl_idx, c->d_wl_geo, c->d_wl_self, c->d_wl_small, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles, c->d_prim, c->d_fh, c->d_type4, c->d_col, c->d_gcole, c->d_fflag, c->d_cbase, c->d_crec, c->d_bfc,
+                    c->d_smalllist, c->d_actlist, c->d_lsq_off, c->d_lsq_idx, c->d_lsq_c, c->d_lsq_ev, c->d_lsq_nev, c->d_wl_off, c->d_wl_idx, c->d_wl_geo, c->d_wl_self, c->d_wl_small, c->d_uhat, c->d_qhat, c->d_sig,  c->d_tiles, c->d_prim, c->d_fh, c->d_type4, c->d_col, c->d_gcole, c->d_fflag, c->d_cbase, c->d_cut_n, c->d_cut_w, c->d_bfc,
                     c->d_ptab, c->d_ftab, c->d_utab, c->d_sten, c->d_upd, c->d_q_idx, c->d_q_w, c->d_q_den, c->d_q_n, c->d_chk, c->d_part, c->d_dummy,
                     c->d_srcf, c->d_srcd, c->d_srcv, c->d_dop_off, c->d_dop_idx, c->d_dop_w, c->d_dop_cell,
                     c->d_dflux, c->d_dtab, c->d_vop_off, c->d_vop_pt, c->d_vop_w, c->d_vflux,

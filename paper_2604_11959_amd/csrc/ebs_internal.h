@@ -160,7 +160,10 @@ struct ebs_ctx {
     int32_t* d_gcole = nullptr;      // [Ge]
     uint32_t* d_fflag = nullptr;     // [G]
     int32_t* d_cbase = nullptr;      // [G] first cut-face record of each general cell
-    void* d_crec = nullptr;          // cut-face interpolation records (stage.hip)
+    // cut-face interpolation records (stage.hip): {n0, n1, n2, own |
+    // (instance * 3 + direction) << 28} and [5][ncut] {b, c0..c3}
+    int4* d_cut_n = nullptr;
+    double* d_cut_w = nullptr;
     double* d_bfc = nullptr;         // [2][ncut] interpolated flux per record (per stage)
     int32_t ncut = 0;
     double* d_geo = nullptr;
@@ -197,7 +200,7 @@ struct ebs_ctx {
     int64_t nlsq_pts = 0;             // least-squares fit points, all small CVs
     int32_t* d_lsq_off = nullptr;     // [nlsq + 1] first fit point of each small CV
     uint32_t* d_lsq_idx = nullptr;    // [pts] general index (| flag: Q-hat is the CV's own)
-    double* d_lsq_c = nullptr;        // [pts][3] A^-1 e_s in mesh units
+    double* d_lsq_c = nullptr;        // [3][pts] A^-1 e_s in mesh units
     double* d_lsq_ev = nullptr;       // [nlsq][8][3] limiter evaluation offsets
     int8_t* d_lsq_nev = nullptr;      // [nlsq]
     int32_t abase[4] = {0, 0, 0, 0};  // offset of each instance in the concatenated active list

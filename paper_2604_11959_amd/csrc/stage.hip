@@ -63,7 +63,10 @@ struct GenArgs {
     const int32_t* upd;    // [9][G] update table: the three upper neighbours' lower faces
     double* fh;    // [5][3][Ge] provisional flux on the lower faces
     const int32_t* cbase;  // [G] first cut-face record of each general cell
-    const struct CutRec* crec;
+    // cut-face records: {n0, n1, n2, own | (instance * 3 + direction) << 28}
+    // and [5][ncut] {b, c0, c1, c2, c3}
+    const int4* cut_n;
+    const double* cut_w;
     double* bfc;           // [2][ncut] area fraction x interpolated flux per record
     int32_t ncut;
     double cdt;
@@ -687,23 +690,40 @@ __global__ void __launch_bounds__(256) k_gen_update(GenArgs<T> a) {
 
 // Area fraction x flux moved to the centroid on every partial face, for the
 // field(s) of the face's instance (slot 1: rho theta of the cell-centred CVs).
+// The records are stored as structure of arrays, so each of their loads
+// reads consecutive words across the wave.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gen_cut(GenArgs<T> a) {
     const int r = xcd_block() * blockDim.x + threadIdx.x;
     if (r >= a.ncut) return;
-    const CutRec c = a.crec[r];
-    const int s = c.sd / 3, d = c.sd - 3 * s;
-    const int n0 = max(c.n[0], 0), n1 = max(c.n[1], 0), n2 = max(c.n[2], 0);
+    const size_t N = a.ncut;
+    const int4 nn = a.cut_n[r];
+    const int own = nn.w & 0x0FFFFFFF, sd = (int)((uint32_t)nn.w >> 28);
+    const double b = a.cut_w[r], c0 = a.cut_w[N + r], c1 = a.cut_w[2 * N + r], c2 = a.cut_w[3 * N + r],
+                 c3 = a.cut_w[4 * N + r];
+    const int s = sd / 3, d = sd - 3 * s;
+    const int n0 = max(nn.x, 0), n1 = max(nn.y, 0), n2 = max(nn.z, 0);
     for (int q = 0; q < (s == 0 ? 2 : 1); ++q) {
         const int f = s == 0 ? q : s + 1;
         const double* fhd = a.fh + ((size_t)f * 3 + d) * a.v.Ge;
-        const double F0 = fhd[c.own], F1 = fhd[n0], F2 = fhd[n1], F3 = fhd[n2];
-        double Fv = c.c[0] * F0;
-        if (c.n[0] >= 0) Fv += c.c[1] * F1;
-        if (c.n[1] >= 0) Fv += c.c[2] * F2;
-        if (c.n[2] >= 0) Fv += c.c[3] * F3;
-        a.bfc[(size_t)q * a.ncut + r] = c.b * Fv;
+        const double F0 = fhd[own], F1 = fhd[n0], F2 = fhd[n1], F3 = fhd[n2];
+        double Fv = c0 * F0;
+        if (nn.x >= 0) Fv += c1 * F1;
+        if (nn.y >= 0) Fv += c2 * F2;
+        if (nn.z >= 0) Fv += c3 * F3;
+        a.bfc[(size_t)q * N + r] = b * Fv;
     }
+}
+
+// the records as structure of arrays (set-up)
+__global__ void __launch_bounds__(256) k_cut_soa(const CutRec* rec, int32_t n, int4* cn, double* cw) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const CutRec c = rec[r];
+    cn[r] = make_int4(c.n[0], c.n[1], c.n[2], (int32_t)((uint32_t)c.own | ((uint32_t)c.sd << 28)));
+    const size_t N = n;
+    cw[r] = c.b;
+    for (int q = 0; q < 4; ++q) cw[(q + 1) * N + r] = c.c[q];
 }
 
 // number of partial lower faces (area fraction > 0 and not exactly 1) per general cell
@@ -809,9 +829,11 @@ __global__ void __launch_bounds__(256) k_ptab_fill(GenArgs<double> a, const int2
 ebs_status build_cut_faces(ebs_ctx* cx) {
     const int32_t G = cx->G;
     if (cx->d_cbase) (void)hipFree(cx->d_cbase);
-    if (cx->d_crec) (void)hipFree(cx->d_crec);
+    if (cx->d_cut_n) (void)hipFree(cx->d_cut_n);
+    if (cx->d_cut_w) (void)hipFree(cx->d_cut_w);
     cx->d_cbase = nullptr;
-    cx->d_crec = nullptr;
+    cx->d_cut_n = nullptr;
+    cx->d_cut_w = nullptr;
     cx->ncut = 0;
     if (G == 0) return EBS_OK;
     int32_t* d_bad = nullptr;
@@ -838,32 +860,49 @@ ebs_status build_cut_faces(ebs_ctx* cx) {
         cx->err = "too many cut faces";
         return EBS_E_UNSUPPORTED;
     }
+    if (cx->Ge >= (1 << 28)) {  // face-range indices share a word with (instance, direction)
+        (void)hipFree(d_bad);
+        cx->err = "face range too large for the cut-face records";
+        return EBS_E_UNSUPPORTED;
+    }
     cx->ncut = (int32_t)tot;
     if (cx->d_bfc) (void)hipFree(cx->d_bfc);
     cx->d_bfc = nullptr;
-    if (hipMalloc(&cx->d_crec, sizeof(CutRec) * std::max<int64_t>(tot, 1)) != hipSuccess ||
-        hipMalloc(&cx->d_bfc, sizeof(double) * 2 * std::max<int64_t>(tot, 1)) != hipSuccess) {
+    const int64_t n1 = std::max<int64_t>(tot, 1);
+    CutRec* rec = nullptr;  // the records as built (set-up only)
+    auto fail = [&](ebs_status st, const char* msg) {
+        if (rec) (void)hipFree(rec);
         (void)hipFree(d_bad);
-        cx->err = "cut-face table allocation failed";
-        return EBS_E_OOM;
-    }
-    EBS_HIP(cx, hipMemcpyAsync(cx->d_cbase, cnt.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, cx->stream));
-    EBS_HIP(cx, hipMemsetAsync(d_bad, 0, sizeof(int32_t), cx->stream));
+        cx->err = msg;
+        return st;
+    };
+    if (hipMalloc(&rec, sizeof(CutRec) * n1) != hipSuccess || hipMalloc(&cx->d_bfc, sizeof(double) * 2 * n1) != hipSuccess ||
+        hipMalloc(&cx->d_cut_n, sizeof(int4) * n1) != hipSuccess ||
+        hipMalloc(&cx->d_cut_w, sizeof(double) * 5 * n1) != hipSuccess)
+        return fail(EBS_E_OOM, "cut-face table allocation failed");
+    auto hip_ok = [&](hipError_t e) { return e == hipSuccess; };
+    if (!hip_ok(hipMemcpyAsync(cx->d_cbase, cnt.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, cx->stream)) ||
+        !hip_ok(hipMemsetAsync(d_bad, 0, sizeof(int32_t), cx->stream)))
+        return fail(EBS_E_HIP, "cut-face table upload failed");
     GenArgs<double> a{};
     a.D = Dims{cx->nx, cx->ny, cx->nz};
     a.v = v;
     a.cbase = cx->d_cbase;
-    hipLaunchKernelGGL(k_cut_fill, dim3((G + 127) / 128), dim3(128), 0, cx->stream, a, (CutRec*)cx->d_crec,
-                       d_bad);
-    EBS_HIP(cx, hipGetLastError());
+    hipLaunchKernelGGL(k_cut_fill, dim3((G + 127) / 128), dim3(128), 0, cx->stream, a, rec, d_bad);
     int32_t bad = 0;
-    EBS_HIP(cx, hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, cx->stream));
-    EBS_HIP(cx, hipStreamSynchronize(cx->stream));
-    (void)hipFree(d_bad);
-    if (bad != 0) {
-        cx->err = "a cut-face interpolation neighbour lies outside the stored face range";
-        return EBS_E_UNSUPPORTED;
+    if (!hip_ok(hipGetLastError()) ||
+        !hip_ok(hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, cx->stream)) ||
+        !hip_ok(hipStreamSynchronize(cx->stream)))
+        return fail(EBS_E_HIP, "cut-face record build failed");
+    if (bad != 0) return fail(EBS_E_UNSUPPORTED, "a cut-face interpolation neighbour lies outside the stored face range");
+    if (tot > 0) {
+        hipLaunchKernelGGL(k_cut_soa, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, cx->stream, rec, (int32_t)tot,
+                           cx->d_cut_n, cx->d_cut_w);
+        if (!hip_ok(hipGetLastError()) || !hip_ok(hipStreamSynchronize(cx->stream)))
+            return fail(EBS_E_HIP, "cut-face record build failed");
     }
+    (void)hipFree(rec);
+    (void)hipFree(d_bad);
     return EBS_OK;
 }
 
@@ -1045,7 +1084,8 @@ static ebs_status advance_t(ebs_ctx* cx, const ebs_state* Un, const ebs_state* U
         a.upd = cx->d_upd;
         a.fh = cx->d_fh;
         a.cbase = cx->d_cbase;
-        a.crec = (const CutRec*)cx->d_crec;
+        a.cut_n = cx->d_cut_n;
+        a.cut_w = cx->d_cut_w;
         a.bfc = cx->d_bfc;
         a.ncut = cx->ncut;
         a.cdt = cdt;

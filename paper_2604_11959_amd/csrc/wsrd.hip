@@ -269,7 +269,8 @@ struct AArgs {
     int32_t sbase[NINST]; // offset of each instance in the concatenated small list
     const int32_t* loff;  // [S+1] least-squares operators (CSR)
     const uint32_t* lidx; // [P]
-    const double* lc;     // [P][3]
+    const double* lc;     // [3][P]
+    int64_t npts;         // P
     const double* lev;    // [S][LSQ_MAXEV][3]
     const int8_t* lnev;   // [S]
     int32_t abase[NINST]; // offset of each instance in the concatenated active list
@@ -393,7 +394,7 @@ __device__ __forceinline__ void grad_group(const AArgs& a, int inst, int f0, int
     }
     for (int p = p0 + lane; p < p1; p += GRAD_LANES) {
         const uint32_t id = a.lidx[p];
-        const double c0 = a.lc[3 * (size_t)p], c1 = a.lc[3 * (size_t)p + 1], c2 = a.lc[3 * (size_t)p + 2];
+        const double c0 = a.lc[p], c1 = a.lc[a.npts + p], c2 = a.lc[2 * a.npts + p];
 #pragma unroll
         for (int n = 0; n < NF; ++n) {
             const size_t fo = (size_t)(f0 + n) * v.G;
@@ -631,7 +632,8 @@ struct LArgs {
     int32_t* cnt;          // [S]
     const int32_t* off;    // [S+1]
     uint32_t* idx;
-    double* c;
+    double* c;             // [3][npts]
+    int64_t npts;
     double* ev;
     int8_t* nev;
     int32_t* bad;          // counts fit points above the general range
@@ -737,7 +739,7 @@ __global__ void __launch_bounds__(64) k_lsq(LArgs a) {
                 const bool own = a.small[(size_t)inst * v.G + gs] && W(WQ_KAPPA, gs) > 0.0;
                 a.idx[p] = (uint32_t)gs | (own ? LSQ_QHAT : 0u);
                 for (int r = 0; r < 3; ++r)
-                    a.c[3 * (size_t)p + r] = inv[r][0] * es[0] + inv[r][1] * es[1] + inv[r][2] * es[2];
+                    a.c[r * a.npts + p] = inv[r][0] * es[0] + inv[r][1] * es[1] + inv[r][2] * es[2];
                 ++p;
             }
     const int32_t m = a.mask[(size_t)inst * v.G + g];
@@ -921,6 +923,7 @@ ebs_status wsrd_setup(ebs_ctx* cx) {
         L.off = cx->d_lsq_off;
         L.idx = cx->d_lsq_idx;
         L.c = cx->d_lsq_c;
+        L.npts = P;
         L.ev = cx->d_lsq_ev;
         L.nev = cx->d_lsq_nev;
         hipLaunchKernelGGL(k_lsq, lgrid, dim3(64), 0, cx->stream, L);
@@ -1082,6 +1085,7 @@ static ebs_status redistribute_t(ebs_ctx* cx, ebs_state* Uout) {
     a.loff = cx->d_lsq_off;
     a.lidx = cx->d_lsq_idx;
     a.lc = cx->d_lsq_c;
+    a.npts = cx->nlsq_pts;
     a.lev = cx->d_lsq_ev;
     a.lnev = cx->d_lsq_nev;
     for (int inst = 0; inst < NINST; ++inst) a.abase[inst] = cx->abase[inst];
