@@ -11,6 +11,8 @@ counter (FETCH_SIZE counts some request sizes at half width).  The summary
 records the mean calibrated bytes per regular-region launch, a SHA-256 of
 the kernel source and the algorithmic bytes of one launch (which fix the
 regular region it covered), so that a later change of either invalidates it.
+It also records the calibrated bytes per stage of each pass over the general
+range and the redistribution, with a SHA-256 of their sources.
 """
 from __future__ import annotations
 
@@ -30,7 +32,7 @@ GENERAL_PASSES = ("k_gen_prims", "k_gen_fhat", "k_gen_cut", "k_gen_update", "k_q
 
 
 def source_sha256(paths=None) -> str:
-    """SHA-256 over the regular-region kernel's sources."""
+    """SHA-256 over the given sources (default: the regular-region kernel's)."""
     h = hashlib.sha256()
     for path in paths or KERNEL_SOURCES:
         with open(path, "rb") as f:
