@@ -164,7 +164,14 @@ __device__ __forceinline__ T ld(const T* __restrict__ base, uint32_t off) {
 }
 template <typename T>
 __device__ __forceinline__ void st(T* base, uint32_t off, T v) {
-    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(off * (uint32_t)sizeof(T))) = v;
+    // written once per stage and not read again by this launch: streaming store
+    __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(off * (uint32_t)sizeof(T))));
+}
+// own-cell U^n values, read once per launch: streaming load
+template <typename T>
+__device__ __forceinline__ T ld_once(const T* __restrict__ base, uint32_t off) {
+    return __builtin_nontemporal_load(
+        reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(off * (uint32_t)sizeof(T))));
 }
 
 // One tile of the regular-region update (the whole 2.5-D march of a block).
@@ -350,11 +357,11 @@ __device__ __forceinline__ void bulk_tile(const BulkArgs<T>& a, int t, T* sm) {
     const uint32_t ov0 = (uint32_t)(j * nx + i);
     auto fetch_un = [&](int kk, T (&dst)[5]) {
         if (act && kk < z1 && kk >= ge) {
-            dst[0] = ld(a.un[0], (uint32_t)kk * pc + c0);
-            dst[1] = ld(a.un[1], (uint32_t)kk * pc + c0);
-            dst[2] = ld(a.un[2], (uint32_t)kk * pu + u0);
-            dst[3] = ld(a.un[3], (uint32_t)kk * pv + ov0);
-            dst[4] = ld(a.un[4], (uint32_t)kk * pc + c0);
+            dst[0] = ld_once(a.un[0], (uint32_t)kk * pc + c0);
+            dst[1] = ld_once(a.un[1], (uint32_t)kk * pc + c0);
+            dst[2] = ld_once(a.un[2], (uint32_t)kk * pu + u0);
+            dst[3] = ld_once(a.un[3], (uint32_t)kk * pv + ov0);
+            dst[4] = ld_once(a.un[4], (uint32_t)kk * pc + c0);
         } else {
 #pragma unroll
             for (int f = 0; f < 5; ++f) dst[f] = T(0);

@@ -125,11 +125,12 @@ __global__ void __launch_bounds__(TX * TY) k_diff_regular(RegDiffArgs<T> a) {
     T oo[4] = {T(0), T(0), T(0), T(0)};
     auto fetch_out = [&](int kk) {
         if (!(act && kk >= kmin && kk >= kg && kk < nz)) return;
-        if (TH) oo[0] = a.out_rt[((size_t)kk * ny + j) * nx + i];
+        // read once and written back once by this launch: streaming accesses
+        if (TH) oo[0] = __builtin_nontemporal_load(&a.out_rt[((size_t)kk * ny + j) * nx + i]);
         if (VI) {
-            oo[1] = a.out[0][((size_t)kk * ny + j) * (nx + 1) + i];
-            oo[2] = a.out[1][((size_t)kk * (ny + 1) + j) * nx + i];
-            if (kk >= 1) oo[3] = a.out[2][((size_t)kk * ny + j) * nx + i];
+            oo[1] = __builtin_nontemporal_load(&a.out[0][((size_t)kk * ny + j) * (nx + 1) + i]);
+            oo[2] = __builtin_nontemporal_load(&a.out[1][((size_t)kk * (ny + 1) + j) * nx + i]);
+            if (kk >= 1) oo[3] = __builtin_nontemporal_load(&a.out[2][((size_t)kk * ny + j) * nx + i]);
         }
     };
     fetch_out(kmin - 1);
@@ -187,7 +188,7 @@ __global__ void __launch_bounds__(TX * TY) k_diff_regular(RegDiffArgs<T> a) {
                 if (k > 0) bz += face(rhm1, thm1);
                 br += bz * (rdz * rdz);
                 const size_t o = ((size_t)k * ny + j) * nx + i;
-                a.out_rt[o] = on[0] + a.cdt * br;
+                __builtin_nontemporal_store(on[0] + a.cdt * br, &a.out_rt[o]);
             }
             if (VI) {
                 // velocity slots of planes k - 1, k, k + 1
@@ -229,8 +230,8 @@ __global__ void __launch_bounds__(TX * TY) k_diff_regular(RegDiffArgs<T> a) {
                     const T br = (t1 - t0) * rdx + (exy(0, 1) - xy00) * rdy + (zhi - zlo) * rdz;
                     const size_t o = ((size_t)k * ny + j) * (nx + 1) + i;
                     const T val = on[1] + a.cdt * br;
-                    a.out[0][o] = val;
-                    if (i == 0) a.out[0][o + nx] = val;
+                    __builtin_nontemporal_store(val, &a.out[0][o]);
+                    if (i == 0) __builtin_nontemporal_store(val, &a.out[0][o + nx]);
                 }
                 // v CV (faces at the cell centres j - 1 and j)
                 {
@@ -241,8 +242,8 @@ __global__ void __launch_bounds__(TX * TY) k_diff_regular(RegDiffArgs<T> a) {
                     const T br = (exy(1, 0) - xy00) * rdx + (t1 - t0) * rdy + (zhi - zlo) * rdz;
                     const size_t o = ((size_t)k * (ny + 1) + j) * nx + i;
                     const T val = on[2] + a.cdt * br;
-                    a.out[1][o] = val;
-                    if (j == 0) a.out[1][o + (size_t)ny * nx] = val;
+                    __builtin_nontemporal_store(val, &a.out[1][o]);
+                    if (j == 0) __builtin_nontemporal_store(val, &a.out[1][o + (size_t)ny * nx]);
                 }
                 // w CV (faces at the cell centres k - 1 and k; none on the bottom wall)
                 if (k >= 1) {
@@ -251,7 +252,7 @@ __global__ void __launch_bounds__(TX * TY) k_diff_regular(RegDiffArgs<T> a) {
                     const T br =
                         (exz(Vm, V0, 1) - xz_lo) * rdx + (eyz(Vm, V0, 1) - yz_lo) * rdy + (t1 - t0) * rdz;
                     const size_t o = ((size_t)k * ny + j) * nx + i;
-                    a.out[2][o] = on[3] + a.cdt * br;
+                    __builtin_nontemporal_store(on[3] + a.cdt * br, &a.out[2][o]);
                 }
             }
         }

@@ -230,7 +230,7 @@ def _hills_with_flat_ground(nz=40):
 @pytest.mark.parametrize("terrain", ["hills", "flat"])
 @pytest.mark.parametrize("precision,tiles,tol", [
     (ebs.EBS_F64, ((16, 4, 16), (16, 8, 64)), 1e-12),
-    (ebs.EBS_F32_BULK, ((16, 16, 16), (32, 8, 32), (32, 8, 64, 1), (64, 16, 64, 1)), 2e-5),
+    (ebs.EBS_F32_BULK, ((16, 16, 16), (32, 8, 32), (32, 16, 16), (32, 8, 64, 1), (64, 16, 64, 1)), 2e-5),
 ])
 def test_bottom_wall_and_flat_ground(terrain, precision, tiles, tol):
     """Columns with no cut CV nearby have an empty general range: the
@@ -651,7 +651,7 @@ def test_stage_parity_rough_vertical_momentum_c2():
 
 
 @pytest.mark.parametrize("precision,tile", [(ebs.EBS_F64, (16, 8, 32, 0)), (ebs.EBS_F32_BULK, (64, 16, 64, 0)),
-                                            (ebs.EBS_F32_BULK, (32, 8, 16, 0))])
+                                            (ebs.EBS_F32_BULK, (32, 8, 16, 0)), (ebs.EBS_F32_BULK, (32, 16, 16, 0))])
 def test_persistent_schedule_gives_identical_bits(precision, tile):
     """Per-box tiles (many more tiles than resident blocks) run by a grid of
     resident blocks walking the tile list give the same bits as one block
