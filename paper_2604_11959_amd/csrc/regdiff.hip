@@ -29,6 +29,7 @@
 
 #include "ebs_internal.h"
 #include "stage_common.h"
+#include "xcd.h"
 
 namespace ebs {
 namespace {
@@ -61,7 +62,12 @@ __global__ void __launch_bounds__(TX * TY) k_diff_regular(RegDiffArgs<T> a) {
     const int nx = a.D.nx, ny = a.D.ny, nz = a.D.nz;
     const int t = threadIdx.x;
     const int tx = t % TX, ty = t / TX;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    // tiles in row-major order, one contiguous run of rows of tiles per XCD
+    // (xcd.h), so the halo lines two neighbouring tiles share stay in one L2
+    const int ntx = (nx + TX - 1) / TX;
+    const int tile = xcd_block();
+    if (tile >= ntx * ((ny + TY - 1) / TY)) return;  // block uniform
+    const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
     const int i = x0 + tx, j = y0 + ty;
     const bool act = i < nx && j < ny;
     const int kg = act ? a.g1[j * nx + i] : nz;
@@ -287,7 +293,7 @@ ebs_status launch_t(ebs_ctx* cx, const ebs_state* Ucur, ebs_state* Uh, double cd
     a.lam = (T)(-2.0 / 3.0 * mu);
     a.cdt = (T)cdt;
     for (int d = 0; d < 3; ++d) a.rd[d] = (T)(1.0 / cx->g.dx[d]);
-    const dim3 grid((cx->nx + RD_TX - 1) / RD_TX, (cx->ny + RD_TY - 1) / RD_TY);
+    const dim3 grid(xcd_grid((long long)((cx->nx + RD_TX - 1) / RD_TX) * ((cx->ny + RD_TY - 1) / RD_TY)));
     hipLaunchKernelGGL((k_diff_regular<T, RD_TX, RD_TY, TH, VI>), grid, dim3(RD_TX * RD_TY), 0, s, a);
     EBS_HIP(cx, hipGetLastError());
     return EBS_OK;
