@@ -175,7 +175,7 @@ struct ebs_ctx {
     // redistribution reads or writes, h_ftop, per column)
     int range_mode = 1;
     int geo_merged = 0;  // the build in progress merges the geometry of the grid refined by 2
-    int range_rule = 2;
+    int range_rule = 2;  // the strictest mode the geometry build tries (ebs_set_range_rule)
     // momentum sources (ebs_set_sources): per-level tables [5][nz] of p0,
     // rho theta0 (high, low part), 1 / rho theta0, rho0 in the state precision
     // and in FP64; per position of the prims pass {p', rho'} (FP64)
@@ -183,7 +183,7 @@ struct ebs_ctx {
     ebs_source_params src{};
     float* d_srcf = nullptr;
     double* d_srcd = nullptr;
-    double* d_srcv = nullptr;  // the strictest mode the geometry build tries (ebs_set_range_rule)
+    double* d_srcv = nullptr;  // [G + naux][2] {p', rho'} per position of the prims pass (sources on)
     std::vector<int32_t> h_ftop;  // [ncol] highest level the redistribution touches, -1 if none
 
     // redistribution
